@@ -1,0 +1,198 @@
+"""Phase-field twin evolution and energies (oracle, test only).
+
+Free energy, eq. (12): G = G_dw + G_gd + G_me, with
+* the multiphase double well of eq. (13), c1 sum_{a<b} f_a^2 f_b^2 over the
+  N_tw twin variants and the matrix (f_M = 1 - sum_a f_a, eq. (18));
+* the gradient energy of eq. (14); with eq. (18) its two gradient sums in the
+  rate equation collapse to c2 * laplacian(f_a);
+* the stored elastic energy of eq. (15), 1/2 eps_el : C(x) : eps_el.
+
+Evolution: eq. (16)/(17), linearised per eqs. (19)-(20) with the Laplacian
+implicit and the rest explicit, solved in Fourier space (Table 1, steps 5-9).
+
+Readings (stated once here, used below):
+* Symbols: A = c1, kappa = c2, and the mobility maps as c3 -> 2L on the
+  chemical and gradient terms and c3 -> L on the mechanical ones, so that a
+  single variant follows d(eta)/dt = -L dF/d(eta) for
+  F = int [A eta^2 (1-eta)^2 + kappa |grad eta|^2 + 1/2 eps_el:C:eps_el].
+* Chemical force: chem_a = 2A f_a sum_{b != a} f_b (f_b - f_a), b running
+  over the other variants and the matrix; for one variant this is
+  2A eta (1-eta)(1-2eta).
+* Mechanical force: mech_a = h'(f_a) [sigma : eps0_a
+  - 1/2 eps_el : (C_twin^a - C_g) : eps_el]; eq. (17) prints C_twin^a, the
+  derivative of eq. (5) gives the difference (C_twin^a - C_matrix).
+* One pass per variant per step: with f_M = 1 - sum f the implicit
+  coefficient is constant, so the fixed point i of Table 1 converges in one
+  solve; eq. (18) holds by construction, so the loop j is empty.
+* Mechanics solved at f^n (the paper also holds the strain fixed during the
+  phase-field solve, Sec. 2.2).
+* No clipping of f.
+* Gradient energy reported as kappa sum_a |grad f_a|^2 through Parseval with
+  the -|xi|^2 Laplacian symbol (equal to eq. (14) for one variant).
+"""
+
+import numpy as np
+
+from . import spectral
+from .mech import (GreenOperator, contract, dh_interp, h_interp, ms_solve,
+                   tensor_to_voigt6, voigt6_to_tensor)
+
+
+def chemical_force(eta, A):
+    """chem_a = 2A f_a sum_{b != a} f_b (f_b - f_a), b over variants + matrix."""
+    V = eta.shape[0]
+    f_m = 1.0 - eta.sum(axis=0)
+    chem = np.empty_like(eta)
+    for a in range(V):
+        s = f_m * (f_m - eta[a])
+        for b in range(V):
+            if b != a:
+                s = s + eta[b] * (eta[b] - eta[a])
+        chem[a] = 2.0 * A * eta[a] * s
+    return chem
+
+
+def mechanical_force(eta, sigma, eps_el, gid, C_grain, C_var, eps0, h_kind="linear"):
+    """mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]."""
+    dh = dh_interp(eta, h_kind)
+    if gid is None:
+        return _grain_mech(dh, sigma, eps_el, C_grain[0], C_var[0], eps0[0])
+    mech = np.empty_like(eta)
+    for g in np.unique(gid):
+        mask = gid == g
+        mech[:, mask] = _grain_mech(dh[:, mask], sigma[mask], eps_el[mask], C_grain[g], C_var[g], eps0[g])
+    return mech
+
+
+def _grain_mech(dh, sigma, eps_el, Cg, Cv, e0):
+    mech = np.empty_like(dh)
+    for a in range(dh.shape[0]):
+        work = np.einsum("...ij,ij->...", sigma, e0[a])
+        stiff = 0.5 * np.einsum("...ij,...ij->...", eps_el, contract(Cv[a] - Cg, eps_el))
+        mech[a] = dh[a] * (work - stiff)
+    return mech
+
+
+def double_well_density(eta, A):
+    """A sum_{a<b} f_a^2 f_b^2 over the variants and the matrix."""
+    phases = list(eta) + [1.0 - eta.sum(axis=0)]
+    g = np.zeros_like(eta[0])
+    for a in range(len(phases)):
+        for b in range(a + 1, len(phases)):
+            g = g + phases[a] ** 2 * phases[b] ** 2
+    return A * g
+
+
+def gradient_energy(eta, kappa, dx):
+    """kappa sum_a int |grad f_a|^2 dV by Parseval with the |xi|^2 symbol."""
+    shape = eta.shape[1:]
+    xi = spectral.wavevectors(shape, dx)
+    xi2 = (xi ** 2).sum(axis=-1)
+    w = spectral.half_spectrum_weights(shape)
+    ntot = np.prod(shape)
+    dV = dx ** 3
+    total = 0.0
+    for a in range(eta.shape[0]):
+        F = spectral.rfft3(eta[a], workers=-1)
+        total += (w * xi2 * np.abs(F) ** 2).sum() * dV / ntot
+    return kappa * total
+
+
+def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx):
+    """f^{n+1} = IFFT[ FFT(f^n - L dt (chem - mech)) / (1 + 2 L dt kappa |xi|^2) ]."""
+    shape = eta.shape[1:]
+    xi = spectral.wavevectors(shape, dx)
+    xi2 = (xi ** 2).sum(axis=-1)
+    denom = 1.0 + 2.0 * L * dt * kappa * xi2
+    out = np.empty_like(eta)
+    for a in range(eta.shape[0]):
+        rhs = eta[a] - L * dt * (chem[a] - mech[a])
+        out[a] = spectral.irfft3(spectral.rfft3(rhs, workers=-1) / denom, shape, workers=-1)
+    return out
+
+
+class Problem:
+    """Everything fixed over a run (the analogue of the library's problem).
+
+    tables = (C_grain, C_var, eps0) as returned by crystal.mg_tables.
+    C0: reference stiffness (3,3,3,3) for the fixed point.
+    """
+
+    def __init__(self, shape, dx, tables, A, kappa, L, dt, C0, gid=None,
+                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200):
+        self.shape = tuple(shape)
+        self.dx = float(dx)
+        self.tables = tables
+        self.A, self.kappa, self.L, self.dt = float(A), float(kappa), float(L), float(dt)
+        self.gid = None if gid is None else np.asarray(gid, dtype=np.int64)
+        self.h_kind = h_kind
+        self.ms_tol, self.ms_max_iter = ms_tol, ms_max_iter
+        self.green = GreenOperator(C0, self.shape, self.dx)
+
+
+class State:
+    """eta (V, nz, ny, nx); eps (nz, ny, nx, 3, 3) warm start; ebar (3, 3)."""
+
+    def __init__(self, eta, eps, ebar):
+        self.eta = np.asarray(eta, dtype=np.float64)
+        self.eps = eps
+        self.ebar = ebar
+
+    @classmethod
+    def initial(cls, eta0, eps_bar6):
+        eta0 = np.asarray(eta0, dtype=np.float64)
+        ebar = voigt6_to_tensor(np.asarray(eps_bar6, dtype=np.float64))
+        eps = np.broadcast_to(ebar, eta0.shape[1:] + (3, 3)).copy()
+        return cls(eta0, eps, ebar)
+
+
+def step(prob, state, eps_p6, load):
+    """One time step: equilibrium at f^n, then the Allen-Cahn update.
+
+    eps_p6: (6, nz, ny, nx) plastic strain (tensor-Voigt) or None.
+    load: dict with eps_bar (6), sig_bar (6), stress_mask (6 bools).
+    Returns (new_state, stats) where stats describe the state at f^n.
+    """
+    C_grain, C_var, eps0 = prob.tables
+    shape = prob.shape
+    if eps_p6 is None:
+        eps_p = np.zeros(shape + (3, 3))
+    else:
+        eps_p = voigt6_to_tensor(eps_p6)
+    eps, ebar, sigma, eps_el, _, iters, res = ms_solve(
+        state.eps, state.ebar, state.eta, eps_p, prob.gid, prob.tables, prob.green,
+        load, prob.ms_tol, prob.ms_max_iter, prob.h_kind)
+    chem = chemical_force(state.eta, prob.A)
+    mech = mechanical_force(state.eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
+    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx)
+    dV = prob.dx ** 3
+    stats = {
+        "G_dw": float(double_well_density(state.eta, prob.A).sum() * dV),
+        "G_gd": float(gradient_energy(state.eta, prob.kappa, prob.dx)),
+        "G_me": float(0.5 * np.einsum("...ij,...ij->...", eps_el, sigma).sum() * dV),
+        "sig_mean": tensor_to_voigt6(sigma.mean(axis=(0, 1, 2))),
+        "eps_mean": tensor_to_voigt6(eps.mean(axis=(0, 1, 2))),
+        "eta_mean": state.eta.mean(axis=(1, 2, 3)),
+        "ms_iters": iters,
+        "ms_residual": res,
+    }
+    stats["G"] = stats["G_dw"] + stats["G_gd"] + stats["G_me"]
+    return State(eta_new, eps, ebar), stats, sigma
+
+
+def stress_voigt6(sigma):
+    return tensor_to_voigt6(sigma)
+
+
+def reference_stiffness_average(C_grain, C_var):
+    """Arithmetic mean of every grain and twin-variant stiffness: the default
+    reference medium for the fixed point (reading; the paper has no solver of
+    this kind)."""
+    mats = [C_grain[g] for g in range(C_grain.shape[0])]
+    mats += [C_var[g, a] for g in range(C_var.shape[0]) for a in range(C_var.shape[1])]
+    return np.mean(mats, axis=0)
+
+
+__all__ = ["chemical_force", "mechanical_force", "double_well_density",
+           "gradient_energy", "allen_cahn_update", "Problem", "State", "step",
+           "h_interp", "reference_stiffness_average", "stress_voigt6"]
