@@ -1,0 +1,178 @@
+/*
+ * pf.h - C ABI of the MI355X (gfx950) FFT phase-field twin-propagation step.
+ *
+ * One call of pf_step advances the twin volume fractions f_alpha of one
+ * periodic grid by one time step of the phase-field model of twinning of
+ * Zhang, Ma & Llorca (Sec. 2.2 and Sec. 3 of the paper):
+ *   1. micro-elastic equilibrium at f^n for the eigenstrain
+ *      eps* = eps_p + sum_a h(f_a) eps0_a and the mixture stiffness
+ *      C(x) = C_g + sum_a h(f_a) (C_twin^a - C_g) (eq. (5)), solved by a
+ *      Moulinec-Suquet fixed point with a Fourier-space Green's operator
+ *      under a mixed mean strain/stress condition;
+ *   2. the driving forces of eq. (17): double well (eq. (13)), gradient
+ *      (eq. (14)) and elastic (eq. (15)) terms;
+ *   3. the linearised semi-implicit update of eqs. (19)-(20), solved in
+ *      Fourier space (Table 1, steps 5-9):
+ *      f^{n+1} = IFFT[FFT(f^n - L dt (chem - mech)) / (1 + 2 L dt kappa |xi|^2)];
+ *   4. FP64 reductions: energies (eq. (12)), mean stress and strain, mean f.
+ * The plastic strain eps_p is the per-voxel input handed over by the crystal
+ * plasticity side (Table 1, steps 1-2); f goes back to it (Table 1, step 12).
+ *
+ * Conventions
+ *   Grid fields are float32, component-major, [comp][z][y][x] with x
+ *   contiguous. Symmetric tensors use 6 tensor-Voigt components in the order
+ *   xx, yy, zz, yz, xz, xy with TENSOR (not engineering) shear. 6x6 stiffness
+ *   matrices are Voigt matrices in the engineering convention
+ *   (sigma_I = C_IJ gamma_J, gamma = (e_xx, e_yy, e_zz, 2e_yz, 2e_xz, 2e_xy)),
+ *   row-major, in Pa. Spectra are [comp][z][y][x/2+1] complex float32
+ *   (interleaved re, im), unnormalised forward transform.
+ *
+ * Memory and streams
+ *   Every device buffer is owned by the caller. pf_init receives one device
+ *   workspace of at least pf_workspace_size() bytes and keeps pointers into
+ *   it; the library allocates only a small block of pinned host memory for
+ *   the convergence status (freed by pf_destroy). All work is enqueued on
+ *   the HIP stream given to pf_init (NULL = the default stream).
+ *
+ * Errors
+ *   Every int-returning call returns PF_OK (0) or a negative PF_E* code and
+ *   never throws. Argument errors are detected before any work is enqueued.
+ *   Device-side conditions (non-finite fields, fixed point not converged)
+ *   surface at the end of the pf_step call that met them. pf_last_error()
+ *   gives a text description of the last failure on that context.
+ */
+#ifndef PF_TWIN_H
+#define PF_TWIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_OK             0
+#define PF_EINVAL        -1   /* bad argument or unsupported size          */
+#define PF_ENOMEM        -2   /* workspace too small                        */
+#define PF_EDEVICE       -3   /* HIP runtime error                          */
+#define PF_ENOCONV       -4   /* equilibrium fixed point did not converge   */
+#define PF_ENONFINITE    -5   /* NaN/Inf met in the order parameter         */
+#define PF_EUNSUPPORTED  -6   /* valid request this build does not support  */
+
+#define PF_H_LINEAR   0       /* h(f) = f                                   */
+#define PF_H_QUINTIC  1       /* h(f) = f^3 (6 f^2 - 15 f + 10)             */
+
+/* pf_step flags */
+#define PF_STEP_SAVE_STRESS  1u  /* keep the equilibrium stress of the step  */
+
+/* pf_fields selectors */
+#define PF_FIELD_ETA     0    /* [n_var][nz][ny][nx]  order parameters       */
+#define PF_FIELD_STRAIN  1    /* [6][nz][ny][nx]      total strain (state)   */
+#define PF_FIELD_STRESS  2    /* [6][nz][ny][nx]      stress of the last step
+                                 run with PF_STEP_SAVE_STRESS (get only)     */
+
+typedef struct pf_ctx pf_ctx;
+
+/* Problem fixed over a run. Supported sizes: nx, ny, nz each in
+ * {32, 48, 64, 96, 128, 256}; n_var in 1..6; n_grains in 1..255. */
+typedef struct {
+  int32_t nx, ny, nz;
+  double dx;               /* voxel edge, m                                 */
+  int32_t n_var;           /* twin variants carried per voxel               */
+  double A;                /* double-well height c1 (eq. (13)), J/m^3       */
+  double kappa;            /* gradient coefficient c2 (eq. (14)), J/m       */
+  double L;                /* mobility (c3 of eq. (16)), m^3/(J s)          */
+  double dt;               /* time step, s                                  */
+  int32_t h_kind;          /* PF_H_LINEAR or PF_H_QUINTIC                   */
+  int32_t n_grains;
+  const double *C_grain;   /* host [n_grains][6][6] parent stiffness        */
+  const double *C_var;     /* host [n_grains][n_var][6][6] twin stiffness   */
+  const double *eps0;      /* host [n_grains][n_var][6] twin eigenstrain    */
+  const uint8_t *grain_id; /* device [nz][ny][nx], or NULL if n_grains == 1;
+                              must stay valid until pf_destroy              */
+  const float *eta0;       /* device [n_var][nz][ny][nx] initial f          */
+  double C_ref[36];        /* reference medium of the fixed point (6x6)     */
+  int32_t C_ref_auto;      /* 1: use the mean of all C_grain and C_var      */
+  double ms_tol;           /* ||eps^{k+1}-eps^k|| <= tol ||eps^{k+1}||      */
+  int32_t ms_max_iter;     /* >= 1; a problem with one stiffness everywhere
+                              and C_ref equal to it needs exactly one       */
+  uint32_t bc_stress_mask; /* bit i set: mean stress component i prescribed,
+                              clear: mean strain component i prescribed     */
+} pf_problem;
+
+/* Load of one pf_step call. */
+typedef struct {
+  double eps_bar[6];       /* prescribed mean strain (strain-controlled)    */
+  double sig_bar[6];       /* prescribed mean stress (stress-controlled), Pa */
+  const float *eps_p;      /* device [6][nz][ny][nx] plastic strain; NULL
+                              keeps the previous one (zero at first). The
+                              buffer must stay valid while steps use it.    */
+  uint32_t flags;          /* PF_STEP_* */
+} pf_load;
+
+/* Reductions of the state a step started from (FP64 on the device). */
+typedef struct {
+  int64_t step;            /* steps completed                               */
+  double G_dw, G_gd, G_me; /* energies of eqs. (13)-(15) over the grid, J   */
+  double sig_mean[6];      /* volume-averaged stress, Pa                    */
+  double eps_mean[6];      /* volume-averaged strain                        */
+  double eta_mean[6];      /* volume-averaged f per variant                 */
+  double eta_min, eta_max; /* over all variants and voxels                  */
+  int32_t ms_iters;        /* fixed-point iterations of the last step       */
+  double ms_residual;      /* last relative strain change                   */
+} pf_stats;
+
+/* Workspace bytes for a problem (only the sizes and n_var are read). */
+int pf_workspace_size(const pf_problem *prob, size_t *bytes);
+
+/* Validate, carve the workspace, upload tables, copy eta0 in, set the strain
+ * to the mean load later given by the first pf_step. hip_stream: hipStream_t
+ * or NULL. On success *out receives a new context. */
+int pf_init(const pf_problem *prob, void *workspace, size_t ws_bytes,
+            void *hip_stream, pf_ctx **out);
+
+/* Advance n_steps steps under one load. Work is enqueued on the context's
+ * stream; when the fixed point needs more than one iteration the call waits
+ * on the stream once per iteration to read the convergence flag. */
+int pf_step(pf_ctx *ctx, int32_t n_steps, const pf_load *load);
+
+/* Copy a field between the context and a caller device buffer of the same
+ * layout (set = 0: context -> buf, set = 1: buf -> context), on the stream. */
+int pf_fields(pf_ctx *ctx, int32_t which, int32_t set, float *buf);
+
+/* Synchronise the stream and return the reductions of the last step. */
+int pf_stats_get(pf_ctx *ctx, pf_stats *out);
+
+/* 3D transforms with the context's plan, for checking the FFT passes.
+ * direction +1: real[ncomp][nz][ny][nx] -> spec[ncomp][nz][ny][nx/2+1]
+ * (unnormalised). direction -1: spec -> real with the 1/(nx ny nz) factor;
+ * spec is overwritten. ncomp in 1..6. */
+int pf_fft(pf_ctx *ctx, int32_t direction, int32_t ncomp, float *real, void *spec);
+
+/* Per-kernel timing with HIP events on the context's stream: enable (1) or
+ * disable (0) and reset; read returns up to max_n entries of name, launch
+ * count and total milliseconds, the number of entries in *n. */
+int pf_profile_enable(pf_ctx *ctx, int32_t on);
+int pf_profile_read(pf_ctx *ctx, int32_t max_n, char (*names)[64],
+                    int64_t *counts, double *total_ms, int32_t *n);
+
+int pf_destroy(pf_ctx *ctx);
+const char *pf_last_error(const pf_ctx *ctx);
+
+/* Host helper: sample-frame tables of Mg tension twins for n_grains grains.
+ * Crystal frame x || [10-10], y || [-12-10], z || [0001]; c_over_a and
+ * gamma_tw as in Sec. 2.1 (1.633, 0.129); C_hex = {C11, C12, C13, C33, C44}
+ * in Pa (Table 2); rotations [n_grains][3][3] map crystal to sample vectors;
+ * variant_ids[n_var] pick among the six {10-12}<-1011> variants (0-based);
+ * the twin stiffness is the parent one turned by Q = 2 m m^T - I.
+ * Outputs: C_grain [n_grains][6][6], C_var [n_grains][n_var][6][6],
+ * eps0 [n_grains][n_var][6] (tensor-Voigt). Host memory, caller-owned. */
+int pf_mg_twin_tables(const double C_hex[5], double c_over_a, double gamma_tw,
+                      int32_t n_grains, const double *rotations,
+                      int32_t n_var, const int32_t *variant_ids,
+                      double *C_grain, double *C_var, double *eps0);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_TWIN_H */

@@ -1,0 +1,280 @@
+"""Thin ctypes binding over libpftwin.so (C ABI in include/pf.h).
+
+Argument marshalling only: every step of the path runs in the HIP library.
+PyTorch supplies device memory (caller-owned workspace and fields) and the
+HIP stream. Importing this module does not load the library; ``load()`` does,
+and raises if the library has not been built.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpftwin.so")
+
+PF_OK, PF_EINVAL, PF_ENOMEM, PF_EDEVICE, PF_ENOCONV, PF_ENONFINITE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+ERROR_NAMES = {PF_EINVAL: "PF_EINVAL", PF_ENOMEM: "PF_ENOMEM", PF_EDEVICE: "PF_EDEVICE",
+               PF_ENOCONV: "PF_ENOCONV", PF_ENONFINITE: "PF_ENONFINITE",
+               PF_EUNSUPPORTED: "PF_EUNSUPPORTED"}
+PF_H_LINEAR, PF_H_QUINTIC = 0, 1
+PF_STEP_SAVE_STRESS = 1
+PF_FIELD_ETA, PF_FIELD_STRAIN, PF_FIELD_STRESS = 0, 1, 2
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class PfProblem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("dx", ctypes.c_double),
+        ("n_var", ctypes.c_int32),
+        ("A", ctypes.c_double), ("kappa", ctypes.c_double), ("L", ctypes.c_double), ("dt", ctypes.c_double),
+        ("h_kind", ctypes.c_int32),
+        ("n_grains", ctypes.c_int32),
+        ("C_grain", _dp), ("C_var", _dp), ("eps0", _dp),
+        ("grain_id", ctypes.c_void_p),
+        ("eta0", ctypes.c_void_p),
+        ("C_ref", ctypes.c_double * 36),
+        ("C_ref_auto", ctypes.c_int32),
+        ("ms_tol", ctypes.c_double),
+        ("ms_max_iter", ctypes.c_int32),
+        ("bc_stress_mask", ctypes.c_uint32),
+    ]
+
+
+class PfLoad(ctypes.Structure):
+    _fields_ = [
+        ("eps_bar", ctypes.c_double * 6),
+        ("sig_bar", ctypes.c_double * 6),
+        ("eps_p", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class PfStats(ctypes.Structure):
+    _fields_ = [
+        ("step", ctypes.c_int64),
+        ("G_dw", ctypes.c_double), ("G_gd", ctypes.c_double), ("G_me", ctypes.c_double),
+        ("sig_mean", ctypes.c_double * 6),
+        ("eps_mean", ctypes.c_double * 6),
+        ("eta_mean", ctypes.c_double * 6),
+        ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
+        ("ms_iters", ctypes.c_int32),
+        ("ms_residual", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libpftwin.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2302_13612_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32
+    lib.pf_workspace_size.argtypes = [ctypes.POINTER(PfProblem), ctypes.POINTER(ctypes.c_size_t)]
+    lib.pf_init.argtypes = [ctypes.POINTER(PfProblem), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.pf_step.argtypes = [vp, i32, ctypes.POINTER(PfLoad)]
+    lib.pf_fields.argtypes = [vp, i32, i32, vp]
+    lib.pf_stats_get.argtypes = [vp, ctypes.POINTER(PfStats)]
+    lib.pf_fft.argtypes = [vp, i32, i32, vp, vp]
+    lib.pf_profile_enable.argtypes = [vp, i32]
+    lib.pf_profile_read.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int64),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+    lib.pf_destroy.argtypes = [vp]
+    lib.pf_last_error.argtypes = [vp]
+    lib.pf_last_error.restype = ctypes.c_char_p
+    lib.pf_mg_twin_tables.argtypes = [_dp, ctypes.c_double, ctypes.c_double, i32, _dp, i32,
+                                      ctypes.POINTER(i32), _dp, _dp, _dp]
+    for name in ("pf_workspace_size", "pf_init", "pf_step", "pf_fields", "pf_stats_get", "pf_fft",
+                 "pf_profile_enable", "pf_profile_read", "pf_destroy", "pf_mg_twin_tables"):
+        getattr(lib, name).restype = ctypes.c_int
+    _ = u32
+    _lib = lib
+    return lib
+
+
+class PfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp)
+
+
+def mg_twin_tables(rotations, variant_ids, C_hex=(59.4e9, 25.6e9, 21.4e9, 61.6e9, 16.4e9),
+                   c_over_a=1.633, gamma_tw=0.129):
+    """Sample-frame (C_grain, C_var, eps0) tables computed by the library."""
+    lib = load()
+    R = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 3, 3))
+    G, V = R.shape[0], len(variant_ids)
+    ids = (ctypes.c_int32 * V)(*[int(v) for v in variant_ids])
+    Ch = np.ascontiguousarray(np.asarray(C_hex, dtype=np.float64))
+    Cg = np.zeros((G, 6, 6))
+    Cv = np.zeros((G, V, 6, 6))
+    e0 = np.zeros((G, V, 6))
+    rc = lib.pf_mg_twin_tables(_ptr(Ch), c_over_a, gamma_tw, G, _ptr(R), V, ids, _ptr(Cg), _ptr(Cv), _ptr(e0))
+    if rc != PF_OK:
+        raise PfError(rc, "pf_mg_twin_tables")
+    return Cg, Cv, e0
+
+
+def stress_mask_bits(mask):
+    return int(sum(1 << i for i, m in enumerate(mask) if m))
+
+
+class Solver:
+    """One phase-field context on the current torch CUDA device and stream.
+
+    eta0: torch float32 CUDA tensor (n_var, nz, ny, nx). gid: torch uint8 CUDA
+    tensor (nz, ny, nx) or None. Tables are numpy float64 (G,6,6), (G,V,6,6),
+    (G,V,6). C_ref: 6x6 numpy or None for the mean of all stiffnesses.
+    """
+
+    def __init__(self, eta0, dx, A, kappa, L, dt, tables, stress_mask, gid=None, C_ref=None,
+                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        if eta0.dtype != torch.float32 or not eta0.is_cuda or eta0.dim() != 4:
+            raise ValueError("eta0 must be a float32 CUDA tensor (n_var, nz, ny, nx)")
+        eta0 = eta0.contiguous()
+        V, nz, ny, nx = eta0.shape
+        Cg, Cv, e0 = (np.ascontiguousarray(np.asarray(t, dtype=np.float64)) for t in tables)
+        G = Cg.shape[0]
+        if Cv.shape != (G, V, 6, 6) or e0.shape != (G, V, 6):
+            raise ValueError("table shapes do not match n_var / n_grains")
+        self._keep = [Cg, Cv, e0, eta0]
+        p = PfProblem()
+        p.nx, p.ny, p.nz = nx, ny, nz
+        p.dx = dx
+        p.n_var = V
+        p.A, p.kappa, p.L, p.dt = A, kappa, L, dt
+        p.h_kind = h_kind
+        p.n_grains = G
+        p.C_grain, p.C_var, p.eps0 = _ptr(Cg), _ptr(Cv), _ptr(e0)
+        if gid is not None:
+            if gid.dtype != torch.uint8 or not gid.is_cuda or tuple(gid.shape) != (nz, ny, nx):
+                raise ValueError("gid must be a uint8 CUDA tensor (nz, ny, nx)")
+            gid = gid.contiguous()
+            self._keep.append(gid)
+            p.grain_id = gid.data_ptr()
+        else:
+            p.grain_id = None
+        p.eta0 = eta0.data_ptr()
+        if C_ref is None:
+            p.C_ref_auto = 1
+        else:
+            p.C_ref_auto = 0
+            for i, v in enumerate(np.asarray(C_ref, dtype=np.float64).ravel()):
+                p.C_ref[i] = v
+        p.ms_tol = ms_tol
+        p.ms_max_iter = ms_max_iter
+        p.bc_stress_mask = stress_mask_bits(stress_mask)
+        nbytes = ctypes.c_size_t()
+        rc = self.lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(nbytes))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_workspace_size")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=eta0.device)
+        self.shape = (nz, ny, nx)
+        self.n_var = V
+        self.stream = torch.cuda.current_stream(eta0.device)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.pf_init(ctypes.byref(p), self.workspace.data_ptr(), nbytes.value,
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_init (see stderr)")
+        self.ctx = ctx
+        self._epsp = None
+
+    def _check(self, rc, what):
+        if rc != PF_OK:
+            raise PfError(rc, f"{what}: {self.lib.pf_last_error(self.ctx).decode()}")
+
+    def step(self, n_steps, eps_bar, sig_bar=None, eps_p=None, save_stress=False):
+        ld = PfLoad()
+        for i in range(6):
+            ld.eps_bar[i] = float(eps_bar[i])
+            ld.sig_bar[i] = 0.0 if sig_bar is None else float(sig_bar[i])
+        if eps_p is not None:
+            t = self.torch
+            if eps_p.dtype != t.float32 or not eps_p.is_cuda or tuple(eps_p.shape) != (6,) + self.shape:
+                raise ValueError("eps_p must be a float32 CUDA tensor (6, nz, ny, nx)")
+            self._epsp = eps_p.contiguous()
+            ld.eps_p = self._epsp.data_ptr()
+        else:
+            ld.eps_p = None
+        ld.flags = PF_STEP_SAVE_STRESS if save_stress else 0
+        self._check(self.lib.pf_step(self.ctx, int(n_steps), ctypes.byref(ld)), "pf_step")
+
+    def field(self, which):
+        n = self.n_var if which == PF_FIELD_ETA else 6
+        out = self.torch.empty((n,) + self.shape, dtype=self.torch.float32, device=self.workspace.device)
+        self._check(self.lib.pf_fields(self.ctx, which, 0, out.data_ptr()), "pf_fields")
+        return out
+
+    def set_field(self, which, buf):
+        buf = buf.contiguous()
+        self._check(self.lib.pf_fields(self.ctx, which, 1, buf.data_ptr()), "pf_fields")
+        self.stream.synchronize()
+
+    def stats(self):
+        s = PfStats()
+        self._check(self.lib.pf_stats_get(self.ctx, ctypes.byref(s)), "pf_stats_get")
+        return {
+            "step": s.step, "G_dw": s.G_dw, "G_gd": s.G_gd, "G_me": s.G_me,
+            "G": s.G_dw + s.G_gd + s.G_me,
+            "sig_mean": np.array(s.sig_mean[:]), "eps_mean": np.array(s.eps_mean[:]),
+            "eta_mean": np.array(s.eta_mean[:self.n_var]),
+            "eta_min": s.eta_min, "eta_max": s.eta_max,
+            "ms_iters": s.ms_iters, "ms_residual": s.ms_residual,
+        }
+
+    def fft_forward(self, real):
+        t = self.torch
+        real = real.contiguous()
+        nc = real.shape[0]
+        nz, ny, nx = self.shape
+        spec = t.empty((nc, nz, ny, nx // 2 + 1), dtype=t.complex64, device=real.device)
+        self._check(self.lib.pf_fft(self.ctx, 1, nc, real.data_ptr(), spec.data_ptr()), "pf_fft")
+        return spec
+
+    def fft_inverse(self, spec):
+        t = self.torch
+        spec = spec.clone().contiguous()
+        nc = spec.shape[0]
+        real = t.empty((nc,) + self.shape, dtype=t.float32, device=spec.device)
+        self._check(self.lib.pf_fft(self.ctx, -1, nc, real.data_ptr(), spec.data_ptr()), "pf_fft")
+        return real
+
+    def profile(self, on=True):
+        self._check(self.lib.pf_profile_enable(self.ctx, 1 if on else 0), "pf_profile_enable")
+
+    def profile_read(self):
+        n = ctypes.c_int32()
+        maxn = 64
+        names = (ctypes.c_char * 64 * maxn)()
+        counts = (ctypes.c_int64 * maxn)()
+        tot = (ctypes.c_double * maxn)()
+        self._check(self.lib.pf_profile_read(self.ctx, maxn, names, counts, tot, ctypes.byref(n)),
+                    "pf_profile_read")
+        return {names[i].value.decode(): (counts[i], tot[i]) for i in range(min(n.value, maxn))}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

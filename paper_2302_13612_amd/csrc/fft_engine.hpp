@@ -1,0 +1,207 @@
+// Register/LDS Stockham FFT engine for gfx950.
+//
+// A pencil of length N is transformed cooperatively by T = N / E threads;
+// thread t owns the E elements t + T*m (m = 0..E-1) both before and after
+// the transform (the Stockham formulation sorts itself), so global loads and
+// stores of a pencil are T-wide contiguous runs. Stages exchange data through
+// LDS; each stage of radix R does E/R radix-R butterflies per thread in
+// registers. Twiddles come from a float32 table W_N^n = exp(-2 pi i n / N)
+// built on the host in double precision and rounded once.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pft {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+
+// Multiply by W_4 = -i (forward, DIR = +1) or +i (inverse, DIR = -1).
+template <int DIR>
+__device__ __forceinline__ float2 quarter(float2 a) {
+  return DIR > 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
+}
+
+// Multiply by W_8 = (1 - i)/sqrt2 (forward) or (1 + i)/sqrt2 (inverse).
+template <int DIR>
+__device__ __forceinline__ float2 eighth(float2 a) {
+  constexpr float h = 0.70710678118654752440f;
+  return DIR > 0 ? make_float2((a.x + a.y) * h, (a.y - a.x) * h)
+                 : make_float2((a.x - a.y) * h, (a.x + a.y) * h);
+}
+
+// In-place DFTs of small sizes, natural order in and out:
+// X[k] = sum_j v[j] W_R^{jk}, W_R = exp(-DIR * 2 pi i / R).
+template <int DIR>
+__device__ __forceinline__ void dft2(float2* v) {
+  float2 a = v[0], b = v[1];
+  v[0] = cadd(a, b);
+  v[1] = csub(a, b);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft3(float2* v) {
+  constexpr float s3 = 0.86602540378443864676f;  // sin(pi/3)
+  float2 s = cadd(v[1], v[2]);
+  float2 d = csub(v[1], v[2]);
+  float2 m = make_float2(v[0].x - 0.5f * s.x, v[0].y - 0.5f * s.y);
+  float2 r = cscale(quarter<DIR>(d), s3);
+  v[0] = cadd(v[0], s);
+  v[1] = cadd(m, r);
+  v[2] = csub(m, r);
+}
+
+template <int DIR>
+__device__ __forceinline__ void dft4(float2* v) {
+  float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+  float2 t2 = cadd(v[1], v[3]), t3 = quarter<DIR>(csub(v[1], v[3]));
+  v[0] = cadd(t0, t2);
+  v[2] = csub(t0, t2);
+  v[1] = cadd(t1, t3);
+  v[3] = csub(t1, t3);
+}
+
+// Radix 8 as two radix-4 DFTs (even / odd samples) combined with W_8^k.
+template <int DIR>
+__device__ __forceinline__ void dft8(float2* v) {
+  float2 e[4] = {v[0], v[2], v[4], v[6]};
+  float2 o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<DIR>(e);
+  dft4<DIR>(o);
+  o[1] = eighth<DIR>(o[1]);
+  o[2] = quarter<DIR>(o[2]);
+  o[3] = quarter<DIR>(eighth<DIR>(o[3]));
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+template <int R, int DIR>
+__device__ __forceinline__ void dft(float2* v) {
+  static_assert(R == 2 || R == 3 || R == 4 || R == 8, "unsupported radix");
+  if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 3) dft3<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else dft8<DIR>(v);
+}
+
+// ----------------------------------------------------------------- plans
+template <int... Rs>
+struct Radices {};
+
+// E = elements per thread; every radix divides E; product of radices = N.
+template <int N> struct Plan;
+template <> struct Plan<16>  { static constexpr int E = 4;  using R = Radices<4, 4>; };
+template <> struct Plan<24>  { static constexpr int E = 12; using R = Radices<4, 2, 3>; };
+template <> struct Plan<32>  { static constexpr int E = 8;  using R = Radices<8, 4>; };
+template <> struct Plan<48>  { static constexpr int E = 12; using R = Radices<4, 4, 3>; };
+template <> struct Plan<64>  { static constexpr int E = 8;  using R = Radices<8, 8>; };
+template <> struct Plan<96>  { static constexpr int E = 12; using R = Radices<4, 4, 2, 3>; };
+template <> struct Plan<128> { static constexpr int E = 8;  using R = Radices<8, 4, 4>; };
+template <> struct Plan<256> { static constexpr int E = 8;  using R = Radices<8, 8, 4>; };
+
+// Plans of the x pass (half-length complex transforms of real rows). Fewer
+// elements per thread leave registers for the fused per-voxel physics.
+template <int M> struct XPlan;
+template <> struct XPlan<16>  { static constexpr int E = 4; using R = Radices<4, 4>; };
+template <> struct XPlan<24>  { static constexpr int E = 6; using R = Radices<2, 2, 2, 3>; };
+template <> struct XPlan<32>  { static constexpr int E = 4; using R = Radices<4, 4, 2>; };
+template <> struct XPlan<48>  { static constexpr int E = 6; using R = Radices<2, 2, 2, 2, 3>; };
+template <> struct XPlan<64>  { static constexpr int E = 4; using R = Radices<4, 4, 4>; };
+template <> struct XPlan<128> { static constexpr int E = 4; using R = Radices<4, 4, 4, 2>; };
+
+// ------------------------------------------------------------ LDS views
+// One pencil of a row-major tile, padded by one element every 16 to break
+// the stride-R bank conflicts of the scatter phases.
+struct RowView {
+  float2* base;
+  __device__ __forceinline__ static int pad(int e) { return e + (e >> 4); }
+  __device__ __forceinline__ float2 read(int e) const { return base[pad(e)]; }
+  __device__ __forceinline__ void write(int e, float2 v) const { base[pad(e)] = v; }
+  __host__ __device__ static constexpr int padded(int n) { return n + (n >> 4); }
+};
+
+// One column of a column-interleaved tile: element e of column c at
+// base[e * C + c]; the C columns of a wavefront segment are contiguous.
+template <int C>
+struct ColView {
+  float2* base;
+  __device__ __forceinline__ float2 read(int e) const { return base[e * C]; }
+  __device__ __forceinline__ void write(int e, float2 v) const { base[e * C] = v; }
+};
+
+template <int DIR>
+__device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int idx) {
+  float2 w = tw[idx];
+  return DIR > 0 ? w : cconj(w);
+}
+
+// One Stockham stage. NS = product of the radices of earlier stages.
+// FIRST: inputs from registers; LAST: outputs to registers. Every LDS write
+// phase sits between two block barriers, so callers may reuse the buffer.
+template <int N, class P, int R, int NS, int DIR, bool FIRST, bool LAST, class View>
+__device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& lds, int t,
+                                               const float2* __restrict__ tw) {
+  constexpr int E = P::E;
+  constexpr int T = N / E;
+  constexpr int NB = E / R;  // butterflies per thread
+  static_assert(E % R == 0, "radix must divide elements per thread");
+  float2 a[E];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int j = t + T * q;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (FIRST) a[q * R + r] = v[q + r * NB];
+      else a[q * R + r] = lds.read(j + r * (N / R));
+    }
+    if constexpr (!FIRST) {
+      const int k = j % NS;
+#pragma unroll
+      for (int r = 1; r < R; ++r)
+        a[q * R + r] = cmul(a[q * R + r], twiddle<DIR>(tw, r * k * (N / (NS * R))));
+    }
+    dft<R, DIR>(&a[q * R]);
+  }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q + r * NB] = a[q * R + r];
+  } else {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int j = t + T * q;
+      const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) lds.write(base + r * NS, a[q * R + r]);
+    }
+    __syncthreads();
+  }
+}
+
+template <int N, class P, int NS, int DIR, bool FIRST, class View, int R0, int... Rest>
+__device__ __forceinline__ void run_stages(float2 (&v)[P::E], const View& lds, int t,
+                                           const float2* __restrict__ tw, Radices<R0, Rest...>) {
+  constexpr bool LAST = sizeof...(Rest) == 0;
+  stockham_stage<N, P, R0, NS, DIR, FIRST, LAST>(v, lds, t, tw);
+  if constexpr (!LAST) run_stages<N, P, NS * R0, DIR, false>(v, lds, t, tw, Radices<Rest...>{});
+}
+
+// Transform the pencil held in v (thread t owns elements t + T*m, T = N/E)
+// in place with plan P. All threads of the block must call it together (it
+// contains barriers).
+template <int N, int DIR, class P = Plan<N>, class View>
+__device__ __forceinline__ void fft_pencil(float2 (&v)[P::E], const View& lds, int t,
+                                           const float2* __restrict__ tw) {
+  run_stages<N, P, 1, DIR, true>(v, lds, t, tw, typename P::R{});
+}
+
+}  // namespace pft

@@ -1,0 +1,116 @@
+// Shared declarations between the HIP kernels and the host runtime.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pft {
+
+constexpr int kMaxVar = 6;
+constexpr int kColTile = 16;       // spectral columns per y/z block
+constexpr int kXThreads = 256;     // threads per x-pass block
+
+// Quantities reduced per block (FP64 partial sums / extrema).
+constexpr int kQms = 6;                 // sum of stress (mixed condition)
+constexpr int kQres = 2;                // |eps_new - eps_old|^2, |eps_new|^2
+constexpr int kQac = 2 + 6 + 6 + kMaxVar;  // G_dw, G_me, sum sigma, sum eps, sum eta
+constexpr int kQgd = 1;                 // Parseval gradient sum
+
+// Status copied back to the host after each fixed-point iteration.
+struct Status {
+  double residual;
+  int32_t iters;
+  int32_t done;
+  int32_t nonfinite;
+  int32_t pad;
+};
+
+// Device-resident state of a context (FP64 scalars).
+struct DevState {
+  double ebar_cur[6];    // mean strain of the current iterate
+  double ebar_field[6];  // mean strain of the strain field in memory
+  double ebar_next[6];   // mean strain for the next iterate
+  double eps_target[6];  // load: prescribed mean strain
+  double sig_target[6];  // load: prescribed mean stress
+  double gd_cur;         // gradient energy sum of the current order parameter
+  double stats[32];      // reductions of the last step (layout in the host)
+  Status st;
+};
+
+// Everything a kernel needs, passed by value.
+struct KArgs {
+  int nx, ny, nz, nh, nv;     // grid, nh = nx/2+1, number of variants
+  int h_kind;
+  int n_grains, tab_stride;
+  float A, LDt;               // double-well height, L*dt
+  float ax, ay, az;           // 2 L dt kappa (2 pi / (n dx))^2 per axis
+  double gx, gy, gz;          // (2 pi / (n dx))^2 per axis (energy)
+  float inv_ntot;
+  double tol;
+  float C0[21];               // reference stiffness, packed upper triangle
+  float S0[36];               // reference compliance: Voigt stress -> tensor-Voigt strain
+  double Bss[36];             // mixed-condition correction matrix (stress rows/cols)
+  uint32_t stress_mask;
+  // fields
+  float* eta;                 // [nv][nz][ny][nx]
+  float* eps;                 // [6][nz][ny][nx]
+  float* sig;                 // [6][nz][ny][nx] (only written on request)
+  const float* epsp;          // [6][nz][ny][nx] or null
+  const uint8_t* gid;         // [nz][ny][nx] or null
+  const float* tables;        // [n_grains][tab_stride]
+  float2* spec;               // [6][nz][ny][nh]
+  const float2* tw_xh;        // length nx/2
+  const float2* tw_x;         // length nx
+  const float2* tw_y;         // length ny
+  const float2* tw_z;         // length nz
+  double* part_ms;            // per-block partials
+  double* part_res;
+  double* part_ac;
+  float* part_mm;             // per-block min/max of eta
+  double* part_gd;
+  DevState* state;
+  int save_stress;
+};
+
+// Packed upper-triangle index of a symmetric 6x6 matrix.
+__host__ __device__ constexpr int sym6(int i, int j) {
+  return i <= j ? i * 6 - i * (i - 1) / 2 + (j - i) : j * 6 - j * (j - 1) / 2 + (i - j);
+}
+
+}  // namespace pft
+
+// Launchers implemented in pf_kernels.hip. Each returns a hipError_t value.
+namespace pfl {
+using pft::KArgs;
+int rows_per_block(int nx);
+int x_blocks(const KArgs& a);
+int z_blocks(const KArgs& a, int ncomp);
+hipError_t step_begin(const KArgs& a, const double* eps_target, const double* sig_target,
+                      hipStream_t s);
+hipError_t ms_x_forward(const KArgs& a, hipStream_t s);
+hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
+hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s);
+hipError_t ms_z_green(const KArgs& a, hipStream_t s);
+hipError_t ms_x_inverse(const KArgs& a, hipStream_t s);
+hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward(const KArgs& a, hipStream_t s);
+hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);  // mode 0 update, 1 energy only
+hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
+hipError_t ac_finalize(const KArgs& a, int init_only, hipStream_t s);
+hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s);
+hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);
+hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s);
+bool supported_axis(int n);
+// per variant count, one translation unit each
+hipError_t ms_x_forward_v1(const KArgs& a, hipStream_t s);
+hipError_t ms_x_forward_v2(const KArgs& a, hipStream_t s);
+hipError_t ms_x_forward_v3(const KArgs& a, hipStream_t s);
+hipError_t ms_x_forward_v4(const KArgs& a, hipStream_t s);
+hipError_t ms_x_forward_v5(const KArgs& a, hipStream_t s);
+hipError_t ms_x_forward_v6(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward_v1(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward_v2(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward_v3(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward_v4(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward_v5(const KArgs& a, hipStream_t s);
+hipError_t ac_x_forward_v6(const KArgs& a, hipStream_t s);
+}  // namespace pfl

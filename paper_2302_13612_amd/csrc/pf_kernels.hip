@@ -1,0 +1,623 @@
+// HIP kernels of the FFT phase-field twin step (gfx950).
+//
+// A 3D real-to-complex transform is three passes over HBM:
+//   x: contiguous rows; a real row of length nx is packed into nx/2 complex
+//      samples, transformed, and split into nx/2+1 coefficients. The x pass
+//      fuses the per-voxel physics: the constitutive law (polarisation of the
+//      fixed point) before the forward transform, the strain update after the
+//      inverse one; and the driving forces of the phase-field update.
+//   y: columns of 16 consecutive kx (128-byte runs), in place.
+//   z: columns like y; the forward transform, the per-wavevector operator and
+//      the inverse transform run in one kernel with the pencil in registers,
+//      so the spectrum makes one round trip through HBM for the z stage.
+// Reductions are FP64 partial sums per block followed by a one-block
+// finalize in a fixed order (deterministic).
+#include "pf_common.hpp"
+
+namespace pft {
+
+// -------------------------------------------------------------- x kernels
+// Fixed point, inverse: new strain field from the six spectra, FP64 sums of
+// the squared change and the squared new strain (full tensor norm).
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_inv_ms(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  if (a.state->st.done) return;
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const int nx = a.nx;
+  const size_t vs = (size_t)nrows * nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * nx;
+  const size_t cs = (size_t)nrows * a.nh;
+  const size_t roff = (size_t)(valid ? row : 0) * a.nh;
+  double acc[2] = {0.0, 0.0};
+#pragma unroll 1
+  for (int c = 0; c < 6; ++c) {
+    const float shift = (float)(a.state->ebar_cur[c] - a.state->ebar_field[c]);
+    const float w = c < 3 ? 1.f : 2.f;
+    float2 v[E];
+    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + c * cs + roff, a.tw_xh, a.tw_x);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int x0 = 2 * (t + T * m);
+        float2* ptr = reinterpret_cast<float2*>(a.eps + c * vs + rbase + x0);
+        const float2 old = *ptr;
+        const float dx0 = v[m].x - (old.x + shift), dx1 = v[m].y - (old.y + shift);
+        acc[0] += (double)(w * (dx0 * dx0 + dx1 * dx1));
+        acc[1] += (double)(w * (v[m].x * v[m].x + v[m].y * v[m].y));
+        *ptr = v[m];
+      }
+    }
+  }
+  block_sum<2>(acc, a.part_res + (size_t)blockIdx.x * kQres);
+}
+
+// Phase-field update, inverse: new order parameters, count of non-finite values.
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_inv_ac(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  const size_t cs = (size_t)nrows * a.nh;
+  const size_t roff = (size_t)(valid ? row : 0) * a.nh;
+  double bad[1] = {0.0};
+#pragma unroll 1
+  for (int q = 0; q < a.nv; ++q) {
+    float2 v[E];
+    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + roff, a.tw_xh, a.tw_x);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int x0 = 2 * (t + T * m);
+        if (!isfinite(v[m].x) || !isfinite(v[m].y)) bad[0] += 1.0;
+        *reinterpret_cast<float2*>(a.eta + q * vs + rbase + x0) = v[m];
+      }
+    }
+  }
+  block_sum<1>(bad, a.part_res + (size_t)blockIdx.x * kQres);
+}
+
+// Plain transforms of caller fields (checking the passes).
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_fwd_raw(const KArgs a, const float* __restrict__ real) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const int comp = blockIdx.y;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  float2 v[1][E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int x0 = 2 * (t + T * m);
+    v[0][m] = valid ? *reinterpret_cast<const float2*>(real + comp * vs + rbase + x0) : make_float2(0.f, 0.f);
+  }
+  const size_t cs = (size_t)nrows * a.nh;
+  r2c_rows<M, 1>(v, lds + p * LROW, t, valid, a.spec + comp * cs, (size_t)(valid ? row : 0) * a.nh, cs,
+                 a.tw_xh, a.tw_x);
+}
+
+template <int M>
+__global__ __launch_bounds__(kXThreads) void k_x_inv_raw(const KArgs a, float* __restrict__ real, float scale) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const int comp = blockIdx.y;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  const size_t cs = (size_t)nrows * a.nh;
+  float2 v[E];
+  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.nh, a.tw_xh,
+             a.tw_x);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int x0 = 2 * (t + T * m);
+      *reinterpret_cast<float2*>(real + comp * vs + rbase + x0) = cscale(v[m], scale);
+    }
+  }
+}
+
+// ------------------------------------------------------------ y and z passes
+// y: columns of kColTile consecutive kx at one z, in place. grid (tiles, nz, ncomp).
+template <int N, int DIR>
+__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_y(const KArgs a) {
+  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+  __shared__ float2 lds[N * C];
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  const int kx = blockIdx.x * C + cc;
+  const bool valid = kx < a.nh;
+  const int z = blockIdx.y, comp = blockIdx.z;
+  const size_t cs = (size_t)a.nz * a.ny * a.nh;
+  float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.nh + (valid ? kx : 0);
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * a.nh] : make_float2(0.f, 0.f);
+  fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, a.tw_y);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * a.nh] = v[m];
+  }
+}
+
+// Signed index of coefficient k on an axis of length n (Nyquist -> -n/2).
+__device__ __forceinline__ int signed_k(int k, int n) { return k < n / 2 ? k : k - n; }
+
+// Green's operator step of the fixed point at one wavevector: the new strain
+// coefficient from the polarisation, eps = -Gamma0 : tau (times 1/N); the
+// prescribed mean at xi = 0; the reference compliance at the ambiguous
+// Nyquist wavevectors.
+__device__ __forceinline__ void green_apply(const KArgs& a, int kx, int ky, int kz, float2 (&tau)[6]) {
+  const int sy = signed_k(ky, a.ny), sz = signed_k(kz, a.nz);
+  if (kx == 0 && ky == 0 && kz == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = make_float2((float)a.state->ebar_next[c], 0.f);
+    return;
+  }
+  const bool nqx = kx == a.nx / 2, nqy = ky == a.ny / 2, nqz = kz == a.nz / 2;
+  const bool otx = kx != 0 && !nqx, oty = ky != 0 && !nqy, otz = kz != 0 && !nqz;
+  const float s = a.inv_ntot;
+  if ((nqx || nqy || nqz) && (otx || oty || otz)) {
+    float2 o[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        acc.x += a.S0[6 * i + j] * tau[j].x;
+        acc.y += a.S0[6 * i + j] * tau[j].y;
+      }
+      o[i] = acc;
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = cscale(o[c], -s);
+    return;
+  }
+  float n[3] = {(float)kx / (float)a.nx, (float)sy / (float)a.ny, (float)sz / (float)a.nz};
+  const float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  n[0] *= inv;
+  n[1] *= inv;
+  n[2] *= inv;
+  // K_ik = C0_ijkl n_j n_l
+  constexpr int VI[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+  float K[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int k = i; k < 3; ++k) {
+      float acc = 0.f;
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int l = 0; l < 3; ++l) acc += a.C0[sym6(VI[i][j], VI[k][l])] * n[j] * n[l];
+      K[i][k] = acc;
+      K[k][i] = acc;
+    }
+  const float A00 = K[1][1] * K[2][2] - K[1][2] * K[1][2];
+  const float A01 = K[0][2] * K[1][2] - K[0][1] * K[2][2];
+  const float A02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+  const float A11 = K[0][0] * K[2][2] - K[0][2] * K[0][2];
+  const float A12 = K[0][1] * K[0][2] - K[0][0] * K[1][2];
+  const float A22 = K[0][0] * K[1][1] - K[0][1] * K[0][1];
+  const float rdet = 1.f / (K[0][0] * A00 + K[0][1] * A01 + K[0][2] * A02);
+  const float Nm[3][3] = {{A00 * rdet, A01 * rdet, A02 * rdet},
+                          {A01 * rdet, A11 * rdet, A12 * rdet},
+                          {A02 * rdet, A12 * rdet, A22 * rdet}};
+  // t = tau n (tau symmetric, Voigt xx yy zz yz xz xy)
+  float2 tv[3];
+  tv[0] = make_float2(tau[0].x * n[0] + tau[5].x * n[1] + tau[4].x * n[2],
+                      tau[0].y * n[0] + tau[5].y * n[1] + tau[4].y * n[2]);
+  tv[1] = make_float2(tau[5].x * n[0] + tau[1].x * n[1] + tau[3].x * n[2],
+                      tau[5].y * n[0] + tau[1].y * n[1] + tau[3].y * n[2]);
+  tv[2] = make_float2(tau[4].x * n[0] + tau[3].x * n[1] + tau[2].x * n[2],
+                      tau[4].y * n[0] + tau[3].y * n[1] + tau[2].y * n[2]);
+  float2 u[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    u[i] = make_float2(Nm[i][0] * tv[0].x + Nm[i][1] * tv[1].x + Nm[i][2] * tv[2].x,
+                       Nm[i][0] * tv[0].y + Nm[i][1] * tv[1].y + Nm[i][2] * tv[2].y);
+  // eps = -sym(n (x) u) / N
+  const float h = -0.5f * s;
+  tau[0] = cscale(u[0], -s * n[0]);
+  tau[1] = cscale(u[1], -s * n[1]);
+  tau[2] = cscale(u[2], -s * n[2]);
+  tau[3] = make_float2(h * (n[1] * u[2].x + n[2] * u[1].x), h * (n[1] * u[2].y + n[2] * u[1].y));
+  tau[4] = make_float2(h * (n[0] * u[2].x + n[2] * u[0].x), h * (n[0] * u[2].y + n[2] * u[0].y));
+  tau[5] = make_float2(h * (n[0] * u[1].x + n[1] * u[0].x), h * (n[0] * u[1].y + n[1] * u[0].y));
+}
+
+// z pass of the fixed point: forward z transform of the six polarisation
+// components, Green's operator, inverse z transform. grid (tiles, ny).
+template <int N>
+__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a) {
+  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+  __shared__ float2 lds[N * C];
+  if (a.state->st.done) return;
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  const int kx = blockIdx.x * C + cc;
+  const bool valid = kx < a.nh;
+  const int ky = blockIdx.y;
+  const size_t cs = (size_t)a.nz * a.ny * a.nh;
+  const size_t zs = (size_t)a.ny * a.nh;
+  float2* col = a.spec + (size_t)ky * a.nh + (valid ? kx : 0);
+  float2 v[6][E];
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      v[c][m] = valid ? col[c * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+  const ColView<C> view{lds + cc};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) fft_pencil<N, 1>(v[c], view, t, a.tw_z);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    float2 tau[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = v[c][m];
+    green_apply(a, valid ? kx : 0, ky, t + T * m, tau);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c][m] = tau[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) fft_pencil<N, -1>(v[c], view, t, a.tw_z);
+  if (valid) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+#pragma unroll
+      for (int m = 0; m < E; ++m) col[c * cs + (size_t)(t + T * m) * zs] = v[c][m];
+  }
+}
+
+// z pass of the phase-field update for variant blockIdx.z: forward z
+// transform, semi-implicit divide by 1 + 2 L dt kappa |xi|^2 (and 1/N),
+// Parseval sum of |xi|^2 |f_hat|^2 of the new state, inverse transform.
+// mode 1: Parseval sum of the unmodified spectrum only, nothing stored.
+template <int N>
+__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArgs a, int mode) {
+  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+  __shared__ float2 lds[N * C];
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  const int kx = blockIdx.x * C + cc;
+  const bool valid = kx < a.nh;
+  const int ky = blockIdx.y, q = blockIdx.z;
+  const size_t cs = (size_t)a.nz * a.ny * a.nh;
+  const size_t zs = (size_t)a.ny * a.nh;
+  float2* col = a.spec + q * cs + (size_t)ky * a.nh + (valid ? kx : 0);
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+  const ColView<C> view{lds + cc};
+  fft_pencil<N, 1>(v, view, t, a.tw_z);
+  const int sy = signed_k(ky, a.ny);
+  const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
+  const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
+  double en[1] = {0.0};
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int sz = signed_k(t + T * m, a.nz);
+    const float fz = (float)sz * (float)sz;
+    if (mode == 0) {
+      const float den = 1.f + a.ax * fx + a.ay * fy + a.az * fz;
+      v[m] = cscale(v[m], 1.f / den);
+    }
+    const double x2 = a.gx * fx + a.gy * fy + a.gz * fz;
+    if (valid) en[0] += wgt * x2 * ((double)v[m].x * v[m].x + (double)v[m].y * v[m].y);
+    v[m] = cscale(v[m], a.inv_ntot);
+  }
+  if (mode == 0) {
+    fft_pencil<N, -1>(v, view, t, a.tw_z);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
+    }
+  }
+  const size_t blk = ((size_t)q * gridDim.y + ky) * gridDim.x + blockIdx.x;
+  block_sum<1>(en, a.part_gd + blk);
+}
+
+template <int N, int DIR>
+__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KArgs a) {
+  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+  __shared__ float2 lds[N * C];
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  const int kx = blockIdx.x * C + cc;
+  const bool valid = kx < a.nh;
+  const int ky = blockIdx.y, q = blockIdx.z;
+  const size_t cs = (size_t)a.nz * a.ny * a.nh;
+  const size_t zs = (size_t)a.ny * a.nh;
+  float2* col = a.spec + q * cs + (size_t)ky * a.nh + (valid ? kx : 0);
+  float2 v[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+  fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, a.tw_z);
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
+  }
+}
+
+// ------------------------------------------------------------ small kernels
+__global__ void k_step_begin(const KArgs a, double e0, double e1, double e2, double e3, double e4,
+                             double e5, double s0, double s1, double s2, double s3, double s4,
+                             double s5) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  DevState* st = a.state;
+  const double et[6] = {e0, e1, e2, e3, e4, e5};
+  const double sg[6] = {s0, s1, s2, s3, s4, s5};
+  for (int c = 0; c < 6; ++c) {
+    st->eps_target[c] = et[c];
+    st->sig_target[c] = sg[c];
+    if (!((a.stress_mask >> c) & 1u)) st->ebar_cur[c] = et[c];
+  }
+  st->st.done = 0;
+  st->st.iters = 0;
+}
+
+// Deterministic sum over nblk blocks of Q partials: each thread sums a fixed
+// strided subset in block order, then a fixed-shape tree.
+template <int Q>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nblk, double (&out)[Q]) {
+  __shared__ double res[Q];
+  double acc[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) acc[q] = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] += part[(size_t)b * Q + q];
+  block_sum<Q>(acc, res);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) out[q] = res[q];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_fin_ms(const KArgs a, int nblk) {
+  DevState* st = a.state;
+  if (st->st.done) return;
+  double s[kQms];
+  sum_partials<kQms>(a.part_ms, nblk, s);
+  if (threadIdx.x != 0) return;
+  const double ntot = (double)a.nx * a.ny * a.nz;
+  double r[6];
+  for (int c = 0; c < 6; ++c) r[c] = s[c] / ntot - st->sig_target[c];
+  for (int i = 0; i < 6; ++i) {
+    if ((a.stress_mask >> i) & 1u) {
+      double d = 0.0;
+      for (int j = 0; j < 6; ++j)
+        if ((a.stress_mask >> j) & 1u) d += a.Bss[6 * i + j] * r[j];
+      st->ebar_next[i] = st->ebar_cur[i] - d;
+    } else {
+      st->ebar_next[i] = st->eps_target[i];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fin_res(const KArgs a, int nblk) {
+  DevState* st = a.state;
+  if (st->st.done) return;
+  double s[kQres];
+  sum_partials<kQres>(a.part_res, nblk, s);
+  if (threadIdx.x != 0) return;
+  const double r = s[1] > 0.0 ? sqrt(s[0] / s[1]) : (s[0] > 0.0 ? 1.0e300 : 0.0);
+  st->st.residual = r;
+  st->st.iters += 1;
+  st->st.done = r <= a.tol ? 1 : 0;
+  for (int c = 0; c < 6; ++c) {
+    st->ebar_field[c] = st->ebar_next[c];
+    st->ebar_cur[c] = st->ebar_next[c];
+  }
+}
+
+// Stats of the step (raw sums; the host scales them) and the gradient sum of
+// the new state. init_only: only the gradient sum.
+__global__ __launch_bounds__(256) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int init_only) {
+  DevState* st = a.state;
+  double gd[1];
+  sum_partials<1>(a.part_gd, nblk_z, gd);
+  if (init_only) {
+    if (threadIdx.x == 0) st->gd_cur = gd[0];
+    return;
+  }
+  double s[kQac];
+  sum_partials<kQac>(a.part_ac, nblk_x, s);
+  double bad[kQres];
+  sum_partials<kQres>(a.part_res, nblk_x, bad);
+  // extrema
+  __shared__ float mm[2];
+  if (threadIdx.x == 0) {
+    float mn = 3.0e38f, mx = -3.0e38f;
+    for (int b = 0; b < nblk_x; ++b) {
+      mn = fminf(mn, a.part_mm[2 * b]);
+      mx = fmaxf(mx, a.part_mm[2 * b + 1]);
+    }
+    mm[0] = mn;
+    mm[1] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
+  st->stats[kQac] = st->gd_cur;
+  st->stats[kQac + 1] = mm[0];
+  st->stats[kQac + 2] = mm[1];
+  st->gd_cur = gd[0];
+  if (bad[0] > 0.0) st->st.nonfinite = 1;
+}
+
+}  // namespace pft
+
+// ====================================================================== host
+namespace pfl {
+using namespace pft;
+
+bool supported_axis(int n) {
+  return n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 256;
+}
+
+template <int M>
+static int rows_per_block_t() { return kXThreads / (M / XPlan<M>::E); }
+
+int rows_per_block(int nx) {
+  switch (nx / 2) {
+    case 16: return rows_per_block_t<16>();
+    case 24: return rows_per_block_t<24>();
+    case 32: return rows_per_block_t<32>();
+    case 48: return rows_per_block_t<48>();
+    case 64: return rows_per_block_t<64>();
+    case 128: return rows_per_block_t<128>();
+  }
+  return 0;
+}
+
+int x_blocks(const KArgs& a) {
+  const int r = rows_per_block(a.nx);
+  return (a.nz * a.ny + r - 1) / r;
+}
+
+int z_blocks(const KArgs& a, int ncomp) {
+  return ((a.nh + kColTile - 1) / kColTile) * a.ny * ncomp;
+}
+
+template <int N>
+static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
+
+#define PF_SWITCH_M(nx, BODY)                \
+  switch ((nx) / 2) {                         \
+    case 16: { constexpr int M = 16; BODY; } break;  \
+    case 24: { constexpr int M = 24; BODY; } break;  \
+    case 32: { constexpr int M = 32; BODY; } break;  \
+    case 48: { constexpr int M = 48; BODY; } break;  \
+    case 64: { constexpr int M = 64; BODY; } break;  \
+    case 128: { constexpr int M = 128; BODY; } break; \
+    default: return hipErrorInvalidValue;     \
+  }
+
+#define PF_SWITCH_N(n, BODY)                 \
+  switch (n) {                                \
+    case 32: { constexpr int N = 32; BODY; } break;   \
+    case 48: { constexpr int N = 48; BODY; } break;   \
+    case 64: { constexpr int N = 64; BODY; } break;   \
+    case 96: { constexpr int N = 96; BODY; } break;   \
+    case 128: { constexpr int N = 128; BODY; } break; \
+    case 256: { constexpr int N = 256; BODY; } break; \
+    default: return hipErrorInvalidValue;     \
+  }
+
+hipError_t step_begin(const KArgs& a, const double* e, const double* s, hipStream_t st) {
+  k_step_begin<<<1, 64, 0, st>>>(a, e[0], e[1], e[2], e[3], e[4], e[5], s[0], s[1], s[2], s[3], s[4], s[5]);
+  return hipGetLastError();
+}
+
+hipError_t ms_x_forward(const KArgs& a, hipStream_t s) {
+  switch (a.nv) {
+    case 1: return ms_x_forward_v1(a, s);
+    case 2: return ms_x_forward_v2(a, s);
+    case 3: return ms_x_forward_v3(a, s);
+    case 4: return ms_x_forward_v4(a, s);
+    case 5: return ms_x_forward_v5(a, s);
+    case 6: return ms_x_forward_v6(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s) {
+  k_fin_ms<<<1, 256, 0, s>>>(a, x_blocks(a));
+  return hipGetLastError();
+}
+
+hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.nz, ncomp);
+  if (dir > 0) {
+    PF_SWITCH_N(a.ny, (k_y<N, 1><<<grid, col_block<N>(), 0, s>>>(a)));
+  } else {
+    PF_SWITCH_N(a.ny, (k_y<N, -1><<<grid, col_block<N>(), 0, s>>>(a)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t ms_z_green(const KArgs& a, hipStream_t s) {
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny);
+  PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, col_block<N>(), 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t ms_x_inverse(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M(a.nx, (k_x_inv_ms<M><<<grid, kXThreads, 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
+  k_fin_res<<<1, 256, 0, s>>>(a, x_blocks(a));
+  return hipGetLastError();
+}
+
+hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
+  switch (a.nv) {
+    case 1: return ac_x_forward_v1(a, s);
+    case 2: return ac_x_forward_v2(a, s);
+    case 3: return ac_x_forward_v3(a, s);
+    case 4: return ac_x_forward_v4(a, s);
+    case 5: return ac_x_forward_v5(a, s);
+    case 6: return ac_x_forward_v6(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny, a.nv);
+  PF_SWITCH_N(a.nz, (k_z_ac<N><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  return hipGetLastError();
+}
+
+hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M(a.nx, (k_x_inv_ac<M><<<grid, kXThreads, 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t ac_finalize(const KArgs& a, int init_only, hipStream_t s) {
+  k_fin_ac<<<1, 256, 0, s>>>(a, x_blocks(a), z_blocks(a, a.nv), init_only);
+  return hipGetLastError();
+}
+
+hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s) {
+  const dim3 grid(x_blocks(a), ncomp);
+  PF_SWITCH_M(a.nx, (k_x_fwd_raw<M><<<grid, kXThreads, 0, s>>>(a, real)));
+  return hipGetLastError();
+}
+
+hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s) {
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny, ncomp);
+  if (dir > 0) {
+    PF_SWITCH_N(a.nz, (k_z_raw<N, 1><<<grid, col_block<N>(), 0, s>>>(a)));
+  } else {
+    PF_SWITCH_N(a.nz, (k_z_raw<N, -1><<<grid, col_block<N>(), 0, s>>>(a)));
+  }
+  return hipGetLastError();
+}
+
+hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s) {
+  const dim3 grid(x_blocks(a), ncomp);
+  PF_SWITCH_M(a.nx, (k_x_inv_raw<M><<<grid, kXThreads, 0, s>>>(a, real, scale)));
+  return hipGetLastError();
+}
+
+}  // namespace pfl

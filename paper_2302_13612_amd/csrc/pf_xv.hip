@@ -1,0 +1,254 @@
+// Forward x-pass kernels with the per-voxel physics, for PF_NV twin variants
+// per voxel (this file is compiled once per PF_NV = 1..6).
+//
+// Each thread owns E packed complex samples (two voxels each) of one row; the
+// x-pass plans keep E small (4 for power-of-two rows) so the per-voxel physics
+// fits in registers next to the FFT data.
+#include "pf_common.hpp"
+
+#ifndef PF_NV
+#error "PF_NV (number of twin variants) must be defined"
+#endif
+
+namespace pft {
+
+// Loads of one packed sample (voxels x0, x0+1) of a row.
+template <int V>
+struct Sample {
+  float2 e[6], p[6], h[V];
+  int g0, g1;
+};
+
+template <int V>
+__device__ __forceinline__ void load_sample(const KArgs& a, bool valid, size_t vs, size_t off, Sample<V>& s) {
+  s.g0 = s.g1 = 0;
+  if (!valid) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s.e[c] = s.p[c] = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int q = 0; q < V; ++q) s.h[q] = make_float2(0.f, 0.f);
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s.e[c] = *reinterpret_cast<const float2*>(a.eps + c * vs + off);
+#pragma unroll
+  for (int q = 0; q < V; ++q) s.h[q] = *reinterpret_cast<const float2*>(a.eta + q * vs + off);
+  if (a.epsp) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s.p[c] = *reinterpret_cast<const float2*>(a.epsp + c * vs + off);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s.p[c] = make_float2(0.f, 0.f);
+  }
+  if (a.gid) {
+    const uint16_t gg = *reinterpret_cast<const uint16_t*>(a.gid + off);
+    s.g0 = gg & 0xff;
+    s.g1 = gg >> 8;
+  }
+}
+
+// Fixed point, forward: polarisation tau = C(x):(eps - eps*) - C0:eps of
+// every voxel, FP64 sum of the stress, R2C of the six components.
+template <int M, int V>
+__global__ __launch_bounds__(kXThreads) void k_x_fwd_ms(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  if (a.state->st.done) return;
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  float shift[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) shift[c] = (float)(a.state->ebar_cur[c] - a.state->ebar_field[c]);
+  float2 v[6][E];
+  double ssum[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int x0 = 2 * (t + T * m);
+    Sample<V> s;
+    load_sample<V>(a, valid, vs, rbase + x0, s);
+    float o[2][6];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      float e[6], ep[6], et[V];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        e[c] = (half ? s.e[c].y : s.e[c].x) + shift[c];
+        ep[c] = half ? s.p[c].y : s.p[c].x;
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
+      float tau[6], sig[6];
+      with_table(a, half ? s.g1 : s.g0, [&](auto tab) {
+        Mat<V> mt;
+        constitutive<V>(e, et, ep, tab, a.h_kind, mt);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sig[c] = mt.sig[c];
+      });
+      float ge[6], c0e[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) ge[c] = c < 3 ? e[c] : 2.f * e[c];
+      symv6(a.C0, ge, c0e);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        tau[c] = sig[c] - c0e[c];
+        o[half][c] = tau[c];
+        if (valid) ssum[c] += (double)sig[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c][m] = make_float2(o[0][c], o[1][c]);
+  }
+  r2c_rows<M, 6>(v, lds + p * LROW, t, valid, a.spec, (size_t)(valid ? row : 0) * a.nh,
+                 (size_t)nrows * a.nh, a.tw_xh, a.tw_x);
+  block_sum<6>(ssum, a.part_ms + (size_t)blockIdx.x * kQms);
+}
+
+// Phase-field update, forward: driving forces and the explicit right-hand
+// side RHS_a = f_a - L dt (chem_a - mech_a) of every voxel, FP64 energy and
+// mean sums, extrema of f; R2C of the V right-hand sides.
+template <int M, int V>
+__global__ __launch_bounds__(kXThreads) void k_x_fwd_ac(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  float2 v[V][E];
+  double acc[kQac];
+#pragma unroll
+  for (int q = 0; q < kQac; ++q) acc[q] = 0.0;
+  float mn = 3.0e38f, mx = -3.0e38f;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int x0 = 2 * (t + T * m);
+    Sample<V> s;
+    load_sample<V>(a, valid, vs, rbase + x0, s);
+    float o[2][V];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      float e[6], ep[6], et[V];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        e[c] = half ? s.e[c].y : s.e[c].x;
+        ep[c] = half ? s.p[c].y : s.p[c].x;
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
+      float sig[6], gam[6], mech[V];
+      with_table(a, half ? s.g1 : s.g0, [&](auto tab) {
+        Mat<V> mt;
+        constitutive<V>(e, et, ep, tab, a.h_kind, mt);
+        const auto e0 = tab + 21 * (V + 1);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          sig[c] = mt.sig[c];
+          gam[c] = mt.gam[c];
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
+          const auto e0q = e0 + 6 * q;
+          const float work = sig[0] * e0q[0] + sig[1] * e0q[1] + sig[2] * e0q[2] +
+                             2.f * (sig[3] * e0q[3] + sig[4] * e0q[4] + sig[5] * e0q[5]);
+          float dcg[6];
+          symv6(tab + 21 * (q + 1), gam, dcg);
+          float quad = 0.f;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) quad += gam[c] * dcg[c];
+          mech[q] = dh_of(et[q], a.h_kind) * (work - 0.5f * quad);
+        }
+      });
+      float fm = 1.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) fm -= et[q];
+      // double well over the variants and the matrix: sum_{a<b} f_a^2 f_b^2
+      float fdw = 0.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        fdw += et[q] * et[q] * fm * fm;
+#pragma unroll
+        for (int r = q + 1; r < V; ++r) fdw += et[q] * et[q] * et[r] * et[r];
+      }
+      float fme = 0.f;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) fme += sig[c] * gam[c];
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        // chem_a = 2A f_a sum_{b != a} f_b (f_b - f_a), b over variants + matrix
+        float sm = fm * (fm - et[q]);
+#pragma unroll
+        for (int r = 0; r < V; ++r)
+          if (r != q) sm += et[r] * (et[r] - et[q]);
+        const float chem = 2.f * a.A * et[q] * sm;
+        o[half][q] = et[q] - a.LDt * (chem - mech[q]);
+      }
+      if (valid) {
+        acc[0] += (double)fdw;
+        acc[1] += (double)(0.5f * fme);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          acc[2 + c] += (double)sig[c];
+          acc[8 + c] += (double)e[c];
+        }
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          acc[14 + q] += (double)et[q];
+          mn = fminf(mn, et[q]);
+          mx = fmaxf(mx, et[q]);
+        }
+        if (a.save_stress) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) a.sig[c * vs + rbase + x0 + half] = sig[c];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) v[q][m] = make_float2(o[0][q], o[1][q]);
+  }
+  r2c_rows<M, V>(v, lds + p * LROW, t, valid, a.spec, (size_t)(valid ? row : 0) * a.nh,
+                 (size_t)nrows * a.nh, a.tw_xh, a.tw_x);
+  block_sum<kQac>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
+  block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
+}
+
+}  // namespace pft
+
+#define PF_CAT2(a, b) a##b
+#define PF_CAT(a, b) PF_CAT2(a, b)
+
+namespace pfl {
+using namespace pft;
+
+#define PF_SWITCH_M_LOCAL(nx, BODY)                   \
+  switch ((nx) / 2) {                                  \
+    case 16: { constexpr int M = 16; BODY; } break;   \
+    case 24: { constexpr int M = 24; BODY; } break;   \
+    case 32: { constexpr int M = 32; BODY; } break;   \
+    case 48: { constexpr int M = 48; BODY; } break;   \
+    case 64: { constexpr int M = 64; BODY; } break;   \
+    case 128: { constexpr int M = 128; BODY; } break; \
+    default: return hipErrorInvalidValue;              \
+  }
+
+hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ms<M, PF_NV><<<grid, kXThreads, 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ac<M, PF_NV><<<grid, kXThreads, 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+}  // namespace pfl

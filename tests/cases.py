@@ -1,0 +1,88 @@
+"""Build the same workload for the HIP library and for the oracle (tests only).
+
+Both sides receive the identical float32 inputs from the seeded generator;
+each computes its own material tables (the library in C++, the oracle in
+NumPy) and its own reference medium (the mean of every stiffness).
+"""
+
+import numpy as np
+
+from oracle import crystal as cr
+from oracle import mech
+from oracle import phasefield as opf
+from paper_2302_13612_amd import inputs
+
+
+def stress_rel_l2(sig_gpu6, sig_ref6):
+    """Frobenius relative error of tensor-Voigt stress fields (shear twice)."""
+    w = np.array([1, 1, 1, 2, 2, 2], dtype=np.float64).reshape(6, *([1] * (sig_ref6.ndim - 1)))
+    d = np.asarray(sig_gpu6, np.float64) - sig_ref6
+    return float(np.sqrt((w * d * d).sum() / (w * sig_ref6 * sig_ref6).sum()))
+
+
+def loads(cfg, n):
+    """(eps_bar, sig_bar) of step n for a recipe."""
+    if "final_strain" in cfg:
+        return inputs.ramp_load(cfg, n)
+    return cfg["eps_bar"], cfg["sig_bar"]
+
+
+def oracle_problem(cfg, tol=1e-10):
+    tabs = cr.mg_tables(cfg["rotations"], cfg["variant_ids"])
+    if cfg["homogeneous"]:
+        tabs = (tabs[0], np.broadcast_to(tabs[0][:, None], tabs[1].shape).copy(), tabs[2])
+    C0 = opf.reference_stiffness_average(tabs[0], tabs[1])
+    return opf.Problem(cfg["shape"], cfg["dx"], tabs, cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], C0,
+                       gid=cfg["gid"], h_kind=cfg.get("h_kind", "linear"), ms_tol=tol, ms_max_iter=300)
+
+
+def oracle_run(cfg, steps, tol=1e-10):
+    """Returns (eta after `steps` steps, stress of the last step (6, ...), stats list)."""
+    prob = oracle_problem(cfg, tol)
+    st = opf.State.initial(cfg["eta0"].astype(np.float64), np.zeros(6))
+    epsp = None if cfg["eps_p"] is None else cfg["eps_p"].astype(np.float64)
+    all_stats = []
+    sigma = None
+    for n in range(steps):
+        e, s = loads(cfg, n)
+        ld = dict(eps_bar=e, sig_bar=s, stress_mask=cfg["stress_mask"])
+        st, stats, sigma = opf.step(prob, st, epsp, ld)
+        all_stats.append(stats)
+    return st.eta, mech.tensor_to_voigt6(sigma), all_stats
+
+
+def gpu_solver(cfg, device="cuda"):
+    import torch
+    from paper_2302_13612_amd import binding
+    Cg, Cv, e0 = binding.mg_twin_tables(cfg["rotations"], cfg["variant_ids"])
+    if cfg["homogeneous"]:
+        Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
+    eta0 = torch.from_numpy(np.ascontiguousarray(cfg["eta0"])).to(device)
+    gid = None if cfg["gid"] is None else torch.from_numpy(np.ascontiguousarray(cfg["gid"])).to(device)
+    h_kind = binding.PF_H_QUINTIC if cfg.get("h_kind") == "quintic" else binding.PF_H_LINEAR
+    solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
+                            cfg["stress_mask"], gid=gid, h_kind=h_kind, ms_tol=cfg["ms_tol"],
+                            ms_max_iter=cfg["ms_max_iter"])
+    epsp = None if cfg["eps_p"] is None else torch.from_numpy(np.ascontiguousarray(cfg["eps_p"])).to(device)
+    return solver, epsp
+
+
+def gpu_run(cfg, steps, save_stress_last=True):
+    """Returns (solver, eta (numpy), stress of the last step (numpy) or None)."""
+    from paper_2302_13612_amd import binding
+    solver, epsp = gpu_solver(cfg)
+    for n in range(steps):
+        e, s = loads(cfg, n)
+        solver.step(1, e, s, eps_p=epsp if n == 0 else None,
+                    save_stress=save_stress_last and n == steps - 1)
+    eta = solver.field(binding.PF_FIELD_ETA).cpu().numpy()
+    sig = solver.field(binding.PF_FIELD_STRESS).cpu().numpy() if save_stress_last else None
+    return solver, eta, sig
+
+
+def small_polycrystal(shape=(32, 32, 32), n_grains=6, seed=5, n_var=6):
+    return inputs.polycrystal(shape=shape, n_grains=n_grains, seed=seed, n_var=n_var)
+
+
+def small_lamellae(shape=(64, 32, 32), seed=7):
+    return inputs.single_crystal_lamellae(shape=shape, seed=seed, radius=6.0)
