@@ -117,12 +117,14 @@ def main():
         f"{cfg['n_interfaces']} interfaces)")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    Cg, Cv, e0 = binding.mg_twin_tables(cfg["rotations"], cfg["variant_ids"])
+    # one crystal-frame Mg material shared by the grains, turned per grain
+    Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], cfg["variant_ids"])
     eta0 = torch.from_numpy(cfg["eta0"]).to(dev)
     gid = torch.from_numpy(cfg["gid"]).to(dev)
     epsp = torch.from_numpy(cfg["eps_p"]).to(dev)
     solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
-                            cfg["stress_mask"], gid=gid, ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"])
+                            cfg["stress_mask"], gid=gid, ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"],
+                            rotations=cfg["rotations"])
     del eta0
     log("warmup")
     solver.step(1, cfg["eps_bar"], cfg["sig_bar"], eps_p=epsp)

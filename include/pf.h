@@ -88,6 +88,11 @@ typedef struct {
   const double *C_grain;   /* host [n_grains][6][6] parent stiffness        */
   const double *C_var;     /* host [n_grains][n_var][6][6] twin stiffness   */
   const double *eps0;      /* host [n_grains][n_var][6] twin eigenstrain    */
+  const double *grain_rot; /* optional host [n_grains][3][3] crystal->sample
+                              rotations (row-major). When given, C_grain,
+                              C_var and eps0 are read for index 0 only, as
+                              the crystal-frame material every grain shares;
+                              grain g uses it turned by its rotation.       */
   const uint8_t *grain_id; /* device [nz][ny][nx], or NULL if n_grains == 1;
                               must stay valid until pf_destroy              */
   const float *eta0;       /* device [n_var][nz][ny][nx] initial f          */

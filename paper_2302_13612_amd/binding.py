@@ -34,6 +34,7 @@ class PfProblem(ctypes.Structure):
         ("h_kind", ctypes.c_int32),
         ("n_grains", ctypes.c_int32),
         ("C_grain", _dp), ("C_var", _dp), ("eps0", _dp),
+        ("grain_rot", _dp),
         ("grain_id", ctypes.c_void_p),
         ("eta0", ctypes.c_void_p),
         ("C_ref", ctypes.c_double * 36),
@@ -137,10 +138,12 @@ class Solver:
     eta0: torch float32 CUDA tensor (n_var, nz, ny, nx). gid: torch uint8 CUDA
     tensor (nz, ny, nx) or None. Tables are numpy float64 (G,6,6), (G,V,6,6),
     (G,V,6). C_ref: 6x6 numpy or None for the mean of all stiffnesses.
+    rotations: optional (G,3,3) crystal->sample rotations; then the tables
+    hold one crystal-frame material (leading dimension 1) shared by all grains.
     """
 
     def __init__(self, eta0, dx, A, kappa, L, dt, tables, stress_mask, gid=None, C_ref=None,
-                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50):
+                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None):
         import torch
         self.lib = load()
         self.torch = torch
@@ -152,7 +155,13 @@ class Solver:
         G = Cg.shape[0]
         if Cv.shape != (G, V, 6, 6) or e0.shape != (G, V, 6):
             raise ValueError("table shapes do not match n_var / n_grains")
-        self._keep = [Cg, Cv, e0, eta0]
+        rot = None
+        if rotations is not None:
+            rot = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 3, 3))
+            if G != 1:
+                raise ValueError("with rotations the tables hold one crystal-frame material")
+            G = rot.shape[0]
+        self._keep = [Cg, Cv, e0, eta0, rot]
         p = PfProblem()
         p.nx, p.ny, p.nz = nx, ny, nz
         p.dx = dx
@@ -161,6 +170,7 @@ class Solver:
         p.h_kind = h_kind
         p.n_grains = G
         p.C_grain, p.C_var, p.eps0 = _ptr(Cg), _ptr(Cv), _ptr(e0)
+        p.grain_rot = _ptr(rot) if rot is not None else None
         if gid is not None:
             if gid.dtype != torch.uint8 or not gid.is_cuda or tuple(gid.shape) != (nz, ny, nx):
                 raise ValueError("gid must be a uint8 CUDA tensor (nz, ny, nx)")

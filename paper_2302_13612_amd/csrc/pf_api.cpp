@@ -11,6 +11,8 @@
 #include "../../include/pf.h"
 #include "pf_device.hpp"
 
+void pf_rotate_voigt(const double* Cv, const double* R9, double* out);  // pf_crystal.cpp
+
 using pft::DevState;
 using pft::KArgs;
 using pft::Status;
@@ -22,7 +24,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout (byte offsets from the workspace base).
 struct Layout {
-  size_t eta, eps, sig, spec, tables, tw, part_ms, part_res, part_ac, part_mm, part_gd, state, total;
+  size_t eta, eps, sig, spec, tables, rot, tw, part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
 
@@ -30,13 +32,18 @@ int tab_stride_for(int nv) { return 21 * (nv + 1) + 6 * nv; }
 
 bool axis_ok(int n) { return pfl::supported_axis(n); }
 
+// Spectral rows of nx/2+1 coefficients are padded to a multiple of 16
+// complex values (128 bytes) so every 16-column tile of the y and z passes is
+// one aligned cache line per row.
+int spec_stride(int nx) { return (nx / 2 + 1 + 15) / 16 * 16; }
+
 Layout make_layout(int nx, int ny, int nz, int nv, int n_grains) {
   Layout L{};
   const size_t nvox = (size_t)nx * ny * nz;
   const size_t nh = (size_t)nx / 2 + 1;
-  const size_t nspec = nh * ny * nz;
+  const size_t nspec = (size_t)spec_stride(nx) * ny * nz;
   KArgs a{};
-  a.nx = nx; a.ny = ny; a.nz = nz; a.nh = (int)nh; a.nv = nv;
+  a.nx = nx; a.ny = ny; a.nz = nz; a.nh = (int)nh; a.sh = spec_stride(nx); a.nv = nv;
   const size_t xb = (size_t)pfl::x_blocks(a);
   const size_t zb = (size_t)pfl::z_blocks(a, nv > 6 ? nv : 6);
   size_t off = 0;
@@ -47,6 +54,7 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains) {
   L.spec = take(sizeof(float) * 2 * nspec * 6);
   L.tab_stride = tab_stride_for(nv);
   L.tables = take(sizeof(float) * (size_t)L.tab_stride * (n_grains > 0 ? n_grains : 1));
+  L.rot = take(sizeof(float) * 12 * (size_t)(n_grains > 0 ? n_grains : 1));
   L.tw = take(sizeof(float) * 2 * (size_t)(nx / 2 + nx + ny + nz));
   L.part_ms = take(sizeof(double) * xb * pft::kQms);
   L.part_res = take(sizeof(double) * xb * pft::kQres);
@@ -240,29 +248,61 @@ int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_str
   c->prof_on = false;
   c->ms_max_iter = p->ms_max_iter;
 
-  // material tables
+  // material tables: per-grain sample-frame tables (rotated from the shared
+  // crystal-frame material when rotations are given)
   const int nv = p->n_var, G = p->n_grains;
+  const bool rotated = p->grain_rot != nullptr;
+  std::vector<double> Cg_s((size_t)36 * G), Cv_s((size_t)36 * G * nv), e0_s((size_t)6 * G * nv);
+  for (int g = 0; g < G; ++g) {
+    if (rotated) {
+      const double* R = p->grain_rot + 9 * g;
+      pf_rotate_voigt(p->C_grain, R, &Cg_s[36 * g]);
+      for (int q = 0; q < nv; ++q) {
+        pf_rotate_voigt(p->C_var + 36 * q, R, &Cv_s[36 * ((size_t)g * nv + q)]);
+        const double* e = p->eps0 + 6 * q;
+        const double A[3][3] = {{e[0], e[5], e[4]}, {e[5], e[1], e[3]}, {e[4], e[3], e[2]}};
+        double B[3][3];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m)
+              for (int n = 0; n < 3; ++n) acc += R[3 * i + m] * A[m][n] * R[3 * k + n];
+            B[i][k] = acc;
+          }
+        double* o = &e0_s[6 * ((size_t)g * nv + q)];
+        o[0] = B[0][0]; o[1] = B[1][1]; o[2] = B[2][2]; o[3] = B[1][2]; o[4] = B[0][2]; o[5] = B[0][1];
+      }
+    } else {
+      std::memcpy(&Cg_s[36 * g], p->C_grain + 36 * g, 36 * sizeof(double));
+      std::memcpy(&Cv_s[36 * (size_t)g * nv], p->C_var + 36 * (size_t)g * nv, 36 * nv * sizeof(double));
+      std::memcpy(&e0_s[6 * (size_t)g * nv], p->eps0 + 6 * (size_t)g * nv, 6 * nv * sizeof(double));
+    }
+  }
   std::vector<float> tab((size_t)L.tab_stride * G, 0.f);
   for (int g = 0; g < G; ++g) {
     float* t = tab.data() + (size_t)g * L.tab_stride;
-    const double* Cg = p->C_grain + 36 * g;
+    const double* Cg = &Cg_s[36 * g];
     pack_sym(Cg, t);
     for (int q = 0; q < nv; ++q) {
-      const double* Cv = p->C_var + 36 * ((size_t)g * nv + q);
+      const double* Cv = &Cv_s[36 * ((size_t)g * nv + q)];
       double d[36];
       for (int i = 0; i < 36; ++i) d[i] = Cv[i] - Cg[i];
       pack_sym(d, t + 21 * (q + 1));
-      for (int k = 0; k < 6; ++k) t[21 * (nv + 1) + 6 * q + k] = (float)p->eps0[6 * ((size_t)g * nv + q) + k];
+      for (int k = 0; k < 6; ++k) t[21 * (nv + 1) + 6 * q + k] = (float)e0_s[6 * ((size_t)g * nv + q) + k];
     }
   }
+  std::vector<float> rot((size_t)12 * G, 0.f);
+  if (rotated)
+    for (int g = 0; g < G; ++g)
+      for (int k = 0; k < 9; ++k) rot[12 * g + k] = (float)p->grain_rot[9 * g + k];
   // reference medium
   double C0[36];
   if (p->C_ref_auto) {
     for (int i = 0; i < 36; ++i) {
       double s = 0.0;
       for (int g = 0; g < G; ++g) {
-        s += p->C_grain[36 * g + i];
-        for (int q = 0; q < nv; ++q) s += p->C_var[36 * ((size_t)g * nv + q) + i];
+        s += Cg_s[36 * g + i];
+        for (int q = 0; q < nv; ++q) s += Cv_s[36 * ((size_t)g * nv + q) + i];
       }
       C0[i] = s / (double)(G * (nv + 1));
     }
@@ -273,16 +313,16 @@ int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_str
   // after one iteration.
   bool one = (G == 1);
   for (int i = 0; i < 36 && one; ++i) {
-    if (p->C_grain[i] != C0[i]) one = false;
+    if (Cg_s[i] != C0[i]) one = false;
     for (int q = 0; q < nv && one; ++q)
-      if (p->C_var[36 * q + i] != p->C_grain[i]) one = false;
+      if (Cv_s[36 * q + i] != Cg_s[i]) one = false;
   }
   c->one_iteration = one;
 
   // kernel arguments
   KArgs& a = c->args;
   std::memset(&a, 0, sizeof(a));
-  a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.nh = c->nh; a.nv = nv;
+  a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.nh = c->nh; a.sh = spec_stride(p->nx); a.nv = nv;
   a.h_kind = p->h_kind;
   a.n_grains = G;
   a.tab_stride = L.tab_stride;
@@ -331,6 +371,18 @@ int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_str
   a.epsp = nullptr;
   a.gid = G > 1 ? p->grain_id : nullptr;
   a.tables = reinterpret_cast<float*>(ws + L.tables);
+  // one grain: its rotated table serves every voxel (no per-voxel rotation)
+  a.rot = (rotated && G > 1) ? reinterpret_cast<float*>(ws + L.rot) : nullptr;
+  if (rotated) {
+    // crystal-frame table shared by every grain: [C 21][dC_q 21 x V][eps0_q 6 x V]
+    pack_sym(p->C_grain, a.xtab);
+    for (int q = 0; q < nv; ++q) {
+      double d[36];
+      for (int i = 0; i < 36; ++i) d[i] = p->C_var[36 * q + i] - p->C_grain[i];
+      pack_sym(d, a.xtab + 21 * (q + 1));
+      for (int k = 0; k < 6; ++k) a.xtab[21 * (nv + 1) + 6 * q + k] = (float)p->eps0[6 * q + k];
+    }
+  }
   a.spec = reinterpret_cast<float2*>(ws + L.spec);
   float2* tw = reinterpret_cast<float2*>(ws + L.tw);
   a.tw_xh = tw;
@@ -371,6 +423,9 @@ int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_str
   if ((e = hipMemcpyAsync(const_cast<float*>(a.tables), tab.data(), tab.size() * sizeof(float),
                           hipMemcpyHostToDevice, c->stream)) != hipSuccess)
     return bail(e, "tables");
+  if (rotated && (e = hipMemcpyAsync(const_cast<float*>(a.rot), rot.data(), rot.size() * sizeof(float),
+                                     hipMemcpyHostToDevice, c->stream)) != hipSuccess)
+    return bail(e, "rotations");
   if ((e = hipMemcpyAsync(tw, twh.data(), twh.size() * sizeof(float), hipMemcpyHostToDevice, c->stream)) !=
       hipSuccess)
     return bail(e, "twiddles");
@@ -507,6 +562,7 @@ int pf_fft(pf_ctx* c, int32_t direction, int32_t ncomp, float* real, void* spec)
     return fail(c, PF_EINVAL, "pf_fft: bad arguments");
   KArgs a = c->args;
   a.spec = reinterpret_cast<float2*>(spec);
+  a.sh = c->nh;  // caller layout: unpadded rows
   hipStream_t s = c->stream;
   if (direction == 1) {
     PF_TRY(launch(c, "fft_x_forward", [&] { return pfl::raw_x_forward(a, real, ncomp, s); }));

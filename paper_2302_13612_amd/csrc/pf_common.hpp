@@ -109,7 +109,88 @@ __device__ __forceinline__ void constitutive(const float e[6], const float eta[V
   symv6(Cx, o.gam, o.sig);
 }
 
+// Rotation form of the constitutive law for a polycrystal whose grains share
+// one crystal-frame material: the elastic strain is turned into the crystal
+// frame of the voxel's grain (e_c = R^T e R), the crystal-frame mixture
+// stiffness and twin eigenstrains (wave-uniform constants) give the stress,
+// which is turned back (sigma = R sigma_c R^T).
+template <int V>
+struct MatR {
+  float gam_c[6];  // elastic strain in the crystal frame, engineering shear
+  float sig_c[6];  // stress in the crystal frame
+  float sig[6];    // stress in the sample frame
+};
+
+// out = R^T A R (to_crystal) or R A R^T, A symmetric (tensor-Voigt).
+template <bool TO_CRYSTAL>
+__device__ __forceinline__ void rotate_sym(const float (&R)[9], const float (&A)[6], float (&out)[6]) {
+  const float M[3][3] = {{A[0], A[5], A[4]}, {A[5], A[1], A[3]}, {A[4], A[3], A[2]}};
+  float B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += M[i][k] * (TO_CRYSTAL ? R[3 * k + j] : R[3 * j + k]);
+      B[i][j] = acc;
+    }
+  constexpr int PI[6] = {0, 1, 2, 1, 0, 0}, PJ[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const int i = PI[c], j = PJ[c];
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc += (TO_CRYSTAL ? R[3 * k + i] : R[3 * i + k]) * B[k][j];
+    out[c] = acc;
+  }
+}
+
+template <int V>
+__device__ __forceinline__ void constitutive_rot(const KArgs& a, const float e[6], const float eta[V],
+                                                 const float ep[6], const float (&R)[9], MatR<V>& o) {
+  float h[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) h[q] = h_of(eta[q], a.h_kind);
+  float d[6], dc[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) d[c] = e[c] - ep[c];
+  rotate_sym<true>(R, d, dc);
+  const float* xt = a.xtab;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    float es = 0.f;
+#pragma unroll
+    for (int q = 0; q < V; ++q) es += h[q] * xt[21 * (V + 1) + 6 * q + c];
+    const float el = dc[c] - es;
+    o.gam_c[c] = c < 3 ? el : 2.f * el;
+  }
+  float Cx[21];
+#pragma unroll
+  for (int i = 0; i < 21; ++i) {
+    float v = xt[i];
+#pragma unroll
+    for (int q = 0; q < V; ++q) v += h[q] * xt[21 * (q + 1) + i];
+    Cx[i] = v;
+  }
+  symv6(Cx, o.gam_c, o.sig_c);
+  rotate_sym<false>(R, o.sig_c, o.sig);
+}
+
+__device__ __forceinline__ void load_rotation(const KArgs& a, int g, float (&R)[9]) {
+  const float4* r = reinterpret_cast<const float4*>(a.rot + 12 * g);
+  const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+  R[0] = r0.x; R[1] = r0.y; R[2] = r0.z; R[3] = r0.w;
+  R[4] = r1.x; R[5] = r1.y; R[6] = r1.z; R[7] = r1.w;
+  R[8] = r2.x;
+}
+
 // ----------------------------------------------------------- x pass parts
+// Threads per x-pass block for half-length M (smaller for the radix-3 rows so
+// the staging slabs stay within 64 KiB of LDS).
+template <int M>
+__host__ __device__ constexpr int xthreads() { return (M == 24 || M == 48) ? 128 : 256; }
+
 // Forward: the NC complex rows held in v (packed real pairs) -> R2C spectra.
 template <int M, int NC>
 __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* ldsrow, int t, bool valid,
@@ -139,6 +220,33 @@ __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* l
     }
     if (t == 0 && valid) spec[c * cstride + rowoff + M] = make_float2(v[c][0].x - v[c][0].y, 0.f);
   }
+}
+
+// Forward of one staged row: v (packed real pairs) -> FFT -> split into the
+// nx/2+1 coefficients stored at dst. ldsrow is this row's exchange buffer.
+template <int M>
+__device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
+                                        float2* __restrict__ dst, const float2* __restrict__ tw_m,
+                                        const float2* __restrict__ tw_n) {
+  constexpr int E = XPlan<M>::E, T = M / E;
+  RowView view{ldsrow};
+  fft_pencil<M, 1, XPlan<M>>(v, view, t, tw_m);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) view.write(t + T * m, v[m]);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const float2 zk = v[m];
+    const float2 zm = view.read(k == 0 ? 0 : M - k);
+    const float2 ev = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
+    const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
+    const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);
+    const float2 X = cadd(ev, cmul(tw_n[k], od));
+    if (valid) dst[k] = X;
+  }
+  if (t == 0 && valid) dst[M] = make_float2(v[0].x - v[0].y, 0.f);
 }
 
 // Inverse: one spectral row (M+1 coefficients) -> packed real pairs in v
@@ -176,19 +284,24 @@ __device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow
   fft_pencil<M, -1, XPlan<M>>(v, view, t, tw_m);
 }
 
-// Per-voxel material table of grain g. When the whole wavefront sits in one
-// grain the table is read through the constant address space (scalar loads
-// into SGPRs); otherwise through per-lane global loads.
+// Per-voxel material table of grain g, always read through the constant
+// address space with a wave-uniform address (scalar loads into SGPRs): the
+// distinct grains of a wavefront are visited one after the other, each with
+// only its lanes active (usually one grain, two or three at boundaries).
 typedef const __attribute__((address_space(4))) float* ctab_t;
-typedef const __attribute__((address_space(1))) float* gtab_t;
 
 template <class F>
 __device__ __forceinline__ void with_table(const KArgs& a, int g, F&& f) {
-  const int gu = __builtin_amdgcn_readfirstlane(g);
-  if (__all(g == gu)) {
-    f((ctab_t)(a.tables + gu * a.tab_stride));
-  } else {
-    f((gtab_t)(a.tables + g * a.tab_stride));
+  bool todo = true;
+  while (true) {
+    if (todo) {
+      const int gu = __builtin_amdgcn_readfirstlane(g);
+      if (g == gu) {
+        f((ctab_t)(a.tables + gu * a.tab_stride));
+        todo = false;
+      }
+    }
+    if (!__any(todo)) break;
   }
 }
 

@@ -89,6 +89,14 @@ void rotate_voigt(const double* Cv, const double R[3][3], double* out) {
 
 }  // namespace
 
+// Used by the runtime to turn a crystal-frame material into grain frames.
+void pf_rotate_voigt(const double* Cv, const double* R9, double* out) {
+  double R[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R[i][j] = R9[3 * i + j];
+  rotate_voigt(Cv, R, out);
+}
+
 extern "C" int pf_mg_twin_tables(const double C_hex[5], double c_over_a, double gamma_tw, int32_t n_grains,
                                  const double* rotations, int32_t n_var, const int32_t* variant_ids,
                                  double* C_grain, double* C_var, double* eps0) {

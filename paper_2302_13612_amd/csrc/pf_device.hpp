@@ -7,6 +7,7 @@ namespace pft {
 
 constexpr int kMaxVar = 6;
 constexpr int kColTile = 16;       // spectral columns per y/z block
+constexpr int kZmsTile = 8;        // spectral columns per block of the Green z pass
 constexpr int kXThreads = 256;     // threads per x-pass block
 
 // Quantities reduced per block (FP64 partial sums / extrema).
@@ -39,6 +40,7 @@ struct DevState {
 // Everything a kernel needs, passed by value.
 struct KArgs {
   int nx, ny, nz, nh, nv;     // grid, nh = nx/2+1, number of variants
+  int sh;                     // spectral row stride (complex elements, >= nh)
   int h_kind;
   int n_grains, tab_stride;
   float A, LDt;               // double-well height, L*dt
@@ -57,6 +59,8 @@ struct KArgs {
   const float* epsp;          // [6][nz][ny][nx] or null
   const uint8_t* gid;         // [nz][ny][nx] or null
   const float* tables;        // [n_grains][tab_stride]
+  const float* rot;           // [n_grains][12] crystal->sample rotations (row-major 3x3), or null
+  float xtab[21 + 27 * kMaxVar];  // crystal-frame table shared by every grain (rotation form)
   float2* spec;               // [6][nz][ny][nh]
   const float2* tw_xh;        // length nx/2
   const float2* tw_x;         // length nx

@@ -20,8 +20,8 @@ namespace pft {
 // Fixed point, inverse: new strain field from the six spectra, FP64 sums of
 // the squared change and the squared new strain (full tensor norm).
 template <int M>
-__global__ __launch_bounds__(kXThreads) void k_x_inv_ms(const KArgs a) {
-  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+__global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   if (a.state->st.done) return;
@@ -32,8 +32,8 @@ __global__ __launch_bounds__(kXThreads) void k_x_inv_ms(const KArgs a) {
   const int nx = a.nx;
   const size_t vs = (size_t)nrows * nx;
   const size_t rbase = (size_t)(valid ? row : 0) * nx;
-  const size_t cs = (size_t)nrows * a.nh;
-  const size_t roff = (size_t)(valid ? row : 0) * a.nh;
+  const size_t cs = (size_t)nrows * a.sh;
+  const size_t roff = (size_t)(valid ? row : 0) * a.sh;
   double acc[2] = {0.0, 0.0};
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
@@ -59,8 +59,8 @@ __global__ __launch_bounds__(kXThreads) void k_x_inv_ms(const KArgs a) {
 
 // Phase-field update, inverse: new order parameters, count of non-finite values.
 template <int M>
-__global__ __launch_bounds__(kXThreads) void k_x_inv_ac(const KArgs a) {
-  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+__global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
@@ -69,8 +69,8 @@ __global__ __launch_bounds__(kXThreads) void k_x_inv_ac(const KArgs a) {
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  const size_t cs = (size_t)nrows * a.nh;
-  const size_t roff = (size_t)(valid ? row : 0) * a.nh;
+  const size_t cs = (size_t)nrows * a.sh;
+  const size_t roff = (size_t)(valid ? row : 0) * a.sh;
   double bad[1] = {0.0};
 #pragma unroll 1
   for (int q = 0; q < a.nv; ++q) {
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(kXThreads) void k_x_inv_ac(const KArgs a) {
 
 // Plain transforms of caller fields (checking the passes).
 template <int M>
-__global__ __launch_bounds__(kXThreads) void k_x_fwd_raw(const KArgs a, const float* __restrict__ real) {
-  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_raw(const KArgs a, const float* __restrict__ real) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
@@ -107,14 +107,14 @@ __global__ __launch_bounds__(kXThreads) void k_x_fwd_raw(const KArgs a, const fl
     const int x0 = 2 * (t + T * m);
     v[0][m] = valid ? *reinterpret_cast<const float2*>(real + comp * vs + rbase + x0) : make_float2(0.f, 0.f);
   }
-  const size_t cs = (size_t)nrows * a.nh;
-  r2c_rows<M, 1>(v, lds + p * LROW, t, valid, a.spec + comp * cs, (size_t)(valid ? row : 0) * a.nh, cs,
+  const size_t cs = (size_t)nrows * a.sh;
+  r2c_rows<M, 1>(v, lds + p * LROW, t, valid, a.spec + comp * cs, (size_t)(valid ? row : 0) * a.sh, cs,
                  a.tw_xh, a.tw_x);
 }
 
 template <int M>
-__global__ __launch_bounds__(kXThreads) void k_x_inv_raw(const KArgs a, float* __restrict__ real, float scale) {
-  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+__global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, float* __restrict__ real, float scale) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
@@ -124,9 +124,9 @@ __global__ __launch_bounds__(kXThreads) void k_x_inv_raw(const KArgs a, float* _
   const int comp = blockIdx.y;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  const size_t cs = (size_t)nrows * a.nh;
+  const size_t cs = (size_t)nrows * a.sh;
   float2 v[E];
-  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.nh, a.tw_xh,
+  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.sh, a.tw_xh,
              a.tw_x);
   if (valid) {
 #pragma unroll
@@ -147,27 +147,59 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_y(const KArgs a
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
   const int z = blockIdx.y, comp = blockIdx.z;
-  const size_t cs = (size_t)a.nz * a.ny * a.nh;
-  float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.nh + (valid ? kx : 0);
+  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * a.nh] : make_float2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * a.sh] : make_float2(0.f, 0.f);
   fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, a.tw_y);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * a.nh] = v[m];
+    for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * a.sh] = v[m];
   }
 }
 
 // Signed index of coefficient k on an axis of length n (Nyquist -> -n/2).
 __device__ __forceinline__ int signed_k(int k, int n) { return k < n / 2 ? k : k - n; }
 
-// Green's operator step of the fixed point at one wavevector: the new strain
-// coefficient from the polarisation, eps = -Gamma0 : tau (times 1/N); the
-// prescribed mean at xi = 0; the reference compliance at the ambiguous
-// Nyquist wavevectors.
-__device__ __forceinline__ void green_apply(const KArgs& a, int kx, int ky, int kz, float2 (&tau)[6]) {
-  const int sy = signed_k(ky, a.ny), sz = signed_k(kz, a.nz);
+// Logical block index that gives consecutive ids to the blocks the hardware
+// deals to one XCD (blocks go round-robin to the 8 XCDs), so neighbouring
+// column tiles that share 128-byte lines run under the same L2.
+__device__ __forceinline__ int xcd_logical(int b, int nb) {
+  const int q = nb / 8, r = nb % 8;
+  const int x = b % 8, i = b / 8;
+  return x * q + (x < r ? x : r) + i;
+}
+
+// Acoustic tensor K_ik(xi) = C0_ijkl xi_j xi_l of a column (xi_x, xi_y fixed,
+// xi_z = c varying) as K0 + c (K1 + c K2); entries in the order 00 01 02 11 12 22.
+__device__ __forceinline__ void acoustic_parts(const KArgs& a, float x0, float x1, float (&K0)[6],
+                                               float (&K1)[6], float (&K2)[6]) {
+  constexpr int VI[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
+  constexpr int II[6] = {0, 0, 0, 1, 1, 2}, KK[6] = {0, 1, 2, 1, 2, 2};
+  const float xi[2] = {x0, x1};
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    const int i = II[e], k = KK[e];
+    float k0 = 0.f, k1 = 0.f;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int l = 0; l < 2; ++l) k0 += a.C0[sym6(VI[i][j], VI[k][l])] * xi[j] * xi[l];
+      k1 += (a.C0[sym6(VI[i][j], VI[k][2])] + a.C0[sym6(VI[i][2], VI[k][j])]) * xi[j];
+    }
+    K0[e] = k0;
+    K1[e] = k1;
+    K2[e] = a.C0[sym6(VI[i][2], VI[k][2])];
+  }
+}
+
+// Green's operator step of the fixed point at one wavevector xi (any scale:
+// the operator is homogeneous of degree 0): eps = -Gamma0 : tau / N with
+// Gamma0 : tau = sym(xi (x) K(xi)^{-1} (tau xi)); the prescribed mean at
+// xi = 0; the reference compliance at the ambiguous Nyquist wavevectors.
+__device__ __forceinline__ void green_apply(const KArgs& a, int kx, int ky, int kz, const float (&xi)[3],
+                                            const float (&K)[6], float2 (&tau)[6]) {
   if (kx == 0 && ky == 0 && kz == 0) {
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau[c] = make_float2((float)a.state->ebar_next[c], 0.f);
@@ -192,73 +224,56 @@ __device__ __forceinline__ void green_apply(const KArgs& a, int kx, int ky, int 
     for (int c = 0; c < 6; ++c) tau[c] = cscale(o[c], -s);
     return;
   }
-  float n[3] = {(float)kx / (float)a.nx, (float)sy / (float)a.ny, (float)sz / (float)a.nz};
-  const float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
-  n[0] *= inv;
-  n[1] *= inv;
-  n[2] *= inv;
-  // K_ik = C0_ijkl n_j n_l
-  constexpr int VI[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
-  float K[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int k = i; k < 3; ++k) {
-      float acc = 0.f;
-#pragma unroll
-      for (int j = 0; j < 3; ++j)
-#pragma unroll
-        for (int l = 0; l < 3; ++l) acc += a.C0[sym6(VI[i][j], VI[k][l])] * n[j] * n[l];
-      K[i][k] = acc;
-      K[k][i] = acc;
-    }
-  const float A00 = K[1][1] * K[2][2] - K[1][2] * K[1][2];
-  const float A01 = K[0][2] * K[1][2] - K[0][1] * K[2][2];
-  const float A02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-  const float A11 = K[0][0] * K[2][2] - K[0][2] * K[0][2];
-  const float A12 = K[0][1] * K[0][2] - K[0][0] * K[1][2];
-  const float A22 = K[0][0] * K[1][1] - K[0][1] * K[0][1];
-  const float rdet = 1.f / (K[0][0] * A00 + K[0][1] * A01 + K[0][2] * A02);
+  const float A00 = K[3] * K[5] - K[4] * K[4];
+  const float A01 = K[2] * K[4] - K[1] * K[5];
+  const float A02 = K[1] * K[4] - K[2] * K[3];
+  const float A11 = K[0] * K[5] - K[2] * K[2];
+  const float A12 = K[1] * K[2] - K[0] * K[4];
+  const float A22 = K[0] * K[3] - K[1] * K[1];
+  const float rdet = 1.f / (K[0] * A00 + K[1] * A01 + K[2] * A02);
   const float Nm[3][3] = {{A00 * rdet, A01 * rdet, A02 * rdet},
                           {A01 * rdet, A11 * rdet, A12 * rdet},
                           {A02 * rdet, A12 * rdet, A22 * rdet}};
-  // t = tau n (tau symmetric, Voigt xx yy zz yz xz xy)
+  // t = tau xi (tau symmetric, Voigt xx yy zz yz xz xy)
   float2 tv[3];
-  tv[0] = make_float2(tau[0].x * n[0] + tau[5].x * n[1] + tau[4].x * n[2],
-                      tau[0].y * n[0] + tau[5].y * n[1] + tau[4].y * n[2]);
-  tv[1] = make_float2(tau[5].x * n[0] + tau[1].x * n[1] + tau[3].x * n[2],
-                      tau[5].y * n[0] + tau[1].y * n[1] + tau[3].y * n[2]);
-  tv[2] = make_float2(tau[4].x * n[0] + tau[3].x * n[1] + tau[2].x * n[2],
-                      tau[4].y * n[0] + tau[3].y * n[1] + tau[2].y * n[2]);
+  tv[0] = make_float2(tau[0].x * xi[0] + tau[5].x * xi[1] + tau[4].x * xi[2],
+                      tau[0].y * xi[0] + tau[5].y * xi[1] + tau[4].y * xi[2]);
+  tv[1] = make_float2(tau[5].x * xi[0] + tau[1].x * xi[1] + tau[3].x * xi[2],
+                      tau[5].y * xi[0] + tau[1].y * xi[1] + tau[3].y * xi[2]);
+  tv[2] = make_float2(tau[4].x * xi[0] + tau[3].x * xi[1] + tau[2].x * xi[2],
+                      tau[4].y * xi[0] + tau[3].y * xi[1] + tau[2].y * xi[2]);
   float2 u[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     u[i] = make_float2(Nm[i][0] * tv[0].x + Nm[i][1] * tv[1].x + Nm[i][2] * tv[2].x,
                        Nm[i][0] * tv[0].y + Nm[i][1] * tv[1].y + Nm[i][2] * tv[2].y);
-  // eps = -sym(n (x) u) / N
+  // eps = -sym(xi (x) u) / N
   const float h = -0.5f * s;
-  tau[0] = cscale(u[0], -s * n[0]);
-  tau[1] = cscale(u[1], -s * n[1]);
-  tau[2] = cscale(u[2], -s * n[2]);
-  tau[3] = make_float2(h * (n[1] * u[2].x + n[2] * u[1].x), h * (n[1] * u[2].y + n[2] * u[1].y));
-  tau[4] = make_float2(h * (n[0] * u[2].x + n[2] * u[0].x), h * (n[0] * u[2].y + n[2] * u[0].y));
-  tau[5] = make_float2(h * (n[0] * u[1].x + n[1] * u[0].x), h * (n[0] * u[1].y + n[1] * u[0].y));
+  tau[0] = cscale(u[0], -s * xi[0]);
+  tau[1] = cscale(u[1], -s * xi[1]);
+  tau[2] = cscale(u[2], -s * xi[2]);
+  tau[3] = make_float2(h * (xi[1] * u[2].x + xi[2] * u[1].x), h * (xi[1] * u[2].y + xi[2] * u[1].y));
+  tau[4] = make_float2(h * (xi[0] * u[2].x + xi[2] * u[0].x), h * (xi[0] * u[2].y + xi[2] * u[0].y));
+  tau[5] = make_float2(h * (xi[0] * u[1].x + xi[1] * u[0].x), h * (xi[0] * u[1].y + xi[1] * u[0].y));
 }
 
 // z pass of the fixed point: forward z transform of the six polarisation
-// components, Green's operator, inverse z transform. grid (tiles, ny).
+// components, Green's operator, inverse z transform. 1D grid of
+// (column tile, ky) blocks in XCD-aware order; tiles of kZmsTile columns.
 template <int N>
-__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a) {
-  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+__global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a) {
+  constexpr int E = Plan<N>::E, T = N / E, C = kZmsTile;
   __shared__ float2 lds[N * C];
   if (a.state->st.done) return;
+  const int ntile = (a.nh + C - 1) / C;
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int tile = lb % ntile, ky = lb / ntile;
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = blockIdx.x * C + cc;
+  const int kx = tile * C + cc;
   const bool valid = kx < a.nh;
-  const int ky = blockIdx.y;
-  const size_t cs = (size_t)a.nz * a.ny * a.nh;
-  const size_t zs = (size_t)a.ny * a.nh;
-  float2* col = a.spec + (size_t)ky * a.nh + (valid ? kx : 0);
+  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const size_t zs = (size_t)a.ny * a.sh;
+  float2* col = a.spec + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[6][E];
 #pragma unroll
   for (int c = 0; c < 6; ++c)
@@ -268,12 +283,21 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ms(const KArg
   const ColView<C> view{lds + cc};
 #pragma unroll
   for (int c = 0; c < 6; ++c) fft_pencil<N, 1>(v[c], view, t, a.tw_z);
+  const int kxv = valid ? kx : 0;
+  float xi[3] = {(float)kxv / (float)a.nx, (float)signed_k(ky, a.ny) / (float)a.ny, 0.f};
+  float K0[6], K1[6], K2[6];
+  acoustic_parts(a, xi[0], xi[1], K0, K1, K2);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
+    const int kz = t + T * m;
+    xi[2] = (float)signed_k(kz, a.nz) / (float)a.nz;
+    float K[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) K[e] = K0[e] + xi[2] * (K1[e] + xi[2] * K2[e]);
     float2 tau[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau[c] = v[c][m];
-    green_apply(a, valid ? kx : 0, ky, t + T * m, tau);
+    green_apply(a, kxv, ky, kz, xi, K, tau);
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][m] = tau[c];
   }
@@ -299,9 +323,9 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
   const int ky = blockIdx.y, q = blockIdx.z;
-  const size_t cs = (size_t)a.nz * a.ny * a.nh;
-  const size_t zs = (size_t)a.ny * a.nh;
-  float2* col = a.spec + q * cs + (size_t)ky * a.nh + (valid ? kx : 0);
+  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const size_t zs = (size_t)a.ny * a.sh;
+  float2* col = a.spec + q * cs + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
@@ -342,9 +366,9 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
   const int ky = blockIdx.y, q = blockIdx.z;
-  const size_t cs = (size_t)a.nz * a.ny * a.nh;
-  const size_t zs = (size_t)a.ny * a.nh;
-  float2* col = a.spec + q * cs + (size_t)ky * a.nh + (valid ? kx : 0);
+  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const size_t zs = (size_t)a.ny * a.sh;
+  float2* col = a.spec + q * cs + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
@@ -442,16 +466,12 @@ __global__ __launch_bounds__(256) void k_fin_ac(const KArgs a, int nblk_x, int n
   sum_partials<kQres>(a.part_res, nblk_x, bad);
   // extrema
   __shared__ float mm[2];
-  if (threadIdx.x == 0) {
-    float mn = 3.0e38f, mx = -3.0e38f;
-    for (int b = 0; b < nblk_x; ++b) {
-      mn = fminf(mn, a.part_mm[2 * b]);
-      mx = fmaxf(mx, a.part_mm[2 * b + 1]);
-    }
-    mm[0] = mn;
-    mm[1] = mx;
+  float mn = 3.0e38f, mx = -3.0e38f;
+  for (int b = threadIdx.x; b < nblk_x; b += blockDim.x) {
+    mn = fminf(mn, a.part_mm[2 * b]);
+    mx = fmaxf(mx, a.part_mm[2 * b + 1]);
   }
-  __syncthreads();
+  block_minmax(mn, mx, mm);
   if (threadIdx.x != 0) return;
   for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
   st->stats[kQac] = st->gd_cur;
@@ -472,7 +492,7 @@ bool supported_axis(int n) {
 }
 
 template <int M>
-static int rows_per_block_t() { return kXThreads / (M / XPlan<M>::E); }
+static int rows_per_block_t() { return xthreads<M>() / (M / XPlan<M>::E); }
 
 int rows_per_block(int nx) {
   switch (nx / 2) {
@@ -553,14 +573,14 @@ hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
 }
 
 hipError_t ms_z_green(const KArgs& a, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny);
-  PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, col_block<N>(), 0, s>>>(a)));
+  const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny);
+  PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
   return hipGetLastError();
 }
 
 hipError_t ms_x_inverse(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));
-  PF_SWITCH_M(a.nx, (k_x_inv_ms<M><<<grid, kXThreads, 0, s>>>(a)));
+  PF_SWITCH_M(a.nx, (k_x_inv_ms<M><<<grid, xthreads<M>(), 0, s>>>(a)));
   return hipGetLastError();
 }
 
@@ -589,7 +609,7 @@ hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
 
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));
-  PF_SWITCH_M(a.nx, (k_x_inv_ac<M><<<grid, kXThreads, 0, s>>>(a)));
+  PF_SWITCH_M(a.nx, (k_x_inv_ac<M><<<grid, xthreads<M>(), 0, s>>>(a)));
   return hipGetLastError();
 }
 
@@ -600,7 +620,7 @@ hipError_t ac_finalize(const KArgs& a, int init_only, hipStream_t s) {
 
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s) {
   const dim3 grid(x_blocks(a), ncomp);
-  PF_SWITCH_M(a.nx, (k_x_fwd_raw<M><<<grid, kXThreads, 0, s>>>(a, real)));
+  PF_SWITCH_M(a.nx, (k_x_fwd_raw<M><<<grid, xthreads<M>(), 0, s>>>(a, real)));
   return hipGetLastError();
 }
 
@@ -616,7 +636,7 @@ hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s) {
 
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s) {
   const dim3 grid(x_blocks(a), ncomp);
-  PF_SWITCH_M(a.nx, (k_x_inv_raw<M><<<grid, kXThreads, 0, s>>>(a, real, scale)));
+  PF_SWITCH_M(a.nx, (k_x_inv_raw<M><<<grid, xthreads<M>(), 0, s>>>(a, real, scale)));
   return hipGetLastError();
 }
 

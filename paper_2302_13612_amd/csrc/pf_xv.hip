@@ -1,9 +1,19 @@
 // Forward x-pass kernels with the per-voxel physics, for PF_NV twin variants
 // per voxel (this file is compiled once per PF_NV = 1..6).
 //
-// Each thread owns E packed complex samples (two voxels each) of one row; the
-// x-pass plans keep E small (4 for power-of-two rows) so the per-voxel physics
-// fits in registers next to the FFT data.
+// Two phases per block of rows:
+//   1. every thread evaluates the physics of its voxels (two per packed
+//      complex sample) and stages the outputs in LDS, one slab per output
+//      component, at the positions its own FFT lanes read back;
+//   2. for each component the row FFT runs from its slab, which then serves
+//      as that transform's exchange buffer, and the split coefficients go to
+//      HBM.
+// The FFT data never share registers with the physics, which keeps register
+// use low enough for three blocks per CU.
+//
+// Material: either per-grain sample-frame tables (any material), or, for a
+// polycrystal of one crystal (ROT), the grain rotation per voxel and one
+// crystal-frame table held in kernel arguments (scalar registers).
 #include "pf_common.hpp"
 
 #ifndef PF_NV
@@ -12,7 +22,7 @@
 
 namespace pft {
 
-// Loads of one packed sample (voxels x0, x0+1) of a row.
+// Inputs of one packed sample (voxels x0, x0+1) of a row.
 template <int V>
 struct Sample {
   float2 e[6], p[6], h[V];
@@ -47,13 +57,72 @@ __device__ __forceinline__ void load_sample(const KArgs& a, bool valid, size_t v
   }
 }
 
+// Stress of one voxel (sample frame) and the elastic strain and stress in
+// the frame of the material table (crystal frame for ROT, sample otherwise).
+struct VoxelOut {
+  float sig[6];
+  float sig_m[6];
+  float gam_m[6];  // engineering shear
+};
+
+// Twin-variant terms of one voxel in the material frame: work = sigma : eps0_q
+// and quad = eps_el : dC_q : eps_el for every variant.
+template <int V, class TP>
+__device__ __forceinline__ void variant_terms(TP tab, const float (&sig_m)[6], const float (&gam_m)[6],
+                                              float (&work)[V], float (&quad)[V]) {
+  const auto e0 = tab + 21 * (V + 1);
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const auto e0q = e0 + 6 * q;
+    work[q] = sig_m[0] * e0q[0] + sig_m[1] * e0q[1] + sig_m[2] * e0q[2] +
+              2.f * (sig_m[3] * e0q[3] + sig_m[4] * e0q[4] + sig_m[5] * e0q[5]);
+    float dcg[6];
+    symv6(tab + 21 * (q + 1), gam_m, dcg);
+    float s = 0.f;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s += gam_m[c] * dcg[c];
+    quad[q] = s;
+  }
+}
+
+template <int V, bool ROT, bool AC>
+__device__ __forceinline__ void eval_voxel(const KArgs& a, const float (&e)[6], const float (&et)[V],
+                                           const float (&ep)[6], int g, VoxelOut& o, float (&work)[V],
+                                           float (&quad)[V]) {
+  if constexpr (ROT) {
+    float R[9];
+    load_rotation(a, g, R);
+    MatR<V> m;
+    constitutive_rot<V>(a, e, et, ep, R, m);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      o.sig[c] = m.sig[c];
+      o.sig_m[c] = m.sig_c[c];
+      o.gam_m[c] = m.gam_c[c];
+    }
+    if constexpr (AC) variant_terms<V>(a.xtab, o.sig_m, o.gam_m, work, quad);
+  } else {
+    with_table(a, g, [&](auto tab) {
+      Mat<V> m;
+      constitutive<V>(e, et, ep, tab, a.h_kind, m);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        o.sig[c] = m.sig[c];
+        o.sig_m[c] = m.sig[c];
+        o.gam_m[c] = m.gam[c];
+      }
+      if constexpr (AC) variant_terms<V>(tab, o.sig_m, o.gam_m, work, quad);
+    });
+  }
+}
+
 // Fixed point, forward: polarisation tau = C(x):(eps - eps*) - C0:eps of
 // every voxel, FP64 sum of the stress, R2C of the six components.
-template <int M, int V>
-__global__ __launch_bounds__(kXThreads) void k_x_fwd_ms(const KArgs a) {
-  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+template <int M, int V, bool ROT>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
-  __shared__ float2 lds[ROWS * LROW];
+  __shared__ float2 stage[6 * ROWS * LROW];
   if (a.state->st.done) return;
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.nz * a.ny;
@@ -64,13 +133,12 @@ __global__ __launch_bounds__(kXThreads) void k_x_fwd_ms(const KArgs a) {
   float shift[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) shift[c] = (float)(a.state->ebar_cur[c] - a.state->ebar_field[c]);
-  float2 v[6][E];
   double ssum[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
+#pragma unroll 1
   for (int m = 0; m < E; ++m) {
-    const int x0 = 2 * (t + T * m);
+    const int k = t + T * m;
     Sample<V> s;
-    load_sample<V>(a, valid, vs, rbase + x0, s);
+    load_sample<V>(a, valid, vs, rbase + 2 * k, s);
     float o[2][6];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -82,54 +150,58 @@ __global__ __launch_bounds__(kXThreads) void k_x_fwd_ms(const KArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
-      float tau[6], sig[6];
-      with_table(a, half ? s.g1 : s.g0, [&](auto tab) {
-        Mat<V> mt;
-        constitutive<V>(e, et, ep, tab, a.h_kind, mt);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) sig[c] = mt.sig[c];
-      });
+      VoxelOut vo;
+      float work[V], quad[V];
+      eval_voxel<V, ROT, false>(a, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
       float ge[6], c0e[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) ge[c] = c < 3 ? e[c] : 2.f * e[c];
       symv6(a.C0, ge, c0e);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        tau[c] = sig[c] - c0e[c];
-        o[half][c] = tau[c];
-        if (valid) ssum[c] += (double)sig[c];
+        o[half][c] = vo.sig[c] - c0e[c];
+        if (valid) ssum[c] += (double)vo.sig[c];
       }
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) v[c][m] = make_float2(o[0][c], o[1][c]);
+    for (int c = 0; c < 6; ++c)
+      stage[(c * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][c], o[1][c]);
   }
-  r2c_rows<M, 6>(v, lds + p * LROW, t, valid, a.spec, (size_t)(valid ? row : 0) * a.nh,
-                 (size_t)nrows * a.nh, a.tw_xh, a.tw_x);
+  const size_t cs = (size_t)nrows * a.sh;
+  float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+#pragma unroll 1
+  for (int c = 0; c < 6; ++c) {
+    float2* slab = stage + (c * ROWS + p) * LROW;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, a.tw_xh, a.tw_x);
+  }
   block_sum<6>(ssum, a.part_ms + (size_t)blockIdx.x * kQms);
 }
 
 // Phase-field update, forward: driving forces and the explicit right-hand
 // side RHS_a = f_a - L dt (chem_a - mech_a) of every voxel, FP64 energy and
 // mean sums, extrema of f; R2C of the V right-hand sides.
-template <int M, int V>
-__global__ __launch_bounds__(kXThreads) void k_x_fwd_ac(const KArgs a) {
-  constexpr int E = XPlan<M>::E, T = M / E, ROWS = kXThreads / T;
+template <int M, int V, bool ROT>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
-  __shared__ float2 lds[ROWS * LROW];
+  __shared__ float2 stage[V * ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.nz * a.ny;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  float2 v[V][E];
   double acc[kQac];
 #pragma unroll
   for (int q = 0; q < kQac; ++q) acc[q] = 0.0;
   float mn = 3.0e38f, mx = -3.0e38f;
-#pragma unroll
+#pragma unroll 1
   for (int m = 0; m < E; ++m) {
-    const int x0 = 2 * (t + T * m);
+    const int k = t + T * m;
+    const int x0 = 2 * k;
     Sample<V> s;
     load_sample<V>(a, valid, vs, rbase + x0, s);
     float o[2][V];
@@ -143,30 +215,9 @@ __global__ __launch_bounds__(kXThreads) void k_x_fwd_ac(const KArgs a) {
       }
 #pragma unroll
       for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
-      float sig[6], gam[6], mech[V];
-      with_table(a, half ? s.g1 : s.g0, [&](auto tab) {
-        Mat<V> mt;
-        constitutive<V>(e, et, ep, tab, a.h_kind, mt);
-        const auto e0 = tab + 21 * (V + 1);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          sig[c] = mt.sig[c];
-          gam[c] = mt.gam[c];
-        }
-#pragma unroll
-        for (int q = 0; q < V; ++q) {
-          // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
-          const auto e0q = e0 + 6 * q;
-          const float work = sig[0] * e0q[0] + sig[1] * e0q[1] + sig[2] * e0q[2] +
-                             2.f * (sig[3] * e0q[3] + sig[4] * e0q[4] + sig[5] * e0q[5]);
-          float dcg[6];
-          symv6(tab + 21 * (q + 1), gam, dcg);
-          float quad = 0.f;
-#pragma unroll
-          for (int c = 0; c < 6; ++c) quad += gam[c] * dcg[c];
-          mech[q] = dh_of(et[q], a.h_kind) * (work - 0.5f * quad);
-        }
-      });
+      VoxelOut vo;
+      float work[V], quad[V];
+      eval_voxel<V, ROT, true>(a, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
       float fm = 1.f;
 #pragma unroll
       for (int q = 0; q < V; ++q) fm -= et[q];
@@ -180,23 +231,25 @@ __global__ __launch_bounds__(kXThreads) void k_x_fwd_ac(const KArgs a) {
       }
       float fme = 0.f;
 #pragma unroll
-      for (int c = 0; c < 6; ++c) fme += sig[c] * gam[c];
+      for (int c = 0; c < 6; ++c) fme += vo.sig_m[c] * vo.gam_m[c];
 #pragma unroll
       for (int q = 0; q < V; ++q) {
+        // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
+        const float mech = dh_of(et[q], a.h_kind) * (work[q] - 0.5f * quad[q]);
         // chem_a = 2A f_a sum_{b != a} f_b (f_b - f_a), b over variants + matrix
         float sm = fm * (fm - et[q]);
 #pragma unroll
         for (int r = 0; r < V; ++r)
           if (r != q) sm += et[r] * (et[r] - et[q]);
         const float chem = 2.f * a.A * et[q] * sm;
-        o[half][q] = et[q] - a.LDt * (chem - mech[q]);
+        o[half][q] = et[q] - a.LDt * (chem - mech);
       }
       if (valid) {
         acc[0] += (double)fdw;
         acc[1] += (double)(0.5f * fme);
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          acc[2 + c] += (double)sig[c];
+          acc[2 + c] += (double)vo.sig[c];
           acc[8 + c] += (double)e[c];
         }
 #pragma unroll
@@ -207,15 +260,24 @@ __global__ __launch_bounds__(kXThreads) void k_x_fwd_ac(const KArgs a) {
         }
         if (a.save_stress) {
 #pragma unroll
-          for (int c = 0; c < 6; ++c) a.sig[c * vs + rbase + x0 + half] = sig[c];
+          for (int c = 0; c < 6; ++c) a.sig[c * vs + rbase + x0 + half] = vo.sig[c];
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < V; ++q) v[q][m] = make_float2(o[0][q], o[1][q]);
+    for (int q = 0; q < V; ++q)
+      stage[(q * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][q], o[1][q]);
   }
-  r2c_rows<M, V>(v, lds + p * LROW, t, valid, a.spec, (size_t)(valid ? row : 0) * a.nh,
-                 (size_t)nrows * a.nh, a.tw_xh, a.tw_x);
+  const size_t cs = (size_t)nrows * a.sh;
+  float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+#pragma unroll 1
+  for (int q = 0; q < V; ++q) {
+    float2* slab = stage + (q * ROWS + p) * LROW;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
+    r2c_one<M>(v, slab, t, valid, dst + q * cs, a.tw_xh, a.tw_x);
+  }
   block_sum<kQac>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
   block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
@@ -241,13 +303,21 @@ using namespace pft;
 
 hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));
-  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ms<M, PF_NV><<<grid, kXThreads, 0, s>>>(a)));
+  if (a.rot) {
+    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ms<M, PF_NV, true><<<grid, xthreads<M>(), 0, s>>>(a)));
+  } else {
+    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ms<M, PF_NV, false><<<grid, xthreads<M>(), 0, s>>>(a)));
+  }
   return hipGetLastError();
 }
 
 hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));
-  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ac<M, PF_NV><<<grid, kXThreads, 0, s>>>(a)));
+  if (a.rot) {
+    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ac<M, PF_NV, true><<<grid, xthreads<M>(), 0, s>>>(a)));
+  } else {
+    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ac<M, PF_NV, false><<<grid, xthreads<M>(), 0, s>>>(a)));
+  }
   return hipGetLastError();
 }
 

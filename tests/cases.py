@@ -51,10 +51,17 @@ def oracle_run(cfg, steps, tol=1e-10):
     return st.eta, mech.tensor_to_voigt6(sigma), all_stats
 
 
-def gpu_solver(cfg, device="cuda"):
+def gpu_solver(cfg, device="cuda", rotation_form=True):
+    """rotation_form: for a polycrystal, hand the library one crystal-frame
+    material plus the grain rotations (else per-grain sample-frame tables)."""
     import torch
     from paper_2302_13612_amd import binding
-    Cg, Cv, e0 = binding.mg_twin_tables(cfg["rotations"], cfg["variant_ids"])
+    rotations = None
+    if cfg["gid"] is not None and rotation_form:
+        Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], cfg["variant_ids"])
+        rotations = cfg["rotations"]
+    else:
+        Cg, Cv, e0 = binding.mg_twin_tables(cfg["rotations"], cfg["variant_ids"])
     if cfg["homogeneous"]:
         Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
     eta0 = torch.from_numpy(np.ascontiguousarray(cfg["eta0"])).to(device)
@@ -62,15 +69,15 @@ def gpu_solver(cfg, device="cuda"):
     h_kind = binding.PF_H_QUINTIC if cfg.get("h_kind") == "quintic" else binding.PF_H_LINEAR
     solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
                             cfg["stress_mask"], gid=gid, h_kind=h_kind, ms_tol=cfg["ms_tol"],
-                            ms_max_iter=cfg["ms_max_iter"])
+                            ms_max_iter=cfg["ms_max_iter"], rotations=rotations)
     epsp = None if cfg["eps_p"] is None else torch.from_numpy(np.ascontiguousarray(cfg["eps_p"])).to(device)
     return solver, epsp
 
 
-def gpu_run(cfg, steps, save_stress_last=True):
+def gpu_run(cfg, steps, save_stress_last=True, rotation_form=True):
     """Returns (solver, eta (numpy), stress of the last step (numpy) or None)."""
     from paper_2302_13612_amd import binding
-    solver, epsp = gpu_solver(cfg)
+    solver, epsp = gpu_solver(cfg, rotation_form=rotation_form)
     for n in range(steps):
         e, s = loads(cfg, n)
         solver.step(1, e, s, eps_p=epsp if n == 0 else None,

@@ -16,9 +16,9 @@ ETA_TOL = 1e-4
 SIG_TOL = 1e-5
 
 
-def compare(cfg, steps, label, sig_tol=SIG_TOL, eta_tol=ETA_TOL):
+def compare(cfg, steps, label, sig_tol=SIG_TOL, eta_tol=ETA_TOL, rotation_form=True):
     print(f"\n[step] {label} shape={cfg['shape']} n_var={cfg['n_var']} steps={steps}", flush=True)
-    solver, eta_g, sig_g = cases.gpu_run(cfg, steps)
+    solver, eta_g, sig_g = cases.gpu_run(cfg, steps, rotation_form=rotation_form)
     st_g = solver.stats()
     eta_o, sig_o, stats_o = cases.oracle_run(cfg, steps)
     d_eta = np.abs(eta_g - eta_o).max()
@@ -59,7 +59,17 @@ def test_lamellae_small_radix3():
 
 
 def test_polycrystal_small_six_variants():
-    compare(cases.small_polycrystal(), 3, "polycrystal 32^3 6 variants")
+    compare(cases.small_polycrystal(), 3, "polycrystal 32^3 6 variants (rotation form)")
+
+
+def test_polycrystal_small_six_variants_grain_tables():
+    compare(cases.small_polycrystal(), 3, "polycrystal 32^3 6 variants (per-grain tables)",
+            rotation_form=False)
+
+
+def test_polycrystal_radix3_longer_run():
+    cfg = cases.small_polycrystal(shape=(48, 32, 96), n_grains=7, seed=13)
+    compare(cfg, 20, "polycrystal 48x32x96 6 variants 20 steps")
 
 
 def test_polycrystal_two_variants_quintic():
