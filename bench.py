@@ -99,6 +99,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
@@ -117,6 +119,13 @@ def main():
         f"{cfg['n_interfaces']} interfaces)")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: 268435456 bytes read + 268435456 bytes written")
+        del src, dst
     # one crystal-frame Mg material shared by the grains, turned per grain
     Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], cfg["variant_ids"])
     eta0 = torch.from_numpy(cfg["eta0"]).to(dev)

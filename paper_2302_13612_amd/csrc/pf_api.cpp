@@ -24,7 +24,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout (byte offsets from the workspace base).
 struct Layout {
-  size_t eta, eps, sig, spec, tables, rot, tw, part_ms, part_res, part_ac, part_mm, part_gd, state, total;
+  size_t eta, eps, eps_prev, sig, spec, tables, rot, tw, part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
 
@@ -50,6 +50,7 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains) {
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.eta = take(sizeof(float) * nvox * nv);
   L.eps = take(sizeof(float) * nvox * 6);
+  L.eps_prev = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
   L.spec = take(sizeof(float) * 2 * nspec * 6);
   L.tab_stride = tab_stride_for(nv);
@@ -124,6 +125,7 @@ struct pf_ctx {
   bool one_iteration;
   int ms_max_iter;
   int64_t steps;
+  int64_t hist;         // consecutive steps whose strain history is valid
   Status* host_status;  // pinned
   std::string err;
   bool prof_on;
@@ -245,6 +247,7 @@ int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_str
   c->ws = static_cast<char*>(workspace);
   c->L = L;
   c->steps = 0;
+  c->hist = 0;
   c->prof_on = false;
   c->ms_max_iter = p->ms_max_iter;
 
@@ -367,6 +370,8 @@ int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_str
   char* ws = c->ws;
   a.eta = reinterpret_cast<float*>(ws + L.eta);
   a.eps = reinterpret_cast<float*>(ws + L.eps);
+  a.eps_prev = reinterpret_cast<float*>(ws + L.eps_prev);
+  a.iter_mode = 0;
   a.sig = reinterpret_cast<float*>(ws + L.sig);
   a.epsp = nullptr;
   a.gid = G > 1 ? p->grain_id : nullptr;
@@ -455,8 +460,9 @@ static int read_status(pf_ctx* c) {
   return PF_OK;
 }
 
-static int ms_iteration(pf_ctx* c) {
-  const KArgs& a = c->args;
+static int ms_iteration(pf_ctx* c, int mode) {
+  KArgs a = c->args;
+  a.iter_mode = mode;
   hipStream_t s = c->stream;
   PF_TRY(launch(c, "ms_x_forward", [&] { return pfl::ms_x_forward(a, s); }));
   PF_TRY(launch(c, "ms_finalize_mean", [&] { return pfl::ms_finalize_mean(a, s); }));
@@ -476,13 +482,19 @@ int pf_step(pf_ctx* c, int32_t n_steps, const pf_load* load) {
   const KArgs& a = c->args;
   hipStream_t s = c->stream;
   for (int n = 0; n < n_steps; ++n) {
-    PF_TRY(launch(c, "step_begin", [&] { return pfl::step_begin(a, load->eps_bar, load->sig_bar, s); }));
+    // From the third step on, the first iterate extrapolates the strain of
+    // the two previous steps; from the second on, the step's starting strain
+    // is kept for that.
+    const int first_mode = c->one_iteration ? 0 : (c->hist >= 2 ? 2 : (c->hist >= 1 ? 1 : 0));
+    KArgs ab = a;
+    ab.iter_mode = first_mode;
+    PF_TRY(launch(c, "step_begin", [&] { return pfl::step_begin(ab, load->eps_bar, load->sig_bar, s); }));
     if (c->one_iteration) {
-      PF_TRY(ms_iteration(c));
+      PF_TRY(ms_iteration(c, 0));
     } else {
       bool conv = false;
       for (int k = 0; k < c->ms_max_iter; ++k) {
-        PF_TRY(ms_iteration(c));
+        PF_TRY(ms_iteration(c, k == 0 ? first_mode : 0));
         PF_TRY(read_status(c));
         if (c->host_status->done) {
           conv = true;
@@ -503,6 +515,7 @@ int pf_step(pf_ctx* c, int32_t n_steps, const pf_load* load) {
     PF_TRY(launch(c, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
     PF_TRY(launch(c, "ac_finalize", [&] { return pfl::ac_finalize(a, 0, s); }));
     c->steps += 1;
+    c->hist += 1;
   }
   if (n_steps > 0) {
     PF_TRY(read_status(c));
@@ -524,6 +537,7 @@ int pf_fields(pf_ctx* c, int32_t which, int32_t set, float* buf) {
       f = c->args.sig; n = c->nvox * 6; break;
     default: return fail(c, PF_EINVAL, "pf_fields: unknown field");
   }
+  if (set) c->hist = 0;  // the strain history no longer describes the state
   hipError_t e = set ? hipMemcpyAsync(f, buf, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream)
                      : hipMemcpyAsync(buf, f, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "pf_fields");

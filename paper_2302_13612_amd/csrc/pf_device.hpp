@@ -30,6 +30,7 @@ struct DevState {
   double ebar_cur[6];    // mean strain of the current iterate
   double ebar_field[6];  // mean strain of the strain field in memory
   double ebar_next[6];   // mean strain for the next iterate
+  double ebar_prev[6];   // mean strain of the previous step's field (eps_prev)
   double eps_target[6];  // load: prescribed mean strain
   double sig_target[6];  // load: prescribed mean stress
   double gd_cur;         // gradient energy sum of the current order parameter
@@ -55,6 +56,10 @@ struct KArgs {
   // fields
   float* eta;                 // [nv][nz][ny][nx]
   float* eps;                 // [6][nz][ny][nx]
+  float* eps_prev;            // [6][nz][ny][nx] strain of the previous step
+  int iter_mode;              // first iteration of a step: 0 none, 1 keep the step's
+                              // starting strain in eps_prev, 2 also start from the
+                              // linear extrapolation 2 eps - eps_prev
   float* sig;                 // [6][nz][ny][nx] (only written on request)
   const float* epsp;          // [6][nz][ny][nx] or null
   const uint8_t* gid;         // [nz][ny][nx] or null

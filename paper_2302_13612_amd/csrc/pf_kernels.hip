@@ -37,7 +37,9 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   double acc[2] = {0.0, 0.0};
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
-    const float shift = (float)(a.state->ebar_cur[c] - a.state->ebar_field[c]);
+    const DevState* st = a.state;
+    const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
+    const float shift = (float)(st->ebar_cur[c] - base);
     const float w = c < 3 ? 1.f : 2.f;
     float2 v[E];
     c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + c * cs + roff, a.tw_xh, a.tw_x);
@@ -45,8 +47,15 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int x0 = 2 * (t + T * m);
-        float2* ptr = reinterpret_cast<float2*>(a.eps + c * vs + rbase + x0);
-        const float2 old = *ptr;
+        const size_t off = c * vs + rbase + x0;
+        float2* ptr = reinterpret_cast<float2*>(a.eps + off);
+        const float2 stored = *ptr;
+        float2 old = stored;
+        if (a.iter_mode == 2) {
+          const float2 q = *reinterpret_cast<const float2*>(a.eps_prev + off);
+          old = make_float2(2.f * stored.x - q.x, 2.f * stored.y - q.y);
+        }
+        if (a.iter_mode >= 1) *reinterpret_cast<float2*>(a.eps_prev + off) = stored;
         const float dx0 = v[m].x - (old.x + shift), dx1 = v[m].y - (old.y + shift);
         acc[0] += (double)(w * (dx0 * dx0 + dx1 * dx1));
         acc[1] += (double)(w * (v[m].x * v[m].x + v[m].y * v[m].y));
@@ -391,6 +400,7 @@ __global__ void k_step_begin(const KArgs a, double e0, double e1, double e2, dou
     st->eps_target[c] = et[c];
     st->sig_target[c] = sg[c];
     if (!((a.stress_mask >> c) & 1u)) st->ebar_cur[c] = et[c];
+    else if (a.iter_mode == 2) st->ebar_cur[c] = 2.0 * st->ebar_field[c] - st->ebar_prev[c];
   }
   st->st.done = 0;
   st->st.iters = 0;
@@ -445,6 +455,7 @@ __global__ __launch_bounds__(256) void k_fin_res(const KArgs a, int nblk) {
   st->st.iters += 1;
   st->st.done = r <= a.tol ? 1 : 0;
   for (int c = 0; c < 6; ++c) {
+    if (a.iter_mode >= 1) st->ebar_prev[c] = st->ebar_field[c];
     st->ebar_field[c] = st->ebar_next[c];
     st->ebar_cur[c] = st->ebar_next[c];
   }

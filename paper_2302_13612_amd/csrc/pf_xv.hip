@@ -29,6 +29,26 @@ struct Sample {
   int g0, g1;
 };
 
+// Strain of the first iterate of a step: the stored field, or its linear
+// extrapolation 2 eps - eps_prev from the two previous steps.
+__device__ __forceinline__ void extrapolate_strain(const KArgs& a, bool valid, size_t vs, size_t off,
+                                                   float2 (&e)[6]) {
+  if (a.iter_mode != 2 || !valid) return;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const float2 q = *reinterpret_cast<const float2*>(a.eps_prev + c * vs + off);
+    e[c] = make_float2(2.f * e[c].x - q.x, 2.f * e[c].y - q.y);
+  }
+}
+
+// Offset added to the strain read in the first iterate so its mean is the
+// iterate's prescribed mean.
+__device__ __forceinline__ float mean_shift(const KArgs& a, int c) {
+  const DevState* st = a.state;
+  const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
+  return (float)(st->ebar_cur[c] - base);
+}
+
 template <int V>
 __device__ __forceinline__ void load_sample(const KArgs& a, bool valid, size_t vs, size_t off, Sample<V>& s) {
   s.g0 = s.g1 = 0;
@@ -132,13 +152,14 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
   float shift[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) shift[c] = (float)(a.state->ebar_cur[c] - a.state->ebar_field[c]);
+  for (int c = 0; c < 6; ++c) shift[c] = mean_shift(a, c);
   double ssum[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll 1
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
     Sample<V> s;
     load_sample<V>(a, valid, vs, rbase + 2 * k, s);
+    extrapolate_strain(a, valid, vs, rbase + 2 * k, s.e);
     float o[2][6];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
