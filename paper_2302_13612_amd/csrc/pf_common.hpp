@@ -249,23 +249,36 @@ __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow
   if (t == 0 && valid) dst[M] = make_float2(v[0].x - v[0].y, 0.f);
 }
 
-// Inverse: one spectral row (M+1 coefficients) -> packed real pairs in v
-// (unnormalised); the imaginary parts of the kx = 0 and kx = M terms are
-// ignored, as for the spectrum of a real field.
+// Inverse of one spectral row, in two parts so the global loads of the next
+// row can be issued before the current one is transformed:
+// c2r_fetch loads the M+1 coefficients a thread needs into registers;
+// c2r_from_regs builds the packed half-length spectrum through LDS and runs
+// the inverse FFT (unnormalised). The imaginary parts of the kx = 0 and
+// kx = M terms are ignored, as for the spectrum of a real field.
 template <int M>
-__device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
-                                        const float2* __restrict__ srow,
-                                        const float2* __restrict__ tw_m,
-                                        const float2* __restrict__ tw_n) {
+struct RowFetch {
+  float2 x[XPlan<M>::E];
+  float2 last;  // coefficient M (thread 0 only)
+};
+
+template <int M>
+__device__ __forceinline__ void c2r_fetch(RowFetch<M>& f, int t, bool valid, const float2* __restrict__ srow) {
+  constexpr int E = XPlan<M>::E, T = M / E;
+#pragma unroll
+  for (int m = 0; m < E; ++m) f.x[m] = valid ? srow[t + T * m] : make_float2(0.f, 0.f);
+  f.last = (valid && t == 0) ? srow[M] : make_float2(0.f, 0.f);
+}
+
+template <int M>
+__device__ __forceinline__ void c2r_from_regs(float2 (&v)[XPlan<M>::E], const RowFetch<M>& f, float2* ldsrow,
+                                              int t, const float2* __restrict__ tw_m,
+                                              const float2* __restrict__ tw_n) {
   constexpr int E = XPlan<M>::E, T = M / E;
   RowView view{ldsrow};
   __syncthreads();
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int k = t + T * m;
-    view.write(k, valid ? srow[k] : make_float2(0.f, 0.f));
-  }
-  if (t == 0) view.write(M, valid ? srow[M] : make_float2(0.f, 0.f));
+  for (int m = 0; m < E; ++m) view.write(t + T * m, f.x[m]);
+  if (t == 0) view.write(M, f.last);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -282,6 +295,16 @@ __device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow
     v[m] = make_float2(ev.x - od.y, ev.y + od.x);
   }
   fft_pencil<M, -1, XPlan<M>>(v, view, t, tw_m);
+}
+
+template <int M>
+__device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
+                                        const float2* __restrict__ srow,
+                                        const float2* __restrict__ tw_m,
+                                        const float2* __restrict__ tw_n) {
+  RowFetch<M> f;
+  c2r_fetch<M>(f, t, valid, srow);
+  c2r_from_regs<M>(v, f, ldsrow, t, tw_m, tw_n);
 }
 
 // Per-voxel material table of grain g, always read through the constant

@@ -35,21 +35,35 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   const size_t cs = (size_t)nrows * a.sh;
   const size_t roff = (size_t)(valid ? row : 0) * a.sh;
   double acc[2] = {0.0, 0.0};
+  // component c+1's spectral row and old strain are fetched while component c
+  // is transformed
+  RowFetch<M> cur, nxt;
+  c2r_fetch<M>(cur, t, valid, a.spec + roff);
+  float2 old_c[E], old_n[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m)
+    old_c[m] = valid ? *reinterpret_cast<const float2*>(a.eps + rbase + 2 * (t + T * m)) : make_float2(0.f, 0.f);
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
+    if (c + 1 < 6) {
+      c2r_fetch<M>(nxt, t, valid, a.spec + (c + 1) * cs + roff);
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        old_n[m] = valid ? *reinterpret_cast<const float2*>(a.eps + (c + 1) * vs + rbase + 2 * (t + T * m))
+                         : make_float2(0.f, 0.f);
+    }
     const DevState* st = a.state;
     const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
     const float shift = (float)(st->ebar_cur[c] - base);
     const float w = c < 3 ? 1.f : 2.f;
     float2 v[E];
-    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + c * cs + roff, a.tw_xh, a.tw_x);
+    c2r_from_regs<M>(v, cur, lds + p * LROW, t, a.tw_xh, a.tw_x);
+    float dsum = 0.f, nsum = 0.f;
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int x0 = 2 * (t + T * m);
-        const size_t off = c * vs + rbase + x0;
-        float2* ptr = reinterpret_cast<float2*>(a.eps + off);
-        const float2 stored = *ptr;
+        const size_t off = c * vs + rbase + 2 * (t + T * m);
+        const float2 stored = old_c[m];
         float2 old = stored;
         if (a.iter_mode == 2) {
           const float2 q = *reinterpret_cast<const float2*>(a.eps_prev + off);
@@ -57,11 +71,16 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
         }
         if (a.iter_mode >= 1) *reinterpret_cast<float2*>(a.eps_prev + off) = stored;
         const float dx0 = v[m].x - (old.x + shift), dx1 = v[m].y - (old.y + shift);
-        acc[0] += (double)(w * (dx0 * dx0 + dx1 * dx1));
-        acc[1] += (double)(w * (v[m].x * v[m].x + v[m].y * v[m].y));
-        *ptr = v[m];
+        dsum += dx0 * dx0 + dx1 * dx1;
+        nsum += v[m].x * v[m].x + v[m].y * v[m].y;
+        *reinterpret_cast<float2*>(a.eps + off) = v[m];
       }
     }
+    acc[0] += (double)(w * dsum);
+    acc[1] += (double)(w * nsum);
+    cur = nxt;
+#pragma unroll
+    for (int m = 0; m < E; ++m) old_c[m] = old_n[m];
   }
   block_sum<2>(acc, a.part_res + (size_t)blockIdx.x * kQres);
 }
@@ -81,10 +100,13 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   const size_t cs = (size_t)nrows * a.sh;
   const size_t roff = (size_t)(valid ? row : 0) * a.sh;
   double bad[1] = {0.0};
+  RowFetch<M> cur, nxt;
+  c2r_fetch<M>(cur, t, valid, a.spec + roff);
 #pragma unroll 1
   for (int q = 0; q < a.nv; ++q) {
+    if (q + 1 < a.nv) c2r_fetch<M>(nxt, t, valid, a.spec + (q + 1) * cs + roff);
     float2 v[E];
-    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + roff, a.tw_xh, a.tw_x);
+    c2r_from_regs<M>(v, cur, lds + p * LROW, t, a.tw_xh, a.tw_x);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -93,6 +115,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
         *reinterpret_cast<float2*>(a.eta + q * vs + rbase + x0) = v[m];
       }
     }
+    cur = nxt;
   }
   block_sum<1>(bad, a.part_res + (size_t)blockIdx.x * kQres);
 }
@@ -423,7 +446,7 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   __syncthreads();
 }
 
-__global__ __launch_bounds__(256) void k_fin_ms(const KArgs a, int nblk) {
+__global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
   DevState* st = a.state;
   if (st->st.done) return;
   double s[kQms];
@@ -444,7 +467,7 @@ __global__ __launch_bounds__(256) void k_fin_ms(const KArgs a, int nblk) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_fin_res(const KArgs a, int nblk) {
+__global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
   DevState* st = a.state;
   if (st->st.done) return;
   double s[kQres];
@@ -463,7 +486,7 @@ __global__ __launch_bounds__(256) void k_fin_res(const KArgs a, int nblk) {
 
 // Stats of the step (raw sums; the host scales them) and the gradient sum of
 // the new state. init_only: only the gradient sum.
-__global__ __launch_bounds__(256) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int init_only) {
+__global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int init_only) {
   DevState* st = a.state;
   double gd[1];
   sum_partials<1>(a.part_gd, nblk_z, gd);
@@ -569,7 +592,7 @@ hipError_t ms_x_forward(const KArgs& a, hipStream_t s) {
 }
 
 hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s) {
-  k_fin_ms<<<1, 256, 0, s>>>(a, x_blocks(a));
+  k_fin_ms<<<1, 1024, 0, s>>>(a, x_blocks(a));
   return hipGetLastError();
 }
 
@@ -596,7 +619,7 @@ hipError_t ms_x_inverse(const KArgs& a, hipStream_t s) {
 }
 
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
-  k_fin_res<<<1, 256, 0, s>>>(a, x_blocks(a));
+  k_fin_res<<<1, 1024, 0, s>>>(a, x_blocks(a));
   return hipGetLastError();
 }
 
@@ -625,7 +648,7 @@ hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
 }
 
 hipError_t ac_finalize(const KArgs& a, int init_only, hipStream_t s) {
-  k_fin_ac<<<1, 256, 0, s>>>(a, x_blocks(a), z_blocks(a, a.nv), init_only);
+  k_fin_ac<<<1, 1024, 0, s>>>(a, x_blocks(a), z_blocks(a, a.nv), init_only);
   return hipGetLastError();
 }
 

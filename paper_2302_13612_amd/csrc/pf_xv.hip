@@ -153,7 +153,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
   float shift[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) shift[c] = mean_shift(a, c);
-  double ssum[6] = {0, 0, 0, 0, 0, 0};
+  float fsum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's voxels, then FP64
 #pragma unroll 1
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         o[half][c] = vo.sig[c] - c0e[c];
-        if (valid) ssum[c] += (double)vo.sig[c];
+        if (valid) fsum[c] += vo.sig[c];
       }
     }
 #pragma unroll
@@ -198,6 +198,9 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
     r2c_one<M>(v, slab, t, valid, dst + c * cs, a.tw_xh, a.tw_x);
   }
+  double ssum[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) ssum[c] = (double)fsum[c];
   block_sum<6>(ssum, a.part_ms + (size_t)blockIdx.x * kQms);
 }
 
@@ -215,9 +218,9 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  double acc[kQac];
+  float facc[kQac];  // this thread's voxels, then FP64
 #pragma unroll
-  for (int q = 0; q < kQac; ++q) acc[q] = 0.0;
+  for (int q = 0; q < kQac; ++q) facc[q] = 0.f;
   float mn = 3.0e38f, mx = -3.0e38f;
 #pragma unroll 1
   for (int m = 0; m < E; ++m) {
@@ -266,16 +269,16 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
         o[half][q] = et[q] - a.LDt * (chem - mech);
       }
       if (valid) {
-        acc[0] += (double)fdw;
-        acc[1] += (double)(0.5f * fme);
+        facc[0] += fdw;
+        facc[1] += 0.5f * fme;
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          acc[2 + c] += (double)vo.sig[c];
-          acc[8 + c] += (double)e[c];
+          facc[2 + c] += vo.sig[c];
+          facc[8 + c] += e[c];
         }
 #pragma unroll
         for (int q = 0; q < V; ++q) {
-          acc[14 + q] += (double)et[q];
+          facc[14 + q] += et[q];
           mn = fminf(mn, et[q]);
           mx = fmaxf(mx, et[q]);
         }
@@ -299,6 +302,9 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
     r2c_one<M>(v, slab, t, valid, dst + q * cs, a.tw_xh, a.tw_x);
   }
+  double acc[kQac];
+#pragma unroll
+  for (int q = 0; q < kQac; ++q) acc[q] = (double)facc[q];
   block_sum<kQac>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
   block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
