@@ -27,6 +27,29 @@
  *   row-major, in Pa. Spectra are [comp][z][y][x/2+1] complex float32
  *   (interleaved re, im), unnormalised forward transform.
  *
+ * Two paths compute the equilibrium of a step. The general one is the
+ * fixed point above. When an instance has one stiffness everywhere
+ * (n_grains == 1 and every C_var equal to C_grain), linear h, n_var <= 3 and
+ * no plastic strain, the equilibrium stress of each wavevector is known in
+ * closed form (the microelasticity of a homogeneous body, as used for
+ * phase-field models with Fourier solvers): sigma_hat : eps0_a =
+ * -sum_b B_ab(n) f_hat_b with B_ab(n) = eps0_a:C:eps0_b - (C:eps0_a n) .
+ * K(n)^{-1} (C:eps0_b n), K(n) = C n n, and the mean strain follows from the
+ * mixed condition. That is the exact solution the fixed point converges to
+ * (the iteration is not needed), so the library takes it by itself; it keeps
+ * no strain field, and PF_STEP_SAVE_STRESS or PF_STEP_FIXED_POINT select the
+ * fixed point for a step.
+ *
+ * Batches
+ *   pf_batch_init takes n_inst independent problems (e.g. an ensemble of
+ *   representative volume elements of several sizes). Instances of one grid
+ *   size are stacked along z in the workspace and every pass over them is
+ *   one launch; a step of the whole batch that needs no host decision is
+ *   captured once in a HIP graph and replayed. Batched instances are one
+ *   grain each and share n_var, h_kind, A, kappa, L, dt, dx, ms_tol,
+ *   ms_max_iter and bc_stress_mask; each has its own material, reference
+ *   medium, eta0 and load.
+ *
  * Memory and streams
  *   Every device buffer is owned by the caller. pf_init receives one device
  *   workspace of at least pf_workspace_size() bytes and keeps pointers into
@@ -64,6 +87,8 @@ extern "C" {
 
 /* pf_step flags */
 #define PF_STEP_SAVE_STRESS  1u  /* keep the equilibrium stress of the step  */
+#define PF_STEP_FIXED_POINT  2u  /* use the fixed-point path even where the
+                                    homogeneous spectral path applies        */
 
 /* pf_fields selectors */
 #define PF_FIELD_ETA     0    /* [n_var][nz][ny][nx]  order parameters       */
@@ -127,7 +152,7 @@ typedef struct {
   double ms_residual;      /* last relative strain change                   */
 } pf_stats;
 
-/* Workspace bytes for a problem (only the sizes and n_var are read). */
+/* Workspace bytes for a problem (only the sizes, n_var and n_grains are read). */
 int pf_workspace_size(const pf_problem *prob, size_t *bytes);
 
 /* Validate, carve the workspace, upload tables, copy eta0 in, set the strain
@@ -163,6 +188,25 @@ int pf_profile_read(pf_ctx *ctx, int32_t max_n, char (*names)[64],
 
 int pf_destroy(pf_ctx *ctx);
 const char *pf_last_error(const pf_ctx *ctx);
+
+/* Batches of independent instances (see "Batches" above). The single-instance
+ * calls are these with n_inst = 1; pf_step, pf_fields and pf_stats_get act on
+ * instance 0 of a one-instance context only.
+ *   pf_batch_workspace_size: bytes for the whole batch (validates it).
+ *   pf_batch_init: as pf_init for probs[0..n_inst-1].
+ *   pf_batch_step: loads[n_inst], one per instance. A given eps_p is copied
+ *     into the batch's own plastic-strain field (zero until first given).
+ *     The flags of all loads are or-ed.
+ *   pf_batch_fields, pf_batch_stats: as pf_fields, pf_stats_get for
+ *     instance inst (0-based, in the order of probs). */
+int pf_batch_workspace_size(const pf_problem *probs, int32_t n_inst, size_t *bytes);
+int pf_batch_init(const pf_problem *probs, int32_t n_inst, void *workspace,
+                  size_t ws_bytes, void *hip_stream, pf_ctx **out);
+int pf_batch_step(pf_ctx *ctx, int32_t n_steps, const pf_load *loads);
+int pf_batch_fields(pf_ctx *ctx, int32_t inst, int32_t which, int32_t set,
+                    float *buf);
+int pf_batch_stats(pf_ctx *ctx, int32_t inst, pf_stats *out);
+int pf_batch_size(const pf_ctx *ctx);  /* number of instances, 0 for NULL */
 
 /* Host helper: sample-frame tables of Mg tension twins for n_grains grains.
  * Crystal frame x || [10-10], y || [-12-10], z || [0001]; c_over_a and

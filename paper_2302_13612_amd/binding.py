@@ -19,7 +19,7 @@ ERROR_NAMES = {PF_EINVAL: "PF_EINVAL", PF_ENOMEM: "PF_ENOMEM", PF_EDEVICE: "PF_E
                PF_ENOCONV: "PF_ENOCONV", PF_ENONFINITE: "PF_ENONFINITE",
                PF_EUNSUPPORTED: "PF_EUNSUPPORTED"}
 PF_H_LINEAR, PF_H_QUINTIC = 0, 1
-PF_STEP_SAVE_STRESS = 1
+PF_STEP_SAVE_STRESS, PF_STEP_FIXED_POINT = 1, 2
 PF_FIELD_ETA, PF_FIELD_STRAIN, PF_FIELD_STRESS = 0, 1, 2
 
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -93,8 +93,16 @@ def load():
     lib.pf_last_error.restype = ctypes.c_char_p
     lib.pf_mg_twin_tables.argtypes = [_dp, ctypes.c_double, ctypes.c_double, i32, _dp, i32,
                                       ctypes.POINTER(i32), _dp, _dp, _dp]
+    lib.pf_batch_workspace_size.argtypes = [ctypes.POINTER(PfProblem), i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pf_batch_init.argtypes = [ctypes.POINTER(PfProblem), i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.pf_batch_step.argtypes = [vp, i32, ctypes.POINTER(PfLoad)]
+    lib.pf_batch_fields.argtypes = [vp, i32, i32, i32, vp]
+    lib.pf_batch_stats.argtypes = [vp, i32, ctypes.POINTER(PfStats)]
+    lib.pf_batch_size.argtypes = [vp]
     for name in ("pf_workspace_size", "pf_init", "pf_step", "pf_fields", "pf_stats_get", "pf_fft",
-                 "pf_profile_enable", "pf_profile_read", "pf_destroy", "pf_mg_twin_tables"):
+                 "pf_profile_enable", "pf_profile_read", "pf_destroy", "pf_mg_twin_tables",
+                 "pf_batch_workspace_size", "pf_batch_init", "pf_batch_step", "pf_batch_fields",
+                 "pf_batch_stats", "pf_batch_size"):
         getattr(lib, name).restype = ctypes.c_int
     _ = u32
     _lib = lib
@@ -130,6 +138,25 @@ def mg_twin_tables(rotations, variant_ids, C_hex=(59.4e9, 25.6e9, 21.4e9, 61.6e9
 
 def stress_mask_bits(mask):
     return int(sum(1 << i for i, m in enumerate(mask) if m))
+
+
+def _fill_load(ld, eps_bar, sig_bar, eps_p_ptr, flags):
+    for i in range(6):
+        ld.eps_bar[i] = float(eps_bar[i])
+        ld.sig_bar[i] = 0.0 if sig_bar is None else float(sig_bar[i])
+    ld.eps_p = eps_p_ptr
+    ld.flags = flags
+
+
+def _stats_dict(s, n_var):
+    return {
+        "step": s.step, "G_dw": s.G_dw, "G_gd": s.G_gd, "G_me": s.G_me,
+        "G": s.G_dw + s.G_gd + s.G_me,
+        "sig_mean": np.array(s.sig_mean[:]), "eps_mean": np.array(s.eps_mean[:]),
+        "eta_mean": np.array(s.eta_mean[:n_var]),
+        "eta_min": s.eta_min, "eta_max": s.eta_max,
+        "ms_iters": s.ms_iters, "ms_residual": s.ms_residual,
+    }
 
 
 class Solver:
@@ -209,20 +236,17 @@ class Solver:
         if rc != PF_OK:
             raise PfError(rc, f"{what}: {self.lib.pf_last_error(self.ctx).decode()}")
 
-    def step(self, n_steps, eps_bar, sig_bar=None, eps_p=None, save_stress=False):
+    def step(self, n_steps, eps_bar, sig_bar=None, eps_p=None, save_stress=False, fixed_point=False):
         ld = PfLoad()
-        for i in range(6):
-            ld.eps_bar[i] = float(eps_bar[i])
-            ld.sig_bar[i] = 0.0 if sig_bar is None else float(sig_bar[i])
+        ptr = None
         if eps_p is not None:
             t = self.torch
             if eps_p.dtype != t.float32 or not eps_p.is_cuda or tuple(eps_p.shape) != (6,) + self.shape:
                 raise ValueError("eps_p must be a float32 CUDA tensor (6, nz, ny, nx)")
             self._epsp = eps_p.contiguous()
-            ld.eps_p = self._epsp.data_ptr()
-        else:
-            ld.eps_p = None
-        ld.flags = PF_STEP_SAVE_STRESS if save_stress else 0
+            ptr = self._epsp.data_ptr()
+        flags = (PF_STEP_SAVE_STRESS if save_stress else 0) | (PF_STEP_FIXED_POINT if fixed_point else 0)
+        _fill_load(ld, eps_bar, sig_bar, ptr, flags)
         self._check(self.lib.pf_step(self.ctx, int(n_steps), ctypes.byref(ld)), "pf_step")
 
     def field(self, which):
@@ -239,14 +263,7 @@ class Solver:
     def stats(self):
         s = PfStats()
         self._check(self.lib.pf_stats_get(self.ctx, ctypes.byref(s)), "pf_stats_get")
-        return {
-            "step": s.step, "G_dw": s.G_dw, "G_gd": s.G_gd, "G_me": s.G_me,
-            "G": s.G_dw + s.G_gd + s.G_me,
-            "sig_mean": np.array(s.sig_mean[:]), "eps_mean": np.array(s.eps_mean[:]),
-            "eta_mean": np.array(s.eta_mean[:self.n_var]),
-            "eta_min": s.eta_min, "eta_max": s.eta_max,
-            "ms_iters": s.ms_iters, "ms_residual": s.ms_residual,
-        }
+        return _stats_dict(s, self.n_var)
 
     def fft_forward(self, real):
         t = self.torch
@@ -277,6 +294,138 @@ class Solver:
         self._check(self.lib.pf_profile_read(self.ctx, maxn, names, counts, tot, ctypes.byref(n)),
                     "pf_profile_read")
         return {names[i].value.decode(): (counts[i], tot[i]) for i in range(min(n.value, maxn))}
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.pf_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """A batch of independent single-grain instances in one context.
+
+    instances: list of dicts with keys
+      eta0      torch float32 CUDA tensor (n_var, nz, ny, nx)
+      tables    (C_grain (1,6,6), C_var (1,V,6,6), eps0 (1,V,6)) numpy float64;
+                crystal frame when "rotation" is given
+      rotation  optional (3,3) crystal->sample rotation
+      C_ref     optional 6x6 reference medium (default: the mean stiffness)
+    The shared parameters are keyword arguments as for Solver.
+    """
+
+    def __init__(self, instances, dx, A, kappa, L, dt, stress_mask, h_kind=PF_H_LINEAR, ms_tol=1e-6,
+                 ms_max_iter=50):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        n = len(instances)
+        probs = (PfProblem * n)()
+        self._keep = []
+        self.shapes = []
+        self.n_var = None
+        dev = None
+        for i, inst in enumerate(instances):
+            eta0 = inst["eta0"]
+            if eta0.dtype != torch.float32 or not eta0.is_cuda or eta0.dim() != 4:
+                raise ValueError("eta0 must be a float32 CUDA tensor (n_var, nz, ny, nx)")
+            eta0 = eta0.contiguous()
+            dev = eta0.device
+            V, nz, ny, nx = eta0.shape
+            if self.n_var is None:
+                self.n_var = V
+            Cg, Cv, e0 = (np.ascontiguousarray(np.asarray(t, dtype=np.float64)) for t in inst["tables"])
+            if Cg.shape != (1, 6, 6) or Cv.shape != (1, V, 6, 6) or e0.shape != (1, V, 6):
+                raise ValueError("batched instances take one-grain tables")
+            rot = inst.get("rotation")
+            if rot is not None:
+                rot = np.ascontiguousarray(np.asarray(rot, dtype=np.float64).reshape(1, 3, 3))
+            self._keep += [Cg, Cv, e0, eta0, rot]
+            p = probs[i]
+            p.nx, p.ny, p.nz = nx, ny, nz
+            p.dx = dx
+            p.n_var = V
+            p.A, p.kappa, p.L, p.dt = A, kappa, L, dt
+            p.h_kind = h_kind
+            p.n_grains = 1
+            p.C_grain, p.C_var, p.eps0 = _ptr(Cg), _ptr(Cv), _ptr(e0)
+            p.grain_rot = _ptr(rot) if rot is not None else None
+            p.grain_id = None
+            p.eta0 = eta0.data_ptr()
+            C_ref = inst.get("C_ref")
+            if C_ref is None:
+                p.C_ref_auto = 1
+            else:
+                p.C_ref_auto = 0
+                for k, v in enumerate(np.asarray(C_ref, dtype=np.float64).ravel()):
+                    p.C_ref[k] = v
+            p.ms_tol = ms_tol
+            p.ms_max_iter = ms_max_iter
+            p.bc_stress_mask = stress_mask_bits(stress_mask)
+            self.shapes.append((nz, ny, nx))
+        nbytes = ctypes.c_size_t()
+        rc = self.lib.pf_batch_workspace_size(probs, n, ctypes.byref(nbytes))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_batch_workspace_size")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.pf_batch_init(probs, n, self.workspace.data_ptr(), nbytes.value,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_batch_init (see stderr)")
+        self.ctx = ctx
+        self.n = n
+        self._loads = (PfLoad * n)()
+        self._epsp = [None] * n
+
+    def _check(self, rc, what):
+        if rc != PF_OK:
+            raise PfError(rc, f"{what}: {self.lib.pf_last_error(self.ctx).decode()}")
+
+    def step(self, n_steps, eps_bar, sig_bar=None, eps_p=None, save_stress=False, fixed_point=False):
+        """eps_bar, sig_bar: (n_inst, 6) arrays; eps_p: None or a list with a
+        tensor (6, nz, ny, nx) or None per instance."""
+        eb = np.asarray(eps_bar, dtype=np.float64).reshape(self.n, 6)
+        sb = np.zeros((self.n, 6)) if sig_bar is None else np.asarray(sig_bar, dtype=np.float64).reshape(self.n, 6)
+        flags = (PF_STEP_SAVE_STRESS if save_stress else 0) | (PF_STEP_FIXED_POINT if fixed_point else 0)
+        for i in range(self.n):
+            ptr = None
+            if eps_p is not None and eps_p[i] is not None:
+                e = eps_p[i].contiguous()
+                if tuple(e.shape) != (6,) + self.shapes[i]:
+                    raise ValueError("eps_p[i] must be (6, nz, ny, nx)")
+                self._epsp[i] = e
+                ptr = e.data_ptr()
+            _fill_load(self._loads[i], eb[i], sb[i], ptr, flags)
+        self._check(self.lib.pf_batch_step(self.ctx, int(n_steps), self._loads), "pf_batch_step")
+
+    def field(self, inst, which, out=None):
+        n = self.n_var if which == PF_FIELD_ETA else 6
+        if out is None:
+            out = self.torch.empty((n,) + self.shapes[inst], dtype=self.torch.float32, device=self.workspace.device)
+        self._check(self.lib.pf_batch_fields(self.ctx, int(inst), which, 0, out.data_ptr()), "pf_batch_fields")
+        return out
+
+    def set_field(self, inst, which, buf):
+        buf = buf.contiguous()
+        self._check(self.lib.pf_batch_fields(self.ctx, int(inst), which, 1, buf.data_ptr()), "pf_batch_fields")
+        self.stream.synchronize()
+
+    def stats(self, inst):
+        s = PfStats()
+        self._check(self.lib.pf_batch_stats(self.ctx, int(inst), ctypes.byref(s)), "pf_batch_stats")
+        return _stats_dict(s, self.n_var)
+
+    def profile(self, on=True):
+        self._check(self.lib.pf_profile_enable(self.ctx, 1 if on else 0), "pf_profile_enable")
+
+    profile_read = Solver.profile_read
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -1,4 +1,18 @@
 // Host runtime and C ABI of the phase-field twin step (see include/pf.h).
+//
+// A context holds one or more independent instances. Instances of one grid
+// size form a group: their fields are stacked along z so that every pass
+// over the group is one kernel launch, whatever the number of instances.
+// A step of a group runs either
+//   - the fixed-point path: Moulinec-Suquet iterations, then the driving
+//     forces and the semi-implicit Allen-Cahn update; or
+//   - the homogeneous spectral path, when an instance has one stiffness
+//     everywhere, linear interpolation and no plastic strain: the
+//     equilibrium is then known per wavevector and the step is one
+//     forward and one inverse transform.
+// When no group needs a host decision inside the step (no iterated fixed
+// point, no profiling, no stress output), the launches of one step are
+// captured once in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -22,9 +36,10 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
-// Workspace layout (byte offsets from the workspace base).
+// Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
-  size_t eta, eps, eps_prev, sig, spec, tables, rot, tw, part_ms, part_res, part_ac, part_mm, part_gd, state, total;
+  size_t eta, eps, eps_prev, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, tw;
+  size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
 
@@ -37,32 +52,40 @@ bool axis_ok(int n) { return pfl::supported_axis(n); }
 // one aligned cache line per row.
 int spec_stride(int nx) { return (nx / 2 + 1 + 15) / 16 * 16; }
 
-Layout make_layout(int nx, int ny, int nz, int nv, int n_grains) {
+// ninst instances of one size; own_epsp: the group keeps its own stacked
+// plastic strain (batches), else the caller's buffer is used in place.
+Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool own_epsp) {
   Layout L{};
-  const size_t nvox = (size_t)nx * ny * nz;
-  const size_t nh = (size_t)nx / 2 + 1;
-  const size_t nspec = (size_t)spec_stride(nx) * ny * nz;
+  const size_t nvox = (size_t)nx * ny * nz * ninst;
+  const size_t nspec = (size_t)spec_stride(nx) * ny * nz * ninst;
+  const int G = n_grains > 0 ? n_grains : 1;
   KArgs a{};
-  a.nx = nx; a.ny = ny; a.nz = nz; a.nh = (int)nh; a.sh = spec_stride(nx); a.nv = nv;
+  a.nx = nx; a.ny = ny; a.nz = nz; a.nh = nx / 2 + 1; a.sh = spec_stride(nx); a.nv = nv; a.ninst = ninst;
   const size_t xb = (size_t)pfl::x_blocks(a);
-  const size_t zb = (size_t)pfl::z_blocks(a, nv > 6 ? nv : 6);
+  const size_t zb = (size_t)pfl::z_blocks(a, nv);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
   L.eta = take(sizeof(float) * nvox * nv);
   L.eps = take(sizeof(float) * nvox * 6);
   L.eps_prev = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
+  L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
   L.spec = take(sizeof(float) * 2 * nspec * 6);
   L.tab_stride = tab_stride_for(nv);
-  L.tables = take(sizeof(float) * (size_t)L.tab_stride * (n_grains > 0 ? n_grains : 1));
-  L.rot = take(sizeof(float) * 12 * (size_t)(n_grains > 0 ? n_grains : 1));
+  L.tables = take(sizeof(float) * (size_t)L.tab_stride * G * ninst);
+  L.rot = take(sizeof(float) * 12 * (size_t)G);
+  L.ref = take(sizeof(float) * pft::kRefStride * (size_t)ninst);
+  L.bss = take(sizeof(double) * 36 * (size_t)ninst);
+  L.loads = take(sizeof(double) * 12 * (size_t)ninst);
+  L.kh = take(sizeof(float) * pft::kKhStride * (size_t)ninst);
+  L.khd = take(sizeof(double) * pft::kKhdStride * (size_t)ninst);
   L.tw = take(sizeof(float) * 2 * (size_t)(nx / 2 + nx + ny + nz));
   L.part_ms = take(sizeof(double) * xb * pft::kQms);
   L.part_res = take(sizeof(double) * xb * pft::kQres);
   L.part_ac = take(sizeof(double) * xb * pft::kQac);
   L.part_mm = take(sizeof(float) * xb * 2);
   L.part_gd = take(sizeof(double) * zb * pft::kQgd);
-  L.state = take(sizeof(DevState));
+  L.state = take(sizeof(DevState) * (size_t)ninst);
   L.total = off;
   return L;
 }
@@ -98,6 +121,29 @@ void pack_sym(const double* C, float* out) {
     for (int j = i; j < 6; ++j) out[pft::sym6(i, j)] = (float)(0.5 * (C[6 * i + j] + C[6 * j + i]));
 }
 
+// Tensor-Voigt form of a Voigt stiffness: sigma = M eps with eps in tensor
+// shear (M = C diag(1,1,1,2,2,2)), symmetrised.
+void tensor_voigt(const double* C, double* M) {
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) M[6 * i + j] = 0.5 * (C[6 * i + j] + C[6 * j + i]) * (j < 3 ? 1.0 : 2.0);
+}
+
+// Inverse of the stress-controlled block of M, embedded in a 6x6 matrix.
+bool stress_block_inverse(const double* M, uint32_t mask, double* out) {
+  int idx[6], ns = 0;
+  for (int i = 0; i < 6; ++i)
+    if ((mask >> i) & 1u) idx[ns++] = i;
+  for (int i = 0; i < 36; ++i) out[i] = 0.0;
+  if (ns == 0) return true;
+  double sub[36], inv[36];
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < ns; ++j) sub[i * ns + j] = M[6 * idx[i] + idx[j]];
+  if (!invert(ns, sub, inv)) return false;
+  for (int i = 0; i < ns; ++i)
+    for (int j = 0; j < ns; ++j) out[6 * idx[i] + idx[j]] = inv[i * ns + j];
+  return true;
+}
+
 // W_N^n = exp(-2 pi i n / N), computed in double, rounded once.
 void twiddles(int N, float* out) {
   for (int n = 0; n < N; ++n) {
@@ -107,27 +153,178 @@ void twiddles(int N, float* out) {
   }
 }
 
+// Host-side preparation of one instance: sample-frame tables and everything
+// derived from them.
+struct InstanceHost {
+  std::vector<float> tab;   // [G][tab_stride]
+  std::vector<float> rot;   // [G][12]
+  float ref[pft::kRefStride];
+  double bss[36];
+  float kh[pft::kKhStride];
+  double khd[pft::kKhdStride];
+  bool one_iteration;       // one stiffness everywhere, equal to the reference
+  bool homogeneous;         // one stiffness everywhere (spectral path possible)
+};
+
+int prepare_instance(const pf_problem* p, InstanceHost& h, std::string& why) {
+  const int nv = p->n_var, G = p->n_grains;
+  const bool rotated = p->grain_rot != nullptr;
+  std::vector<double> Cg_s((size_t)36 * G), Cv_s((size_t)36 * G * nv), e0_s((size_t)6 * G * nv);
+  for (int g = 0; g < G; ++g) {
+    if (rotated) {
+      const double* R = p->grain_rot + 9 * g;
+      pf_rotate_voigt(p->C_grain, R, &Cg_s[36 * g]);
+      for (int q = 0; q < nv; ++q) {
+        pf_rotate_voigt(p->C_var + 36 * q, R, &Cv_s[36 * ((size_t)g * nv + q)]);
+        const double* e = p->eps0 + 6 * q;
+        const double A[3][3] = {{e[0], e[5], e[4]}, {e[5], e[1], e[3]}, {e[4], e[3], e[2]}};
+        double B[3][3];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; ++m)
+              for (int n = 0; n < 3; ++n) acc += R[3 * i + m] * A[m][n] * R[3 * k + n];
+            B[i][k] = acc;
+          }
+        double* o = &e0_s[6 * ((size_t)g * nv + q)];
+        o[0] = B[0][0]; o[1] = B[1][1]; o[2] = B[2][2]; o[3] = B[1][2]; o[4] = B[0][2]; o[5] = B[0][1];
+      }
+    } else {
+      std::memcpy(&Cg_s[36 * g], p->C_grain + 36 * g, 36 * sizeof(double));
+      std::memcpy(&Cv_s[36 * (size_t)g * nv], p->C_var + 36 * (size_t)g * nv, 36 * nv * sizeof(double));
+      std::memcpy(&e0_s[6 * (size_t)g * nv], p->eps0 + 6 * (size_t)g * nv, 6 * nv * sizeof(double));
+    }
+  }
+  const int ts = tab_stride_for(nv);
+  h.tab.assign((size_t)ts * G, 0.f);
+  for (int g = 0; g < G; ++g) {
+    float* t = h.tab.data() + (size_t)g * ts;
+    const double* Cg = &Cg_s[36 * g];
+    pack_sym(Cg, t);
+    for (int q = 0; q < nv; ++q) {
+      const double* Cv = &Cv_s[36 * ((size_t)g * nv + q)];
+      double d[36];
+      for (int i = 0; i < 36; ++i) d[i] = Cv[i] - Cg[i];
+      pack_sym(d, t + 21 * (q + 1));
+      for (int k = 0; k < 6; ++k) t[21 * (nv + 1) + 6 * q + k] = (float)e0_s[6 * ((size_t)g * nv + q) + k];
+    }
+  }
+  h.rot.assign((size_t)12 * G, 0.f);
+  if (rotated)
+    for (int g = 0; g < G; ++g)
+      for (int k = 0; k < 9; ++k) h.rot[12 * g + k] = (float)p->grain_rot[9 * g + k];
+  // reference medium
+  double C0[36];
+  if (p->C_ref_auto) {
+    for (int i = 0; i < 36; ++i) {
+      double s = 0.0;
+      for (int g = 0; g < G; ++g) {
+        s += Cg_s[36 * g + i];
+        for (int q = 0; q < nv; ++q) s += Cv_s[36 * ((size_t)g * nv + q) + i];
+      }
+      C0[i] = s / (double)(G * (nv + 1));
+    }
+  } else {
+    std::memcpy(C0, p->C_ref, sizeof(C0));
+  }
+  bool homog = (G == 1);
+  for (int i = 0; i < 36 && homog; ++i)
+    for (int q = 0; q < nv && homog; ++q)
+      if (Cv_s[36 * q + i] != Cg_s[i]) homog = false;
+  bool one = homog;
+  for (int i = 0; i < 36 && one; ++i)
+    if (Cg_s[i] != C0[i]) one = false;
+  h.homogeneous = homog;
+  h.one_iteration = one;
+  pack_sym(C0, h.ref);
+  double M0[36], S0[36];
+  tensor_voigt(C0, M0);
+  if (!invert(6, M0, S0)) {
+    why = "reference stiffness is singular";
+    return PF_EINVAL;
+  }
+  for (int i = 0; i < 36; ++i) h.ref[21 + i] = (float)S0[i];
+  if (!stress_block_inverse(M0, p->bc_stress_mask, h.bss)) {
+    why = "stress-controlled block of the reference stiffness is singular";
+    return PF_EINVAL;
+  }
+  // spectral-path tables (grain 0)
+  std::memset(h.kh, 0, sizeof(h.kh));
+  std::memset(h.khd, 0, sizeof(h.khd));
+  if (homog && nv <= pft::kKhMaxVar) {
+    double M[36];
+    tensor_voigt(&Cg_s[0], M);
+    pack_sym(&Cg_s[0], h.kh);
+    double s0[pft::kMaxVar][6];
+    for (int q = 0; q < nv; ++q) {
+      const double* e = &e0_s[6 * q];
+      for (int i = 0; i < 6; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < 6; ++j) acc += M[6 * i + j] * e[j];
+        s0[q][i] = acc;
+        h.kh[21 + 6 * q + i] = (float)acc;
+      }
+    }
+    for (int q = 0; q < nv; ++q)
+      for (int r = 0; r < nv; ++r) {
+        double w = 0.0;
+        for (int c = 0; c < 6; ++c) w += (c < 3 ? 1.0 : 2.0) * s0[q][c] * e0_s[6 * r + c];
+        h.kh[21 + 6 * pft::kMaxVar + nv * q + r] = (float)w;
+      }
+    std::memcpy(h.khd, M, sizeof(M));
+    if (!stress_block_inverse(M, p->bc_stress_mask, h.khd + 36)) {
+      why = "stress-controlled block of the stiffness is singular";
+      return PF_EINVAL;
+    }
+    for (int q = 0; q < nv; ++q)
+      for (int c = 0; c < 6; ++c) h.khd[72 + 6 * q + c] = e0_s[6 * q + c];
+  }
+  return PF_OK;
+}
+
 struct ProfEntry {
   std::string name;
   hipEvent_t start, stop;
 };
 
+// One group of same-size instances.
+struct Group {
+  int nx, ny, nz, nh, ninst;
+  size_t nvox;           // voxels per instance
+  size_t base;           // workspace offset
+  Layout L;
+  KArgs args;
+  bool one_iteration;    // every instance exact after one fixed-point iteration
+  bool homogeneous;      // every instance eligible for the spectral path
+  bool strain_valid;     // the strain field describes the current state
+  int64_t hist;          // consecutive fixed-point steps with a valid strain history
+  bool own_epsp, epsp_given;
+  std::vector<int> members;
+};
+
 }  // namespace
 
 struct pf_ctx {
-  int nx, ny, nz, nh, nv;
-  size_t nvox;
+  int nv, n_inst;
   double dx, kappa;
   hipStream_t stream;
   char* ws;
-  Layout L;
-  KArgs args;
-  bool one_iteration;
+  std::vector<Group> groups;
+  std::vector<std::pair<int, int>> where;  // instance -> (group, index in group)
   int ms_max_iter;
+  uint32_t stress_mask;
+  int h_kind;
   int64_t steps;
-  int64_t hist;         // consecutive steps whose strain history is valid
-  Status* host_status;  // pinned
+  Status* host_status;   // pinned, [n_inst]
+  double* host_loads;    // pinned, [n_inst][12]
+  bool loads_uploaded;
   std::string err;
+  // graph replay of one step
+  hipStream_t cap_stream;
+  hipGraphExec_t gexec;
+  std::string gkey;
+  bool capturing;
+  // profiling
   bool prof_on;
   std::vector<ProfEntry> prof;
   std::vector<hipEvent_t> ev_pool;
@@ -158,20 +355,21 @@ hipEvent_t get_event(pf_ctx* c) {
   return e;
 }
 
-// Launch one stage, bracketed by events when profiling is on.
+// Launch one stage on stream s, bracketed by events when profiling is on.
 template <class F>
-int launch(pf_ctx* c, const char* name, F&& f) {
+int launch(pf_ctx* c, hipStream_t s, const char* name, F&& f) {
   ProfEntry pe;
-  if (c->prof_on) {
+  const bool prof = c->prof_on && !c->capturing;
+  if (prof) {
     pe.name = name;
     pe.start = get_event(c);
     pe.stop = get_event(c);
-    if (pe.start) hipEventRecord(pe.start, c->stream);
+    if (pe.start) hipEventRecord(pe.start, s);
   }
   hipError_t e = f();
   if (e != hipSuccess) return hip_fail(c, e, name);
-  if (c->prof_on && pe.start && pe.stop) {
-    hipEventRecord(pe.stop, c->stream);
+  if (prof && pe.start && pe.stop) {
+    hipEventRecord(pe.stop, s);
     c->prof.push_back(pe);
   }
   return PF_OK;
@@ -205,356 +403,632 @@ int validate(const pf_problem* p, std::string& why) {
   return PF_OK;
 }
 
+// Batch-wide checks: what the instances of one context must share.
+int validate_batch(const pf_problem* probs, int n, std::string& why) {
+  if (!probs || n < 1) { why = "need at least one problem"; return PF_EINVAL; }
+  for (int i = 0; i < n; ++i) {
+    const int rc = validate(&probs[i], why);
+    if (rc != PF_OK) {
+      why = "instance " + std::to_string(i) + ": " + why;
+      return rc;
+    }
+  }
+  if (n == 1) return PF_OK;
+  const pf_problem& p0 = probs[0];
+  for (int i = 0; i < n; ++i) {
+    const pf_problem& p = probs[i];
+    if (p.n_grains != 1) { why = "batched instances must each be one grain"; return PF_EINVAL; }
+    if (p.n_var != p0.n_var || p.h_kind != p0.h_kind || p.A != p0.A || p.kappa != p0.kappa || p.L != p0.L ||
+        p.dt != p0.dt || p.dx != p0.dx || p.ms_tol != p0.ms_tol || p.ms_max_iter != p0.ms_max_iter ||
+        p.bc_stress_mask != p0.bc_stress_mask) {
+      why = "batched instances must share n_var, h_kind, A, kappa, L, dt, dx, ms_tol, ms_max_iter and "
+            "bc_stress_mask";
+      return PF_EINVAL;
+    }
+  }
+  return PF_OK;
+}
+
+// Group the instances by grid size, in order of first appearance.
+std::vector<Group> plan_groups(const pf_problem* probs, int n) {
+  std::vector<Group> gs;
+  for (int i = 0; i < n; ++i) {
+    const pf_problem& p = probs[i];
+    size_t k = 0;
+    while (k < gs.size() && !(gs[k].nx == p.nx && gs[k].ny == p.ny && gs[k].nz == p.nz)) ++k;
+    if (k == gs.size()) {
+      Group g{};
+      g.nx = p.nx; g.ny = p.ny; g.nz = p.nz; g.nh = p.nx / 2 + 1;
+      g.nvox = (size_t)p.nx * p.ny * p.nz;
+      gs.push_back(g);
+    }
+    gs[k].members.push_back(i);
+  }
+  size_t off = 0;
+  for (auto& g : gs) {
+    g.ninst = (int)g.members.size();
+    g.own_epsp = n > 1;
+    g.L = make_layout(g.nx, g.ny, g.nz, probs[0].n_var, probs[g.members[0]].n_grains, g.ninst, g.own_epsp);
+    g.base = off;
+    off += g.L.total;
+  }
+  return gs;
+}
+
+size_t batch_bytes(const pf_problem* probs, int n) {
+  size_t total = 0;
+  for (auto& g : plan_groups(probs, n)) total += g.L.total;
+  return total;
+}
+
+int read_status(pf_ctx* c) {
+  size_t off = 0;
+  for (auto& g : c->groups) {
+    hipError_t e = hipMemcpy2DAsync(c->host_status + off, sizeof(Status), &g.args.state->st, sizeof(DevState),
+                                    sizeof(Status), g.ninst, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "status copy");
+    off += g.ninst;
+  }
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "stream sync");
+  return PF_OK;
+}
+
+// host_status index range of a group
+size_t status_base(pf_ctx* c, size_t gi) {
+  size_t off = 0;
+  for (size_t k = 0; k < gi; ++k) off += c->groups[k].ninst;
+  return off;
+}
+
+int ms_iteration(pf_ctx* c, const Group& g, int mode, hipStream_t s) {
+  KArgs a = g.args;
+  a.iter_mode = mode;
+  PF_TRY(launch(c, s, "ms_x_forward", [&] { return pfl::ms_x_forward(a, s); }));
+  PF_TRY(launch(c, s, "ms_finalize_mean", [&] { return pfl::ms_finalize_mean(a, s); }));
+  PF_TRY(launch(c, s, "ms_y_forward", [&] { return pfl::y_pass(a, 6, 1, s); }));
+  PF_TRY(launch(c, s, "ms_z_green", [&] { return pfl::ms_z_green(a, s); }));
+  PF_TRY(launch(c, s, "ms_y_inverse", [&] { return pfl::y_pass(a, 6, -1, s); }));
+  PF_TRY(launch(c, s, "ms_x_inverse", [&] { return pfl::ms_x_inverse(a, s); }));
+  PF_TRY(launch(c, s, "ms_finalize_residual", [&] { return pfl::ms_finalize_residual(a, s); }));
+  return PF_OK;
+}
+
+int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
+  const KArgs& a = g.args;
+  PF_TRY(launch(c, s, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
+  PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
+  PF_TRY(launch(c, s, "ac_z_update", [&] { return pfl::ac_z_update(a, 0, s); }));
+  PF_TRY(launch(c, s, "ac_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
+  PF_TRY(launch(c, s, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
+  PF_TRY(launch(c, s, "ac_finalize", [&] { return pfl::ac_finalize(a, 0, s); }));
+  return PF_OK;
+}
+
+// The whole homogeneous spectral step of a group.
+int kh_step(pf_ctx* c, const Group& g, hipStream_t s) {
+  const KArgs& a = g.args;
+  PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(a, s); }));
+  PF_TRY(launch(c, s, "kh_x_forward", [&] { return pfl::kh_x_forward(a, s); }));
+  PF_TRY(launch(c, s, "kh_mean", [&] { return pfl::kh_mean(a, s); }));
+  PF_TRY(launch(c, s, "kh_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
+  PF_TRY(launch(c, s, "kh_z_update", [&] { return pfl::kh_z_update(a, s); }));
+  PF_TRY(launch(c, s, "kh_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
+  PF_TRY(launch(c, s, "kh_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
+  PF_TRY(launch(c, s, "kh_finalize", [&] { return pfl::ac_finalize(a, 2, s); }));
+  return PF_OK;
+}
+
+// One step of a group that needs no host decision (spectral path or one
+// fixed-point iteration).
+int fixed_step(pf_ctx* c, const Group& g, bool kh, hipStream_t s) {
+  if (kh) return kh_step(c, g, s);
+  KArgs ab = g.args;
+  ab.iter_mode = 0;
+  PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(ab, s); }));
+  PF_TRY(ms_iteration(c, g, 0, s));
+  return ac_update(c, g, s);
+}
+
+void drop_graph(pf_ctx* c) {
+  if (c->gexec) hipGraphExecDestroy(c->gexec);
+  c->gexec = nullptr;
+  c->gkey.clear();
+}
+
+// Capture (or reuse) the graph of one step of every group and replay it.
+int run_graph(pf_ctx* c, int n_steps, const std::vector<char>& use_kh, const std::string& key) {
+  hipError_t e;
+  if (!c->gexec || c->gkey != key) {
+    drop_graph(c);
+    if (!c->cap_stream) {
+      if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(c, e, "capture stream");
+    }
+    if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return hip_fail(c, e, "begin capture");
+    c->capturing = true;
+    int rc = PF_OK;
+    for (size_t k = 0; k < c->groups.size() && rc == PF_OK; ++k)
+      rc = fixed_step(c, c->groups[k], use_kh[k] != 0, c->cap_stream);
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc != PF_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    e = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      c->gexec = nullptr;
+      return hip_fail(c, e, "graph instantiate");
+    }
+    c->gkey = key;
+  }
+  for (int n = 0; n < n_steps; ++n)
+    if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  return PF_OK;
+}
+
+int check_instance(pf_ctx* c, int32_t inst) {
+  if (inst < 0 || inst >= c->n_inst) return fail(c, PF_EINVAL, "instance index out of range");
+  return PF_OK;
+}
+
 }  // namespace
 
 extern "C" {
 
-int pf_workspace_size(const pf_problem* p, size_t* bytes) {
+int pf_batch_workspace_size(const pf_problem* probs, int32_t n_inst, size_t* bytes) {
+  if (!bytes) return PF_EINVAL;
   std::string why;
+  if (validate_batch(probs, n_inst, why) != PF_OK) return PF_EINVAL;
+  *bytes = batch_bytes(probs, n_inst);
+  return PF_OK;
+}
+
+int pf_workspace_size(const pf_problem* p, size_t* bytes) {
   if (!bytes) return PF_EINVAL;
   if (!p || !axis_ok(p->nx) || !axis_ok(p->ny) || !axis_ok(p->nz) || p->n_var < 1 ||
       p->n_var > pft::kMaxVar || p->n_grains < 1 || p->n_grains > 255)
     return PF_EINVAL;
-  *bytes = make_layout(p->nx, p->ny, p->nz, p->n_var, p->n_grains).total;
+  *bytes = batch_bytes(p, 1);
   return PF_OK;
 }
 
-int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_stream, pf_ctx** out) {
+int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size_t ws_bytes, void* hip_stream,
+                  pf_ctx** out) {
   if (!out) return PF_EINVAL;
   *out = nullptr;
   std::string why;
-  int rc = validate(p, why);
+  int rc = validate_batch(probs, n_inst, why);
   if (rc != PF_OK) {
     fprintf(stderr, "pf_init: %s\n", why.c_str());
     return rc;
   }
-  const Layout L = make_layout(p->nx, p->ny, p->nz, p->n_var, p->n_grains);
-  if (!workspace || ws_bytes < L.total) {
-    fprintf(stderr, "pf_init: workspace of %zu bytes needed\n", L.total);
+  std::vector<Group> groups = plan_groups(probs, n_inst);
+  size_t need = 0;
+  for (auto& g : groups) need += g.L.total;
+  if (!workspace || ws_bytes < need) {
+    fprintf(stderr, "pf_init: workspace of %zu bytes needed\n", need);
     return PF_ENOMEM;
   }
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) {
     fprintf(stderr, "pf_init: workspace must be 256-byte aligned\n");
     return PF_EINVAL;
   }
+  std::vector<InstanceHost> hosts(n_inst);
+  for (int i = 0; i < n_inst; ++i) {
+    rc = prepare_instance(&probs[i], hosts[i], why);
+    if (rc != PF_OK) {
+      fprintf(stderr, "pf_init: instance %d: %s\n", i, why.c_str());
+      return rc;
+    }
+  }
   pf_ctx* c = new (std::nothrow) pf_ctx();
   if (!c) return PF_ENOMEM;
-  c->nx = p->nx; c->ny = p->ny; c->nz = p->nz; c->nh = p->nx / 2 + 1; c->nv = p->n_var;
-  c->nvox = (size_t)p->nx * p->ny * p->nz;
-  c->dx = p->dx;
-  c->kappa = p->kappa;
+  const pf_problem& p0 = probs[0];
+  c->nv = p0.n_var;
+  c->n_inst = n_inst;
+  c->dx = p0.dx;
+  c->kappa = p0.kappa;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   c->ws = static_cast<char*>(workspace);
-  c->L = L;
+  c->ms_max_iter = p0.ms_max_iter;
+  c->stress_mask = p0.bc_stress_mask;
+  c->h_kind = p0.h_kind;
   c->steps = 0;
-  c->hist = 0;
+  c->loads_uploaded = false;
+  c->cap_stream = nullptr;
+  c->gexec = nullptr;
+  c->capturing = false;
   c->prof_on = false;
-  c->ms_max_iter = p->ms_max_iter;
-
-  // material tables: per-grain sample-frame tables (rotated from the shared
-  // crystal-frame material when rotations are given)
-  const int nv = p->n_var, G = p->n_grains;
-  const bool rotated = p->grain_rot != nullptr;
-  std::vector<double> Cg_s((size_t)36 * G), Cv_s((size_t)36 * G * nv), e0_s((size_t)6 * G * nv);
-  for (int g = 0; g < G; ++g) {
-    if (rotated) {
-      const double* R = p->grain_rot + 9 * g;
-      pf_rotate_voigt(p->C_grain, R, &Cg_s[36 * g]);
-      for (int q = 0; q < nv; ++q) {
-        pf_rotate_voigt(p->C_var + 36 * q, R, &Cv_s[36 * ((size_t)g * nv + q)]);
-        const double* e = p->eps0 + 6 * q;
-        const double A[3][3] = {{e[0], e[5], e[4]}, {e[5], e[1], e[3]}, {e[4], e[3], e[2]}};
-        double B[3][3];
-        for (int i = 0; i < 3; ++i)
-          for (int k = 0; k < 3; ++k) {
-            double acc = 0.0;
-            for (int m = 0; m < 3; ++m)
-              for (int n = 0; n < 3; ++n) acc += R[3 * i + m] * A[m][n] * R[3 * k + n];
-            B[i][k] = acc;
-          }
-        double* o = &e0_s[6 * ((size_t)g * nv + q)];
-        o[0] = B[0][0]; o[1] = B[1][1]; o[2] = B[2][2]; o[3] = B[1][2]; o[4] = B[0][2]; o[5] = B[0][1];
-      }
-    } else {
-      std::memcpy(&Cg_s[36 * g], p->C_grain + 36 * g, 36 * sizeof(double));
-      std::memcpy(&Cv_s[36 * (size_t)g * nv], p->C_var + 36 * (size_t)g * nv, 36 * nv * sizeof(double));
-      std::memcpy(&e0_s[6 * (size_t)g * nv], p->eps0 + 6 * (size_t)g * nv, 6 * nv * sizeof(double));
-    }
-  }
-  std::vector<float> tab((size_t)L.tab_stride * G, 0.f);
-  for (int g = 0; g < G; ++g) {
-    float* t = tab.data() + (size_t)g * L.tab_stride;
-    const double* Cg = &Cg_s[36 * g];
-    pack_sym(Cg, t);
-    for (int q = 0; q < nv; ++q) {
-      const double* Cv = &Cv_s[36 * ((size_t)g * nv + q)];
-      double d[36];
-      for (int i = 0; i < 36; ++i) d[i] = Cv[i] - Cg[i];
-      pack_sym(d, t + 21 * (q + 1));
-      for (int k = 0; k < 6; ++k) t[21 * (nv + 1) + 6 * q + k] = (float)e0_s[6 * ((size_t)g * nv + q) + k];
-    }
-  }
-  std::vector<float> rot((size_t)12 * G, 0.f);
-  if (rotated)
-    for (int g = 0; g < G; ++g)
-      for (int k = 0; k < 9; ++k) rot[12 * g + k] = (float)p->grain_rot[9 * g + k];
-  // reference medium
-  double C0[36];
-  if (p->C_ref_auto) {
-    for (int i = 0; i < 36; ++i) {
-      double s = 0.0;
-      for (int g = 0; g < G; ++g) {
-        s += Cg_s[36 * g + i];
-        for (int q = 0; q < nv; ++q) s += Cv_s[36 * ((size_t)g * nv + q) + i];
-      }
-      C0[i] = s / (double)(G * (nv + 1));
-    }
-  } else {
-    std::memcpy(C0, p->C_ref, sizeof(C0));
-  }
-  // one stiffness everywhere equal to the reference: the fixed point is exact
-  // after one iteration.
-  bool one = (G == 1);
-  for (int i = 0; i < 36 && one; ++i) {
-    if (Cg_s[i] != C0[i]) one = false;
-    for (int q = 0; q < nv && one; ++q)
-      if (Cv_s[36 * q + i] != Cg_s[i]) one = false;
-  }
-  c->one_iteration = one;
-
-  // kernel arguments
-  KArgs& a = c->args;
-  std::memset(&a, 0, sizeof(a));
-  a.nx = p->nx; a.ny = p->ny; a.nz = p->nz; a.nh = c->nh; a.sh = spec_stride(p->nx); a.nv = nv;
-  a.h_kind = p->h_kind;
-  a.n_grains = G;
-  a.tab_stride = L.tab_stride;
-  a.A = (float)p->A;
-  a.LDt = (float)(p->L * p->dt);
-  const double twopi = 2.0 * M_PI;
-  const double kx = twopi / (p->nx * p->dx), ky = twopi / (p->ny * p->dx), kz = twopi / (p->nz * p->dx);
-  const double f = 2.0 * p->L * p->dt * p->kappa;
-  a.ax = (float)(f * kx * kx); a.ay = (float)(f * ky * ky); a.az = (float)(f * kz * kz);
-  a.gx = kx * kx; a.gy = ky * ky; a.gz = kz * kz;
-  a.inv_ntot = (float)(1.0 / (double)c->nvox);
-  a.tol = p->ms_tol;
-  pack_sym(C0, a.C0);
-  double M0[36], S0[36];
-  for (int i = 0; i < 6; ++i)
-    for (int j = 0; j < 6; ++j) M0[6 * i + j] = 0.5 * (C0[6 * i + j] + C0[6 * j + i]) * (j < 3 ? 1.0 : 2.0);
-  if (!invert(6, M0, S0)) {
-    delete c;
-    fprintf(stderr, "pf_init: reference stiffness is singular\n");
-    return PF_EINVAL;
-  }
-  for (int i = 0; i < 36; ++i) a.S0[i] = (float)S0[i];
-  a.stress_mask = p->bc_stress_mask;
-  {
-    int idx[6], ns = 0;
-    for (int i = 0; i < 6; ++i)
-      if ((p->bc_stress_mask >> i) & 1u) idx[ns++] = i;
-    for (int i = 0; i < 36; ++i) a.Bss[i] = 0.0;
-    if (ns > 0) {
-      double sub[36], inv[36];
-      for (int i = 0; i < ns; ++i)
-        for (int j = 0; j < ns; ++j) sub[i * ns + j] = M0[6 * idx[i] + idx[j]];
-      if (!invert(ns, sub, inv)) {
-        delete c;
-        fprintf(stderr, "pf_init: stress-controlled block of the reference stiffness is singular\n");
-        return PF_EINVAL;
-      }
-      for (int i = 0; i < ns; ++i)
-        for (int j = 0; j < ns; ++j) a.Bss[6 * idx[i] + idx[j]] = inv[i * ns + j];
-    }
-  }
-  char* ws = c->ws;
-  a.eta = reinterpret_cast<float*>(ws + L.eta);
-  a.eps = reinterpret_cast<float*>(ws + L.eps);
-  a.eps_prev = reinterpret_cast<float*>(ws + L.eps_prev);
-  a.iter_mode = 0;
-  a.sig = reinterpret_cast<float*>(ws + L.sig);
-  a.epsp = nullptr;
-  a.gid = G > 1 ? p->grain_id : nullptr;
-  a.tables = reinterpret_cast<float*>(ws + L.tables);
-  // one grain: its rotated table serves every voxel (no per-voxel rotation)
-  a.rot = (rotated && G > 1) ? reinterpret_cast<float*>(ws + L.rot) : nullptr;
-  if (rotated) {
-    // crystal-frame table shared by every grain: [C 21][dC_q 21 x V][eps0_q 6 x V]
-    pack_sym(p->C_grain, a.xtab);
-    for (int q = 0; q < nv; ++q) {
-      double d[36];
-      for (int i = 0; i < 36; ++i) d[i] = p->C_var[36 * q + i] - p->C_grain[i];
-      pack_sym(d, a.xtab + 21 * (q + 1));
-      for (int k = 0; k < 6; ++k) a.xtab[21 * (nv + 1) + 6 * q + k] = (float)p->eps0[6 * q + k];
-    }
-  }
-  a.spec = reinterpret_cast<float2*>(ws + L.spec);
-  float2* tw = reinterpret_cast<float2*>(ws + L.tw);
-  a.tw_xh = tw;
-  a.tw_x = tw + p->nx / 2;
-  a.tw_y = tw + p->nx / 2 + p->nx;
-  a.tw_z = tw + p->nx / 2 + p->nx + p->ny;
-  a.part_ms = reinterpret_cast<double*>(ws + L.part_ms);
-  a.part_res = reinterpret_cast<double*>(ws + L.part_res);
-  a.part_ac = reinterpret_cast<double*>(ws + L.part_ac);
-  a.part_mm = reinterpret_cast<float*>(ws + L.part_mm);
-  a.part_gd = reinterpret_cast<double*>(ws + L.part_gd);
-  a.state = reinterpret_cast<DevState*>(ws + L.state);
-  a.save_stress = 0;
-
-  std::vector<float> twh(2 * (size_t)(p->nx / 2 + p->nx + p->ny + p->nz));
-  twiddles(p->nx / 2, twh.data());
-  twiddles(p->nx, twh.data() + 2 * (p->nx / 2));
-  twiddles(p->ny, twh.data() + 2 * (p->nx / 2 + p->nx));
-  twiddles(p->nz, twh.data() + 2 * (p->nx / 2 + p->nx + p->ny));
-
-  DevState st0;
-  std::memset(&st0, 0, sizeof(st0));
+  c->groups = groups;
+  c->where.resize(n_inst);
+  for (size_t k = 0; k < c->groups.size(); ++k)
+    for (size_t j = 0; j < c->groups[k].members.size(); ++j) c->where[c->groups[k].members[j]] = {(int)k, (int)j};
 
   hipError_t e;
-  if ((e = hipHostMalloc(reinterpret_cast<void**>(&c->host_status), sizeof(Status), hipHostMallocDefault)) !=
-      hipSuccess) {
-    delete c;
-    fprintf(stderr, "pf_init: hipHostMalloc: %s\n", hipGetErrorString(e));
-    return PF_EDEVICE;
-  }
-  std::memset(c->host_status, 0, sizeof(Status));
+  c->host_status = nullptr;
+  c->host_loads = nullptr;
   auto bail = [&](hipError_t err, const char* what) {
     fprintf(stderr, "pf_init: %s: %s\n", what, hipGetErrorString(err));
-    hipHostFree(c->host_status);
+    if (c->host_status) hipHostFree(c->host_status);
+    if (c->host_loads) hipHostFree(c->host_loads);
     delete c;
     return PF_EDEVICE;
   };
-  if ((e = hipMemcpyAsync(const_cast<float*>(a.tables), tab.data(), tab.size() * sizeof(float),
-                          hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-    return bail(e, "tables");
-  if (rotated && (e = hipMemcpyAsync(const_cast<float*>(a.rot), rot.data(), rot.size() * sizeof(float),
-                                     hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-    return bail(e, "rotations");
-  if ((e = hipMemcpyAsync(tw, twh.data(), twh.size() * sizeof(float), hipMemcpyHostToDevice, c->stream)) !=
-      hipSuccess)
-    return bail(e, "twiddles");
-  if ((e = hipMemcpyAsync(a.state, &st0, sizeof(st0), hipMemcpyHostToDevice, c->stream)) != hipSuccess)
-    return bail(e, "state");
-  if ((e = hipMemcpyAsync(a.eta, p->eta0, sizeof(float) * c->nvox * nv, hipMemcpyDeviceToDevice, c->stream)) !=
-      hipSuccess)
-    return bail(e, "eta0");
-  if ((e = hipMemsetAsync(a.eps, 0, sizeof(float) * c->nvox * 6, c->stream)) != hipSuccess)
-    return bail(e, "strain");
-  // gradient energy of the initial state
-  if ((e = pfl::raw_x_forward(a, a.eta, nv, c->stream)) != hipSuccess) return bail(e, "init x");
-  if ((e = pfl::y_pass(a, nv, 1, c->stream)) != hipSuccess) return bail(e, "init y");
-  if ((e = pfl::ac_z_update(a, 1, c->stream)) != hipSuccess) return bail(e, "init z");
-  if ((e = pfl::ac_finalize(a, 1, c->stream)) != hipSuccess) return bail(e, "init fin");
-  if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "init sync");
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&c->host_status), sizeof(Status) * n_inst,
+                         hipHostMallocDefault)) != hipSuccess)
+    return bail(e, "hipHostMalloc");
+  if ((e = hipHostMalloc(reinterpret_cast<void**>(&c->host_loads), sizeof(double) * 12 * n_inst,
+                         hipHostMallocDefault)) != hipSuccess)
+    return bail(e, "hipHostMalloc");
+  std::memset(c->host_status, 0, sizeof(Status) * n_inst);
+  std::memset(c->host_loads, 0, sizeof(double) * 12 * n_inst);
+
+  const int nv = p0.n_var;
+  for (auto& g : c->groups) {
+    const Layout& L = g.L;
+    const pf_problem& pg = probs[g.members[0]];
+    const int G = pg.n_grains;
+    g.one_iteration = true;
+    g.homogeneous = nv <= pft::kKhMaxVar && p0.h_kind == PF_H_LINEAR;
+    for (int m : g.members) {
+      g.one_iteration = g.one_iteration && hosts[m].one_iteration;
+      g.homogeneous = g.homogeneous && hosts[m].homogeneous;
+    }
+    g.strain_valid = true;
+    g.hist = 0;
+    g.epsp_given = false;
+    char* ws = c->ws + g.base;
+    KArgs& a = g.args;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.nh = g.nh; a.sh = spec_stride(g.nx); a.nv = nv;
+    a.ninst = g.ninst;
+    a.h_kind = p0.h_kind;
+    a.n_grains = G;
+    a.tab_stride = L.tab_stride;
+    a.tab_inst = L.tab_stride * G;
+    a.A = (float)p0.A;
+    a.LDt = (float)(p0.L * p0.dt);
+    const double twopi = 2.0 * M_PI;
+    const double kx = twopi / (g.nx * p0.dx), ky = twopi / (g.ny * p0.dx), kz = twopi / (g.nz * p0.dx);
+    const double f = 2.0 * p0.L * p0.dt * p0.kappa;
+    a.ax = (float)(f * kx * kx); a.ay = (float)(f * ky * ky); a.az = (float)(f * kz * kz);
+    a.gx = kx * kx; a.gy = ky * ky; a.gz = kz * kz;
+    a.inv_ntot = (float)(1.0 / (double)g.nvox);
+    a.tol = p0.ms_tol;
+    a.stress_mask = p0.bc_stress_mask;
+    a.eta = reinterpret_cast<float*>(ws + L.eta);
+    a.eps = reinterpret_cast<float*>(ws + L.eps);
+    a.eps_prev = reinterpret_cast<float*>(ws + L.eps_prev);
+    a.iter_mode = 0;
+    a.sig = reinterpret_cast<float*>(ws + L.sig);
+    a.epsp = nullptr;
+    a.gid = G > 1 ? pg.grain_id : nullptr;
+    a.tables = reinterpret_cast<float*>(ws + L.tables);
+    a.ref = reinterpret_cast<float*>(ws + L.ref);
+    a.bss = reinterpret_cast<double*>(ws + L.bss);
+    a.loads = reinterpret_cast<double*>(ws + L.loads);
+    a.kh = reinterpret_cast<float*>(ws + L.kh);
+    a.khd = reinterpret_cast<double*>(ws + L.khd);
+    // one grain: its rotated table serves every voxel (no per-voxel rotation)
+    const bool rotated = pg.grain_rot != nullptr;
+    a.rot = (rotated && G > 1) ? reinterpret_cast<float*>(ws + L.rot) : nullptr;
+    if (rotated && G > 1) {
+      // crystal-frame table shared by every grain: [C 21][dC_q 21 x V][eps0_q 6 x V]
+      pack_sym(pg.C_grain, a.xtab);
+      for (int q = 0; q < nv; ++q) {
+        double d[36];
+        for (int i = 0; i < 36; ++i) d[i] = pg.C_var[36 * q + i] - pg.C_grain[i];
+        pack_sym(d, a.xtab + 21 * (q + 1));
+        for (int k = 0; k < 6; ++k) a.xtab[21 * (nv + 1) + 6 * q + k] = (float)pg.eps0[6 * q + k];
+      }
+    }
+    a.spec = reinterpret_cast<float2*>(ws + L.spec);
+    float2* tw = reinterpret_cast<float2*>(ws + L.tw);
+    a.tw_xh = tw;
+    a.tw_x = tw + g.nx / 2;
+    a.tw_y = tw + g.nx / 2 + g.nx;
+    a.tw_z = tw + g.nx / 2 + g.nx + g.ny;
+    a.part_ms = reinterpret_cast<double*>(ws + L.part_ms);
+    a.part_res = reinterpret_cast<double*>(ws + L.part_res);
+    a.part_ac = reinterpret_cast<double*>(ws + L.part_ac);
+    a.part_mm = reinterpret_cast<float*>(ws + L.part_mm);
+    a.part_gd = reinterpret_cast<double*>(ws + L.part_gd);
+    a.state = reinterpret_cast<DevState*>(ws + L.state);
+    a.save_stress = 0;
+
+    // per-instance tables, stacked
+    std::vector<float> tab, ref, kh;
+    std::vector<double> bss, khd;
+    for (int m : g.members) {
+      const InstanceHost& h = hosts[m];
+      tab.insert(tab.end(), h.tab.begin(), h.tab.end());
+      ref.insert(ref.end(), h.ref, h.ref + pft::kRefStride);
+      kh.insert(kh.end(), h.kh, h.kh + pft::kKhStride);
+      bss.insert(bss.end(), h.bss, h.bss + 36);
+      khd.insert(khd.end(), h.khd, h.khd + pft::kKhdStride);
+    }
+    std::vector<float> twh(2 * (size_t)(g.nx / 2 + g.nx + g.ny + g.nz));
+    twiddles(g.nx / 2, twh.data());
+    twiddles(g.nx, twh.data() + 2 * (g.nx / 2));
+    twiddles(g.ny, twh.data() + 2 * (g.nx / 2 + g.nx));
+    twiddles(g.nz, twh.data() + 2 * (g.nx / 2 + g.nx + g.ny));
+    std::vector<DevState> st0(g.ninst);
+    std::memset(st0.data(), 0, sizeof(DevState) * g.ninst);
+    auto h2d = [&](const void* dst, const void* src, size_t bytes) {
+      return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice, c->stream);
+    };
+    if ((e = h2d(a.tables, tab.data(), tab.size() * sizeof(float))) != hipSuccess) return bail(e, "tables");
+    if (a.rot && (e = h2d(a.rot, hosts[g.members[0]].rot.data(), hosts[g.members[0]].rot.size() * sizeof(float))) !=
+                     hipSuccess)
+      return bail(e, "rotations");
+    if ((e = h2d(a.ref, ref.data(), ref.size() * sizeof(float))) != hipSuccess) return bail(e, "reference");
+    if ((e = h2d(a.kh, kh.data(), kh.size() * sizeof(float))) != hipSuccess) return bail(e, "spectral tables");
+    if ((e = h2d(a.bss, bss.data(), bss.size() * sizeof(double))) != hipSuccess) return bail(e, "mixed condition");
+    if ((e = h2d(a.khd, khd.data(), khd.size() * sizeof(double))) != hipSuccess) return bail(e, "spectral tables");
+    if ((e = h2d(tw, twh.data(), twh.size() * sizeof(float))) != hipSuccess) return bail(e, "twiddles");
+    if ((e = h2d(a.state, st0.data(), st0.size() * sizeof(DevState))) != hipSuccess) return bail(e, "state");
+    // the host vectors above are pageable: the copies complete before return
+    for (size_t j = 0; j < g.members.size(); ++j) {
+      const pf_problem& pm = probs[g.members[j]];
+      for (int q = 0; q < nv; ++q) {
+        float* dst = a.eta + ((size_t)q * g.ninst + j) * g.nvox;
+        if ((e = hipMemcpyAsync(dst, pm.eta0 + (size_t)q * g.nvox, sizeof(float) * g.nvox, hipMemcpyDeviceToDevice,
+                                c->stream)) != hipSuccess)
+          return bail(e, "eta0");
+      }
+    }
+    if ((e = hipMemsetAsync(a.eps, 0, sizeof(float) * g.nvox * g.ninst * 6, c->stream)) != hipSuccess)
+      return bail(e, "strain");
+    if (g.own_epsp &&
+        (e = hipMemsetAsync(ws + L.epsp, 0, sizeof(float) * g.nvox * g.ninst * 6, c->stream)) != hipSuccess)
+      return bail(e, "plastic strain");
+    // gradient energy of the initial state
+    if ((e = pfl::raw_x_forward(a, a.eta, nv, c->stream)) != hipSuccess) return bail(e, "init x");
+    if ((e = pfl::y_pass(a, nv, 1, c->stream)) != hipSuccess) return bail(e, "init y");
+    if ((e = pfl::ac_z_update(a, 1, c->stream)) != hipSuccess) return bail(e, "init z");
+    if ((e = pfl::ac_finalize(a, 1, c->stream)) != hipSuccess) return bail(e, "init fin");
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return bail(e, "init sync");
+  }
   *out = c;
   return PF_OK;
 }
 
-static int read_status(pf_ctx* c) {
-  hipError_t e = hipMemcpyAsync(c->host_status, &c->args.state->st, sizeof(Status), hipMemcpyDeviceToHost,
-                                c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "status copy");
-  e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "stream sync");
-  return PF_OK;
+int pf_init(const pf_problem* p, void* workspace, size_t ws_bytes, void* hip_stream, pf_ctx** out) {
+  return pf_batch_init(p, 1, workspace, ws_bytes, hip_stream, out);
 }
 
-static int ms_iteration(pf_ctx* c, int mode) {
-  KArgs a = c->args;
-  a.iter_mode = mode;
-  hipStream_t s = c->stream;
-  PF_TRY(launch(c, "ms_x_forward", [&] { return pfl::ms_x_forward(a, s); }));
-  PF_TRY(launch(c, "ms_finalize_mean", [&] { return pfl::ms_finalize_mean(a, s); }));
-  PF_TRY(launch(c, "ms_y_forward", [&] { return pfl::y_pass(a, 6, 1, s); }));
-  PF_TRY(launch(c, "ms_z_green", [&] { return pfl::ms_z_green(a, s); }));
-  PF_TRY(launch(c, "ms_y_inverse", [&] { return pfl::y_pass(a, 6, -1, s); }));
-  PF_TRY(launch(c, "ms_x_inverse", [&] { return pfl::ms_x_inverse(a, s); }));
-  PF_TRY(launch(c, "ms_finalize_residual", [&] { return pfl::ms_finalize_residual(a, s); }));
+int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
+  if (!c) return PF_EINVAL;
+  if (!loads || n_steps < 0) return fail(c, PF_EINVAL, "pf_step: bad arguments");
+  uint32_t flags = 0;
+  for (int i = 0; i < c->n_inst; ++i) flags |= loads[i].flags;
+  const bool save_stress = (flags & PF_STEP_SAVE_STRESS) != 0;
+  const bool force_fp = (flags & PF_STEP_FIXED_POINT) != 0;
+  hipError_t e;
+  // plastic strain: the caller's buffer in place for one instance, a copy
+  // into the group's stacked field for a batch
+  for (int i = 0; i < c->n_inst; ++i) {
+    if (!loads[i].eps_p) continue;
+    Group& g = c->groups[c->where[i].first];
+    if (!g.own_epsp) {
+      g.args.epsp = loads[i].eps_p;
+    } else {
+      float* stack = reinterpret_cast<float*>(c->ws + g.base + g.L.epsp);
+      const int j = c->where[i].second;
+      for (int comp = 0; comp < 6; ++comp) {
+        e = hipMemcpyAsync(stack + ((size_t)comp * g.ninst + j) * g.nvox, loads[i].eps_p + (size_t)comp * g.nvox,
+                           sizeof(float) * g.nvox, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "plastic strain copy");
+      }
+      g.args.epsp = stack;
+    }
+    g.epsp_given = true;
+  }
+  // loads -> device (the pinned staging buffer is free: every call ends with
+  // a synchronisation of the stream)
+  bool changed = !c->loads_uploaded;
+  for (int i = 0; i < c->n_inst; ++i) {
+    double* h = c->host_loads + 12 * (size_t)i;
+    for (int k = 0; k < 6; ++k) {
+      if (h[k] != loads[i].eps_bar[k] || h[6 + k] != loads[i].sig_bar[k]) changed = true;
+    }
+  }
+  if (changed) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream sync");
+    for (auto& g : c->groups) {
+      for (size_t j = 0; j < g.members.size(); ++j) {
+        double* h = c->host_loads + 12 * (size_t)g.members[j];
+        const pf_load& ld = loads[g.members[j]];
+        for (int k = 0; k < 6; ++k) {
+          h[k] = ld.eps_bar[k];
+          h[6 + k] = ld.sig_bar[k];
+        }
+      }
+    }
+    for (auto& g : c->groups)
+      for (size_t j = 0; j < g.members.size(); ++j) {
+        e = hipMemcpyAsync(const_cast<double*>(g.args.loads) + 12 * j, c->host_loads + 12 * (size_t)g.members[j],
+                           sizeof(double) * 12, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "load copy");
+      }
+    c->loads_uploaded = true;
+  }
+  // path of each group
+  std::vector<char> use_kh(c->groups.size());
+  bool graphable = !save_stress && !c->prof_on && n_steps > 0;
+  std::string key;
+  for (size_t k = 0; k < c->groups.size(); ++k) {
+    Group& g = c->groups[k];
+    g.args.save_stress = save_stress ? 1 : 0;
+    use_kh[k] = g.homogeneous && !g.epsp_given && !save_stress && !force_fp;
+    if (!use_kh[k] && !g.one_iteration) graphable = false;
+    char buf[64];
+    snprintf(buf, sizeof(buf), "%d:%p;", (int)use_kh[k], (const void*)g.args.epsp);
+    key += buf;
+  }
+  if (graphable) {
+    PF_TRY(run_graph(c, n_steps, use_kh, key));
+    for (size_t k = 0; k < c->groups.size(); ++k) {
+      Group& g = c->groups[k];
+      if (use_kh[k]) {
+        g.strain_valid = false;
+        g.hist = 0;
+      } else {
+        g.strain_valid = true;
+        g.hist += n_steps;
+      }
+    }
+  } else {
+    hipStream_t s = c->stream;
+    for (int n = 0; n < n_steps; ++n) {
+      // fixed-point groups that iterate: first iterate extrapolated from the
+      // two previous steps (from the third step on), the step's starting
+      // strain kept for that from the second step on
+      std::vector<size_t> iterating;
+      for (size_t k = 0; k < c->groups.size(); ++k) {
+        Group& g = c->groups[k];
+        if (use_kh[k] || g.one_iteration) {
+          PF_TRY(fixed_step(c, g, use_kh[k] != 0, s));
+          continue;
+        }
+        iterating.push_back(k);
+      }
+      std::vector<int> first_mode(c->groups.size(), 0);
+      for (size_t k : iterating) {
+        Group& g = c->groups[k];
+        first_mode[k] = (g.hist >= 2 && g.strain_valid) ? 2 : ((g.hist >= 1 && g.strain_valid) ? 1 : 0);
+        KArgs ab = g.args;
+        ab.iter_mode = first_mode[k];
+        PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(ab, s); }));
+      }
+      std::vector<size_t> active = iterating;
+      for (int it = 0; it < c->ms_max_iter && !active.empty(); ++it) {
+        for (size_t k : active) PF_TRY(ms_iteration(c, c->groups[k], it == 0 ? first_mode[k] : 0, s));
+        PF_TRY(read_status(c));
+        std::vector<size_t> still;
+        for (size_t k : active) {
+          const size_t b = status_base(c, k);
+          bool all = true;
+          for (int j = 0; j < c->groups[k].ninst; ++j) all = all && c->host_status[b + j].done;
+          if (!all) still.push_back(k);
+        }
+        active.swap(still);
+      }
+      if (!active.empty()) {
+        const size_t k = active[0];
+        const size_t b = status_base(c, k);
+        double worst = 0.0;
+        for (int j = 0; j < c->groups[k].ninst; ++j)
+          if (!c->host_status[b + j].done && c->host_status[b + j].residual > worst)
+            worst = c->host_status[b + j].residual;
+        char buf[160];
+        snprintf(buf, sizeof(buf), "fixed point not converged after %d iterations (residual %.3e)",
+                 c->ms_max_iter, worst);
+        return fail(c, PF_ENOCONV, buf);
+      }
+      for (size_t k : iterating) PF_TRY(ac_update(c, c->groups[k], s));
+      for (size_t k = 0; k < c->groups.size(); ++k) {
+        Group& g = c->groups[k];
+        if (use_kh[k]) {
+          g.strain_valid = false;
+          g.hist = 0;
+        } else {
+          g.strain_valid = true;
+          g.hist += 1;
+        }
+      }
+    }
+  }
+  c->steps += n_steps;
+  if (n_steps > 0) {
+    PF_TRY(read_status(c));
+    size_t b = 0;
+    for (auto& g : c->groups) {
+      for (int j = 0; j < g.ninst; ++j)
+        if (c->host_status[b + j].nonfinite)
+          return fail(c, PF_ENONFINITE, "non-finite order parameter in instance " + std::to_string(g.members[j]));
+      b += g.ninst;
+    }
+  }
   return PF_OK;
 }
 
 int pf_step(pf_ctx* c, int32_t n_steps, const pf_load* load) {
   if (!c) return PF_EINVAL;
-  if (!load || n_steps < 0) return fail(c, PF_EINVAL, "pf_step: bad arguments");
-  if (load->eps_p) c->args.epsp = load->eps_p;
-  c->args.save_stress = (load->flags & PF_STEP_SAVE_STRESS) ? 1 : 0;
-  const KArgs& a = c->args;
-  hipStream_t s = c->stream;
-  for (int n = 0; n < n_steps; ++n) {
-    // From the third step on, the first iterate extrapolates the strain of
-    // the two previous steps; from the second on, the step's starting strain
-    // is kept for that.
-    const int first_mode = c->one_iteration ? 0 : (c->hist >= 2 ? 2 : (c->hist >= 1 ? 1 : 0));
-    KArgs ab = a;
-    ab.iter_mode = first_mode;
-    PF_TRY(launch(c, "step_begin", [&] { return pfl::step_begin(ab, load->eps_bar, load->sig_bar, s); }));
-    if (c->one_iteration) {
-      PF_TRY(ms_iteration(c, 0));
-    } else {
-      bool conv = false;
-      for (int k = 0; k < c->ms_max_iter; ++k) {
-        PF_TRY(ms_iteration(c, k == 0 ? first_mode : 0));
-        PF_TRY(read_status(c));
-        if (c->host_status->done) {
-          conv = true;
-          break;
-        }
-      }
-      if (!conv) {
-        char buf[160];
-        snprintf(buf, sizeof(buf), "fixed point not converged after %d iterations (residual %.3e)",
-                 c->ms_max_iter, c->host_status->residual);
-        return fail(c, PF_ENOCONV, buf);
-      }
-    }
-    PF_TRY(launch(c, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
-    PF_TRY(launch(c, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
-    PF_TRY(launch(c, "ac_z_update", [&] { return pfl::ac_z_update(a, 0, s); }));
-    PF_TRY(launch(c, "ac_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
-    PF_TRY(launch(c, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
-    PF_TRY(launch(c, "ac_finalize", [&] { return pfl::ac_finalize(a, 0, s); }));
-    c->steps += 1;
-    c->hist += 1;
+  if (c->n_inst != 1) return fail(c, PF_EINVAL, "pf_step: batched context, use pf_batch_step");
+  return pf_batch_step(c, n_steps, load);
+}
+
+int pf_batch_fields(pf_ctx* c, int32_t inst, int32_t which, int32_t set, float* buf) {
+  if (!c) return PF_EINVAL;
+  PF_TRY(check_instance(c, inst));
+  if (!buf) return fail(c, PF_EINVAL, "pf_fields: null buffer");
+  Group& g = c->groups[c->where[inst].first];
+  const int j = c->where[inst].second;
+  float* f = nullptr;
+  int ncomp = 0;
+  switch (which) {
+    case PF_FIELD_ETA: f = g.args.eta; ncomp = c->nv; break;
+    case PF_FIELD_STRAIN:
+      if (!set && !g.strain_valid)
+        return fail(c, PF_EINVAL,
+                    "pf_fields: the homogeneous spectral path keeps no strain field; run the step with "
+                    "PF_STEP_SAVE_STRESS or PF_STEP_FIXED_POINT");
+      f = g.args.eps; ncomp = 6; break;
+    case PF_FIELD_STRESS:
+      if (set) return fail(c, PF_EINVAL, "pf_fields: stress is read-only");
+      f = g.args.sig; ncomp = 6; break;
+    default: return fail(c, PF_EINVAL, "pf_fields: unknown field");
   }
-  if (n_steps > 0) {
-    PF_TRY(read_status(c));
-    if (c->host_status->nonfinite) return fail(c, PF_ENONFINITE, "non-finite order parameter");
+  if (set) {
+    g.hist = 0;  // the strain history no longer describes the state
+    if (which == PF_FIELD_STRAIN) g.strain_valid = true;
+  }
+  for (int comp = 0; comp < ncomp; ++comp) {
+    float* slot = f + ((size_t)comp * g.ninst + j) * g.nvox;
+    float* ext = buf + (size_t)comp * g.nvox;
+    hipError_t e = set ? hipMemcpyAsync(slot, ext, g.nvox * sizeof(float), hipMemcpyDeviceToDevice, c->stream)
+                       : hipMemcpyAsync(ext, slot, g.nvox * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pf_fields");
+  }
+  if (set && which == PF_FIELD_ETA) {
+    // gradient energy of the new state (reported by the next step's stats)
+    const KArgs& a = g.args;
+    hipStream_t s = c->stream;
+    PF_TRY(launch(c, s, "init_x", [&] { return pfl::raw_x_forward(a, a.eta, c->nv, s); }));
+    PF_TRY(launch(c, s, "init_y", [&] { return pfl::y_pass(a, c->nv, 1, s); }));
+    PF_TRY(launch(c, s, "init_z", [&] { return pfl::ac_z_update(a, 1, s); }));
+    PF_TRY(launch(c, s, "init_fin", [&] { return pfl::ac_finalize(a, 1, s); }));
   }
   return PF_OK;
 }
 
 int pf_fields(pf_ctx* c, int32_t which, int32_t set, float* buf) {
   if (!c) return PF_EINVAL;
-  if (!buf) return fail(c, PF_EINVAL, "pf_fields: null buffer");
-  float* f = nullptr;
-  size_t n = 0;
-  switch (which) {
-    case PF_FIELD_ETA: f = c->args.eta; n = c->nvox * c->nv; break;
-    case PF_FIELD_STRAIN: f = c->args.eps; n = c->nvox * 6; break;
-    case PF_FIELD_STRESS:
-      if (set) return fail(c, PF_EINVAL, "pf_fields: stress is read-only");
-      f = c->args.sig; n = c->nvox * 6; break;
-    default: return fail(c, PF_EINVAL, "pf_fields: unknown field");
-  }
-  if (set) c->hist = 0;  // the strain history no longer describes the state
-  hipError_t e = set ? hipMemcpyAsync(f, buf, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream)
-                     : hipMemcpyAsync(buf, f, n * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "pf_fields");
-  return PF_OK;
+  return pf_batch_fields(c, 0, which, set, buf);
 }
 
-int pf_stats_get(pf_ctx* c, pf_stats* out) {
+int pf_batch_stats(pf_ctx* c, int32_t inst, pf_stats* out) {
   if (!c || !out) return PF_EINVAL;
+  PF_TRY(check_instance(c, inst));
+  const Group& g = c->groups[c->where[inst].first];
   DevState st;
-  hipError_t e = hipMemcpyAsync(&st, c->args.state, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipMemcpyAsync(&st, g.args.state + c->where[inst].second, sizeof(DevState),
+                                hipMemcpyDeviceToHost, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "stats copy");
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "stats sync");
-  const double ntot = (double)c->nvox, dV = c->dx * c->dx * c->dx;
+  const double ntot = (double)g.nvox, dV = c->dx * c->dx * c->dx;
   std::memset(out, 0, sizeof(*out));
   out->step = c->steps;
-  out->G_dw = c->args.A * st.stats[0] * dV;
+  out->G_dw = g.args.A * st.stats[0] * dV;
   out->G_me = st.stats[1] * dV;
   for (int k = 0; k < 6; ++k) {
     out->sig_mean[k] = st.stats[2 + k] / ntot;
@@ -570,23 +1044,30 @@ int pf_stats_get(pf_ctx* c, pf_stats* out) {
   return PF_OK;
 }
 
+int pf_stats_get(pf_ctx* c, pf_stats* out) {
+  if (!c || !out) return PF_EINVAL;
+  return pf_batch_stats(c, 0, out);
+}
+
 int pf_fft(pf_ctx* c, int32_t direction, int32_t ncomp, float* real, void* spec) {
   if (!c) return PF_EINVAL;
+  if (c->n_inst != 1) return fail(c, PF_EUNSUPPORTED, "pf_fft: single-instance contexts only");
   if (!real || !spec || ncomp < 1 || ncomp > 6 || (direction != 1 && direction != -1))
     return fail(c, PF_EINVAL, "pf_fft: bad arguments");
-  KArgs a = c->args;
+  const Group& g = c->groups[0];
+  KArgs a = g.args;
   a.spec = reinterpret_cast<float2*>(spec);
-  a.sh = c->nh;  // caller layout: unpadded rows
+  a.sh = g.nh;  // caller layout: unpadded rows
   hipStream_t s = c->stream;
   if (direction == 1) {
-    PF_TRY(launch(c, "fft_x_forward", [&] { return pfl::raw_x_forward(a, real, ncomp, s); }));
-    PF_TRY(launch(c, "fft_y_forward", [&] { return pfl::y_pass(a, ncomp, 1, s); }));
-    PF_TRY(launch(c, "fft_z_forward", [&] { return pfl::raw_z(a, ncomp, 1, s); }));
+    PF_TRY(launch(c, s, "fft_x_forward", [&] { return pfl::raw_x_forward(a, real, ncomp, s); }));
+    PF_TRY(launch(c, s, "fft_y_forward", [&] { return pfl::y_pass(a, ncomp, 1, s); }));
+    PF_TRY(launch(c, s, "fft_z_forward", [&] { return pfl::raw_z(a, ncomp, 1, s); }));
   } else {
-    PF_TRY(launch(c, "fft_z_inverse", [&] { return pfl::raw_z(a, ncomp, -1, s); }));
-    PF_TRY(launch(c, "fft_y_inverse", [&] { return pfl::y_pass(a, ncomp, -1, s); }));
-    PF_TRY(launch(c, "fft_x_inverse",
-                  [&] { return pfl::raw_x_inverse(a, real, ncomp, (float)(1.0 / (double)c->nvox), s); }));
+    PF_TRY(launch(c, s, "fft_z_inverse", [&] { return pfl::raw_z(a, ncomp, -1, s); }));
+    PF_TRY(launch(c, s, "fft_y_inverse", [&] { return pfl::y_pass(a, ncomp, -1, s); }));
+    PF_TRY(launch(c, s, "fft_x_inverse",
+                  [&] { return pfl::raw_x_inverse(a, real, ncomp, (float)(1.0 / (double)g.nvox), s); }));
   }
   return PF_OK;
 }
@@ -643,12 +1124,15 @@ int pf_profile_read(pf_ctx* c, int32_t max_n, char (*names)[64], int64_t* counts
 int pf_destroy(pf_ctx* c) {
   if (!c) return PF_EINVAL;
   hipStreamSynchronize(c->stream);
+  drop_graph(c);
+  if (c->cap_stream) hipStreamDestroy(c->cap_stream);
   for (auto& pe : c->prof) {
     hipEventDestroy(pe.start);
     hipEventDestroy(pe.stop);
   }
   for (auto ev : c->ev_pool) hipEventDestroy(ev);
   if (c->host_status) hipHostFree(c->host_status);
+  if (c->host_loads) hipHostFree(c->host_loads);
   delete c;
   return PF_OK;
 }
@@ -657,5 +1141,7 @@ const char* pf_last_error(const pf_ctx* c) {
   if (!c) return "null context";
   return c->err.c_str();
 }
+
+int pf_batch_size(const pf_ctx* c) { return c ? c->n_inst : 0; }
 
 }  // extern "C"

@@ -314,13 +314,13 @@ __device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow
 typedef const __attribute__((address_space(4))) float* ctab_t;
 
 template <class F>
-__device__ __forceinline__ void with_table(const KArgs& a, int g, F&& f) {
+__device__ __forceinline__ void with_table(const KArgs& a, const float* base, int g, F&& f) {
   bool todo = true;
   while (true) {
     if (todo) {
       const int gu = __builtin_amdgcn_readfirstlane(g);
       if (g == gu) {
-        f((ctab_t)(a.tables + gu * a.tab_stride));
+        f((ctab_t)(base + gu * a.tab_stride));
         todo = false;
       }
     }

@@ -8,13 +8,12 @@ namespace pft {
 constexpr int kMaxVar = 6;
 constexpr int kColTile = 16;       // spectral columns per y/z block
 constexpr int kZmsTile = 8;        // spectral columns per block of the Green z pass
-constexpr int kXThreads = 256;     // threads per x-pass block
 
 // Quantities reduced per block (FP64 partial sums / extrema).
 constexpr int kQms = 6;                 // sum of stress (mixed condition)
 constexpr int kQres = 2;                // |eps_new - eps_old|^2, |eps_new|^2
 constexpr int kQac = 2 + 6 + 6 + kMaxVar;  // G_dw, G_me, sum sigma, sum eps, sum eta
-constexpr int kQgd = 1;                 // Parseval gradient sum
+constexpr int kQgd = 2;                 // Parseval gradient sum, spectral elastic energy
 
 // Status copied back to the host after each fixed-point iteration.
 struct Status {
@@ -35,12 +34,32 @@ struct DevState {
   double sig_target[6];  // load: prescribed mean stress
   double gd_cur;         // gradient energy sum of the current order parameter
   double stats[32];      // reductions of the last step (layout in the host)
+  double mean_kh[13];    // homogeneous spectral path: N<sigma> (6), N<eps> (6),
+                         // mean-field elastic energy sum (1)
+  double kh_drive[kMaxVar];  // L dt N <sigma> : eps0_a (mean of the elastic force)
   Status st;
 };
 
-// Everything a kernel needs, passed by value.
+// Per-instance reference medium: packed C0 (21) then its compliance S0 (36,
+// Voigt stress -> tensor-Voigt strain).
+constexpr int kRefStride = 21 + 36;
+
+// Per-instance tables of the homogeneous spectral path (one stiffness C in
+// the whole instance, linear h, no plastic strain). Float part: C packed (21),
+// sigma0_a = C : eps0_a (6 per variant), W_ab = eps0_a : C : eps0_b (V x V).
+// Double part: M = C in tensor-Voigt form (36), the inverse of its
+// stress-controlled block embedded in 6x6 (36), eps0_a (6 per variant).
+constexpr int kKhStride = 21 + 6 * kMaxVar + kMaxVar * kMaxVar;
+constexpr int kKhdStride = 36 + 36 + 6 * kMaxVar;
+constexpr int kKhMaxVar = 3;       // variants handled by the spectral path (2 V <= 6 spectra)
+
+// Everything a kernel needs, passed by value. A context holds ninst
+// independent instances of one grid size stacked along z: fields are
+// [comp][inst][z][y][x] and spectra [comp][inst][z][y][sh]; every x-pass block
+// and every z column lies in one instance.
 struct KArgs {
-  int nx, ny, nz, nh, nv;     // grid, nh = nx/2+1, number of variants
+  int nx, ny, nz, nh, nv;     // grid of one instance, nh = nx/2+1, number of variants
+  int ninst;                  // instances stacked along z
   int sh;                     // spectral row stride (complex elements, >= nh)
   int h_kind;
   int n_grains, tab_stride;
@@ -49,24 +68,27 @@ struct KArgs {
   double gx, gy, gz;          // (2 pi / (n dx))^2 per axis (energy)
   float inv_ntot;
   double tol;
-  float C0[21];               // reference stiffness, packed upper triangle
-  float S0[36];               // reference compliance: Voigt stress -> tensor-Voigt strain
-  double Bss[36];             // mixed-condition correction matrix (stress rows/cols)
+  const float* ref;           // [ninst][kRefStride] reference medium per instance
+  const double* bss;          // [ninst][36] mixed-condition correction matrix
+  const double* loads;        // [ninst][12] prescribed mean strain (6) and stress (6)
+  int tab_inst;               // table stride between instances (n_grains * tab_stride)
+  const float* kh;            // [ninst][kKhStride] or null
+  const double* khd;          // [ninst][kKhdStride] or null
   uint32_t stress_mask;
   // fields
-  float* eta;                 // [nv][nz][ny][nx]
-  float* eps;                 // [6][nz][ny][nx]
-  float* eps_prev;            // [6][nz][ny][nx] strain of the previous step
+  float* eta;                 // [nv][ninst][nz][ny][nx]
+  float* eps;                 // [6][ninst][nz][ny][nx]
+  float* eps_prev;            // [6][ninst][nz][ny][nx] strain of the previous step
   int iter_mode;              // first iteration of a step: 0 none, 1 keep the step's
                               // starting strain in eps_prev, 2 also start from the
                               // linear extrapolation 2 eps - eps_prev
-  float* sig;                 // [6][nz][ny][nx] (only written on request)
-  const float* epsp;          // [6][nz][ny][nx] or null
-  const uint8_t* gid;         // [nz][ny][nx] or null
-  const float* tables;        // [n_grains][tab_stride]
+  float* sig;                 // [6][ninst][nz][ny][nx] (only written on request)
+  const float* epsp;          // [6][ninst][nz][ny][nx] or null
+  const uint8_t* gid;         // [nz][ny][nx] or null (one instance only)
+  const float* tables;        // [ninst][n_grains][tab_stride]
   const float* rot;           // [n_grains][12] crystal->sample rotations (row-major 3x3), or null
   float xtab[21 + 27 * kMaxVar];  // crystal-frame table shared by every grain (rotation form)
-  float2* spec;               // [6][nz][ny][nh]
+  float2* spec;               // [6][ninst][nz][ny][sh]
   const float2* tw_xh;        // length nx/2
   const float2* tw_x;         // length nx
   const float2* tw_y;         // length ny
@@ -76,7 +98,7 @@ struct KArgs {
   double* part_ac;
   float* part_mm;             // per-block min/max of eta
   double* part_gd;
-  DevState* state;
+  DevState* state;            // [ninst]
   int save_stress;
 };
 
@@ -93,8 +115,7 @@ using pft::KArgs;
 int rows_per_block(int nx);
 int x_blocks(const KArgs& a);
 int z_blocks(const KArgs& a, int ncomp);
-hipError_t step_begin(const KArgs& a, const double* eps_target, const double* sig_target,
-                      hipStream_t s);
+hipError_t step_begin(const KArgs& a, hipStream_t s);
 hipError_t ms_x_forward(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
 hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s);
@@ -104,7 +125,9 @@ hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward(const KArgs& a, hipStream_t s);
 hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);  // mode 0 update, 1 energy only
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
-hipError_t ac_finalize(const KArgs& a, int init_only, hipStream_t s);
+hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s);  // 0 step, 1 init, 2 spectral path
+hipError_t kh_mean(const KArgs& a, hipStream_t s);
+hipError_t kh_z_update(const KArgs& a, hipStream_t s);
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s);
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s);
@@ -122,4 +145,8 @@ hipError_t ac_x_forward_v3(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v4(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v5(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v6(const KArgs& a, hipStream_t s);
+hipError_t kh_x_forward_v1(const KArgs& a, hipStream_t s);
+hipError_t kh_x_forward_v2(const KArgs& a, hipStream_t s);
+hipError_t kh_x_forward_v3(const KArgs& a, hipStream_t s);
+hipError_t kh_x_forward(const KArgs& a, hipStream_t s);
 }  // namespace pfl

@@ -24,9 +24,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
-  if (a.state->st.done) return;
+  const int rpi = a.nz * a.ny;
+  const DevState* st = a.state + blockIdx.x * ROWS / rpi;
+  if (st->st.done) return;
   const int t = threadIdx.x % T, p = threadIdx.x / T;
-  const int nrows = a.nz * a.ny;
+  const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const int nx = a.nx;
@@ -52,7 +54,6 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
         old_n[m] = valid ? *reinterpret_cast<const float2*>(a.eps + (c + 1) * vs + rbase + 2 * (t + T * m))
                          : make_float2(0.f, 0.f);
     }
-    const DevState* st = a.state;
     const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
     const float shift = (float)(st->ebar_cur[c] - base);
     const float w = c < 3 ? 1.f : 2.f;
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
-  const int nrows = a.nz * a.ny;
+  const int nrows = a.ninst * a.nz * a.ny;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
@@ -127,7 +128,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_raw(const KArgs a, cons
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
-  const int nrows = a.nz * a.ny;
+  const int nrows = a.ninst * a.nz * a.ny;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const int comp = blockIdx.y;
@@ -150,7 +151,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, floa
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int t = threadIdx.x % T, p = threadIdx.x / T;
-  const int nrows = a.nz * a.ny;
+  const int nrows = a.ninst * a.nz * a.ny;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const int comp = blockIdx.y;
@@ -178,8 +179,8 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_y(const KArgs a
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
-  const int z = blockIdx.y, comp = blockIdx.z;
-  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const int z = blockIdx.y, comp = blockIdx.z;  // z over all instances
+  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
   float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
@@ -205,7 +206,7 @@ __device__ __forceinline__ int xcd_logical(int b, int nb) {
 
 // Acoustic tensor K_ik(xi) = C0_ijkl xi_j xi_l of a column (xi_x, xi_y fixed,
 // xi_z = c varying) as K0 + c (K1 + c K2); entries in the order 00 01 02 11 12 22.
-__device__ __forceinline__ void acoustic_parts(const KArgs& a, float x0, float x1, float (&K0)[6],
+__device__ __forceinline__ void acoustic_parts(ctab_t C0, float x0, float x1, float (&K0)[6],
                                                float (&K1)[6], float (&K2)[6]) {
   constexpr int VI[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};
   constexpr int II[6] = {0, 0, 0, 1, 1, 2}, KK[6] = {0, 1, 2, 1, 2, 2};
@@ -217,12 +218,12 @@ __device__ __forceinline__ void acoustic_parts(const KArgs& a, float x0, float x
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
 #pragma unroll
-      for (int l = 0; l < 2; ++l) k0 += a.C0[sym6(VI[i][j], VI[k][l])] * xi[j] * xi[l];
-      k1 += (a.C0[sym6(VI[i][j], VI[k][2])] + a.C0[sym6(VI[i][2], VI[k][j])]) * xi[j];
+      for (int l = 0; l < 2; ++l) k0 += C0[sym6(VI[i][j], VI[k][l])] * xi[j] * xi[l];
+      k1 += (C0[sym6(VI[i][j], VI[k][2])] + C0[sym6(VI[i][2], VI[k][j])]) * xi[j];
     }
     K0[e] = k0;
     K1[e] = k1;
-    K2[e] = a.C0[sym6(VI[i][2], VI[k][2])];
+    K2[e] = C0[sym6(VI[i][2], VI[k][2])];
   }
 }
 
@@ -230,25 +231,32 @@ __device__ __forceinline__ void acoustic_parts(const KArgs& a, float x0, float x
 // the operator is homogeneous of degree 0): eps = -Gamma0 : tau / N with
 // Gamma0 : tau = sym(xi (x) K(xi)^{-1} (tau xi)); the prescribed mean at
 // xi = 0; the reference compliance at the ambiguous Nyquist wavevectors.
-__device__ __forceinline__ void green_apply(const KArgs& a, int kx, int ky, int kz, const float (&xi)[3],
-                                            const float (&K)[6], float2 (&tau)[6]) {
-  if (kx == 0 && ky == 0 && kz == 0) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) tau[c] = make_float2((float)a.state->ebar_next[c], 0.f);
-    return;
-  }
+// Wavevector with a Nyquist index and another non-zero, non-Nyquist index:
+// the continuous operator is not Hermitian-consistent there.
+__device__ __forceinline__ bool ambiguous_nyquist(const KArgs& a, int kx, int ky, int kz) {
   const bool nqx = kx == a.nx / 2, nqy = ky == a.ny / 2, nqz = kz == a.nz / 2;
   const bool otx = kx != 0 && !nqx, oty = ky != 0 && !nqy, otz = kz != 0 && !nqz;
+  return (nqx || nqy || nqz) && (otx || oty || otz);
+}
+
+__device__ __forceinline__ void green_apply(const KArgs& a, const DevState* st, ctab_t S0, int kx, int ky,
+                                            int kz, const float (&xi)[3], const float (&K)[6],
+                                            float2 (&tau)[6]) {
+  if (kx == 0 && ky == 0 && kz == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) tau[c] = make_float2((float)st->ebar_next[c], 0.f);
+    return;
+  }
   const float s = a.inv_ntot;
-  if ((nqx || nqy || nqz) && (otx || oty || otz)) {
+  if (ambiguous_nyquist(a, kx, ky, kz)) {
     float2 o[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
       float2 acc = make_float2(0.f, 0.f);
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        acc.x += a.S0[6 * i + j] * tau[j].x;
-        acc.y += a.S0[6 * i + j] * tau[j].y;
+        acc.x += S0[6 * i + j] * tau[j].x;
+        acc.y += S0[6 * i + j] * tau[j].y;
       }
       o[i] = acc;
     }
@@ -296,16 +304,18 @@ template <int N>
 __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a) {
   constexpr int E = Plan<N>::E, T = N / E, C = kZmsTile;
   __shared__ float2 lds[N * C];
-  if (a.state->st.done) return;
   const int ntile = (a.nh + C - 1) / C;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  const int tile = lb % ntile, ky = lb / ntile;
+  const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
+  const DevState* st = a.state + inst;
+  if (st->st.done) return;
+  const ctab_t ref = (ctab_t)(a.ref + (size_t)inst * kRefStride);
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = tile * C + cc;
   const bool valid = kx < a.nh;
-  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
   const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + (size_t)ky * a.sh + (valid ? kx : 0);
+  float2* col = a.spec + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[6][E];
 #pragma unroll
   for (int c = 0; c < 6; ++c)
@@ -318,7 +328,7 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
   const int kxv = valid ? kx : 0;
   float xi[3] = {(float)kxv / (float)a.nx, (float)signed_k(ky, a.ny) / (float)a.ny, 0.f};
   float K0[6], K1[6], K2[6];
-  acoustic_parts(a, xi[0], xi[1], K0, K1, K2);
+  acoustic_parts(ref, xi[0], xi[1], K0, K1, K2);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = t + T * m;
@@ -329,7 +339,7 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
     float2 tau[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau[c] = v[c][m];
-    green_apply(a, kxv, ky, kz, xi, K, tau);
+    green_apply(a, st, ref + 21, kxv, ky, kz, xi, K, tau);
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][m] = tau[c];
   }
@@ -354,10 +364,10 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
-  const int ky = blockIdx.y, q = blockIdx.z;
-  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const int ky = blockIdx.y % a.ny, inst = blockIdx.y / a.ny, q = blockIdx.z;
+  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
   const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + q * cs + (size_t)ky * a.sh + (valid ? kx : 0);
+  float2* col = a.spec + q * cs + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
@@ -366,7 +376,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const int sy = signed_k(ky, a.ny);
   const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
-  double en[1] = {0.0};
+  double en[kQgd] = {0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int sz = signed_k(t + T * m, a.nz);
@@ -386,8 +396,9 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
       for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
     }
   }
-  const size_t blk = ((size_t)q * gridDim.y + ky) * gridDim.x + blockIdx.x;
-  block_sum<1>(en, a.part_gd + blk);
+  // partials ordered [inst][variant][ky][tile] so each instance's are contiguous
+  const size_t blk = (((size_t)inst * a.nv + q) * a.ny + ky) * gridDim.x + blockIdx.x;
+  block_sum<kQgd>(en, a.part_gd + blk * kQgd);
 }
 
 template <int N, int DIR>
@@ -397,10 +408,10 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
-  const int ky = blockIdx.y, q = blockIdx.z;
-  const size_t cs = (size_t)a.nz * a.ny * a.sh;
+  const int ky = blockIdx.y % a.ny, inst = blockIdx.y / a.ny, q = blockIdx.z;
+  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
   const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + q * cs + (size_t)ky * a.sh + (valid ? kx : 0);
+  float2* col = a.spec + q * cs + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
@@ -411,18 +422,147 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
   }
 }
 
+// z pass of the homogeneous spectral path (one stiffness C per instance,
+// linear h, no plastic strain) for V variants. With a single stiffness the
+// equilibrium stress is known in closed form per wavevector, so no fixed
+// point is needed: for xi != 0,
+//   sigma_hat : eps0_a = -sum_b B_ab(n) f_hat_b,
+//   B_ab(n) = eps0_a : C : eps0_b - (sigma0_a n) . K(n)^{-1} (sigma0_b n),
+// with sigma0_a = C : eps0_a and K(n) = C n n; B = 0 at the ambiguous Nyquist
+// wavevectors (stress-free there, as in the fixed point). At xi = 0 the mean
+// strain follows from the mixed condition (k_kh_mean). Components 0..V-1 hold f_hat on
+// entry and the new order parameters' spectra on exit; V..2V-1 hold the
+// transform of f - L dt chem. FP64 partials: gradient sum of the new state
+// and the fluctuation part of the elastic energy.
+template <int V>
+__host__ __device__ constexpr int kh_tile() { return V == 1 ? kColTile : kZmsTile; }
+
+template <int N, int V>
+__global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a) {
+  constexpr int E = Plan<N>::E, T = N / E, C = kh_tile<V>();
+  __shared__ float2 lds[N * C];
+  const int ntile = (a.nh + C - 1) / C;
+  const int lb = xcd_logical(blockIdx.x, gridDim.x);
+  const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
+  const ctab_t kt = (ctab_t)(a.kh + (size_t)inst * kKhStride);
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  const int kx = tile * C + cc;
+  const bool valid = kx < a.nh;
+  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
+  const size_t zs = (size_t)a.ny * a.sh;
+  float2* col = a.spec + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
+  float2 th[V][E], rh[V][E];
+#pragma unroll
+  for (int q = 0; q < V; ++q)
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      th[q][m] = valid ? col[q * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+      rh[q][m] = valid ? col[(V + q) * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+    }
+  const ColView<C> view{lds + cc};
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    fft_pencil<N, 1>(th[q], view, t, a.tw_z);
+    fft_pencil<N, 1>(rh[q], view, t, a.tw_z);
+  }
+  const int kxv = valid ? kx : 0;
+  const int sy = signed_k(ky, a.ny);
+  const float xi0 = (float)kxv / (float)a.nx, xi1 = (float)sy / (float)a.ny;
+  float K0[6], K1[6], K2[6];
+  acoustic_parts(kt, xi0, xi1, K0, K1, K2);
+  // sigma0_a xi = u0_a + xi_z u1_a
+  float u0[V][3], u1[V][3];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const ctab_t s0 = kt + 21 + 6 * q;
+    u0[q][0] = s0[0] * xi0 + s0[5] * xi1;
+    u0[q][1] = s0[5] * xi0 + s0[1] * xi1;
+    u0[q][2] = s0[4] * xi0 + s0[3] * xi1;
+    u1[q][0] = s0[4];
+    u1[q][1] = s0[3];
+    u1[q][2] = s0[2];
+  }
+  const ctab_t W = kt + 21 + 6 * kMaxVar;
+  const float fx = (float)kxv * (float)kxv, fy = (float)sy * (float)sy;
+  const double wgt = (kxv == 0 || kxv == a.nx / 2) ? 1.0 : 2.0;
+  double en[kQgd] = {0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kz = t + T * m;
+    const int sz = signed_k(kz, a.nz);
+    const float xi2 = (float)sz / (float)a.nz;
+    const float fz = (float)sz * (float)sz;
+    float2 y[V];  // sum_b B_ab f_hat_b
+#pragma unroll
+    for (int q = 0; q < V; ++q) y[q] = make_float2(0.f, 0.f);
+    const bool dc = kxv == 0 && ky == 0 && kz == 0;
+    if (!dc && !ambiguous_nyquist(a, kxv, ky, kz)) {
+      float K[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) K[e] = K0[e] + xi2 * (K1[e] + xi2 * K2[e]);
+      const float A00 = K[3] * K[5] - K[4] * K[4];
+      const float A01 = K[2] * K[4] - K[1] * K[5];
+      const float A02 = K[1] * K[4] - K[2] * K[3];
+      const float A11 = K[0] * K[5] - K[2] * K[2];
+      const float A12 = K[1] * K[2] - K[0] * K[4];
+      const float A22 = K[0] * K[3] - K[1] * K[1];
+      const float rdet = 1.f / (K[0] * A00 + K[1] * A01 + K[2] * A02);
+      float u[V][3], nu[V][3];
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u[q][i] = u0[q][i] + xi2 * u1[q][i];
+        nu[q][0] = (A00 * u[q][0] + A01 * u[q][1] + A02 * u[q][2]) * rdet;
+        nu[q][1] = (A01 * u[q][0] + A11 * u[q][1] + A12 * u[q][2]) * rdet;
+        nu[q][2] = (A02 * u[q][0] + A12 * u[q][1] + A22 * u[q][2]) * rdet;
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+#pragma unroll
+        for (int r = 0; r < V; ++r) {
+          const float b = W[V * q + r] - (u[q][0] * nu[r][0] + u[q][1] * nu[r][1] + u[q][2] * nu[r][2]);
+          y[q].x += b * th[r][m].x;
+          y[q].y += b * th[r][m].y;
+        }
+      if (valid) {
+        double e2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < V; ++q) e2 += (double)th[q][m].x * y[q].x + (double)th[q][m].y * y[q].y;
+        en[1] += wgt * e2;
+      }
+    }
+    const float den = 1.f + a.ax * fx + a.ay * fy + a.az * fz;
+    const double x2 = a.gx * fx + a.gy * fy + a.gz * fz;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      float2 nv = make_float2((rh[q][m].x - a.LDt * y[q].x) / den, (rh[q][m].y - a.LDt * y[q].y) / den);
+      if (dc && valid) nv = make_float2(rh[q][m].x + (float)a.state[inst].kh_drive[q], 0.f);
+      if (valid) en[0] += wgt * x2 * ((double)nv.x * nv.x + (double)nv.y * nv.y);
+      th[q][m] = cscale(nv, a.inv_ntot);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) fft_pencil<N, -1>(th[q], view, t, a.tw_z);
+  if (valid) {
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+#pragma unroll
+      for (int m = 0; m < E; ++m) col[q * cs + (size_t)(t + T * m) * zs] = th[q][m];
+  }
+  block_sum<kQgd>(en, a.part_gd + (size_t)lb * kQgd);
+}
+
 // ------------------------------------------------------------ small kernels
-__global__ void k_step_begin(const KArgs a, double e0, double e1, double e2, double e3, double e4,
-                             double e5, double s0, double s1, double s2, double s3, double s4,
-                             double s5) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  DevState* st = a.state;
-  const double et[6] = {e0, e1, e2, e3, e4, e5};
-  const double sg[6] = {s0, s1, s2, s3, s4, s5};
+// One thread per instance: take the step's load, reset the iteration status.
+__global__ void k_step_begin(const KArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.ninst) return;
+  DevState* st = a.state + i;
+  const double* ld = a.loads + 12 * (size_t)i;
   for (int c = 0; c < 6; ++c) {
-    st->eps_target[c] = et[c];
-    st->sig_target[c] = sg[c];
-    if (!((a.stress_mask >> c) & 1u)) st->ebar_cur[c] = et[c];
+    st->eps_target[c] = ld[c];
+    st->sig_target[c] = ld[6 + c];
+    if (!((a.stress_mask >> c) & 1u)) st->ebar_cur[c] = ld[c];
     else if (a.iter_mode == 2) st->ebar_cur[c] = 2.0 * st->ebar_field[c] - st->ebar_prev[c];
   }
   st->st.done = 0;
@@ -446,12 +586,67 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   __syncthreads();
 }
 
+// Mean fields of the homogeneous spectral path, one block per instance:
+// <f_a> from the FP64 sums of the forward x pass; the mean strain from the
+// mixed condition, <sigma>_S = sigma_bar_S with <eps>_E = eps_bar_E and
+// <sigma> = C : (<eps> - sum_a <f_a> eps0_a); the mean elastic force
+// <sigma> : eps0_a (added to the xi = 0 coefficient by the z pass) and the
+// mean-field part of the elastic energy.
+__global__ __launch_bounds__(1024) void k_kh_mean(const KArgs a, int nblk) {
+  const int inst = blockIdx.x;
+  double s[kQac];
+  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk * kQac, nblk, s);
+  if (threadIdx.x != 0) return;
+  DevState* st = a.state + inst;
+  const double* kd = a.khd + (size_t)inst * kKhdStride;
+  const double ntot = (double)a.nx * a.ny * a.nz;
+  double es[6] = {0, 0, 0, 0, 0, 0};
+  for (int r = 0; r < a.nv; ++r) {
+    const double fr = s[14 + r] / ntot;
+    for (int c = 0; c < 6; ++c) es[c] += fr * kd[72 + 6 * r + c];
+  }
+  double d[6], rs[6];
+  for (int c = 0; c < 6; ++c) d[c] = ((a.stress_mask >> c) & 1u) ? 0.0 : st->eps_target[c] - es[c];
+  for (int i = 0; i < 6; ++i) {
+    double acc = st->sig_target[i];
+    for (int j = 0; j < 6; ++j) acc -= kd[6 * i + j] * d[j];
+    rs[i] = acc;
+  }
+  for (int i = 0; i < 6; ++i)
+    if ((a.stress_mask >> i) & 1u) {
+      double acc = 0.0;
+      for (int j = 0; j < 6; ++j)
+        if ((a.stress_mask >> j) & 1u) acc += kd[36 + 6 * i + j] * rs[j];
+      d[i] = acc;
+    }
+  double sg[6], e2 = 0.0;
+  for (int i = 0; i < 6; ++i) {
+    double acc = 0.0;
+    for (int j = 0; j < 6; ++j) acc += kd[6 * i + j] * d[j];
+    sg[i] = acc;
+  }
+  for (int c = 0; c < 6; ++c) {
+    st->mean_kh[c] = ntot * sg[c];
+    st->mean_kh[6 + c] = ntot * (d[c] + es[c]);
+    e2 += (c < 3 ? 1.0 : 2.0) * sg[c] * d[c];
+  }
+  st->mean_kh[12] = 0.5 * ntot * e2;
+  for (int q = 0; q < a.nv; ++q) {
+    double work = 0.0;
+    for (int c = 0; c < 6; ++c) work += (c < 3 ? 1.0 : 2.0) * sg[c] * kd[72 + 6 * q + c];
+    st->kh_drive[q] = (double)a.LDt * ntot * work;
+  }
+}
+
+// Finalize kernels: one block per instance; nblk partial blocks per instance.
 __global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
-  DevState* st = a.state;
+  const int inst = blockIdx.x;
+  DevState* st = a.state + inst;
   if (st->st.done) return;
   double s[kQms];
-  sum_partials<kQms>(a.part_ms, nblk, s);
+  sum_partials<kQms>(a.part_ms + (size_t)inst * nblk * kQms, nblk, s);
   if (threadIdx.x != 0) return;
+  const double* Bss = a.bss + 36 * (size_t)inst;
   const double ntot = (double)a.nx * a.ny * a.nz;
   double r[6];
   for (int c = 0; c < 6; ++c) r[c] = s[c] / ntot - st->sig_target[c];
@@ -459,7 +654,7 @@ __global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
     if ((a.stress_mask >> i) & 1u) {
       double d = 0.0;
       for (int j = 0; j < 6; ++j)
-        if ((a.stress_mask >> j) & 1u) d += a.Bss[6 * i + j] * r[j];
+        if ((a.stress_mask >> j) & 1u) d += Bss[6 * i + j] * r[j];
       st->ebar_next[i] = st->ebar_cur[i] - d;
     } else {
       st->ebar_next[i] = st->eps_target[i];
@@ -468,10 +663,11 @@ __global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
 }
 
 __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
-  DevState* st = a.state;
+  const int inst = blockIdx.x;
+  DevState* st = a.state + inst;
   if (st->st.done) return;
   double s[kQres];
-  sum_partials<kQres>(a.part_res, nblk, s);
+  sum_partials<kQres>(a.part_res + (size_t)inst * nblk * kQres, nblk, s);
   if (threadIdx.x != 0) return;
   const double r = s[1] > 0.0 ? sqrt(s[0] / s[1]) : (s[0] > 0.0 ? 1.0e300 : 0.0);
   st->st.residual = r;
@@ -485,29 +681,44 @@ __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
 }
 
 // Stats of the step (raw sums; the host scales them) and the gradient sum of
-// the new state. init_only: only the gradient sum.
-__global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int init_only) {
-  DevState* st = a.state;
-  double gd[1];
-  sum_partials<1>(a.part_gd, nblk_z, gd);
-  if (init_only) {
+// the new state. mode 0: fixed-point path; 1: only the gradient sum of the
+// initial state; 2: homogeneous spectral path (stress, strain and the
+// mean-field elastic energy from the z pass).
+__global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int mode) {
+  const int inst = blockIdx.x;
+  DevState* st = a.state + inst;
+  double gd[kQgd];
+  sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd);
+  if (mode == 1) {
     if (threadIdx.x == 0) st->gd_cur = gd[0];
     return;
   }
   double s[kQac];
-  sum_partials<kQac>(a.part_ac, nblk_x, s);
+  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, s);
   double bad[kQres];
-  sum_partials<kQres>(a.part_res, nblk_x, bad);
+  sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad);
   // extrema
   __shared__ float mm[2];
+  const float* pm = a.part_mm + 2 * (size_t)inst * nblk_x;
   float mn = 3.0e38f, mx = -3.0e38f;
   for (int b = threadIdx.x; b < nblk_x; b += blockDim.x) {
-    mn = fminf(mn, a.part_mm[2 * b]);
-    mx = fmaxf(mx, a.part_mm[2 * b + 1]);
+    mn = fminf(mn, pm[2 * b]);
+    mx = fmaxf(mx, pm[2 * b + 1]);
   }
   block_minmax(mn, mx, mm);
   if (threadIdx.x != 0) return;
   for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
+  if (mode == 2) {
+    const double ntot = (double)a.nx * a.ny * a.nz;
+    st->stats[1] = st->mean_kh[12] + 0.5 * gd[1] / ntot;
+    for (int c = 0; c < 6; ++c) {
+      st->stats[2 + c] = st->mean_kh[c];
+      st->stats[8 + c] = st->mean_kh[6 + c];
+    }
+    st->st.iters = 1;
+    st->st.residual = 0.0;
+    st->st.done = 1;
+  }
   st->stats[kQac] = st->gd_cur;
   st->stats[kQac + 1] = mm[0];
   st->stats[kQac + 2] = mm[1];
@@ -540,14 +751,24 @@ int rows_per_block(int nx) {
   return 0;
 }
 
-int x_blocks(const KArgs& a) {
+// x-pass blocks per instance (the rows of one block never straddle two
+// instances: every supported ny * nz is a multiple of the rows per block).
+static int x_blocks_inst(const KArgs& a) {
   const int r = rows_per_block(a.nx);
   return (a.nz * a.ny + r - 1) / r;
 }
 
-int z_blocks(const KArgs& a, int ncomp) {
-  return ((a.nh + kColTile - 1) / kColTile) * a.ny * ncomp;
+int x_blocks(const KArgs& a) { return a.ninst * x_blocks_inst(a); }
+
+// z-pass partial blocks per instance, for the widest use (the Allen-Cahn
+// pass over ncomp variants, or the spectral path's narrower tiles).
+static int z_blocks_inst(const KArgs& a, int ncomp) {
+  const int ac = ((a.nh + kColTile - 1) / kColTile) * a.ny * ncomp;
+  const int kh = ((a.nh + kZmsTile - 1) / kZmsTile) * a.ny;
+  return ac > kh ? ac : kh;
 }
+
+int z_blocks(const KArgs& a, int ncomp) { return a.ninst * z_blocks_inst(a, ncomp); }
 
 template <int N>
 static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
@@ -574,8 +795,8 @@ static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
     default: return hipErrorInvalidValue;     \
   }
 
-hipError_t step_begin(const KArgs& a, const double* e, const double* s, hipStream_t st) {
-  k_step_begin<<<1, 64, 0, st>>>(a, e[0], e[1], e[2], e[3], e[4], e[5], s[0], s[1], s[2], s[3], s[4], s[5]);
+hipError_t step_begin(const KArgs& a, hipStream_t st) {
+  k_step_begin<<<(a.ninst + 63) / 64, 64, 0, st>>>(a);
   return hipGetLastError();
 }
 
@@ -592,12 +813,12 @@ hipError_t ms_x_forward(const KArgs& a, hipStream_t s) {
 }
 
 hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s) {
-  k_fin_ms<<<1, 1024, 0, s>>>(a, x_blocks(a));
+  k_fin_ms<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
   return hipGetLastError();
 }
 
 hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.nz, ncomp);
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.nz * a.ninst, ncomp);
   if (dir > 0) {
     PF_SWITCH_N(a.ny, (k_y<N, 1><<<grid, col_block<N>(), 0, s>>>(a)));
   } else {
@@ -607,7 +828,7 @@ hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
 }
 
 hipError_t ms_z_green(const KArgs& a, hipStream_t s) {
-  const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny);
+  const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
   PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
   return hipGetLastError();
 }
@@ -619,7 +840,7 @@ hipError_t ms_x_inverse(const KArgs& a, hipStream_t s) {
 }
 
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
-  k_fin_res<<<1, 1024, 0, s>>>(a, x_blocks(a));
+  k_fin_res<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
   return hipGetLastError();
 }
 
@@ -636,7 +857,7 @@ hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
 }
 
 hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny, a.nv);
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, a.nv);
   PF_SWITCH_N(a.nz, (k_z_ac<N><<<grid, col_block<N>(), 0, s>>>(a, mode)));
   return hipGetLastError();
 }
@@ -647,8 +868,52 @@ hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t ac_finalize(const KArgs& a, int init_only, hipStream_t s) {
-  k_fin_ac<<<1, 1024, 0, s>>>(a, x_blocks(a), z_blocks(a, a.nv), init_only);
+// The z-pass partials of an instance: the Allen-Cahn pass writes
+// ntile16 * ny * nv blocks, the spectral path ntile(V) * ny; the finalize reads
+// exactly the count the preceding z pass wrote.
+static int z_written(const KArgs& a, int mode) {
+  if (mode == 2) {
+    const int C = a.nv == 1 ? kColTile : kZmsTile;
+    return ((a.nh + C - 1) / C) * a.ny;
+  }
+  return ((a.nh + kColTile - 1) / kColTile) * a.ny * a.nv;
+}
+
+hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s) {
+  k_fin_ac<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a), z_written(a, mode), mode);
+  return hipGetLastError();
+}
+
+hipError_t kh_x_forward(const KArgs& a, hipStream_t s) {
+  switch (a.nv) {
+    case 1: return kh_x_forward_v1(a, s);
+    case 2: return kh_x_forward_v2(a, s);
+    case 3: return kh_x_forward_v3(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t kh_mean(const KArgs& a, hipStream_t s) {
+  k_kh_mean<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
+  return hipGetLastError();
+}
+
+hipError_t kh_z_update(const KArgs& a, hipStream_t s) {
+  switch (a.nv) {
+    case 1: {
+      const dim3 grid(((a.nh + kColTile - 1) / kColTile) * a.ny * a.ninst);
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 1><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a)));
+    } break;
+    case 2: {
+      const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 2><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
+    } break;
+    case 3: {
+      const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 3><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
+    } break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -659,7 +924,7 @@ hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream
 }
 
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny, ncomp);
+  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, ncomp);
   if (dir > 0) {
     PF_SWITCH_N(a.nz, (k_z_raw<N, 1><<<grid, col_block<N>(), 0, s>>>(a)));
   } else {

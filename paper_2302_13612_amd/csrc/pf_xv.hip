@@ -43,8 +43,7 @@ __device__ __forceinline__ void extrapolate_strain(const KArgs& a, bool valid, s
 
 // Offset added to the strain read in the first iterate so its mean is the
 // iterate's prescribed mean.
-__device__ __forceinline__ float mean_shift(const KArgs& a, int c) {
-  const DevState* st = a.state;
+__device__ __forceinline__ float mean_shift(const KArgs& a, const DevState* st, int c) {
   const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
   return (float)(st->ebar_cur[c] - base);
 }
@@ -106,9 +105,9 @@ __device__ __forceinline__ void variant_terms(TP tab, const float (&sig_m)[6], c
 }
 
 template <int V, bool ROT, bool AC>
-__device__ __forceinline__ void eval_voxel(const KArgs& a, const float (&e)[6], const float (&et)[V],
-                                           const float (&ep)[6], int g, VoxelOut& o, float (&work)[V],
-                                           float (&quad)[V]) {
+__device__ __forceinline__ void eval_voxel(const KArgs& a, const float* tabs, const float (&e)[6],
+                                           const float (&et)[V], const float (&ep)[6], int g, VoxelOut& o,
+                                           float (&work)[V], float (&quad)[V]) {
   if constexpr (ROT) {
     float R[9];
     load_rotation(a, g, R);
@@ -122,7 +121,7 @@ __device__ __forceinline__ void eval_voxel(const KArgs& a, const float (&e)[6], 
     }
     if constexpr (AC) variant_terms<V>(a.xtab, o.sig_m, o.gam_m, work, quad);
   } else {
-    with_table(a, g, [&](auto tab) {
+    with_table(a, tabs, g, [&](auto tab) {
       Mat<V> m;
       constitutive<V>(e, et, ep, tab, a.h_kind, m);
 #pragma unroll
@@ -136,6 +135,17 @@ __device__ __forceinline__ void eval_voxel(const KArgs& a, const float (&e)[6], 
   }
 }
 
+// Chemical force of variant q: 2A f_q sum_{b != q} f_b (f_b - f_q), b over
+// the other variants and the matrix f_M = 1 - sum f.
+template <int V>
+__device__ __forceinline__ float chem_force(float A, const float (&et)[V], float fm, int q) {
+  float sm = fm * (fm - et[q]);
+#pragma unroll
+  for (int r = 0; r < V; ++r)
+    if (r != q) sm += et[r] * (et[r] - et[q]);
+  return 2.f * A * et[q] * sm;
+}
+
 // Fixed point, forward: polarisation tau = C(x):(eps - eps*) - C0:eps of
 // every voxel, FP64 sum of the stress, R2C of the six components.
 template <int M, int V, bool ROT>
@@ -143,16 +153,21 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[6 * ROWS * LROW];
-  if (a.state->st.done) return;
+  const int rpi = a.nz * a.ny;
+  const int inst = blockIdx.x * ROWS / rpi;
+  const DevState* st = a.state + inst;
+  if (st->st.done) return;
+  const ctab_t C0 = (ctab_t)(a.ref + (size_t)inst * kRefStride);
+  const float* tabs = a.tables + (size_t)inst * a.tab_inst;
   const int t = threadIdx.x % T, p = threadIdx.x / T;
-  const int nrows = a.nz * a.ny;
+  const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
   float shift[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) shift[c] = mean_shift(a, c);
+  for (int c = 0; c < 6; ++c) shift[c] = mean_shift(a, st, c);
   float fsum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's voxels, then FP64
 #pragma unroll 1
   for (int m = 0; m < E; ++m) {
@@ -173,11 +188,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
       for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
       VoxelOut vo;
       float work[V], quad[V];
-      eval_voxel<V, ROT, false>(a, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
+      eval_voxel<V, ROT, false>(a, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
       float ge[6], c0e[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) ge[c] = c < 3 ? e[c] : 2.f * e[c];
-      symv6(a.C0, ge, c0e);
+      symv6(C0, ge, c0e);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         o[half][c] = vo.sig[c] - c0e[c];
@@ -212,8 +227,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[V * ROWS * LROW];
+  const int rpi = a.nz * a.ny;
+  const int inst = blockIdx.x * ROWS / rpi;
+  const float* tabs = a.tables + (size_t)inst * a.tab_inst;
   const int t = threadIdx.x % T, p = threadIdx.x / T;
-  const int nrows = a.nz * a.ny;
+  const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
@@ -241,7 +259,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
       for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
       VoxelOut vo;
       float work[V], quad[V];
-      eval_voxel<V, ROT, true>(a, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
+      eval_voxel<V, ROT, true>(a, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
       float fm = 1.f;
 #pragma unroll
       for (int q = 0; q < V; ++q) fm -= et[q];
@@ -260,13 +278,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
       for (int q = 0; q < V; ++q) {
         // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
         const float mech = dh_of(et[q], a.h_kind) * (work[q] - 0.5f * quad[q]);
-        // chem_a = 2A f_a sum_{b != a} f_b (f_b - f_a), b over variants + matrix
-        float sm = fm * (fm - et[q]);
-#pragma unroll
-        for (int r = 0; r < V; ++r)
-          if (r != q) sm += et[r] * (et[r] - et[q]);
-        const float chem = 2.f * a.A * et[q] * sm;
-        o[half][q] = et[q] - a.LDt * (chem - mech);
+        o[half][q] = et[q] - a.LDt * (chem_force<V>(a.A, et, fm, q) - mech);
       }
       if (valid) {
         facc[0] += fdw;
@@ -309,6 +321,87 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
   block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
 
+
+#if PF_NV <= 3
+// Homogeneous spectral path, forward: R2C of f_a (components 0..V-1) and of
+// f_a - L dt chem_a (components V..2V-1); FP64 double-well and mean sums,
+// extrema of f. The elastic force is applied per wavevector in the z pass.
+template <int M, int V>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 stage[2 * V * ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.ninst * a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  float facc[1 + V];
+#pragma unroll
+  for (int q = 0; q <= V; ++q) facc[q] = 0.f;
+  float mn = 3.0e38f, mx = -3.0e38f;
+#pragma unroll 1
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    float2 h[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+      h[q] = valid ? *reinterpret_cast<const float2*>(a.eta + q * vs + rbase + 2 * k) : make_float2(0.f, 0.f);
+    float o[2][V];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      float et[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) et[q] = half ? h[q].y : h[q].x;
+      float fm = 1.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) fm -= et[q];
+      float fdw = 0.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        fdw += et[q] * et[q] * fm * fm;
+#pragma unroll
+        for (int r = q + 1; r < V; ++r) fdw += et[q] * et[q] * et[r] * et[r];
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) o[half][q] = et[q] - a.LDt * chem_force<V>(a.A, et, fm, q);
+      if (valid) {
+        facc[0] += fdw;
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          facc[1 + q] += et[q];
+          mn = fminf(mn, et[q]);
+          mx = fmaxf(mx, et[q]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      stage[(q * ROWS + p) * LROW + RowView::pad(k)] = h[q];
+      stage[((V + q) * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][q], o[1][q]);
+    }
+  }
+  const size_t cs = (size_t)nrows * a.sh;
+  float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+#pragma unroll 1
+  for (int c = 0; c < 2 * V; ++c) {
+    float2* slab = stage + (c * ROWS + p) * LROW;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, a.tw_xh, a.tw_x);
+  }
+  double acc[kQac];
+#pragma unroll
+  for (int q = 0; q < kQac; ++q) acc[q] = 0.0;
+  acc[0] = (double)facc[0];
+#pragma unroll
+  for (int q = 0; q < V; ++q) acc[14 + q] = (double)facc[1 + q];
+  block_sum<kQac>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
+  block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
+}
+#endif
 }  // namespace pft
 
 #define PF_CAT2(a, b) a##b
@@ -337,6 +430,14 @@ hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
   }
   return hipGetLastError();
 }
+
+#if PF_NV <= 3
+hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_kh<M, PF_NV><<<grid, xthreads<M>(), 0, s>>>(a)));
+  return hipGetLastError();
+}
+#endif
 
 hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));

@@ -15,6 +15,9 @@ Workload recipes (grids follow the paper's FFT grids: a 1:1:2 box like the
 * polycrystal: 256^3, 64 periodic Voronoi grains with uniformly random
   orientations, six twin variants, nuclei at 5% of the grain-pair
   interfaces, Gaussian-random-field plastic strain, fixed load.
+* rve_batch: an ensemble of 256 single-crystal cubes of edge 32, 48, 64 or 96
+  (uniform), each with a random orientation, homogeneous stiffness, one to
+  four spherical nuclei and its own uniaxial strain along x.
 """
 
 import numpy as np
@@ -261,3 +264,28 @@ def polycrystal(shape=(256, 256, 256), n_grains=64, seed=3, n_var=6,
         eps_bar=eps_bar, sig_bar=np.zeros(6),
         stress_mask=np.array([False, True, True, True, True, True]),
         ms_tol=1e-6, ms_max_iter=50, **params)
+
+
+def rve_batch(n_inst=256, seed=4, sizes=(32, 48, 64, 96), radius=4.0, max_nuclei=4,
+              strain_range=(-5e-3, -1e-3), steps=512, save_every=16):
+    """Ensemble of independent single-crystal cubes (one twin variant each,
+    chosen by the caller: the one most favoured by compression along x)."""
+    rng = rng_for(seed)
+    insts = []
+    for _ in range(n_inst):
+        n = int(sizes[rng.integers(len(sizes))])
+        shape = (n, n, n)
+        R = random_rotations(1, rng)[0]
+        k = int(rng.integers(1, max_nuclei + 1))
+        eta = np.zeros(shape, dtype=bool)
+        for _ in range(k):
+            eta |= sphere(shape, tuple(rng.random(3) * n), radius)
+        eps_bar = np.zeros(6)
+        eps_bar[0] = rng.uniform(*strain_range)
+        insts.append(dict(shape=shape, rotation=R, eta0=eta[None].astype(np.float32), eps_bar=eps_bar,
+                          n_nuclei=k))
+    return dict(
+        name="rve_batch", instances=insts, n_var=1, homogeneous=True, gid=None, eps_p=None,
+        steps=steps, save_every=save_every, sig_bar=np.zeros(6),
+        stress_mask=np.array([False, True, True, True, True, True]),
+        ms_tol=1e-6, ms_max_iter=1, **MG_PARAMS)

@@ -93,3 +93,38 @@ def small_polycrystal(shape=(32, 32, 32), n_grains=6, seed=5, n_var=6):
 
 def small_lamellae(shape=(64, 32, 32), seed=7):
     return inputs.single_crystal_lamellae(shape=shape, seed=seed, radius=6.0)
+
+
+def max_sf_variant(R):
+    """Variant (0..5) whose eigenstrain shortens x the most: the one most
+    favoured by compression along x (ties: lowest index), from the oracle."""
+    _, _, e0 = cr.mg_tables(np.asarray(R)[None], list(range(6)))
+    return int(np.argmin(e0[0, :, 0, 0]))
+
+
+def batch_instance_cfg(batch, i, variant=None):
+    """Single-instance recipe (oracle_run / gpu_solver form) of instance i."""
+    inst = batch["instances"][i]
+    v = max_sf_variant(inst["rotation"]) if variant is None else variant
+    keys = ("A", "kappa", "L", "dt", "dx", "stress_mask", "ms_tol", "ms_max_iter", "sig_bar")
+    cfg = {k: batch[k] for k in keys}
+    cfg.update(name=f"rve{i}", shape=inst["shape"], n_var=1, variant_ids=[v], rotations=inst["rotation"][None],
+               homogeneous=True, gid=None, eta0=inst["eta0"], eps_p=None, eps_bar=inst["eps_bar"])
+    return cfg
+
+
+def gpu_batch(batch, idx, variants, device="cuda", **kw):
+    """BatchSolver over instances idx of a batch recipe (library tables in
+    the crystal frame, turned by each instance's rotation)."""
+    import torch
+    from paper_2302_13612_amd import binding
+    insts = []
+    for i, v in zip(idx, variants):
+        inst = batch["instances"][i]
+        Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], [v])
+        Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
+        insts.append(dict(eta0=torch.from_numpy(inst["eta0"]).to(device), tables=(Cg, Cv, e0),
+                          rotation=inst["rotation"]))
+    return binding.BatchSolver(insts, batch["dx"], batch["A"], batch["kappa"], batch["L"], batch["dt"],
+                               batch["stress_mask"], ms_tol=batch["ms_tol"], ms_max_iter=batch["ms_max_iter"],
+                               **kw)
