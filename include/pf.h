@@ -208,6 +208,71 @@ int pf_batch_fields(pf_ctx *ctx, int32_t inst, int32_t which, int32_t set,
 int pf_batch_stats(pf_ctx *ctx, int32_t inst, pf_stats *out);
 int pf_batch_size(const pf_ctx *ctx);  /* number of instances, 0 for NULL */
 
+/* ------------------------------------------------------------ surrogate
+ * A Fourier neural operator (Li et al. 2021) standing in for S plain steps of
+ * a one-variant homogeneous context (a learned macro stepper; the paper has
+ * none: its Sec. 3 notes that small PF time steps dominate the cost):
+ *   v_0 = P [f, c] + p;  v_l = GELU(W_l v + b_l + K_l v), l = 1..4;
+ *   f~  = f + Q_2 GELU(Q_1 v_4 + q_1) + q_2,
+ * K v = inverse real 3D transform of R(k) times the transform of v on the
+ * kept modes kx < m, ky, kz in [0, m) u [n - m, n) (ordered positive, then
+ * negative), zero elsewhere; forward transform unnormalised, inverse with
+ * 1 / (nx ny nz); GELU(x) = x Phi(x). c: 7 constant conditioning values
+ * (sample-frame eps0 / gamma_tw in tensor-Voigt order, applied strain /
+ * 5e-3). The forward pass runs with BF16 activations and weights and FP32
+ * accumulation (matrix cores for the channel mixing and the projection).
+ *
+ * The prediction is accepted when the backward-Euler residual of the macro
+ * step, rho = max |f~ - f^n + S L dt dF/df(f~)| with dF/df = chem
+ * - 2 kappa lap f - mech at the equilibrium of f~, is <= tol; otherwise the
+ * context falls back to S plain steps from f^n. Supported: a single-instance
+ * context, n_var = 1, the homogeneous spectral path (one stiffness, linear h,
+ * no plastic strain), nx a multiple of 32, every axis <= 128, modes <= 16. */
+typedef struct pf_fno pf_fno;
+
+typedef struct {
+  int32_t width, modes, hidden, n_layers, n_cond;  /* 32, m, 128, 4, 7        */
+  const float *P;    /* host [width][1 + n_cond] lift (column 0: f)          */
+  const float *p;    /* host [width]                                        */
+  const float *W;    /* host [n_layers][width][width] (out, in)             */
+  const float *b;    /* host [n_layers][width]                              */
+  const float *R;    /* host [n_layers][width out][width in][2m kz][2m ky][m kx][2]
+                        complex (re, im), kz / ky in kept order              */
+  const float *Q1;   /* host [hidden][width]                                */
+  const float *q1;   /* host [hidden]                                       */
+  const float *Q2;   /* host [hidden]                                       */
+  float q2;
+} pf_fno_weights;
+
+typedef struct {     /* accumulated by pf_fno_advance (zero it first)       */
+  int32_t accepted, rejected;
+  double rho_max_accepted, rho_min_rejected, last_rho;
+} pf_fno_report;
+
+/* Device workspace bytes of a stepper on this context with m modes. */
+int pf_fno_workspace_size(const pf_ctx *ctx, int32_t modes, size_t *bytes);
+/* Convert (BF16) and upload the weights into the caller's workspace. */
+int pf_fno_init(pf_ctx *ctx, const pf_fno_weights *w, void *workspace,
+                size_t ws_bytes, pf_fno **out);
+/* eta_out = f~(eta_in) for conditioning cond[7]; device buffers
+ * [nz][ny][nx], not aliased; on the context's stream. */
+int pf_fno_forward(pf_fno *fno, const double *cond, const float *eta_in,
+                   float *eta_out);
+/* n_calls macro steps of steps_per_call plain steps each on the context's
+ * order parameter: predict, check rho <= tol (one wait on the stream per
+ * call), else fall back to plain steps under load. */
+int pf_fno_advance(pf_fno *fno, int32_t n_calls, int32_t steps_per_call,
+                   const double *cond, const pf_load *load, double tol,
+                   pf_fno_report *report);
+int pf_fno_destroy(pf_fno *fno);
+
+/* Backward-Euler residual of a macro step of n_steps plain steps that ends
+ * at the context's current order parameter, from eta_prev (device
+ * [nz][ny][nx]) under load: *rho = max |f - eta_prev + n_steps L dt dF/df(f)|.
+ * Homogeneous single-instance contexts; waits on the stream. */
+int pf_macro_residual(pf_ctx *ctx, const float *eta_prev, int32_t n_steps,
+                      const pf_load *load, double *rho);
+
 /* Host helper: sample-frame tables of Mg tension twins for n_grains grains.
  * Crystal frame x || [10-10], y || [-12-10], z || [0001]; c_over_a and
  * gamma_tw as in Sec. 2.1 (1.633, 0.129); C_hex = {C11, C12, C13, C33, C44}

@@ -437,3 +437,115 @@ class BatchSolver:
             self.close()
         except Exception:
             pass
+
+
+class PfFnoWeights(ctypes.Structure):
+    _fp = ctypes.POINTER(ctypes.c_float)
+    _fields_ = [
+        ("width", ctypes.c_int32), ("modes", ctypes.c_int32), ("hidden", ctypes.c_int32),
+        ("n_layers", ctypes.c_int32), ("n_cond", ctypes.c_int32),
+        ("P", _fp), ("p", _fp), ("W", _fp), ("b", _fp), ("R", _fp),
+        ("Q1", _fp), ("q1", _fp), ("Q2", _fp), ("q2", ctypes.c_float),
+    ]
+
+
+class PfFnoReport(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("rejected", ctypes.c_int32),
+                ("rho_max_accepted", ctypes.c_double), ("rho_min_rejected", ctypes.c_double),
+                ("last_rho", ctypes.c_double)]
+
+
+def _declare_fno(lib):
+    if getattr(lib, "_fno_declared", False):
+        return
+    vp, i32 = ctypes.c_void_p, ctypes.c_int32
+    lib.pf_fno_workspace_size.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pf_fno_init.argtypes = [vp, ctypes.POINTER(PfFnoWeights), vp, ctypes.c_size_t, ctypes.POINTER(vp)]
+    lib.pf_fno_forward.argtypes = [vp, _dp, vp, vp]
+    lib.pf_fno_advance.argtypes = [vp, i32, i32, _dp, ctypes.POINTER(PfLoad), ctypes.c_double,
+                                   ctypes.POINTER(PfFnoReport)]
+    lib.pf_fno_destroy.argtypes = [vp]
+    lib.pf_macro_residual.argtypes = [vp, vp, i32, ctypes.POINTER(PfLoad), ctypes.POINTER(ctypes.c_double)]
+    for name in ("pf_fno_workspace_size", "pf_fno_init", "pf_fno_forward", "pf_fno_advance", "pf_fno_destroy",
+                 "pf_macro_residual"):
+        getattr(lib, name).restype = ctypes.c_int
+    lib._fno_declared = True
+
+
+def macro_residual(solver, eta_prev, n_steps, eps_bar, sig_bar=None):
+    """Backward-Euler residual max of the macro step ending at the solver's
+    current order parameter (see pf_macro_residual)."""
+    lib = solver.lib
+    _declare_fno(lib)
+    ld = PfLoad()
+    _fill_load(ld, eps_bar, sig_bar, None, 0)
+    prev = eta_prev.contiguous()
+    rho = ctypes.c_double()
+    solver._check(lib.pf_macro_residual(solver.ctx, prev.data_ptr(), int(n_steps), ctypes.byref(ld),
+                                        ctypes.byref(rho)), "pf_macro_residual")
+    return rho.value
+
+
+class Fno:
+    """Learned macro stepper bound to a single-instance Solver.
+
+    params: dict of float arrays (P (32, 8), p (32), W (4, 32, 32), b (4, 32),
+    R complex (4, 32, 32, 2m, 2m, m), Q1 (128, 32), q1 (128), Q2 (1, 128) or
+    (128,), q2 scalar) -- the layout of the checker's parameter set.
+    """
+
+    def __init__(self, solver, params):
+        torch = solver.torch
+        self.solver = solver
+        self.lib = solver.lib
+        _declare_fno(self.lib)
+        R = np.asarray(params["R"])
+        m = R.shape[-1]
+        f32 = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float32))  # noqa: E731
+        self._arrs = dict(P=f32(params["P"]), p=f32(params["p"]), W=f32(params["W"]), b=f32(params["b"]),
+                          R=f32(np.stack([R.real, R.imag], axis=-1)), Q1=f32(params["Q1"]),
+                          q1=f32(params["q1"]), Q2=f32(np.asarray(params["Q2"]).reshape(-1)))
+        w = PfFnoWeights()
+        w.width, w.modes, w.hidden = self._arrs["P"].shape[0], m, self._arrs["Q1"].shape[0]
+        w.n_layers, w.n_cond = self._arrs["W"].shape[0], self._arrs["P"].shape[1] - 1
+        for k, a in self._arrs.items():
+            setattr(w, k, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        w.q2 = float(np.asarray(params["q2"]).reshape(-1)[0])
+        nbytes = ctypes.c_size_t()
+        solver._check(self.lib.pf_fno_workspace_size(solver.ctx, m, ctypes.byref(nbytes)), "pf_fno_workspace_size")
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=solver.workspace.device)
+        h = ctypes.c_void_p()
+        solver._check(self.lib.pf_fno_init(solver.ctx, ctypes.byref(w), self.workspace.data_ptr(), nbytes.value,
+                                           ctypes.byref(h)), "pf_fno_init")
+        self.h = h
+
+    def forward(self, cond, eta_in):
+        t = self.solver.torch
+        eta_in = eta_in.contiguous()
+        out = t.empty_like(eta_in)
+        c = np.ascontiguousarray(np.asarray(cond, dtype=np.float64))
+        self.solver._check(self.lib.pf_fno_forward(self.h, _ptr(c), eta_in.data_ptr(), out.data_ptr()),
+                           "pf_fno_forward")
+        return out
+
+    def advance(self, n_calls, steps_per_call, cond, eps_bar, sig_bar=None, tol=1e-3):
+        ld = PfLoad()
+        _fill_load(ld, eps_bar, sig_bar, None, 0)
+        rep = PfFnoReport()
+        c = np.ascontiguousarray(np.asarray(cond, dtype=np.float64))
+        self.solver._check(self.lib.pf_fno_advance(self.h, int(n_calls), int(steps_per_call), _ptr(c),
+                                                   ctypes.byref(ld), float(tol), ctypes.byref(rep)),
+                           "pf_fno_advance")
+        return {"accepted": rep.accepted, "rejected": rep.rejected, "rho_max_accepted": rep.rho_max_accepted,
+                "rho_min_rejected": rep.rho_min_rejected, "last_rho": rep.last_rho}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pf_fno_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -24,6 +24,7 @@
 
 #include "../../include/pf.h"
 #include "pf_device.hpp"
+#include "pf_fno.hpp"
 
 void pf_rotate_voigt(const double* Cv, const double* R9, double* out);  // pf_crystal.cpp
 
@@ -509,10 +510,10 @@ int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
 int kh_step(pf_ctx* c, const Group& g, hipStream_t s) {
   const KArgs& a = g.args;
   PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(a, s); }));
-  PF_TRY(launch(c, s, "kh_x_forward", [&] { return pfl::kh_x_forward(a, s); }));
+  PF_TRY(launch(c, s, "kh_x_forward", [&] { return pfl::kh_x_forward(a, 0, s); }));
   PF_TRY(launch(c, s, "kh_mean", [&] { return pfl::kh_mean(a, s); }));
   PF_TRY(launch(c, s, "kh_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
-  PF_TRY(launch(c, s, "kh_z_update", [&] { return pfl::kh_z_update(a, s); }));
+  PF_TRY(launch(c, s, "kh_z_update", [&] { return pfl::kh_z_update(a, 0, s); }));
   PF_TRY(launch(c, s, "kh_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
   PF_TRY(launch(c, s, "kh_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
   PF_TRY(launch(c, s, "kh_finalize", [&] { return pfl::ac_finalize(a, 2, s); }));
@@ -569,6 +570,53 @@ int run_graph(pf_ctx* c, int n_steps, const std::vector<char>& use_kh, const std
   }
   for (int n = 0; n < n_steps; ++n)
     if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  return PF_OK;
+}
+
+// Loads -> device through the pinned staging buffer (free at the start of a
+// call: every call that used it ended with a synchronisation of the stream).
+int upload_loads(pf_ctx* c, const pf_load* loads) {
+  hipError_t e;
+  bool changed = !c->loads_uploaded;
+  for (int i = 0; i < c->n_inst; ++i) {
+    double* h = c->host_loads + 12 * (size_t)i;
+    for (int k = 0; k < 6; ++k) {
+      if (h[k] != loads[i].eps_bar[k] || h[6 + k] != loads[i].sig_bar[k]) changed = true;
+    }
+  }
+  if (changed) {
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "stream sync");
+    for (auto& g : c->groups) {
+      for (size_t j = 0; j < g.members.size(); ++j) {
+        double* h = c->host_loads + 12 * (size_t)g.members[j];
+        const pf_load& ld = loads[g.members[j]];
+        for (int k = 0; k < 6; ++k) {
+          h[k] = ld.eps_bar[k];
+          h[6 + k] = ld.sig_bar[k];
+        }
+      }
+    }
+    for (auto& g : c->groups)
+      for (size_t j = 0; j < g.members.size(); ++j) {
+        e = hipMemcpyAsync(const_cast<double*>(g.args.loads) + 12 * j, c->host_loads + 12 * (size_t)g.members[j],
+                           sizeof(double) * 12, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(c, e, "load copy");
+      }
+    c->loads_uploaded = true;
+  }
+  return PF_OK;
+}
+
+// Gradient energy of the group's current order parameters (reported by the
+// next step's stats) after they were replaced from outside a step.
+int refresh_gradient_energy(pf_ctx* c, const Group& g) {
+  const KArgs& a = g.args;
+  hipStream_t s = c->stream;
+  PF_TRY(launch(c, s, "init_x", [&] { return pfl::raw_x_forward(a, a.eta, c->nv, s); }));
+  PF_TRY(launch(c, s, "init_y", [&] { return pfl::y_pass(a, c->nv, 1, s); }));
+  PF_TRY(launch(c, s, "init_z", [&] { return pfl::ac_z_update(a, 1, s); }));
+  PF_TRY(launch(c, s, "init_fin", [&] { return pfl::ac_finalize(a, 1, s); }));
   return PF_OK;
 }
 
@@ -830,36 +878,7 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
     }
     g.epsp_given = true;
   }
-  // loads -> device (the pinned staging buffer is free: every call ends with
-  // a synchronisation of the stream)
-  bool changed = !c->loads_uploaded;
-  for (int i = 0; i < c->n_inst; ++i) {
-    double* h = c->host_loads + 12 * (size_t)i;
-    for (int k = 0; k < 6; ++k) {
-      if (h[k] != loads[i].eps_bar[k] || h[6 + k] != loads[i].sig_bar[k]) changed = true;
-    }
-  }
-  if (changed) {
-    e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "stream sync");
-    for (auto& g : c->groups) {
-      for (size_t j = 0; j < g.members.size(); ++j) {
-        double* h = c->host_loads + 12 * (size_t)g.members[j];
-        const pf_load& ld = loads[g.members[j]];
-        for (int k = 0; k < 6; ++k) {
-          h[k] = ld.eps_bar[k];
-          h[6 + k] = ld.sig_bar[k];
-        }
-      }
-    }
-    for (auto& g : c->groups)
-      for (size_t j = 0; j < g.members.size(); ++j) {
-        e = hipMemcpyAsync(const_cast<double*>(g.args.loads) + 12 * j, c->host_loads + 12 * (size_t)g.members[j],
-                           sizeof(double) * 12, hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return hip_fail(c, e, "load copy");
-      }
-    c->loads_uploaded = true;
-  }
+  PF_TRY(upload_loads(c, loads));
   // path of each group
   std::vector<char> use_kh(c->groups.size());
   bool graphable = !save_stress && !c->prof_on && n_steps > 0;
@@ -998,15 +1017,7 @@ int pf_batch_fields(pf_ctx* c, int32_t inst, int32_t which, int32_t set, float* 
                        : hipMemcpyAsync(ext, slot, g.nvox * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "pf_fields");
   }
-  if (set && which == PF_FIELD_ETA) {
-    // gradient energy of the new state (reported by the next step's stats)
-    const KArgs& a = g.args;
-    hipStream_t s = c->stream;
-    PF_TRY(launch(c, s, "init_x", [&] { return pfl::raw_x_forward(a, a.eta, c->nv, s); }));
-    PF_TRY(launch(c, s, "init_y", [&] { return pfl::y_pass(a, c->nv, 1, s); }));
-    PF_TRY(launch(c, s, "init_z", [&] { return pfl::ac_z_update(a, 1, s); }));
-    PF_TRY(launch(c, s, "init_fin", [&] { return pfl::ac_finalize(a, 1, s); }));
-  }
+  if (set && which == PF_FIELD_ETA) PF_TRY(refresh_gradient_energy(c, g));
   return PF_OK;
 }
 
@@ -1143,5 +1154,256 @@ const char* pf_last_error(const pf_ctx* c) {
 }
 
 int pf_batch_size(const pf_ctx* c) { return c ? c->n_inst : 0; }
+
+// ---------------------------------------------------------------- surrogate
+int pf_macro_residual(pf_ctx* c, const float* eta_prev, int32_t n_steps, const pf_load* load, double* rho) {
+  if (!c) return PF_EINVAL;
+  if (!eta_prev || !load || !rho || n_steps < 1) return fail(c, PF_EINVAL, "pf_macro_residual: bad arguments");
+  if (c->n_inst != 1) return fail(c, PF_EUNSUPPORTED, "pf_macro_residual: single-instance contexts only");
+  Group& g = c->groups[0];
+  if (!g.homogeneous || g.epsp_given)
+    return fail(c, PF_EUNSUPPORTED, "pf_macro_residual: needs one stiffness, linear h, n_var <= 3, no plastic strain");
+  PF_TRY(upload_loads(c, load));
+  const KArgs& a = g.args;
+  hipStream_t s = c->stream;
+  PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(a, s); }));
+  PF_TRY(launch(c, s, "res_x_forward", [&] { return pfl::kh_x_forward(a, 1, s); }));
+  PF_TRY(launch(c, s, "res_mean", [&] { return pfl::kh_mean(a, s); }));
+  PF_TRY(launch(c, s, "res_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
+  PF_TRY(launch(c, s, "res_z", [&] { return pfl::kh_z_update(a, 1, s); }));
+  PF_TRY(launch(c, s, "res_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
+  PF_TRY(launch(c, s, "res_x_inverse", [&] { return pfl::kh_residual(a, eta_prev, n_steps, s); }));
+  double r = 0.0;
+  hipError_t e = hipMemcpyAsync(&r, &a.state->resid_max, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return hip_fail(c, e, "residual copy");
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(c, e, "residual sync");
+  *rho = r;
+  return PF_OK;
+}
+
+}  // extern "C"
+
+struct pf_fno {
+  pf_ctx* ctx;
+  pfn::FArgs fa;
+  std::vector<float> P, p;   // lift weights kept on the host (the constant part is folded per call)
+  float* eta_prev;
+  float* eta_pred;
+};
+
+namespace {
+
+struct FnoLayout {
+  size_t va, vb, x1, y1, x2, y2, tw, W, b, R, Q1, q1, Q2, prev, pred, total;
+};
+
+FnoLayout fno_layout(int nx, int ny, int nz, int m) {
+  FnoLayout L{};
+  const size_t nvox = (size_t)nx * ny * nz;
+  const size_t x1 = (size_t)nz * ny * m * 2 * pfn::kC, x2 = (size_t)nz * 2 * m * m * 2 * pfn::kC;
+  const size_t rl = (size_t)(2 * m) * (2 * m) * m * pfn::kC * pfn::kC * 2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align_up(off + bytes); return o; };
+  L.va = take(nvox * pfn::kC * 2);
+  L.vb = take(nvox * pfn::kC * 2);
+  L.x1 = take(x1 * 4);
+  L.y1 = take(x1 * 4);
+  L.x2 = take(x2 * 4);
+  L.y2 = take(x2 * 4);
+  L.tw = take((size_t)(nx + ny + nz) * 8);
+  L.W = take((size_t)pfn::kLayers * pfn::kC * pfn::kC * 2);
+  L.b = take((size_t)pfn::kLayers * pfn::kC * 4);
+  L.R = take((size_t)pfn::kLayers * rl * 2);
+  L.Q1 = take((size_t)pfn::kH * pfn::kC * 2);
+  L.q1 = take((size_t)pfn::kH * 4);
+  L.Q2 = take((size_t)pfn::kH * 4);
+  L.prev = take(nvox * 4);
+  L.pred = take(nvox * 4);
+  L.total = off;
+  return L;
+}
+
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+int fno_check(const pf_ctx* c, int32_t modes, std::string& why) {
+  if (!c) { why = "null context"; return PF_EINVAL; }
+  if (c->n_inst != 1) { why = "single-instance contexts only"; return PF_EUNSUPPORTED; }
+  const Group& g = c->groups[0];
+  if (c->nv != 1) { why = "one order parameter only"; return PF_EUNSUPPORTED; }
+  if (g.nx % 32 != 0 || g.nx > 128 || g.ny > 128 || g.nz > 128) {
+    why = "grid: nx a multiple of 32, every axis <= 128";
+    return PF_EUNSUPPORTED;
+  }
+  if (modes < 1 || modes > pfn::kMaxModes || 2 * modes > g.ny || 2 * modes > g.nz || modes > g.nx / 2) {
+    why = "modes must be in 1..16 with 2 modes <= ny, nz and modes <= nx / 2";
+    return PF_EINVAL;
+  }
+  return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_fno_workspace_size(const pf_ctx* c, int32_t modes, size_t* bytes) {
+  std::string why;
+  if (!bytes) return PF_EINVAL;
+  const int rc = fno_check(c, modes, why);
+  if (rc != PF_OK) return rc;
+  const Group& g = c->groups[0];
+  *bytes = fno_layout(g.nx, g.ny, g.nz, modes).total;
+  return PF_OK;
+}
+
+int pf_fno_init(pf_ctx* c, const pf_fno_weights* w, void* workspace, size_t ws_bytes, pf_fno** out) {
+  if (!c || !out) return PF_EINVAL;
+  *out = nullptr;
+  std::string why;
+  if (!w) return fail(c, PF_EINVAL, "pf_fno_init: null weights");
+  if (w->width != pfn::kC || w->hidden != pfn::kH || w->n_layers != pfn::kLayers || w->n_cond != pfn::kCond)
+    return fail(c, PF_EUNSUPPORTED, "pf_fno_init: this build supports width 32, hidden 128, 4 layers, 7 "
+                                    "conditioning channels");
+  int rc = fno_check(c, w->modes, why);
+  if (rc != PF_OK) return fail(c, rc, "pf_fno_init: " + why);
+  if (!w->P || !w->p || !w->W || !w->b || !w->R || !w->Q1 || !w->q1 || !w->Q2)
+    return fail(c, PF_EINVAL, "pf_fno_init: missing weights");
+  const Group& g = c->groups[0];
+  const int m = w->modes;
+  const FnoLayout L = fno_layout(g.nx, g.ny, g.nz, m);
+  if (!workspace || ws_bytes < L.total) return fail(c, PF_ENOMEM, "pf_fno_init: workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(c, PF_EINVAL, "pf_fno_init: workspace must be 256-byte aligned");
+  pf_fno* f = new (std::nothrow) pf_fno();
+  if (!f) return PF_ENOMEM;
+  char* ws = static_cast<char*>(workspace);
+  pfn::FArgs& a = f->fa;
+  std::memset(&a, 0, sizeof(a));
+  a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.m = m;
+  a.nvox = g.nvox;
+  a.inv_ntot = (float)(1.0 / (double)g.nvox);
+  a.va = reinterpret_cast<uint16_t*>(ws + L.va);
+  a.vb = reinterpret_cast<uint16_t*>(ws + L.vb);
+  a.X1 = reinterpret_cast<float*>(ws + L.x1);
+  a.Y1 = reinterpret_cast<float*>(ws + L.y1);
+  a.X2 = reinterpret_cast<float*>(ws + L.x2);
+  a.Y2 = reinterpret_cast<float*>(ws + L.y2);
+  float2* tw = reinterpret_cast<float2*>(ws + L.tw);
+  a.twx = tw;
+  a.twy = tw + g.nx;
+  a.twz = tw + g.nx + g.ny;
+  a.W = reinterpret_cast<uint16_t*>(ws + L.W);
+  a.b = reinterpret_cast<float*>(ws + L.b);
+  a.R = reinterpret_cast<uint16_t*>(ws + L.R);
+  a.r_stride = (size_t)(2 * m) * (2 * m) * m * pfn::kC * pfn::kC * 2;
+  a.Q1 = reinterpret_cast<uint16_t*>(ws + L.Q1);
+  a.q1 = reinterpret_cast<float*>(ws + L.q1);
+  a.Q2 = reinterpret_cast<float*>(ws + L.Q2);
+  a.q2 = w->q2;
+  f->eta_prev = reinterpret_cast<float*>(ws + L.prev);
+  f->eta_pred = reinterpret_cast<float*>(ws + L.pred);
+  f->ctx = c;
+  f->P.assign(w->P, w->P + pfn::kC * (1 + pfn::kCond));
+  f->p.assign(w->p, w->p + pfn::kC);
+  // host conversions: BF16 weights, R reordered to [l][kz'][ky'][kx][o][i][re, im]
+  const int C = pfn::kC, my = 2 * m;
+  std::vector<float> twh(2 * (size_t)(g.nx + g.ny + g.nz));
+  twiddles(g.nx, twh.data());
+  twiddles(g.ny, twh.data() + 2 * g.nx);
+  twiddles(g.nz, twh.data() + 2 * (g.nx + g.ny));
+  std::vector<uint16_t> Wb((size_t)pfn::kLayers * C * C), Q1b((size_t)pfn::kH * C);
+  for (size_t i = 0; i < Wb.size(); ++i) Wb[i] = host_bf16(w->W[i]);
+  for (size_t i = 0; i < Q1b.size(); ++i) Q1b[i] = host_bf16(w->Q1[i]);
+  std::vector<uint16_t> Rb((size_t)pfn::kLayers * a.r_stride);
+  for (int l = 0; l < pfn::kLayers; ++l)
+    for (int o = 0; o < C; ++o)
+      for (int i = 0; i < C; ++i)
+        for (int kz = 0; kz < my; ++kz)
+          for (int ky = 0; ky < my; ++ky)
+            for (int kx = 0; kx < m; ++kx) {
+              const size_t src = ((((((size_t)l * C + o) * C + i) * my + kz) * my + ky) * m + kx) * 2;
+              const size_t dst = (size_t)l * a.r_stride + (((((size_t)kz * my + ky) * m + kx) * C + o) * C + i) * 2;
+              Rb[dst] = host_bf16(w->R[src]);
+              Rb[dst + 1] = host_bf16(w->R[src + 1]);
+            }
+  hipError_t e;
+  auto h2d = [&](const void* dst, const void* src, size_t bytes) {
+    return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice, c->stream);
+  };
+  if ((e = h2d(tw, twh.data(), twh.size() * 4)) != hipSuccess || (e = h2d(a.W, Wb.data(), Wb.size() * 2)) != hipSuccess ||
+      (e = h2d(a.b, w->b, (size_t)pfn::kLayers * C * 4)) != hipSuccess ||
+      (e = h2d(a.R, Rb.data(), Rb.size() * 2)) != hipSuccess || (e = h2d(a.Q1, Q1b.data(), Q1b.size() * 2)) != hipSuccess ||
+      (e = h2d(a.q1, w->q1, pfn::kH * 4)) != hipSuccess || (e = h2d(a.Q2, w->Q2, pfn::kH * 4)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess) {
+    delete f;
+    return hip_fail(c, e, "pf_fno_init upload");
+  }
+  *out = f;
+  return PF_OK;
+}
+
+int pf_fno_forward(pf_fno* f, const double* cond, const float* eta_in, float* eta_out) {
+  if (!f) return PF_EINVAL;
+  pf_ctx* c = f->ctx;
+  if (!cond || !eta_in || !eta_out || eta_in == eta_out) return fail(c, PF_EINVAL, "pf_fno_forward: bad arguments");
+  pfn::FArgs a = f->fa;
+  const int C = pfn::kC, ni = 1 + pfn::kCond;
+  for (int o = 0; o < C; ++o) {
+    double k = f->p[o];
+    for (int j = 0; j < pfn::kCond; ++j) k += (double)f->P[o * ni + 1 + j] * cond[j];
+    a.lift[o] = f->P[o * ni];
+    a.lift[C + o] = (float)k;
+  }
+  hipStream_t s = c->stream;
+  return launch(c, s, "fno_forward", [&] { return pfn::forward(a, eta_in, eta_out, s); });
+}
+
+int pf_fno_advance(pf_fno* f, int32_t n_calls, int32_t steps_per_call, const double* cond, const pf_load* load,
+                   double tol, pf_fno_report* rep) {
+  if (!f) return PF_EINVAL;
+  pf_ctx* c = f->ctx;
+  if (!cond || !load || !rep || n_calls < 0 || steps_per_call < 1)
+    return fail(c, PF_EINVAL, "pf_fno_advance: bad arguments");
+  Group& g = c->groups[0];
+  float* eta = g.args.eta;
+  const size_t bytes = sizeof(float) * g.nvox;
+  hipStream_t s = c->stream;
+  for (int n = 0; n < n_calls; ++n) {
+    hipError_t e = hipMemcpyAsync(f->eta_prev, eta, bytes, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(c, e, "pf_fno_advance copy");
+    PF_TRY(pf_fno_forward(f, cond, f->eta_prev, eta));
+    double rho = 0.0;
+    PF_TRY(pf_macro_residual(c, f->eta_prev, steps_per_call, load, &rho));
+    rep->last_rho = rho;
+    if (rho <= tol) {
+      rep->accepted += 1;
+      if (rho > rep->rho_max_accepted) rep->rho_max_accepted = rho;
+      c->steps += steps_per_call;
+      g.hist = 0;
+      g.strain_valid = false;
+      PF_TRY(refresh_gradient_energy(c, g));
+    } else {
+      rep->rejected += 1;
+      if (rep->rho_min_rejected == 0.0 || rho < rep->rho_min_rejected) rep->rho_min_rejected = rho;
+      e = hipMemcpyAsync(eta, f->eta_prev, bytes, hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return hip_fail(c, e, "pf_fno_advance copy");
+      PF_TRY(refresh_gradient_energy(c, g));
+      PF_TRY(pf_batch_step(c, steps_per_call, load));
+    }
+  }
+  return PF_OK;
+}
+
+int pf_fno_destroy(pf_fno* f) {
+  if (!f) return PF_EINVAL;
+  hipStreamSynchronize(f->ctx->stream);
+  delete f;
+  return PF_OK;
+}
 
 }  // extern "C"

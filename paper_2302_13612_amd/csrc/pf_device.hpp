@@ -37,6 +37,7 @@ struct DevState {
   double mean_kh[13];    // homogeneous spectral path: N<sigma> (6), N<eps> (6),
                          // mean-field elastic energy sum (1)
   double kh_drive[kMaxVar];  // L dt N <sigma> : eps0_a (mean of the elastic force)
+  double resid_max;          // max |residual| of the last macro-step check
   Status st;
 };
 
@@ -127,7 +128,7 @@ hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);  // mode 0 upda
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s);  // 0 step, 1 init, 2 spectral path
 hipError_t kh_mean(const KArgs& a, hipStream_t s);
-hipError_t kh_z_update(const KArgs& a, hipStream_t s);
+hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s);  // 0 update, 1 L dt dF/df
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s);
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s);
@@ -145,8 +146,14 @@ hipError_t ac_x_forward_v3(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v4(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v5(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v6(const KArgs& a, hipStream_t s);
-hipError_t kh_x_forward_v1(const KArgs& a, hipStream_t s);
-hipError_t kh_x_forward_v2(const KArgs& a, hipStream_t s);
-hipError_t kh_x_forward_v3(const KArgs& a, hipStream_t s);
-hipError_t kh_x_forward(const KArgs& a, hipStream_t s);
+hipError_t kh_x_forward_v1(const KArgs& a, int resid, hipStream_t s);
+hipError_t kh_x_forward_v2(const KArgs& a, int resid, hipStream_t s);
+hipError_t kh_x_forward_v3(const KArgs& a, int resid, hipStream_t s);
+// resid = 1: the backward-Euler residual of a macro step (see kh_residual)
+hipError_t kh_x_forward(const KArgs& a, int resid, hipStream_t s);
+// Residual of a macro step of n_steps plain steps ending at the current
+// order parameter f~: r = f~ - prev + n_steps L dt dF/df(f~), after
+// kh_x_forward(resid = 1), kh_mean, y forward (2V) and kh_z_update(mode 1),
+// y inverse (V): per-instance max |r| into DevState::resid_max.
+hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
 }  // namespace pfl

@@ -437,8 +437,11 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
 template <int V>
 __host__ __device__ constexpr int kh_tile() { return V == 1 ? kColTile : kZmsTile; }
 
+// mode 1: instead of the update, L dt dF/df of the state whose transforms
+// are in components 0..V-1 (f_hat) and V..2V-1 (L dt chem_hat):
+// L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
 template <int N, int V>
-__global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a) {
+__global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode) {
   constexpr int E = Plan<N>::E, T = N / E, C = kh_tile<V>();
   __shared__ float2 lds[N * C];
   const int ntile = (a.nh + C - 1) / C;
@@ -524,7 +527,7 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
           y[q].x += b * th[r][m].x;
           y[q].y += b * th[r][m].y;
         }
-      if (valid) {
+      if (valid && mode == 0) {
         double e2 = 0.0;
 #pragma unroll
         for (int q = 0; q < V; ++q) e2 += (double)th[q][m].x * y[q].x + (double)th[q][m].y * y[q].y;
@@ -535,9 +538,16 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
     const double x2 = a.gx * fx + a.gy * fy + a.gz * fz;
 #pragma unroll
     for (int q = 0; q < V; ++q) {
-      float2 nv = make_float2((rh[q][m].x - a.LDt * y[q].x) / den, (rh[q][m].y - a.LDt * y[q].y) / den);
-      if (dc && valid) nv = make_float2(rh[q][m].x + (float)a.state[inst].kh_drive[q], 0.f);
-      if (valid) en[0] += wgt * x2 * ((double)nv.x * nv.x + (double)nv.y * nv.y);
+      float2 nv;
+      if (mode == 0) {
+        nv = make_float2((rh[q][m].x - a.LDt * y[q].x) / den, (rh[q][m].y - a.LDt * y[q].y) / den);
+        if (dc && valid) nv = make_float2(rh[q][m].x + (float)a.state[inst].kh_drive[q], 0.f);
+        if (valid) en[0] += wgt * x2 * ((double)nv.x * nv.x + (double)nv.y * nv.y);
+      } else {
+        const float g = den - 1.f;
+        nv = make_float2(rh[q][m].x + g * th[q][m].x + a.LDt * y[q].x, rh[q][m].y + g * th[q][m].y + a.LDt * y[q].y);
+        if (dc && valid) nv = make_float2(rh[q][m].x - (float)a.state[inst].kh_drive[q], 0.f);
+      }
       th[q][m] = cscale(nv, a.inv_ntot);
     }
   }
@@ -549,7 +559,54 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
 #pragma unroll
       for (int m = 0; m < E; ++m) col[q * cs + (size_t)(t + T * m) * zs] = th[q][m];
   }
-  block_sum<kQgd>(en, a.part_gd + (size_t)lb * kQgd);
+  if (mode == 0) block_sum<kQgd>(en, a.part_gd + (size_t)lb * kQgd);
+}
+
+// Residual of a macro step, inverse x pass: r = f~ - prev + S g with g the
+// inverse transform of components 0..V-1 (L dt dF/df); per-block max |r|.
+template <int M>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_resid(const KArgs a, const float* __restrict__ prev,
+                                                          float S) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.ninst * a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  const size_t cs = (size_t)nrows * a.sh;
+  float mx = 0.f;
+#pragma unroll 1
+  for (int q = 0; q < a.nv; ++q) {
+    float2 v[E];
+    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + (size_t)(valid ? row : 0) * a.sh, a.tw_xh, a.tw_x);
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const size_t off = q * vs + rbase + 2 * (t + T * m);
+        const float2 f = *reinterpret_cast<const float2*>(a.eta + off);
+        const float2 f0 = *reinterpret_cast<const float2*>(prev + off);
+        const float r0 = f.x - f0.x + S * v[m].x, r1 = f.y - f0.y + S * v[m].y;
+        // NaN propagates through fmaxf only if both are NaN: count it as huge
+        mx = fmaxf(mx, isfinite(r0) ? fabsf(r0) : 3.0e38f);
+        mx = fmaxf(mx, isfinite(r1) ? fabsf(r1) : 3.0e38f);
+      }
+    }
+    __syncthreads();
+  }
+  block_minmax(0.f, mx, a.part_mm + 2 * (size_t)blockIdx.x);
+}
+
+__global__ __launch_bounds__(1024) void k_resid_fin(const KArgs a, int nblk) {
+  const int inst = blockIdx.x;
+  __shared__ float mm[2];
+  const float* pm = a.part_mm + 2 * (size_t)inst * nblk;
+  float mx = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) mx = fmaxf(mx, pm[2 * b + 1]);
+  block_minmax(0.f, mx, mm);
+  if (threadIdx.x == 0) a.state[inst].resid_max = mm[1];
 }
 
 // ------------------------------------------------------------ small kernels
@@ -884,13 +941,20 @@ hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t kh_x_forward(const KArgs& a, hipStream_t s) {
+hipError_t kh_x_forward(const KArgs& a, int resid, hipStream_t s) {
   switch (a.nv) {
-    case 1: return kh_x_forward_v1(a, s);
-    case 2: return kh_x_forward_v2(a, s);
-    case 3: return kh_x_forward_v3(a, s);
+    case 1: return kh_x_forward_v1(a, resid, s);
+    case 2: return kh_x_forward_v2(a, resid, s);
+    case 3: return kh_x_forward_v3(a, resid, s);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M(a.nx, (k_x_resid<M><<<grid, xthreads<M>(), 0, s>>>(a, prev, (float)n_steps)));
+  k_resid_fin<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
+  return hipGetLastError();
 }
 
 hipError_t kh_mean(const KArgs& a, hipStream_t s) {
@@ -898,19 +962,19 @@ hipError_t kh_mean(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t kh_z_update(const KArgs& a, hipStream_t s) {
+hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s) {
   switch (a.nv) {
     case 1: {
       const dim3 grid(((a.nh + kColTile - 1) / kColTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 1><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a)));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 1><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a, mode)));
     } break;
     case 2: {
       const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 2><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 2><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode)));
     } break;
     case 3: {
       const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 3><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 3><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode)));
     } break;
     default: return hipErrorInvalidValue;
   }

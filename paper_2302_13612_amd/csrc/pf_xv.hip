@@ -324,10 +324,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
 
 #if PF_NV <= 3
 // Homogeneous spectral path, forward: R2C of f_a (components 0..V-1) and of
-// f_a - L dt chem_a (components V..2V-1); FP64 double-well and mean sums,
-// extrema of f. The elastic force is applied per wavevector in the z pass.
+// f_a - L dt chem_a (components V..2V-1; with resid, L dt chem_a); FP64
+// double-well and mean sums, extrema of f. The elastic force is applied per
+// wavevector in the z pass.
 template <int M, int V>
-__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a) {
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int resid) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[2 * V * ROWS * LROW];
@@ -365,7 +366,10 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a) {
         for (int r = q + 1; r < V; ++r) fdw += et[q] * et[q] * et[r] * et[r];
       }
 #pragma unroll
-      for (int q = 0; q < V; ++q) o[half][q] = et[q] - a.LDt * chem_force<V>(a.A, et, fm, q);
+      for (int q = 0; q < V; ++q) {
+        const float lc = a.LDt * chem_force<V>(a.A, et, fm, q);
+        o[half][q] = resid ? lc : et[q] - lc;
+      }
       if (valid) {
         facc[0] += fdw;
 #pragma unroll
@@ -432,9 +436,9 @@ hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
 }
 
 #if PF_NV <= 3
-hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
+hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, int resid, hipStream_t s) {
   const dim3 grid(x_blocks(a));
-  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_kh<M, PF_NV><<<grid, xthreads<M>(), 0, s>>>(a)));
+  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_kh<M, PF_NV><<<grid, xthreads<M>(), 0, s>>>(a, resid)));
   return hipGetLastError();
 }
 #endif

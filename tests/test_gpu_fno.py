@@ -1,0 +1,132 @@
+"""GPU: the learned macro stepper (FNO forward, acceptance residual,
+accept/fallback loop) through the C ABI, against the FP64 oracle.
+
+Tolerance of the forward pass: both sides get the same weights, rounded to
+BF16 where the library stores them in BF16 (W, R, Q1), so the difference
+comes from the BF16 activations (relative rounding 2^-9 at the lift and after
+each of the four layers) and FP32 sums: about sqrt(5) 2^-9 = 0.4% of the
+activations, i.e. of the predicted increment; the test allows 2% (rel-L2)."""
+
+import numpy as np
+import pytest
+
+from oracle import fno as ofno
+from paper_2302_13612_amd import binding, inputs
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    a = np.asarray(a, dtype=np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def gpu_params(seed=0, modes=12):
+    p = ofno.init_params(width=32, modes=modes, hidden=128, n_layers=4, seed=seed, scale_spec=2e-3)
+    p["W"] = bf16_round(p["W"])
+    p["Q1"] = bf16_round(p["Q1"])
+    p["R"] = bf16_round(p["R"].real) + 1j * bf16_round(p["R"].imag)
+    for k in ("P", "p", "b", "q1", "Q2", "q2"):
+        p[k] = np.asarray(p[k], dtype=np.float32).astype(np.float64)
+    return p
+
+
+def smooth_field(shape, seed):
+    rng = inputs.rng_for(seed)
+    g = inputs.gaussian_random_field(shape, 4.0, rng)
+    return (0.5 + 0.3 * g / np.abs(g).max()).astype(np.float32)
+
+
+def homog_solver(shape, eta, seed=31):
+    batch = inputs.rve_batch(n_inst=1, seed=seed, sizes=(shape[0],))
+    cfg = cases.batch_instance_cfg(batch, 0)
+    cfg = dict(cfg, shape=shape, eta0=eta[None])
+    solver, _ = cases.gpu_solver(cfg)
+    return cfg, solver
+
+
+@pytest.mark.parametrize("shape", [(32, 32, 32), (32, 32, 64), (128, 128, 128)])
+def test_fno_forward_vs_oracle(shape):
+    import torch
+    print(f"\n[fno forward] {shape}", flush=True)
+    eta = smooth_field(shape, 3)
+    cfg, solver = homog_solver(shape, eta)
+    p = gpu_params(seed=1)
+    cond = np.random.default_rng(2).normal(size=7)
+    net = binding.Fno(solver, p)
+    out = net.forward(cond, torch.from_numpy(eta).cuda()).cpu().numpy()
+    ref = ofno.forward(p, eta.astype(np.float64), cond)
+    d_gpu, d_ref = out - eta, ref - eta
+    rel = np.linalg.norm(d_gpu - d_ref) / np.linalg.norm(d_ref)
+    print(f"  increment rel-L2 {rel:.2e}, max-abs {np.abs(d_gpu - d_ref).max():.2e} "
+          f"(increment max {np.abs(d_ref).max():.2e})", flush=True)
+    assert np.isfinite(out).all()
+    assert rel <= 2e-2
+    net.close()
+    solver.close()
+
+
+def test_macro_residual_vs_oracle():
+    import torch
+    shape = (32, 32, 32)
+    batch = inputs.rve_batch(n_inst=2, seed=33, sizes=(32,))
+    cfg = cases.batch_instance_cfg(batch, 1)
+    solver, _ = cases.gpu_solver(cfg)
+    solver.step(20, cfg["eps_bar"], cfg["sig_bar"])
+    prev = solver.field(binding.PF_FIELD_ETA)
+    solver.step(16, cfg["eps_bar"], cfg["sig_bar"])
+    cur = solver.field(binding.PF_FIELD_ETA)
+    rho = binding.macro_residual(solver, prev, 16, cfg["eps_bar"], cfg["sig_bar"])
+    prob = cases.oracle_problem(cfg, tol=1e-12)
+    load = dict(eps_bar=cfg["eps_bar"], sig_bar=cfg["sig_bar"], stress_mask=cfg["stress_mask"])
+    _, rho_o = ofno.macro_residual(prob, prev.cpu().numpy().astype(np.float64),
+                                   cur.cpu().numpy().astype(np.float64), 16, load)
+    print(f"\n[residual] gpu {rho:.6e} oracle {rho_o:.6e}", flush=True)
+    assert abs(rho - rho_o) <= 1e-5 + 1e-3 * rho_o
+    # perturbed prediction
+    bumped = cur.clone()
+    bumped[0, 5, 6, 7] += 0.25
+    solver.set_field(binding.PF_FIELD_ETA, bumped)
+    rho_b = binding.macro_residual(solver, prev, 16, cfg["eps_bar"], cfg["sig_bar"])
+    _, rho_bo = ofno.macro_residual(prob, prev.cpu().numpy().astype(np.float64),
+                                    bumped.cpu().numpy().astype(np.float64), 16, load)
+    assert abs(rho_b - rho_bo) <= 1e-5 + 1e-3 * rho_bo
+    assert rho_b > rho + 0.2
+    solver.close()
+    del torch
+
+
+def test_fno_advance_accept_and_fallback():
+    import torch
+    shape = (32, 32, 32)
+    batch = inputs.rve_batch(n_inst=1, seed=34, sizes=(32,))
+    cfg = cases.batch_instance_cfg(batch, 0)
+    p = gpu_params(seed=4)
+    cond = np.random.default_rng(5).normal(size=7)
+    # everything accepted: the state is the network's prediction, call after call
+    s1, _ = cases.gpu_solver(cfg)
+    net = binding.Fno(s1, p)
+    eta0 = s1.field(binding.PF_FIELD_ETA)
+    rep = net.advance(2, 16, cond, cfg["eps_bar"], cfg["sig_bar"], tol=np.inf)
+    assert rep["accepted"] == 2 and rep["rejected"] == 0
+    expect = net.forward(cond, net.forward(cond, eta0[0])[None][0])
+    got = s1.field(binding.PF_FIELD_ETA)[0]
+    assert torch.equal(got, expect)
+    net.close()
+    s1.close()
+    # everything rejected: the state is that of plain steps
+    s2, _ = cases.gpu_solver(cfg)
+    net = binding.Fno(s2, p)
+    rep = net.advance(2, 16, cond, cfg["eps_bar"], cfg["sig_bar"], tol=-1.0)
+    assert rep["accepted"] == 0 and rep["rejected"] == 2
+    got = s2.field(binding.PF_FIELD_ETA).cpu().numpy()
+    net.close()
+    s2.close()
+    s3, _ = cases.gpu_solver(cfg)
+    s3.step(32, cfg["eps_bar"], cfg["sig_bar"])
+    plain = s3.field(binding.PF_FIELD_ETA).cpu().numpy()
+    s3.close()
+    assert np.array_equal(got, plain)
