@@ -245,10 +245,117 @@ def bench_rve_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_surrogate(args):
+    """Learned macro stepper: train on the batched-RVE trajectories, then
+    advance held-out 128^3 instances by 512 steps with the stepper (16 steps
+    per call, residual check, fallback to plain steps) and without it."""
+    import torch
+    from paper_2302_13612_amd import binding, inputs, surrogate
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    train_batch = inputs.rve_batch()
+    trajs, conds = surrogate.generate_trajectories(binding, torch, train_batch, dev, log=log)
+    model = surrogate.make_model(torch).to(dev)
+    info = surrogate.train(torch, model, trajs, conds, seconds=args.train_seconds, log=log)
+    del trajs
+    torch.cuda.empty_cache()
+    params = surrogate.to_params(model)
+    del model
+    held = inputs.rve_batch(n_inst=args.eval_instances, seed=99, sizes=(128,))
+    calls, per = held["steps"] // 16, 16
+    results = []
+    for i, inst in enumerate(held["instances"]):
+        v, cond = surrogate.variant_and_cond(binding, inst["rotation"], inst["eps_bar"][0])
+        Cg, Cv, e0 = binding.mg_twin_tables(inst["rotation"][None], [v])
+        Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
+
+        def solver():
+            return binding.Solver(torch.from_numpy(inst["eta0"]).to(dev), held["dx"], held["A"], held["kappa"],
+                                  held["L"], held["dt"], (Cg, Cv, e0), held["stress_mask"],
+                                  ms_tol=held["ms_tol"], ms_max_iter=held["ms_max_iter"])
+
+        eb, sb = inst["eps_bar"], held["sig_bar"]
+        # plain stepping (graph replay), snapshots every 16 steps
+        sp = solver()
+        sp.step(per, eb, sb)  # warm-up: graph capture
+        sp.close()
+        sp = solver()
+        snaps_plain = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            sp.step(per, eb, sb)
+            snaps_plain.append(sp.field(binding.PF_FIELD_ETA))
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        sp.close()
+        # learned stepper with the residual check and fallback
+        sf = solver()
+        net = binding.Fno(sf, params)
+        warm = net.forward(cond, sf.field(binding.PF_FIELD_ETA)[0])  # warm-up
+        rho0 = binding.macro_residual(sf, sf.field(binding.PF_FIELD_ETA), per, eb, sb)
+        del warm, rho0
+        snaps_fno, reps = [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(calls):
+            reps.append(net.advance(1, per, cond, eb, sb, tol=args.tol))
+            snaps_fno.append(sf.field(binding.PF_FIELD_ETA))
+        torch.cuda.synchronize()
+        t_fno = time.perf_counter() - t0
+        net.close()
+        sf.close()
+        # the network alone (every call accepted) for its error and cost
+        sa = solver()
+        net = binding.Fno(sa, params)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net.advance(1, per, cond, eb, sb, tol=float("inf"))
+        torch.cuda.synchronize()
+        t_call = time.perf_counter() - t0
+        err_free = [float((sa.field(binding.PF_FIELD_ETA) - snaps_plain[0]).abs().max())]
+        for k in range(1, calls):
+            net.advance(1, per, cond, eb, sb, tol=float("inf"))
+            err_free.append(float((sa.field(binding.PF_FIELD_ETA) - snaps_plain[k]).abs().max()))
+        net.close()
+        sa.close()
+        err = [float((a - b).abs().max()) for a, b in zip(snaps_fno, snaps_plain)]
+        acc = sum(r["accepted"] for r in reps)
+        rhos = [r["last_rho"] for r in reps]
+        res = dict(instance=i, variant=v, eps_xx=float(eb[0]), t_plain=t_plain, t_fno=t_fno,
+                   speedup=t_plain / t_fno, accepted=acc, calls=calls, max_err=max(err),
+                   rho_min=float(min(rhos)), rho_median=float(np.median(rhos)),
+                   fno_call_plus_check_s=t_call, plain_16_steps_s=t_plain / calls,
+                   free_rollout_err_first=err_free[0], free_rollout_err_last=err_free[-1])
+        log(f"instance {i}: plain {t_plain * 1e3:.1f} ms, with stepper {t_fno * 1e3:.1f} ms "
+            f"(speedup {res['speedup']:.3f}), accepted {acc}/{calls}, max err {res['max_err']:.2e}, "
+            f"rho min/median {res['rho_min']:.2e}/{res['rho_median']:.2e}; one call + check "
+            f"{t_call * 1e3:.2f} ms vs 16 plain steps {t_plain / calls * 1e3:.2f} ms; free rollout err "
+            f"{err_free[0]:.2e} -> {err_free[-1]:.2e}")
+        results.append(res)
+    speed = float(np.mean([r["speedup"] for r in results]))
+    out = {
+        "metric": "surrogate speedup at <=1e-3 err (512 steps of 128^3, 16 steps per call, residual check + fallback)",
+        "value": speed, "unit": "x", "n_gpus": 1, "steps": held["steps"], "warmup": 1,
+        "ms_per_step": float(np.mean([r["t_fno"] for r in results])) * 1e3 / held["steps"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32",
+        "data": "synthetic",
+        "config": {"workload": f"surrogate: FNO width 32, modes 12, 4 layers trained {args.train_seconds:.0f} s "
+                               f"on the 256-RVE trajectories; {len(results)} held-out 128^3 instances",
+                   "tol": args.tol, "training": info},
+        "max_err": max(r["max_err"] for r in results),
+        "instances": results,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("polycrystal", "rve-batch"), default="polycrystal")
+    ap.add_argument("--workload", choices=("polycrystal", "rve-batch", "surrogate"), default="polycrystal")
+    ap.add_argument("--train-seconds", type=float, default=240.0)
+    ap.add_argument("--eval-instances", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-3, help="acceptance residual of the learned stepper")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
@@ -264,6 +371,8 @@ def main():
     args.steps_given = args.steps is not None
     if args.workload == "rve-batch":
         return bench_rve_batch(args)
+    if args.workload == "surrogate":
+        return bench_surrogate(args)
     if args.steps is None:
         args.steps = 20
 

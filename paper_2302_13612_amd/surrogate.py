@@ -1,0 +1,173 @@
+"""Training data and training of the FNO macro stepper.
+
+Training is an off-line procedure beside the stepping path: trajectories of
+the batched ensemble (single-crystal cubes of edge 32-96, one twin variant
+each, homogeneous stiffness) come from the library's batched spectral path;
+the network is fitted with PyTorch autograd in FP32 on the GPU; the weights
+are then handed to the library (pf_fno_init), whose forward pass, acceptance
+residual and fallback run in HIP.
+
+The network is the one of the library's pf_fno_forward (and of the checker):
+lift of [f, c] to 32 channels, four Fourier layers
+v <- GELU(W v + b + K v) with 12 kept modes per signed axis, projection
+32 -> 128 -> 1 added to f. c = (sample-frame eps0 of the instance's variant
+/ gamma_tw, applied strain / 5e-3).
+"""
+
+import time
+
+import numpy as np
+
+GAMMA_TW = 0.129
+STRAIN_SCALE = 5e-3
+
+
+def variant_and_cond(binding, rotation, eps_bar_xx):
+    """Variant most favoured by compression along x (most negative sample
+    eps0_xx, library tables) and the conditioning vector of an instance."""
+    _, _, e0 = binding.mg_twin_tables(np.asarray(rotation)[None], list(range(6)))
+    v = int(np.argmin(e0[0, :, 0]))
+    cond = np.concatenate([e0[0, v] / GAMMA_TW, [eps_bar_xx / STRAIN_SCALE]])
+    return v, cond
+
+
+def batch_specs(binding, torch, batch, device):
+    specs, conds = [], []
+    for inst in batch["instances"]:
+        v, cond = variant_and_cond(binding, inst["rotation"], inst["eps_bar"][0])
+        Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], [v])
+        Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
+        specs.append(dict(eta0=torch.from_numpy(inst["eta0"]).to(device), tables=(Cg, Cv, e0),
+                          rotation=inst["rotation"]))
+        conds.append(cond)
+    return specs, np.stack(conds)
+
+
+def generate_trajectories(binding, torch, batch, device, log=print):
+    """Snapshots of f every save_every steps for every instance of a batch
+    recipe: list of tensors (n_snap, n, n, n) on the device, and the
+    conditioning vectors (n_inst, 7)."""
+    specs, conds = batch_specs(binding, torch, batch, device)
+    bs = binding.BatchSolver(specs, batch["dx"], batch["A"], batch["kappa"], batch["L"], batch["dt"],
+                             batch["stress_mask"], ms_tol=batch["ms_tol"], ms_max_iter=batch["ms_max_iter"])
+    eb = np.stack([inst["eps_bar"] for inst in batch["instances"]])
+    every, steps = batch["save_every"], batch["steps"]
+    nsnap = steps // every + 1
+    trajs = [torch.empty((nsnap,) + inst["shape"], dtype=torch.float32, device=device) for inst in batch["instances"]]
+    t0 = time.perf_counter()
+    for k in range(nsnap):
+        if k:
+            bs.step(every, eb)
+        for i, tr in enumerate(trajs):
+            bs.field(i, binding.PF_FIELD_ETA, out=tr[k:k + 1])
+    torch.cuda.synchronize()
+    log(f"trajectories: {len(trajs)} instances x {nsnap} snapshots in {time.perf_counter() - t0:.1f} s")
+    bs.close()
+    return trajs, conds
+
+
+def make_model(torch, width=32, modes=12, hidden=128, n_layers=4, n_cond=7, seed=0):
+    nn = torch.nn
+    F = torch.nn.functional
+
+    def kept(n, m, device):
+        return torch.cat([torch.arange(m, device=device), torch.arange(n - m, n, device=device)])
+
+    class TorchFno(nn.Module):
+        def __init__(self):
+            super().__init__()
+            g = torch.Generator().manual_seed(seed)
+            cin = 1 + n_cond
+            self.m = modes
+            self.P = nn.Parameter(torch.randn(width, cin, generator=g) / cin ** 0.5)
+            self.p = nn.Parameter(torch.zeros(width))
+            self.W = nn.Parameter(torch.randn(n_layers, width, width, generator=g) / width ** 0.5)
+            self.b = nn.Parameter(torch.zeros(n_layers, width))
+            scale = 1.0 / (width * width)
+            self.R = nn.Parameter(scale * torch.rand(n_layers, width, width, 2 * modes, 2 * modes, modes, 2,
+                                                     generator=g))
+            self.Q1 = nn.Parameter(torch.randn(hidden, width, generator=g) / width ** 0.5)
+            self.q1 = nn.Parameter(torch.zeros(hidden))
+            self.Q2 = nn.Parameter(torch.randn(1, hidden, generator=g) * 1e-3 / hidden ** 0.5)
+            self.q2 = nn.Parameter(torch.zeros(1))
+
+        def forward(self, eta, cond):
+            """eta (B, nz, ny, nx), cond (B, n_cond) -> predicted eta."""
+            B, nz, ny, nx = eta.shape
+            m = self.m
+            const = cond @ self.P[:, 1:].T + self.p                      # (B, C)
+            v = self.P[:, 0].view(1, -1, 1, 1, 1) * eta[:, None] + const[:, :, None, None, None]
+            iz, iy = kept(nz, m, eta.device), kept(ny, m, eta.device)
+            for l in range(self.W.shape[0]):
+                Vh = torch.fft.rfftn(v, dim=(2, 3, 4))
+                sub = Vh[:, :, iz][:, :, :, iy][..., :m]
+                Rc = torch.view_as_complex(self.R[l])
+                out_sub = torch.einsum("bizyx,oizyx->bozyx", sub, Rc)
+                spec = torch.zeros((B, Rc.shape[0], nz, ny, nx // 2 + 1), dtype=Vh.dtype, device=eta.device)
+                spec[:, :, iz[:, None], iy[None, :], :m] = out_sub
+                kv = torch.fft.irfftn(spec, s=(nz, ny, nx), dim=(2, 3, 4))
+                local = torch.einsum("oi,bizyx->bozyx", self.W[l], v) + self.b[l].view(1, -1, 1, 1, 1)
+                v = F.gelu(local + kv)
+            h = F.gelu(torch.einsum("hi,bizyx->bhzyx", self.Q1, v) + self.q1.view(1, -1, 1, 1, 1))
+            d = torch.einsum("oh,bhzyx->bozyx", self.Q2, h)[:, 0] + self.q2
+            return eta + d
+
+    return TorchFno()
+
+
+def to_params(model):
+    """Weights in the checker's / library binding's layout (float64, R complex)."""
+    g = lambda t: t.detach().double().cpu().numpy()  # noqa: E731
+    R = g(model.R)
+    return {"P": g(model.P), "p": g(model.p), "W": g(model.W), "b": g(model.b),
+            "R": R[..., 0] + 1j * R[..., 1], "Q1": g(model.Q1), "q1": g(model.q1), "Q2": g(model.Q2),
+            "q2": g(model.q2)}
+
+
+def load_params(model, params, torch):
+    with torch.no_grad():
+        for k in ("P", "p", "W", "b", "Q1", "q1", "Q2", "q2"):
+            getattr(model, k).copy_(torch.as_tensor(np.asarray(params[k]).reshape(getattr(model, k).shape)))
+        R = np.asarray(params["R"])
+        model.R.copy_(torch.as_tensor(np.stack([R.real, R.imag], axis=-1)))
+
+
+def train(torch, model, trajs, conds, seconds=240.0, lr=2e-3, batch_size=4, seed=0, log=print):
+    """Adam on MSE of the macro-step increment, pairs (snapshot k, k+1) of
+    every instance, mini-batches of one instance size, cosine-decayed rate,
+    for a wall-clock budget."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dev = trajs[0].device
+    by_size = {}
+    for i, tr in enumerate(trajs):
+        by_size.setdefault(tuple(tr.shape[1:]), []).append(i)
+    pairs = [(i, k) for i, tr in enumerate(trajs) for k in range(tr.shape[0] - 1)]
+    cond_t = torch.as_tensor(conds, dtype=torch.float32, device=dev)
+    opt = torch.optim.Adam(model.parameters(), lr=lr)
+    t0 = time.perf_counter()
+    it, hist = 0, []
+    while True:
+        el = time.perf_counter() - t0
+        if el > seconds:
+            break
+        for gparam in opt.param_groups:
+            gparam["lr"] = lr * 0.5 * (1 + np.cos(np.pi * min(1.0, el / seconds)))
+        shape = list(by_size)[rng.integers(len(by_size))]
+        members = by_size[shape]
+        pick = [(members[rng.integers(len(members))], int(rng.integers(trajs[0].shape[0] - 1)))
+                for _ in range(batch_size)]
+        x = torch.stack([trajs[i][k] for i, k in pick])
+        y = torch.stack([trajs[i][k + 1] for i, k in pick])
+        c = cond_t[[i for i, _ in pick]]
+        pred = model(x, c)
+        loss = torch.mean((pred - y) ** 2)
+        opt.zero_grad(set_to_none=True)
+        loss.backward()
+        opt.step()
+        hist.append(float(loss))
+        it += 1
+        if it % 200 == 0:
+            log(f"  iter {it} ({el:.0f} s) loss {np.mean(hist[-200:]):.3e}")
+    log(f"trained {it} iterations in {time.perf_counter() - t0:.0f} s, last loss {np.mean(hist[-50:]):.3e}")
+    del pairs
+    return {"iterations": it, "final_loss": float(np.mean(hist[-50:])) if hist else None}
