@@ -48,7 +48,7 @@ def _compile(unit, outdir, extra):
     return cmd, res, out
 
 
-def build(verbose=False, jobs=None, extra_flags=()):
+def build(verbose=False, jobs=None, extra_flags=(), out=None):
     jobs = jobs or min(len(UNITS), max(1, min(16, os.cpu_count() or 1)))
     with tempfile.TemporaryDirectory(prefix="pftwin_build_") as tmp:
         with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
@@ -64,14 +64,15 @@ def build(verbose=False, jobs=None, extra_flags=()):
                 sys.stderr.write(res.stderr)
         if failed:
             raise RuntimeError("hipcc failed building libpftwin.so")
-        out_tmp = LIB + ".tmp"
+        lib = out or LIB
+        out_tmp = lib + ".tmp"
         link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC"] + [r[2] for r in results] + ["-o", out_tmp]
         res = subprocess.run(link, capture_output=True, text=True)
         if res.returncode != 0:
             sys.stderr.write(res.stdout + res.stderr)
             raise RuntimeError("link of libpftwin.so failed")
-        os.replace(out_tmp, LIB)
-    return LIB
+        os.replace(out_tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

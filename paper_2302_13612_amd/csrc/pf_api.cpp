@@ -39,7 +39,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
-  size_t eta, eps, eps_prev, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, tw;
+  size_t eta, eps, eps_prev, eps_prev2, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, tw;
   size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
@@ -69,6 +69,7 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.eta = take(sizeof(float) * nvox * nv);
   L.eps = take(sizeof(float) * nvox * 6);
   L.eps_prev = take(sizeof(float) * nvox * 6);
+  L.eps_prev2 = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
   L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
   L.spec = take(sizeof(float) * 2 * nspec * 6);
@@ -301,6 +302,8 @@ struct Group {
   int64_t hist;          // consecutive fixed-point steps with a valid strain history
   bool own_epsp, epsp_given;
   std::vector<int> members;
+  float* ring[3];        // strain fields: ring[cur] the latest converged one, then
+  int cur;               // ring[cur - 1], ring[cur - 2] the ones of the steps before
 };
 
 }  // namespace
@@ -482,9 +485,7 @@ size_t status_base(pf_ctx* c, size_t gi) {
   return off;
 }
 
-int ms_iteration(pf_ctx* c, const Group& g, int mode, hipStream_t s) {
-  KArgs a = g.args;
-  a.iter_mode = mode;
+int ms_iteration(pf_ctx* c, const KArgs& a, hipStream_t s) {
   PF_TRY(launch(c, s, "ms_x_forward", [&] { return pfl::ms_x_forward(a, s); }));
   PF_TRY(launch(c, s, "ms_finalize_mean", [&] { return pfl::ms_finalize_mean(a, s); }));
   PF_TRY(launch(c, s, "ms_y_forward", [&] { return pfl::y_pass(a, 6, 1, s); }));
@@ -509,7 +510,6 @@ int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
 // The whole homogeneous spectral step of a group.
 int kh_step(pf_ctx* c, const Group& g, hipStream_t s) {
   const KArgs& a = g.args;
-  PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(a, s); }));
   PF_TRY(launch(c, s, "kh_x_forward", [&] { return pfl::kh_x_forward(a, 0, s); }));
   PF_TRY(launch(c, s, "kh_mean", [&] { return pfl::kh_mean(a, s); }));
   PF_TRY(launch(c, s, "kh_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
@@ -527,7 +527,7 @@ int fixed_step(pf_ctx* c, const Group& g, bool kh, hipStream_t s) {
   KArgs ab = g.args;
   ab.iter_mode = 0;
   PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(ab, s); }));
-  PF_TRY(ms_iteration(c, g, 0, s));
+  PF_TRY(ms_iteration(c, ab, s));
   return ac_update(c, g, s);
 }
 
@@ -751,8 +751,12 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.tol = p0.ms_tol;
     a.stress_mask = p0.bc_stress_mask;
     a.eta = reinterpret_cast<float*>(ws + L.eta);
-    a.eps = reinterpret_cast<float*>(ws + L.eps);
-    a.eps_prev = reinterpret_cast<float*>(ws + L.eps_prev);
+    g.ring[0] = reinterpret_cast<float*>(ws + L.eps);
+    g.ring[1] = reinterpret_cast<float*>(ws + L.eps_prev);
+    g.ring[2] = reinterpret_cast<float*>(ws + L.eps_prev2);
+    g.cur = 0;
+    a.eps = a.eps_out = g.ring[0];
+    a.eps_h1 = a.eps_h2 = nullptr;
     a.iter_mode = 0;
     a.sig = reinterpret_cast<float*>(ws + L.sig);
     a.epsp = nullptr;
@@ -919,17 +923,32 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         }
         iterating.push_back(k);
       }
-      std::vector<int> first_mode(c->groups.size(), 0);
+      // The first iterate extrapolates the converged strains of the previous
+      // steps (linear from the third step on, quadratic from the fourth) and
+      // is written over the oldest of the three strain fields.
+      std::vector<KArgs> first(c->groups.size()), later(c->groups.size());
       for (size_t k : iterating) {
         Group& g = c->groups[k];
-        first_mode[k] = (g.hist >= 2 && g.strain_valid) ? 2 : ((g.hist >= 1 && g.strain_valid) ? 1 : 0);
-        KArgs ab = g.args;
-        ab.iter_mode = first_mode[k];
-        PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(ab, s); }));
+        const int order = !g.strain_valid ? 0 : (g.hist >= 3 ? 2 : (g.hist == 2 ? 1 : 0));
+        float* out = g.ring[(g.cur + 1) % 3];
+        KArgs& f = first[k];
+        f = g.args;
+        f.eps = g.ring[g.cur];
+        f.eps_out = out;
+        f.eps_h1 = g.ring[(g.cur + 2) % 3];
+        f.eps_h2 = g.ring[(g.cur + 1) % 3];
+        f.iter_mode = order;
+        KArgs& l = later[k];
+        l = g.args;
+        l.eps = out;
+        l.eps_out = out;
+        l.eps_h1 = l.eps_h2 = nullptr;
+        l.iter_mode = 0;
+        PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(f, s); }));
       }
       std::vector<size_t> active = iterating;
       for (int it = 0; it < c->ms_max_iter && !active.empty(); ++it) {
-        for (size_t k : active) PF_TRY(ms_iteration(c, c->groups[k], it == 0 ? first_mode[k] : 0, s));
+        for (size_t k : active) PF_TRY(ms_iteration(c, it == 0 ? first[k] : later[k], s));
         PF_TRY(read_status(c));
         std::vector<size_t> still;
         for (size_t k : active) {
@@ -950,9 +969,15 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         char buf[160];
         snprintf(buf, sizeof(buf), "fixed point not converged after %d iterations (residual %.3e)",
                  c->ms_max_iter, worst);
+        for (size_t kk : iterating) c->groups[kk].hist = 0;
         return fail(c, PF_ENOCONV, buf);
       }
-      for (size_t k : iterating) PF_TRY(ac_update(c, c->groups[k], s));
+      for (size_t k : iterating) {
+        Group& g = c->groups[k];
+        g.cur = (g.cur + 1) % 3;
+        g.args.eps = g.args.eps_out = g.ring[g.cur];
+        PF_TRY(ac_update(c, g, s));
+      }
       for (size_t k = 0; k < c->groups.size(); ++k) {
         Group& g = c->groups[k];
         if (use_kh[k]) {
@@ -1166,7 +1191,6 @@ int pf_macro_residual(pf_ctx* c, const float* eta_prev, int32_t n_steps, const p
   PF_TRY(upload_loads(c, load));
   const KArgs& a = g.args;
   hipStream_t s = c->stream;
-  PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(a, s); }));
   PF_TRY(launch(c, s, "res_x_forward", [&] { return pfl::kh_x_forward(a, 1, s); }));
   PF_TRY(launch(c, s, "res_mean", [&] { return pfl::kh_mean(a, s); }));
   PF_TRY(launch(c, s, "res_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));

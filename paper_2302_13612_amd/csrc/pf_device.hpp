@@ -29,7 +29,8 @@ struct DevState {
   double ebar_cur[6];    // mean strain of the current iterate
   double ebar_field[6];  // mean strain of the strain field in memory
   double ebar_next[6];   // mean strain for the next iterate
-  double ebar_prev[6];   // mean strain of the previous step's field (eps_prev)
+  double ebar_h[3][6];   // mean strains of the last three converged fields (latest first)
+  double ebar_base[6];   // mean of the field the current iterate is formed from
   double eps_target[6];  // load: prescribed mean strain
   double sig_target[6];  // load: prescribed mean stress
   double gd_cur;         // gradient energy sum of the current order parameter
@@ -44,6 +45,7 @@ struct DevState {
 // Per-instance reference medium: packed C0 (21) then its compliance S0 (36,
 // Voigt stress -> tensor-Voigt strain).
 constexpr int kRefStride = 21 + 36;
+
 
 // Per-instance tables of the homogeneous spectral path (one stiffness C in
 // the whole instance, linear h, no plastic strain). Float part: C packed (21),
@@ -78,11 +80,12 @@ struct KArgs {
   uint32_t stress_mask;
   // fields
   float* eta;                 // [nv][ninst][nz][ny][nx]
-  float* eps;                 // [6][ninst][nz][ny][nx]
-  float* eps_prev;            // [6][ninst][nz][ny][nx] strain of the previous step
-  int iter_mode;              // first iteration of a step: 0 none, 1 keep the step's
-                              // starting strain in eps_prev, 2 also start from the
-                              // linear extrapolation 2 eps - eps_prev
+  float* eps;                 // [6][ninst][nz][ny][nx] strain the iterate is formed from
+  float* eps_out;             // where the inverse pass writes the new iterate
+  const float* eps_h1;        // converged strain of the step before (iter_mode >= 1)
+  const float* eps_h2;        // and of the one before that (iter_mode 2)
+  int iter_mode;              // first iterate of a step: 0 eps, 1 linear extrapolation
+                              // 2 eps - h1, 2 quadratic 3 eps - 3 h1 + h2
   float* sig;                 // [6][ninst][nz][ny][nx] (only written on request)
   const float* epsp;          // [6][ninst][nz][ny][nx] or null
   const uint8_t* gid;         // [nz][ny][nx] or null (one instance only)
@@ -118,16 +121,16 @@ int x_blocks(const KArgs& a);
 int z_blocks(const KArgs& a, int ncomp);
 hipError_t step_begin(const KArgs& a, hipStream_t s);
 hipError_t ms_x_forward(const KArgs& a, hipStream_t s);
-hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
 hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t ms_z_green(const KArgs& a, hipStream_t s);
 hipError_t ms_x_inverse(const KArgs& a, hipStream_t s);
-hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward(const KArgs& a, hipStream_t s);
 hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);  // mode 0 update, 1 energy only
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
+hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
+hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
+hipError_t kh_mean(const KArgs& a, hipStream_t s);  // the step's load + mean fields (spectral path)
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s);  // 0 step, 1 init, 2 spectral path
-hipError_t kh_mean(const KArgs& a, hipStream_t s);
 hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s);  // 0 update, 1 L dt dF/df
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s);
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);

@@ -25,7 +25,8 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
   const int rpi = a.nz * a.ny;
-  const DevState* st = a.state + blockIdx.x * ROWS / rpi;
+  const int inst = blockIdx.x * ROWS / rpi;
+  const DevState* st = a.state + inst;
   if (st->st.done) return;
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
@@ -54,8 +55,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
         old_n[m] = valid ? *reinterpret_cast<const float2*>(a.eps + (c + 1) * vs + rbase + 2 * (t + T * m))
                          : make_float2(0.f, 0.f);
     }
-    const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
-    const float shift = (float)(st->ebar_cur[c] - base);
+    const float shift = (float)(st->ebar_cur[c] - st->ebar_base[c]);
     const float w = c < 3 ? 1.f : 2.f;
     float2 v[E];
     c2r_from_regs<M>(v, cur, lds + p * LROW, t, a.tw_xh, a.tw_x);
@@ -64,17 +64,21 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const size_t off = c * vs + rbase + 2 * (t + T * m);
-        const float2 stored = old_c[m];
-        float2 old = stored;
-        if (a.iter_mode == 2) {
-          const float2 q = *reinterpret_cast<const float2*>(a.eps_prev + off);
-          old = make_float2(2.f * stored.x - q.x, 2.f * stored.y - q.y);
+        float2 old = old_c[m];
+        if (a.iter_mode >= 1) {
+          const float2 p1 = *reinterpret_cast<const float2*>(a.eps_h1 + off);
+          if (a.iter_mode == 1) {
+            old = make_float2(2.f * old.x - p1.x, 2.f * old.y - p1.y);
+          } else {
+            const float2 p2 = *reinterpret_cast<const float2*>(a.eps_h2 + off);
+            old = make_float2(3.f * (old.x - p1.x) + p2.x, 3.f * (old.y - p1.y) + p2.y);
+          }
         }
-        if (a.iter_mode >= 1) *reinterpret_cast<float2*>(a.eps_prev + off) = stored;
         const float dx0 = v[m].x - (old.x + shift), dx1 = v[m].y - (old.y + shift);
         dsum += dx0 * dx0 + dx1 * dx1;
         nsum += v[m].x * v[m].x + v[m].y * v[m].y;
-        *reinterpret_cast<float2*>(a.eps + off) = v[m];
+        // the output may be eps_h2 (the oldest field): read above, same element
+        *reinterpret_cast<float2*>(a.eps_out + off) = v[m];
       }
     }
     acc[0] += (double)(w * dsum);
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
 //   B_ab(n) = eps0_a : C : eps0_b - (sigma0_a n) . K(n)^{-1} (sigma0_b n),
 // with sigma0_a = C : eps0_a and K(n) = C n n; B = 0 at the ambiguous Nyquist
 // wavevectors (stress-free there, as in the fixed point). At xi = 0 the mean
-// strain follows from the mixed condition (k_kh_mean). Components 0..V-1 hold f_hat on
+// strain follows from the mixed condition (kh_begin_mean). Components 0..V-1 hold f_hat on
 // entry and the new order parameters' spectra on exit; V..2V-1 hold the
 // transform of f - L dt chem. FP64 partials: gradient sum of the new state
 // and the fluctuation part of the elastic energy.
@@ -599,33 +603,34 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_resid(const KArgs a, const 
   block_minmax(0.f, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
 
-__global__ __launch_bounds__(1024) void k_resid_fin(const KArgs a, int nblk) {
-  const int inst = blockIdx.x;
-  __shared__ float mm[2];
-  const float* pm = a.part_mm + 2 * (size_t)inst * nblk;
-  float mx = 0.f;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x) mx = fmaxf(mx, pm[2 * b + 1]);
-  block_minmax(0.f, mx, mm);
-  if (threadIdx.x == 0) a.state[inst].resid_max = mm[1];
-}
 
 // ------------------------------------------------------------ small kernels
-// One thread per instance: take the step's load, reset the iteration status.
+// One thread per instance: take the step's load, reset the iteration status,
+// shift the history of converged mean strains (the field in memory is the
+// latest converged one) and set the mean of the first iterate: the load for
+// strain-controlled components, the extrapolated mean (as the field itself)
+// for stress-controlled ones.
 __global__ void k_step_begin(const KArgs a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.ninst) return;
   DevState* st = a.state + i;
   const double* ld = a.loads + 12 * (size_t)i;
   for (int c = 0; c < 6; ++c) {
+    st->ebar_h[2][c] = st->ebar_h[1][c];
+    st->ebar_h[1][c] = st->ebar_h[0][c];
+    st->ebar_h[0][c] = st->ebar_field[c];
+    const double l = st->ebar_h[0][c], p1 = st->ebar_h[1][c], p2 = st->ebar_h[2][c];
+    const double base = a.iter_mode == 2 ? 3.0 * (l - p1) + p2 : (a.iter_mode == 1 ? 2.0 * l - p1 : l);
+    st->ebar_base[c] = base;
     st->eps_target[c] = ld[c];
     st->sig_target[c] = ld[6 + c];
-    if (!((a.stress_mask >> c) & 1u)) st->ebar_cur[c] = ld[c];
-    else if (a.iter_mode == 2) st->ebar_cur[c] = 2.0 * st->ebar_field[c] - st->ebar_prev[c];
+    st->ebar_cur[c] = ((a.stress_mask >> c) & 1u) ? base : ld[c];
   }
   st->st.done = 0;
   st->st.iters = 0;
 }
 
+// -------------------------------------------------------------- finalizes
 // Deterministic sum over nblk blocks of Q partials: each thread sums a fixed
 // strided subset in block order, then a fixed-shape tree.
 template <int Q>
@@ -643,18 +648,119 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   __syncthreads();
 }
 
-// Mean fields of the homogeneous spectral path, one block per instance:
-// <f_a> from the FP64 sums of the forward x pass; the mean strain from the
+// Partial-sum blocks per instance written by the z passes: the Allen-Cahn
+// pass (16-column tiles, one per variant), the spectral path (16 columns for
+// one variant, else 8).
+__host__ __device__ inline int z_partials_inst(const KArgs& a, int mode) {
+  if (mode == 2) {
+    const int C = a.nv == 1 ? kColTile : kZmsTile;
+    return ((a.nh + C - 1) / C) * a.ny;
+  }
+  return ((a.nh + kColTile - 1) / kColTile) * a.ny * a.nv;
+}
+
+// Mixed condition after the forward x pass of an iteration: the mean strain
+// of the next iterate.
+__device__ inline void fin_ms(const KArgs& a, int inst, int nblk) {
+  DevState* st = a.state + inst;
+  double s[kQms];
+  sum_partials<kQms>(a.part_ms + (size_t)inst * nblk * kQms, nblk, s);
+  if (threadIdx.x != 0) return;
+  const double* Bss = a.bss + 36 * (size_t)inst;
+  const double ntot = (double)a.nx * a.ny * a.nz;
+  double r[6];
+  for (int c = 0; c < 6; ++c) r[c] = s[c] / ntot - st->sig_target[c];
+  for (int i = 0; i < 6; ++i) {
+    if ((a.stress_mask >> i) & 1u) {
+      double d = 0.0;
+      for (int j = 0; j < 6; ++j)
+        if ((a.stress_mask >> j) & 1u) d += Bss[6 * i + j] * r[j];
+      st->ebar_next[i] = st->ebar_cur[i] - d;
+    } else {
+      st->ebar_next[i] = st->eps_target[i];
+    }
+  }
+}
+
+// Convergence test after the inverse x pass of an iteration.
+__device__ inline void fin_res(const KArgs& a, int inst, int nblk) {
+  DevState* st = a.state + inst;
+  double s[kQres];
+  sum_partials<kQres>(a.part_res + (size_t)inst * nblk * kQres, nblk, s);
+  if (threadIdx.x != 0) return;
+  const double r = s[1] > 0.0 ? sqrt(s[0] / s[1]) : (s[0] > 0.0 ? 1.0e300 : 0.0);
+  st->st.residual = r;
+  st->st.iters += 1;
+  st->st.done = r <= a.tol ? 1 : 0;
+  for (int c = 0; c < 6; ++c) {
+    st->ebar_field[c] = st->ebar_next[c];
+    st->ebar_cur[c] = st->ebar_next[c];
+    st->ebar_base[c] = st->ebar_next[c];
+  }
+}
+
+// Stats of the step (raw sums; the host scales them) and the gradient sum of
+// the new state. mode 0: fixed-point path; 1: only the gradient sum of the
+// initial state; 2: homogeneous spectral path (stress, strain and the
+// mean-field elastic energy from the mean kernel).
+__device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, int mode) {
+  DevState* st = a.state + inst;
+  double gd[kQgd];
+  sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd);
+  if (mode == 1) {
+    if (threadIdx.x == 0) st->gd_cur = gd[0];
+    return;
+  }
+  double s[kQac];
+  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, s);
+  double bad[kQres];
+  sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad);
+  __shared__ float mm[2];
+  const float* pm = a.part_mm + 2 * (size_t)inst * nblk_x;
+  float mn = 3.0e38f, mx = -3.0e38f;
+  for (int b = threadIdx.x; b < nblk_x; b += blockDim.x) {
+    mn = fminf(mn, pm[2 * b]);
+    mx = fmaxf(mx, pm[2 * b + 1]);
+  }
+  block_minmax(mn, mx, mm);
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
+  if (mode == 2) {
+    const double ntot = (double)a.nx * a.ny * a.nz;
+    st->stats[1] = st->mean_kh[12] + 0.5 * gd[1] / ntot;
+    for (int c = 0; c < 6; ++c) {
+      st->stats[2 + c] = st->mean_kh[c];
+      st->stats[8 + c] = st->mean_kh[6 + c];
+    }
+    st->st.iters = 1;
+    st->st.residual = 0.0;
+    st->st.done = 1;
+  }
+  st->stats[kQac] = st->gd_cur;
+  st->stats[kQac + 1] = mm[0];
+  st->stats[kQac + 2] = mm[1];
+  st->gd_cur = gd[0];
+  if (bad[0] > 0.0) st->st.nonfinite = 1;
+}
+
+// Homogeneous spectral path after its forward x pass: the step's load and
+// status, <f_a> from the FP64 sums of the pass; the mean strain from the
 // mixed condition, <sigma>_S = sigma_bar_S with <eps>_E = eps_bar_E and
 // <sigma> = C : (<eps> - sum_a <f_a> eps0_a); the mean elastic force
 // <sigma> : eps0_a (added to the xi = 0 coefficient by the z pass) and the
 // mean-field part of the elastic energy.
-__global__ __launch_bounds__(1024) void k_kh_mean(const KArgs a, int nblk) {
-  const int inst = blockIdx.x;
+__device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk) {
   double s[kQac];
   sum_partials<kQac>(a.part_ac + (size_t)inst * nblk * kQac, nblk, s);
   if (threadIdx.x != 0) return;
   DevState* st = a.state + inst;
+  const double* ld = a.loads + 12 * (size_t)inst;
+  for (int c = 0; c < 6; ++c) {
+    st->eps_target[c] = ld[c];
+    st->sig_target[c] = ld[6 + c];
+  }
+  st->st.done = 0;
+  st->st.iters = 0;
   const double* kd = a.khd + (size_t)inst * kKhdStride;
   const double ntot = (double)a.nx * a.ny * a.nz;
   double es[6] = {0, 0, 0, 0, 0, 0};
@@ -663,9 +769,9 @@ __global__ __launch_bounds__(1024) void k_kh_mean(const KArgs a, int nblk) {
     for (int c = 0; c < 6; ++c) es[c] += fr * kd[72 + 6 * r + c];
   }
   double d[6], rs[6];
-  for (int c = 0; c < 6; ++c) d[c] = ((a.stress_mask >> c) & 1u) ? 0.0 : st->eps_target[c] - es[c];
+  for (int c = 0; c < 6; ++c) d[c] = ((a.stress_mask >> c) & 1u) ? 0.0 : ld[c] - es[c];
   for (int i = 0; i < 6; ++i) {
-    double acc = st->sig_target[i];
+    double acc = ld[6 + i];
     for (int j = 0; j < 6; ++j) acc -= kd[6 * i + j] * d[j];
     rs[i] = acc;
   }
@@ -695,93 +801,36 @@ __global__ __launch_bounds__(1024) void k_kh_mean(const KArgs a, int nblk) {
   }
 }
 
-// Finalize kernels: one block per instance; nblk partial blocks per instance.
+// Macro-step residual: max over the instance's blocks.
+__device__ inline void resid_fin(const KArgs& a, int inst, int nblk) {
+  __shared__ float mm[2];
+  const float* pm = a.part_mm + 2 * (size_t)inst * nblk;
+  float mx = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) mx = fmaxf(mx, pm[2 * b + 1]);
+  block_minmax(0.f, mx, mm);
+  if (threadIdx.x == 0) a.state[inst].resid_max = mm[1];
+}
+
+// One-block-per-instance finalize kernels. (Folding them into the last
+// block of the x passes needs a device-scope fence in every block, which on
+// this multi-L2 part writes back the L2 and costs far more than a launch.)
 __global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
-  const int inst = blockIdx.x;
-  DevState* st = a.state + inst;
-  if (st->st.done) return;
-  double s[kQms];
-  sum_partials<kQms>(a.part_ms + (size_t)inst * nblk * kQms, nblk, s);
-  if (threadIdx.x != 0) return;
-  const double* Bss = a.bss + 36 * (size_t)inst;
-  const double ntot = (double)a.nx * a.ny * a.nz;
-  double r[6];
-  for (int c = 0; c < 6; ++c) r[c] = s[c] / ntot - st->sig_target[c];
-  for (int i = 0; i < 6; ++i) {
-    if ((a.stress_mask >> i) & 1u) {
-      double d = 0.0;
-      for (int j = 0; j < 6; ++j)
-        if ((a.stress_mask >> j) & 1u) d += Bss[6 * i + j] * r[j];
-      st->ebar_next[i] = st->ebar_cur[i] - d;
-    } else {
-      st->ebar_next[i] = st->eps_target[i];
-    }
-  }
+  if (a.state[blockIdx.x].st.done) return;
+  fin_ms(a, blockIdx.x, nblk);
 }
 
 __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
-  const int inst = blockIdx.x;
-  DevState* st = a.state + inst;
-  if (st->st.done) return;
-  double s[kQres];
-  sum_partials<kQres>(a.part_res + (size_t)inst * nblk * kQres, nblk, s);
-  if (threadIdx.x != 0) return;
-  const double r = s[1] > 0.0 ? sqrt(s[0] / s[1]) : (s[0] > 0.0 ? 1.0e300 : 0.0);
-  st->st.residual = r;
-  st->st.iters += 1;
-  st->st.done = r <= a.tol ? 1 : 0;
-  for (int c = 0; c < 6; ++c) {
-    if (a.iter_mode >= 1) st->ebar_prev[c] = st->ebar_field[c];
-    st->ebar_field[c] = st->ebar_next[c];
-    st->ebar_cur[c] = st->ebar_next[c];
-  }
+  if (a.state[blockIdx.x].st.done) return;
+  fin_res(a, blockIdx.x, nblk);
 }
 
-// Stats of the step (raw sums; the host scales them) and the gradient sum of
-// the new state. mode 0: fixed-point path; 1: only the gradient sum of the
-// initial state; 2: homogeneous spectral path (stress, strain and the
-// mean-field elastic energy from the z pass).
 __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int mode) {
-  const int inst = blockIdx.x;
-  DevState* st = a.state + inst;
-  double gd[kQgd];
-  sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd);
-  if (mode == 1) {
-    if (threadIdx.x == 0) st->gd_cur = gd[0];
-    return;
-  }
-  double s[kQac];
-  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, s);
-  double bad[kQres];
-  sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad);
-  // extrema
-  __shared__ float mm[2];
-  const float* pm = a.part_mm + 2 * (size_t)inst * nblk_x;
-  float mn = 3.0e38f, mx = -3.0e38f;
-  for (int b = threadIdx.x; b < nblk_x; b += blockDim.x) {
-    mn = fminf(mn, pm[2 * b]);
-    mx = fmaxf(mx, pm[2 * b + 1]);
-  }
-  block_minmax(mn, mx, mm);
-  if (threadIdx.x != 0) return;
-  for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
-  if (mode == 2) {
-    const double ntot = (double)a.nx * a.ny * a.nz;
-    st->stats[1] = st->mean_kh[12] + 0.5 * gd[1] / ntot;
-    for (int c = 0; c < 6; ++c) {
-      st->stats[2 + c] = st->mean_kh[c];
-      st->stats[8 + c] = st->mean_kh[6 + c];
-    }
-    st->st.iters = 1;
-    st->st.residual = 0.0;
-    st->st.done = 1;
-  }
-  st->stats[kQac] = st->gd_cur;
-  st->stats[kQac + 1] = mm[0];
-  st->stats[kQac + 2] = mm[1];
-  st->gd_cur = gd[0];
-  if (bad[0] > 0.0) st->st.nonfinite = 1;
+  fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode);
 }
+
+__global__ __launch_bounds__(1024) void k_kh_mean(const KArgs a, int nblk) { kh_begin_mean(a, blockIdx.x, nblk); }
+
+__global__ __launch_bounds__(1024) void k_resid_fin(const KArgs a, int nblk) { resid_fin(a, blockIdx.x, nblk); }
 
 }  // namespace pft
 
@@ -869,10 +918,6 @@ hipError_t ms_x_forward(const KArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s) {
-  k_fin_ms<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
-  return hipGetLastError();
-}
 
 hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
   const dim3 grid((a.nh + kColTile - 1) / kColTile, a.nz * a.ninst, ncomp);
@@ -881,6 +926,21 @@ hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
   } else {
     PF_SWITCH_N(a.ny, (k_y<N, -1><<<grid, col_block<N>(), 0, s>>>(a)));
   }
+  return hipGetLastError();
+}
+
+hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s) {
+  k_fin_ms<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
+  return hipGetLastError();
+}
+
+hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
+  k_fin_res<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
+  return hipGetLastError();
+}
+
+hipError_t kh_mean(const KArgs& a, hipStream_t s) {
+  k_kh_mean<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
   return hipGetLastError();
 }
 
@@ -896,10 +956,6 @@ hipError_t ms_x_inverse(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
-  k_fin_res<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
-  return hipGetLastError();
-}
 
 hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
   switch (a.nv) {
@@ -925,19 +981,8 @@ hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// The z-pass partials of an instance: the Allen-Cahn pass writes
-// ntile16 * ny * nv blocks, the spectral path ntile(V) * ny; the finalize reads
-// exactly the count the preceding z pass wrote.
-static int z_written(const KArgs& a, int mode) {
-  if (mode == 2) {
-    const int C = a.nv == 1 ? kColTile : kZmsTile;
-    return ((a.nh + C - 1) / C) * a.ny;
-  }
-  return ((a.nh + kColTile - 1) / kColTile) * a.ny * a.nv;
-}
-
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s) {
-  k_fin_ac<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a), z_written(a, mode), mode);
+  k_fin_ac<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a), z_partials_inst(a, mode), mode);
   return hipGetLastError();
 }
 
@@ -957,10 +1002,6 @@ hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream
   return hipGetLastError();
 }
 
-hipError_t kh_mean(const KArgs& a, hipStream_t s) {
-  k_kh_mean<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
-  return hipGetLastError();
-}
 
 hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s) {
   switch (a.nv) {

@@ -29,23 +29,28 @@ struct Sample {
   int g0, g1;
 };
 
-// Strain of the first iterate of a step: the stored field, or its linear
-// extrapolation 2 eps - eps_prev from the two previous steps.
+// Strain of the first iterate of a step: the stored (latest converged)
+// field L, or its extrapolation from the converged fields of the previous
+// steps: linear 2 L - P, quadratic 3 (L - P) + P2.
 __device__ __forceinline__ void extrapolate_strain(const KArgs& a, bool valid, size_t vs, size_t off,
                                                    float2 (&e)[6]) {
-  if (a.iter_mode != 2 || !valid) return;
+  if (a.iter_mode == 0 || !valid) return;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
-    const float2 q = *reinterpret_cast<const float2*>(a.eps_prev + c * vs + off);
-    e[c] = make_float2(2.f * e[c].x - q.x, 2.f * e[c].y - q.y);
+    const float2 p1 = *reinterpret_cast<const float2*>(a.eps_h1 + c * vs + off);
+    if (a.iter_mode == 1) {
+      e[c] = make_float2(2.f * e[c].x - p1.x, 2.f * e[c].y - p1.y);
+    } else {
+      const float2 p2 = *reinterpret_cast<const float2*>(a.eps_h2 + c * vs + off);
+      e[c] = make_float2(3.f * (e[c].x - p1.x) + p2.x, 3.f * (e[c].y - p1.y) + p2.y);
+    }
   }
 }
 
-// Offset added to the strain read in the first iterate so its mean is the
+// Offset added to the strain the iterate is formed from so its mean is the
 // iterate's prescribed mean.
 __device__ __forceinline__ float mean_shift(const KArgs& a, const DevState* st, int c) {
-  const double base = a.iter_mode == 2 ? 2.0 * st->ebar_field[c] - st->ebar_prev[c] : st->ebar_field[c];
-  return (float)(st->ebar_cur[c] - base);
+  return (float)(st->ebar_cur[c] - st->ebar_base[c]);
 }
 
 template <int V>
