@@ -146,17 +146,44 @@ __device__ __forceinline__ void rotate_sym(const float (&R)[9], const float (&A)
   }
 }
 
+// A wave-uniform table of up to 192 floats held one value per lane in three
+// VGPRs; element i is read with v_readlane (one VALU instruction per distinct
+// element and iteration, CSE-able across the voxels of an iteration; the
+// result is a scalar operand). A table this size does not fit in scalar
+// registers, and the compiler's own spill of it reloads on every use.
+struct LaneTab {
+  float v[3];
+  int base;
+  __device__ __forceinline__ LaneTab operator+(int o) const {
+    LaneTab t = *this;
+    t.base += o;
+    return t;
+  }
+  __device__ __forceinline__ float operator[](int i) const {
+    const int k = base + i;
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[k >> 6]), k & 63));
+  }
+};
+
+__device__ __forceinline__ LaneTab load_lanetab(const float* tab, int n) {
+  LaneTab t;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) t.v[j] = (64 * j + lane < n) ? tab[64 * j + lane] : 0.f;
+  t.base = 0;
+  return t;
+}
+
 template <int V>
-__device__ __forceinline__ void constitutive_rot(const KArgs& a, const float e[6], const float eta[V],
+__device__ __forceinline__ void constitutive_rot(const LaneTab& xt, int hk, const float e[6], const float eta[V],
                                                  const float ep[6], const float (&R)[9], MatR<V>& o) {
   float h[V];
 #pragma unroll
-  for (int q = 0; q < V; ++q) h[q] = h_of(eta[q], a.h_kind);
+  for (int q = 0; q < V; ++q) h[q] = h_of(eta[q], hk);
   float d[6], dc[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) d[c] = e[c] - ep[c];
   rotate_sym<true>(R, d, dc);
-  const float* xt = a.xtab;
 #pragma unroll
   for (int c = 0; c < 6; ++c) {
     float es = 0.f;

@@ -19,6 +19,11 @@
 #ifndef PF_NV
 #error "PF_NV (number of twin variants) must be defined"
 #endif
+// waves per SIMD the forward x passes are compiled for (their LDS staging
+// allows three blocks of 256 threads per CU)
+#ifndef PF_XWAVES
+#define PF_XWAVES 3
+#endif
 
 namespace pft {
 
@@ -109,26 +114,28 @@ __device__ __forceinline__ void variant_terms(TP tab, const float (&sig_m)[6], c
   }
 }
 
-template <int V, bool ROT, bool AC>
-__device__ __forceinline__ void eval_voxel(const KArgs& a, const float* tabs, const float (&e)[6],
+// HK: the interpolation h (PF_H_LINEAR or PF_H_QUINTIC) as a constant, so
+// the linear case carries no polynomial.
+template <int V, bool ROT, bool AC, int HK>
+__device__ __forceinline__ void eval_voxel(const KArgs& a, const LaneTab& xt, const float* tabs, const float (&e)[6],
                                            const float (&et)[V], const float (&ep)[6], int g, VoxelOut& o,
                                            float (&work)[V], float (&quad)[V]) {
   if constexpr (ROT) {
     float R[9];
     load_rotation(a, g, R);
     MatR<V> m;
-    constitutive_rot<V>(a, e, et, ep, R, m);
+    constitutive_rot<V>(xt, HK, e, et, ep, R, m);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       o.sig[c] = m.sig[c];
       o.sig_m[c] = m.sig_c[c];
       o.gam_m[c] = m.gam_c[c];
     }
-    if constexpr (AC) variant_terms<V>(a.xtab, o.sig_m, o.gam_m, work, quad);
+    if constexpr (AC) variant_terms<V>(xt, o.sig_m, o.gam_m, work, quad);
   } else {
     with_table(a, tabs, g, [&](auto tab) {
       Mat<V> m;
-      constitutive<V>(e, et, ep, tab, a.h_kind, m);
+      constitutive<V>(e, et, ep, tab, HK, m);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         o.sig[c] = m.sig[c];
@@ -153,8 +160,8 @@ __device__ __forceinline__ float chem_force(float A, const float (&et)[V], float
 
 // Fixed point, forward: polarisation tau = C(x):(eps - eps*) - C0:eps of
 // every voxel, FP64 sum of the stress, R2C of the six components.
-template <int M, int V, bool ROT>
-__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
+template <int M, int V, bool ROT, int HK>
+__global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(PF_XWAVES))) void k_x_fwd_ms(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[6 * ROWS * LROW];
@@ -164,6 +171,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
   if (st->st.done) return;
   const ctab_t C0 = (ctab_t)(a.ref + (size_t)inst * kRefStride);
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
+  const LaneTab xt = ROT ? load_lanetab(a.xtab, 21 + 27 * V) : LaneTab{};
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
@@ -193,7 +201,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
       for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
       VoxelOut vo;
       float work[V], quad[V];
-      eval_voxel<V, ROT, false>(a, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
+      eval_voxel<V, ROT, false, HK>(a, xt, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
       float ge[6], c0e[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) ge[c] = c < 3 ? e[c] : 2.f * e[c];
@@ -227,14 +235,15 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ms(const KArgs a) {
 // Phase-field update, forward: driving forces and the explicit right-hand
 // side RHS_a = f_a - L dt (chem_a - mech_a) of every voxel, FP64 energy and
 // mean sums, extrema of f; R2C of the V right-hand sides.
-template <int M, int V, bool ROT>
-__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
+template <int M, int V, bool ROT, int HK>
+__global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(PF_XWAVES))) void k_x_fwd_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[V * ROWS * LROW];
   const int rpi = a.nz * a.ny;
   const int inst = blockIdx.x * ROWS / rpi;
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
+  const LaneTab xt = ROT ? load_lanetab(a.xtab, 21 + 27 * V) : LaneTab{};
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
       for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
       VoxelOut vo;
       float work[V], quad[V];
-      eval_voxel<V, ROT, true>(a, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
+      eval_voxel<V, ROT, true, HK>(a, xt, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
       float fm = 1.f;
 #pragma unroll
       for (int q = 0; q < V; ++q) fm -= et[q];
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ac(const KArgs a) {
 #pragma unroll
       for (int q = 0; q < V; ++q) {
         // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
-        const float mech = dh_of(et[q], a.h_kind) * (work[q] - 0.5f * quad[q]);
+        const float mech = dh_of(et[q], HK) * (work[q] - 0.5f * quad[q]);
         o[half][q] = et[q] - a.LDt * (chem_force<V>(a.A, et, fm, q) - mech);
       }
       if (valid) {
@@ -430,13 +439,23 @@ using namespace pft;
     default: return hipErrorInvalidValue;              \
   }
 
+#define PF_LAUNCH_X(KERNEL)                                                                    \
+  do {                                                                                         \
+    const dim3 grid(x_blocks(a));                                                              \
+    const bool q = a.h_kind == 1;                                                              \
+    if (a.rot && q) {                                                                          \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, true, 1><<<grid, xthreads<M>(), 0, s>>>(a)));   \
+    } else if (a.rot) {                                                                        \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, true, 0><<<grid, xthreads<M>(), 0, s>>>(a)));   \
+    } else if (q) {                                                                            \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, false, 1><<<grid, xthreads<M>(), 0, s>>>(a)));  \
+    } else {                                                                                   \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, false, 0><<<grid, xthreads<M>(), 0, s>>>(a)));  \
+    }                                                                                          \
+  } while (0)
+
 hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
-  const dim3 grid(x_blocks(a));
-  if (a.rot) {
-    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ms<M, PF_NV, true><<<grid, xthreads<M>(), 0, s>>>(a)));
-  } else {
-    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ms<M, PF_NV, false><<<grid, xthreads<M>(), 0, s>>>(a)));
-  }
+  PF_LAUNCH_X(k_x_fwd_ms);
   return hipGetLastError();
 }
 
@@ -449,12 +468,7 @@ hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, int resid, hipStream_t 
 #endif
 
 hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
-  const dim3 grid(x_blocks(a));
-  if (a.rot) {
-    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ac<M, PF_NV, true><<<grid, xthreads<M>(), 0, s>>>(a)));
-  } else {
-    PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ac<M, PF_NV, false><<<grid, xthreads<M>(), 0, s>>>(a)));
-  }
+  PF_LAUNCH_X(k_x_fwd_ac);
   return hipGetLastError();
 }
 
