@@ -933,6 +933,7 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         float* out = g.ring[(g.cur + 1) % 3];
         KArgs& f = first[k];
         f = g.args;
+        f.skip_done = 1;
         f.eps = g.ring[g.cur];
         f.eps_out = out;
         f.eps_h1 = g.ring[(g.cur + 2) % 3];
@@ -940,6 +941,7 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         f.iter_mode = order;
         KArgs& l = later[k];
         l = g.args;
+        l.skip_done = 1;
         l.eps = out;
         l.eps_out = out;
         l.eps_h1 = l.eps_h2 = nullptr;

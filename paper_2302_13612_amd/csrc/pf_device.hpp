@@ -7,7 +7,10 @@ namespace pft {
 
 constexpr int kMaxVar = 6;
 constexpr int kColTile = 16;       // spectral columns per y/z block
-constexpr int kZmsTile = 8;        // spectral columns per block of the Green z pass
+#ifndef PF_ZMS_TILE
+#define PF_ZMS_TILE 8
+#endif
+constexpr int kZmsTile = PF_ZMS_TILE;  // spectral columns per block of the Green z pass
 
 // Quantities reduced per block (FP64 partial sums / extrema).
 constexpr int kQms = 6;                 // sum of stress (mixed condition)
@@ -104,6 +107,7 @@ struct KArgs {
   double* part_gd;
   DevState* state;            // [ninst]
   int save_stress;
+  int skip_done;              // y pass: skip instances whose fixed point has converged
 };
 
 // Packed upper-triangle index of a symmetric 6x6 matrix.

@@ -184,6 +184,8 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_y(const KArgs a
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
   const int z = blockIdx.y, comp = blockIdx.z;  // z over all instances
+  // transforms of a fixed-point iteration are skipped for a converged instance
+  if (a.skip_done && a.state[z / a.nz].st.done) return;
   const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
   float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.sh + (valid ? kx : 0);
   float2 v[E];

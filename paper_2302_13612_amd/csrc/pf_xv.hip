@@ -100,16 +100,22 @@ template <int V, class TP>
 __device__ __forceinline__ void variant_terms(TP tab, const float (&sig_m)[6], const float (&gam_m)[6],
                                               float (&work)[V], float (&quad)[V]) {
   const auto e0 = tab + 21 * (V + 1);
+  // quad_q = sum_ij dC_q,ij g_i g_j over the packed upper triangle: the 21
+  // products (off-diagonal ones doubled) are shared by the variants
+  float gg[21];
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+#pragma unroll
+    for (int j = i; j < 6; ++j) gg[sym6(i, j)] = (i == j ? 1.f : 2.f) * gam_m[i] * gam_m[j];
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const auto e0q = e0 + 6 * q;
     work[q] = sig_m[0] * e0q[0] + sig_m[1] * e0q[1] + sig_m[2] * e0q[2] +
               2.f * (sig_m[3] * e0q[3] + sig_m[4] * e0q[4] + sig_m[5] * e0q[5]);
-    float dcg[6];
-    symv6(tab + 21 * (q + 1), gam_m, dcg);
+    const auto dq = tab + 21 * (q + 1);
     float s = 0.f;
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s += gam_m[c] * dcg[c];
+    for (int k = 0; k < 21; ++k) s += dq[k] * gg[k];
     quad[q] = s;
   }
 }
