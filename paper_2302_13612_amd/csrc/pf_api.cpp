@@ -507,23 +507,30 @@ int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
   return PF_OK;
 }
 
-// The whole homogeneous spectral step of a group.
-int kh_step(pf_ctx* c, const Group& g, hipStream_t s) {
+// The statistics of the homogeneous spectral path (reductions of the step's
+// passes); needed after the last step of a call only: every pass of a step
+// reduces what that step needs itself.
+int kh_finalize(pf_ctx* c, const Group& g, hipStream_t s) {
+  const KArgs& a = g.args;
+  return launch(c, s, "kh_finalize", [&] { return pfl::ac_finalize(a, 2, s); });
+}
+
+// The whole homogeneous spectral step of a group (statistics on request).
+int kh_step(pf_ctx* c, const Group& g, bool fin, hipStream_t s) {
   const KArgs& a = g.args;
   PF_TRY(launch(c, s, "kh_x_forward", [&] { return pfl::kh_x_forward(a, 0, s); }));
-  PF_TRY(launch(c, s, "kh_mean", [&] { return pfl::kh_mean(a, s); }));
   PF_TRY(launch(c, s, "kh_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
   PF_TRY(launch(c, s, "kh_z_update", [&] { return pfl::kh_z_update(a, 0, s); }));
   PF_TRY(launch(c, s, "kh_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
   PF_TRY(launch(c, s, "kh_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
-  PF_TRY(launch(c, s, "kh_finalize", [&] { return pfl::ac_finalize(a, 2, s); }));
+  if (fin) PF_TRY(kh_finalize(c, g, s));
   return PF_OK;
 }
 
 // One step of a group that needs no host decision (spectral path or one
-// fixed-point iteration).
-int fixed_step(pf_ctx* c, const Group& g, bool kh, hipStream_t s) {
-  if (kh) return kh_step(c, g, s);
+// fixed-point iteration); fin: the spectral path's statistics too.
+int fixed_step(pf_ctx* c, const Group& g, bool kh, bool fin, hipStream_t s) {
+  if (kh) return kh_step(c, g, fin, s);
   KArgs ab = g.args;
   ab.iter_mode = 0;
   PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(ab, s); }));
@@ -551,7 +558,7 @@ int run_graph(pf_ctx* c, int n_steps, const std::vector<char>& use_kh, const std
     c->capturing = true;
     int rc = PF_OK;
     for (size_t k = 0; k < c->groups.size() && rc == PF_OK; ++k)
-      rc = fixed_step(c, c->groups[k], use_kh[k] != 0, c->cap_stream);
+      rc = fixed_step(c, c->groups[k], use_kh[k] != 0, false, c->cap_stream);
     c->capturing = false;
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(c->cap_stream, &graph);
@@ -570,6 +577,8 @@ int run_graph(pf_ctx* c, int n_steps, const std::vector<char>& use_kh, const std
   }
   for (int n = 0; n < n_steps; ++n)
     if ((e = hipGraphLaunch(c->gexec, c->stream)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  for (size_t k = 0; k < c->groups.size(); ++k)
+    if (use_kh[k]) PF_TRY(kh_finalize(c, c->groups[k], c->stream));
   return PF_OK;
 }
 
@@ -918,7 +927,7 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
       for (size_t k = 0; k < c->groups.size(); ++k) {
         Group& g = c->groups[k];
         if (use_kh[k] || g.one_iteration) {
-          PF_TRY(fixed_step(c, g, use_kh[k] != 0, s));
+          PF_TRY(fixed_step(c, g, use_kh[k] != 0, n == n_steps - 1, s));
           continue;
         }
         iterating.push_back(k);
@@ -1194,7 +1203,6 @@ int pf_macro_residual(pf_ctx* c, const float* eta_prev, int32_t n_steps, const p
   const KArgs& a = g.args;
   hipStream_t s = c->stream;
   PF_TRY(launch(c, s, "res_x_forward", [&] { return pfl::kh_x_forward(a, 1, s); }));
-  PF_TRY(launch(c, s, "res_mean", [&] { return pfl::kh_mean(a, s); }));
   PF_TRY(launch(c, s, "res_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
   PF_TRY(launch(c, s, "res_z", [&] { return pfl::kh_z_update(a, 1, s); }));
   PF_TRY(launch(c, s, "res_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));

@@ -16,7 +16,8 @@ constexpr int kZmsTile = PF_ZMS_TILE;  // spectral columns per block of the Gree
 constexpr int kQms = 6;                 // sum of stress (mixed condition)
 constexpr int kQres = 2;                // |eps_new - eps_old|^2, |eps_new|^2
 constexpr int kQac = 2 + 6 + 6 + kMaxVar;  // G_dw, G_me, sum sigma, sum eps, sum eta
-constexpr int kQgd = 2;                 // Parseval gradient sum, spectral elastic energy
+constexpr int kQgd = 3;                 // Parseval gradient sum (new state), spectral elastic
+                                        // energy, gradient sum of the starting state (spectral path)
 
 // Status copied back to the host after each fixed-point iteration.
 struct Status {
@@ -133,9 +134,10 @@ hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);  // mode 0 upda
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
-hipError_t kh_mean(const KArgs& a, hipStream_t s);  // the step's load + mean fields (spectral path)
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s);  // 0 step, 1 init, 2 spectral path
-hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s);  // 0 update, 1 L dt dF/df
+// 0 update, 1 L dt dF/df; the block owning xi = 0 of an instance first takes
+// the step's load and the mean fields (kh_begin_mean)
+hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s);
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s);
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s);
@@ -160,7 +162,7 @@ hipError_t kh_x_forward_v3(const KArgs& a, int resid, hipStream_t s);
 hipError_t kh_x_forward(const KArgs& a, int resid, hipStream_t s);
 // Residual of a macro step of n_steps plain steps ending at the current
 // order parameter f~: r = f~ - prev + n_steps L dt dF/df(f~), after
-// kh_x_forward(resid = 1), kh_mean, y forward (2V) and kh_z_update(mode 1),
+// kh_x_forward(resid = 1), y forward (2V) and kh_z_update(mode 1),
 // y inverse (V): per-instance max |r| into DevState::resid_max.
 hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
 }  // namespace pfl

@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const int sy = signed_k(ky, a.ny);
   const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
-  double en[kQgd] = {0.0, 0.0};
+  double en[kQgd] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int sz = signed_k(t + T * m, a.nz);
@@ -446,13 +446,20 @@ __host__ __device__ constexpr int kh_tile() { return V == 1 ? kColTile : kZmsTil
 // mode 1: instead of the update, L dt dF/df of the state whose transforms
 // are in components 0..V-1 (f_hat) and V..2V-1 (L dt chem_hat):
 // L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
+__device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk);
+
 template <int N, int V>
-__global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode) {
+__global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode, int nblk_x) {
   constexpr int E = Plan<N>::E, T = N / E, C = kh_tile<V>();
   __shared__ float2 lds[N * C];
   const int ntile = (a.nh + C - 1) / C;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
+  if (tile == 0 && ky == 0) {
+    // this block holds xi = 0: the mean fields of the instance first
+    kh_begin_mean(a, inst, nblk_x);
+    __syncthreads();
+  }
   const ctab_t kt = (ctab_t)(a.kh + (size_t)inst * kKhStride);
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = tile * C + cc;
@@ -494,7 +501,7 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
   const ctab_t W = kt + 21 + 6 * kMaxVar;
   const float fx = (float)kxv * (float)kxv, fy = (float)sy * (float)sy;
   const double wgt = (kxv == 0 || kxv == a.nx / 2) ? 1.0 : 2.0;
-  double en[kQgd] = {0.0, 0.0};
+  double en[kQgd] = {0.0, 0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = t + T * m;
@@ -544,6 +551,8 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
     const double x2 = a.gx * fx + a.gy * fy + a.gz * fz;
 #pragma unroll
     for (int q = 0; q < V; ++q) {
+      if (mode == 0 && valid)
+        en[2] += wgt * x2 * ((double)th[q][m].x * th[q][m].x + (double)th[q][m].y * th[q][m].y);
       float2 nv;
       if (mode == 0) {
         nv = make_float2((rh[q][m].x - a.LDt * y[q].x) / den, (rh[q][m].y - a.LDt * y[q].y) / den);
@@ -727,8 +736,10 @@ __device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, 
   block_minmax(mn, mx, mm);
   if (threadIdx.x != 0) return;
   for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
+  st->stats[kQac] = st->gd_cur;
   if (mode == 2) {
     const double ntot = (double)a.nx * a.ny * a.nz;
+    st->stats[kQac] = gd[2];  // the starting state's, from the spectral z pass
     st->stats[1] = st->mean_kh[12] + 0.5 * gd[1] / ntot;
     for (int c = 0; c < 6; ++c) {
       st->stats[2 + c] = st->mean_kh[c];
@@ -738,7 +749,6 @@ __device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, 
     st->st.residual = 0.0;
     st->st.done = 1;
   }
-  st->stats[kQac] = st->gd_cur;
   st->stats[kQac + 1] = mm[0];
   st->stats[kQac + 2] = mm[1];
   st->gd_cur = gd[0];
@@ -830,7 +840,6 @@ __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int 
   fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode);
 }
 
-__global__ __launch_bounds__(1024) void k_kh_mean(const KArgs a, int nblk) { kh_begin_mean(a, blockIdx.x, nblk); }
 
 __global__ __launch_bounds__(1024) void k_resid_fin(const KArgs a, int nblk) { resid_fin(a, blockIdx.x, nblk); }
 
@@ -941,10 +950,6 @@ hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t kh_mean(const KArgs& a, hipStream_t s) {
-  k_kh_mean<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
-  return hipGetLastError();
-}
 
 hipError_t ms_z_green(const KArgs& a, hipStream_t s) {
   const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
@@ -1009,15 +1014,15 @@ hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s) {
   switch (a.nv) {
     case 1: {
       const dim3 grid(((a.nh + kColTile - 1) / kColTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 1><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a, mode)));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 1><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
     } break;
     case 2: {
       const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 2><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode)));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 2><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
     } break;
     case 3: {
       const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 3><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode)));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 3><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
     } break;
     default: return hipErrorInvalidValue;
   }
