@@ -38,8 +38,8 @@ def log(msg):
 
 
 # first fixed-point iteration of a step: the forward and the inverse x pass
-# each read two more strain fields (the extrapolated warm start)
-EXTRAPOLATION_BYTES_PER_VOXEL = {"ms_x_forward": 48, "ms_x_inverse": 48}
+# each read three more strain fields (the cubic extrapolated warm start)
+EXTRAPOLATION_BYTES_PER_VOXEL = {"ms_x_forward": 72, "ms_x_inverse": 72}
 
 
 def sources_digest():

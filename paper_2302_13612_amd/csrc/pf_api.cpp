@@ -39,7 +39,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
-  size_t eta, eps, eps_prev, eps_prev2, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, tw;
+  size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, tw;
   size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
@@ -70,6 +70,7 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.eps = take(sizeof(float) * nvox * 6);
   L.eps_prev = take(sizeof(float) * nvox * 6);
   L.eps_prev2 = take(sizeof(float) * nvox * 6);
+  L.eps_prev3 = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
   L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
   L.spec = take(sizeof(float) * 2 * nspec * 6);
@@ -302,8 +303,8 @@ struct Group {
   int64_t hist;          // consecutive fixed-point steps with a valid strain history
   bool own_epsp, epsp_given;
   std::vector<int> members;
-  float* ring[3];        // strain fields: ring[cur] the latest converged one, then
-  int cur;               // ring[cur - 1], ring[cur - 2] the ones of the steps before
+  float* ring[4];        // strain fields: ring[cur] the latest converged one, then
+  int cur;               // ring[cur - 1], ring[cur - 2], ring[cur - 3] those of the steps before
 };
 
 }  // namespace
@@ -763,9 +764,10 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     g.ring[0] = reinterpret_cast<float*>(ws + L.eps);
     g.ring[1] = reinterpret_cast<float*>(ws + L.eps_prev);
     g.ring[2] = reinterpret_cast<float*>(ws + L.eps_prev2);
+    g.ring[3] = reinterpret_cast<float*>(ws + L.eps_prev3);
     g.cur = 0;
     a.eps = a.eps_out = g.ring[0];
-    a.eps_h1 = a.eps_h2 = nullptr;
+    a.eps_h1 = a.eps_h2 = a.eps_h3 = nullptr;
     a.iter_mode = 0;
     a.sig = reinterpret_cast<float*>(ws + L.sig);
     a.epsp = nullptr;
@@ -933,27 +935,28 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         iterating.push_back(k);
       }
       // The first iterate extrapolates the converged strains of the previous
-      // steps (linear from the third step on, quadratic from the fourth) and
-      // is written over the oldest of the three strain fields.
+      // steps (linear from the third step on, quadratic from the fourth, cubic
+      // from the fifth) and is written over the oldest of the four fields.
       std::vector<KArgs> first(c->groups.size()), later(c->groups.size());
       for (size_t k : iterating) {
         Group& g = c->groups[k];
-        const int order = !g.strain_valid ? 0 : (g.hist >= 3 ? 2 : (g.hist == 2 ? 1 : 0));
-        float* out = g.ring[(g.cur + 1) % 3];
+        const int order = !g.strain_valid ? 0 : (g.hist >= 4 ? 3 : (g.hist == 3 ? 2 : (g.hist == 2 ? 1 : 0)));
+        float* out = g.ring[(g.cur + 1) % 4];
         KArgs& f = first[k];
         f = g.args;
         f.skip_done = 1;
         f.eps = g.ring[g.cur];
         f.eps_out = out;
-        f.eps_h1 = g.ring[(g.cur + 2) % 3];
-        f.eps_h2 = g.ring[(g.cur + 1) % 3];
+        f.eps_h1 = g.ring[(g.cur + 3) % 4];
+        f.eps_h2 = g.ring[(g.cur + 2) % 4];
+        f.eps_h3 = g.ring[(g.cur + 1) % 4];
         f.iter_mode = order;
         KArgs& l = later[k];
         l = g.args;
         l.skip_done = 1;
         l.eps = out;
         l.eps_out = out;
-        l.eps_h1 = l.eps_h2 = nullptr;
+        l.eps_h1 = l.eps_h2 = l.eps_h3 = nullptr;
         l.iter_mode = 0;
         PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(f, s); }));
       }
@@ -985,7 +988,7 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
       }
       for (size_t k : iterating) {
         Group& g = c->groups[k];
-        g.cur = (g.cur + 1) % 3;
+        g.cur = (g.cur + 1) % 4;
         g.args.eps = g.args.eps_out = g.ring[g.cur];
         PF_TRY(ac_update(c, g, s));
       }

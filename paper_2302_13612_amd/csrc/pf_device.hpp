@@ -33,7 +33,7 @@ struct DevState {
   double ebar_cur[6];    // mean strain of the current iterate
   double ebar_field[6];  // mean strain of the strain field in memory
   double ebar_next[6];   // mean strain for the next iterate
-  double ebar_h[3][6];   // mean strains of the last three converged fields (latest first)
+  double ebar_h[4][6];   // mean strains of the last four converged fields (latest first)
   double ebar_base[6];   // mean of the field the current iterate is formed from
   double eps_target[6];  // load: prescribed mean strain
   double sig_target[6];  // load: prescribed mean stress
@@ -87,9 +87,11 @@ struct KArgs {
   float* eps;                 // [6][ninst][nz][ny][nx] strain the iterate is formed from
   float* eps_out;             // where the inverse pass writes the new iterate
   const float* eps_h1;        // converged strain of the step before (iter_mode >= 1)
-  const float* eps_h2;        // and of the one before that (iter_mode 2)
+  const float* eps_h2;        // of the one before that (iter_mode >= 2)
+  const float* eps_h3;        // and of the one before that (iter_mode 3)
   int iter_mode;              // first iterate of a step: 0 eps, 1 linear extrapolation
-                              // 2 eps - h1, 2 quadratic 3 eps - 3 h1 + h2
+                              // 2 eps - h1, 2 quadratic 3 (eps - h1) + h2, 3 cubic
+                              // 4 eps - 6 h1 + 4 h2 - h3
   float* sig;                 // [6][ninst][nz][ny][nx] (only written on request)
   const float* epsp;          // [6][ninst][nz][ny][nx] or null
   const uint8_t* gid;         // [nz][ny][nx] or null (one instance only)

@@ -71,13 +71,18 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
             old = make_float2(2.f * old.x - p1.x, 2.f * old.y - p1.y);
           } else {
             const float2 p2 = *reinterpret_cast<const float2*>(a.eps_h2 + off);
-            old = make_float2(3.f * (old.x - p1.x) + p2.x, 3.f * (old.y - p1.y) + p2.y);
+            if (a.iter_mode == 2) {
+              old = make_float2(3.f * (old.x - p1.x) + p2.x, 3.f * (old.y - p1.y) + p2.y);
+            } else {
+              const float2 p3 = *reinterpret_cast<const float2*>(a.eps_h3 + off);
+              old = make_float2(4.f * (old.x + p2.x) - 6.f * p1.x - p3.x, 4.f * (old.y + p2.y) - 6.f * p1.y - p3.y);
+            }
           }
         }
         const float dx0 = v[m].x - (old.x + shift), dx1 = v[m].y - (old.y + shift);
         dsum += dx0 * dx0 + dx1 * dx1;
         nsum += v[m].x * v[m].x + v[m].y * v[m].y;
-        // the output may be eps_h2 (the oldest field): read above, same element
+        // the output may be the oldest field (h2 or h3): read above, same element
         *reinterpret_cast<float2*>(a.eps_out + off) = v[m];
       }
     }
@@ -627,11 +632,15 @@ __global__ void k_step_begin(const KArgs a) {
   DevState* st = a.state + i;
   const double* ld = a.loads + 12 * (size_t)i;
   for (int c = 0; c < 6; ++c) {
+    st->ebar_h[3][c] = st->ebar_h[2][c];
     st->ebar_h[2][c] = st->ebar_h[1][c];
     st->ebar_h[1][c] = st->ebar_h[0][c];
     st->ebar_h[0][c] = st->ebar_field[c];
-    const double l = st->ebar_h[0][c], p1 = st->ebar_h[1][c], p2 = st->ebar_h[2][c];
-    const double base = a.iter_mode == 2 ? 3.0 * (l - p1) + p2 : (a.iter_mode == 1 ? 2.0 * l - p1 : l);
+    const double l = st->ebar_h[0][c], p1 = st->ebar_h[1][c], p2 = st->ebar_h[2][c], p3 = st->ebar_h[3][c];
+    const double base = a.iter_mode == 3   ? 4.0 * (l + p2) - 6.0 * p1 - p3
+                        : a.iter_mode == 2 ? 3.0 * (l - p1) + p2
+                        : a.iter_mode == 1 ? 2.0 * l - p1
+                                           : l;
     st->ebar_base[c] = base;
     st->eps_target[c] = ld[c];
     st->sig_target[c] = ld[6 + c];

@@ -36,7 +36,7 @@ struct Sample {
 
 // Strain of the first iterate of a step: the stored (latest converged)
 // field L, or its extrapolation from the converged fields of the previous
-// steps: linear 2 L - P, quadratic 3 (L - P) + P2.
+// steps: linear 2 L - P, quadratic 3 (L - P) + P2, cubic 4 (L + P2) - 6 P - P3.
 __device__ __forceinline__ void extrapolate_strain(const KArgs& a, bool valid, size_t vs, size_t off,
                                                    float2 (&e)[6]) {
   if (a.iter_mode == 0 || !valid) return;
@@ -47,7 +47,12 @@ __device__ __forceinline__ void extrapolate_strain(const KArgs& a, bool valid, s
       e[c] = make_float2(2.f * e[c].x - p1.x, 2.f * e[c].y - p1.y);
     } else {
       const float2 p2 = *reinterpret_cast<const float2*>(a.eps_h2 + c * vs + off);
-      e[c] = make_float2(3.f * (e[c].x - p1.x) + p2.x, 3.f * (e[c].y - p1.y) + p2.y);
+      if (a.iter_mode == 2) {
+        e[c] = make_float2(3.f * (e[c].x - p1.x) + p2.x, 3.f * (e[c].y - p1.y) + p2.y);
+      } else {
+        const float2 p3 = *reinterpret_cast<const float2*>(a.eps_h3 + c * vs + off);
+        e[c] = make_float2(4.f * (e[c].x + p2.x) - 6.f * p1.x - p3.x, 4.f * (e[c].y + p2.y) - 6.f * p1.y - p3.y);
+      }
     }
   }
 }
