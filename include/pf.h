@@ -48,7 +48,8 @@
  *   captured once in a HIP graph and replayed. Batched instances are one
  *   grain each and share n_var, h_kind, A, kappa, L, dt, dx, ms_tol,
  *   ms_max_iter and bc_stress_mask; each has its own material, reference
- *   medium, eta0 and load.
+ *   medium, eta0 and load. The instances of one grid size hold fewer than
+ *   2^30 voxels together (PF_EINVAL otherwise).
  *
  * Memory and streams
  *   Every device buffer is owned by the caller. pf_init receives one device

@@ -418,6 +418,16 @@ int validate_batch(const pf_problem* probs, int n, std::string& why) {
       return rc;
     }
   }
+  // the x passes address a field component with 32-bit element offsets
+  for (int i = 0; i < n; ++i) {
+    size_t same = 0;
+    for (int j = 0; j < n; ++j)
+      if (probs[j].nx == probs[i].nx && probs[j].ny == probs[i].ny && probs[j].nz == probs[i].nz) ++same;
+    if (same * (size_t)probs[i].nx * probs[i].ny * probs[i].nz >= ((size_t)1 << 30)) {
+      why = "instances of one grid size must hold fewer than 2^30 voxels together";
+      return PF_EINVAL;
+    }
+  }
   if (n == 1) return PF_OK;
   const pf_problem& p0 = probs[0];
   for (int i = 0; i < n; ++i) {

@@ -6,6 +6,10 @@
 
 namespace pft {
 
+// Pointer into read-only memory that is the same for every lane (constant
+// address space): loads through it with a uniform address are scalar loads.
+typedef const __attribute__((address_space(4))) float* ctab_t;
+
 // -------------------------------------------------------------- reductions
 template <int Q>
 __device__ __forceinline__ void block_sum(double (&v)[Q], double* __restrict__ out) {
@@ -174,8 +178,78 @@ __device__ __forceinline__ LaneTab load_lanetab(const float* tab, int n) {
   return t;
 }
 
+// The same table read with scalar loads from kernel-argument memory: each
+// element goes through the constant cache into a scalar register and costs
+// no vector instruction. The table does not fit in scalar registers, so it
+// is read block by block where it is used, and each block's base pointer
+// passes through an opaque scalar zero that waits for a value of the block
+// before: the loads cannot be hoisted out of the voxel loop or bunched at
+// its top (either would spill the table to vector lanes), and one block's
+// loads overlap the arithmetic of the one before.
+__device__ __forceinline__ ctab_t smem_after(ctab_t p, float dep) {
+  int zero;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zero) : "v"(dep));
+  return p + zero;
+}
+
+// The crystal table inside the kernel's argument block, for kernels whose
+// only explicit argument is the KArgs block (which then sits at offset 0 of
+// the argument segment). Addressing it this way leaves the by-value
+// parameter's address untaken: a taken address can make the compiler copy
+// the whole block to scratch memory.
+__device__ __forceinline__ ctab_t kernarg_xtab() {
+  typedef const __attribute__((address_space(4))) char* cbyte_t;
+  return (ctab_t)((cbyte_t)__builtin_amdgcn_kernarg_segment_ptr() + offsetof(KArgs, xtab));
+}
+
+// Rotation-form constitutive law of the two voxels of a packed sample, the
+// crystal table read with scalar loads (layout as for constitutive_rot).
 template <int V>
-__device__ __forceinline__ void constitutive_rot(const LaneTab& xt, int hk, const float e[6], const float eta[V],
+__device__ __forceinline__ void constitutive_rot_pair(ctab_t xtab, int hk, const float (&e)[2][6],
+                                                      const float (&eta)[2][V], const float (&ep)[2][6],
+                                                      const float (&R)[2][9], MatR<V> (&o)[2]) {
+  float h[2][V], dc[2][6];
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+#pragma unroll
+    for (int q = 0; q < V; ++q) h[v][q] = h_of(eta[v][q], hk);
+    float d[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) d[c] = e[v][c] - ep[v][c];
+    rotate_sym<true>(R[v], d, dc[v]);
+  }
+  ctab_t t = smem_after(xtab + 21 * (V + 1), dc[1][0]);
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      float es = 0.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) es += h[v][q] * t[6 * q + c];
+      const float el = dc[v][c] - es;
+      o[v].gam_c[c] = c < 3 ? el : 2.f * el;
+    }
+  float Cx[2][21];
+  t = smem_after(xtab, o[1].gam_c[0]);
+#pragma unroll
+  for (int i = 0; i < 21; ++i) Cx[0][i] = Cx[1][i] = t[i];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    t = smem_after(xtab + 21 * (q + 1), Cx[1][10]);
+#pragma unroll
+    for (int i = 0; i < 21; ++i)
+#pragma unroll
+      for (int v = 0; v < 2; ++v) Cx[v][i] += h[v][q] * t[i];
+  }
+#pragma unroll
+  for (int v = 0; v < 2; ++v) {
+    symv6(Cx[v], o[v].gam_c, o[v].sig_c);
+    rotate_sym<false>(R[v], o[v].sig_c, o[v].sig);
+  }
+}
+
+template <int V, class TT>
+__device__ __forceinline__ void constitutive_rot(const TT& xt, int hk, const float e[6], const float eta[V],
                                                  const float ep[6], const float (&R)[9], MatR<V>& o) {
   float h[V];
 #pragma unroll
@@ -338,7 +412,6 @@ __device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow
 // address space with a wave-uniform address (scalar loads into SGPRs): the
 // distinct grains of a wavefront are visited one after the other, each with
 // only its lanes active (usually one grain, two or three at boundaries).
-typedef const __attribute__((address_space(4))) float* ctab_t;
 
 template <class F>
 __device__ __forceinline__ void with_table(const KArgs& a, const float* base, int g, F&& f) {

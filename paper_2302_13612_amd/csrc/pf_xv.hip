@@ -24,8 +24,31 @@
 #ifndef PF_XWAVES
 #define PF_XWAVES 3
 #endif
+// crystal-frame table of the rotation form: scalar loads (1) or one value
+// per lane read with v_readlane (0)
+#ifndef PF_XTAB_SCALAR
+#define PF_XTAB_SCALAR 1
+#endif
 
 namespace pft {
+
+// A scalar zero the compiler cannot see through: added to the component
+// stride inside the voxel loop, it keeps the per-component base addresses
+// from being hoisted out of the loop (held across it, they would not fit in
+// scalar registers).
+__device__ __forceinline__ int opaque_zero() {
+  int zero;
+  asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+  return zero;
+}
+
+// A float2 of a field at a 32-bit element offset from a wave-uniform base:
+// the load takes the base in scalar registers and only the offset in a
+// vector register, so no 64-bit per-lane addresses are kept live. A field
+// component holds fewer than 2^30 elements (the host checks the batch size).
+__device__ __forceinline__ float2 ld_f2(const float* base, uint32_t elem) {
+  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + (elem << 2));
+}
 
 // Inputs of one packed sample (voxels x0, x0+1) of a row.
 template <int V>
@@ -34,27 +57,40 @@ struct Sample {
   int g0, g1;
 };
 
+template <int E> struct GidPack;
+
 // Strain of the first iterate of a step: the stored (latest converged)
 // field L, or its extrapolation from the converged fields of the previous
 // steps: linear 2 L - P, quadratic 3 (L - P) + P2, cubic 4 (L + P2) - 6 P - P3.
-__device__ __forceinline__ void extrapolate_strain(const KArgs& a, bool valid, size_t vs, size_t off,
-                                                   float2 (&e)[6]) {
-  if (a.iter_mode == 0 || !valid) return;
+// Rows past the end read row 0 (their results are not stored), so the
+// loads need no per-lane condition.
+__device__ __forceinline__ void extrapolate_strain(const KArgs& a, size_t vs, uint32_t off, float2 (&e)[6]) {
+  if (a.iter_mode == 0) return;
+  vs += opaque_zero();
+  // every load of a mode is issued before its arithmetic (the mode is
+  // uniform, the branches do not wait on memory)
+  float2 p1[6], p2[6], p3[6];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    const float2 p1 = *reinterpret_cast<const float2*>(a.eps_h1 + c * vs + off);
-    if (a.iter_mode == 1) {
-      e[c] = make_float2(2.f * e[c].x - p1.x, 2.f * e[c].y - p1.y);
-    } else {
-      const float2 p2 = *reinterpret_cast<const float2*>(a.eps_h2 + c * vs + off);
-      if (a.iter_mode == 2) {
-        e[c] = make_float2(3.f * (e[c].x - p1.x) + p2.x, 3.f * (e[c].y - p1.y) + p2.y);
-      } else {
-        const float2 p3 = *reinterpret_cast<const float2*>(a.eps_h3 + c * vs + off);
-        e[c] = make_float2(4.f * (e[c].x + p2.x) - 6.f * p1.x - p3.x, 4.f * (e[c].y + p2.y) - 6.f * p1.y - p3.y);
-      }
-    }
+  for (int c = 0; c < 6; ++c) p1[c] = ld_f2(a.eps_h1 + c * vs, off);
+  if (a.iter_mode == 1) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = make_float2(2.f * e[c].x - p1[c].x, 2.f * e[c].y - p1[c].y);
+    return;
   }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) p2[c] = ld_f2(a.eps_h2 + c * vs, off);
+  if (a.iter_mode == 2) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      e[c] = make_float2(3.f * (e[c].x - p1[c].x) + p2[c].x, 3.f * (e[c].y - p1[c].y) + p2[c].y);
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) p3[c] = ld_f2(a.eps_h3 + c * vs, off);
+#pragma unroll
+  for (int c = 0; c < 6; ++c)
+    e[c] = make_float2(4.f * (e[c].x + p2[c].x) - 6.f * p1[c].x - p3[c].x,
+                       4.f * (e[c].y + p2[c].y) - 6.f * p1[c].y - p3[c].y);
 }
 
 // Offset added to the strain the iterate is formed from so its mean is the
@@ -64,32 +100,44 @@ __device__ __forceinline__ float mean_shift(const KArgs& a, const DevState* st, 
 }
 
 template <int V>
-__device__ __forceinline__ void load_sample(const KArgs& a, bool valid, size_t vs, size_t off, Sample<V>& s) {
+__device__ __forceinline__ void load_sample(const KArgs& a, size_t vs, uint32_t off, Sample<V>& s) {
   s.g0 = s.g1 = 0;
-  if (!valid) {
+  vs += opaque_zero();
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s.e[c] = s.p[c] = make_float2(0.f, 0.f);
+  for (int c = 0; c < 6; ++c) s.e[c] = ld_f2(a.eps + c * vs, off);
 #pragma unroll
-    for (int q = 0; q < V; ++q) s.h[q] = make_float2(0.f, 0.f);
-    return;
-  }
-#pragma unroll
-  for (int c = 0; c < 6; ++c) s.e[c] = *reinterpret_cast<const float2*>(a.eps + c * vs + off);
-#pragma unroll
-  for (int q = 0; q < V; ++q) s.h[q] = *reinterpret_cast<const float2*>(a.eta + q * vs + off);
+  for (int q = 0; q < V; ++q) s.h[q] = ld_f2(a.eta + q * vs, off);
   if (a.epsp) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) s.p[c] = *reinterpret_cast<const float2*>(a.epsp + c * vs + off);
+    for (int c = 0; c < 6; ++c) s.p[c] = ld_f2(a.epsp + c * vs, off);
   } else {
 #pragma unroll
     for (int c = 0; c < 6; ++c) s.p[c] = make_float2(0.f, 0.f);
   }
-  if (a.gid) {
-    const uint16_t gg = *reinterpret_cast<const uint16_t*>(a.gid + off);
-    s.g0 = gg & 0xff;
-    s.g1 = gg >> 8;
-  }
 }
+
+// Grain ids of a thread's E samples (one byte per voxel, two per sample),
+// loaded before the voxel loop so that each iteration's rotation gathers
+// leave together with its field loads instead of waiting for the id load.
+template <int E>
+struct GidPack {
+  uint64_t lo = 0;  // samples 0..3
+  uint32_t hi = 0;  // samples 4, 5
+  __device__ __forceinline__ void load(const KArgs& a, size_t rbase, int t, int T) {
+    if (!a.gid) return;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const uint32_t gg = *reinterpret_cast<const uint16_t*>(a.gid + rbase + 2 * (t + T * m));
+      if (m < 4) lo |= (uint64_t)gg << (16 * m);
+      else hi |= gg << (16 * (m - 4));
+    }
+  }
+  __device__ __forceinline__ void get(int m, int& g0, int& g1) const {
+    const uint32_t gg = (m < 4 ? (uint32_t)(lo >> (16 * m)) : hi >> (16 * (m - 4))) & 0xffffu;
+    g0 = gg & 0xff;
+    g1 = gg >> 8;
+  }
+};
 
 // Stress of one voxel (sample frame) and the elastic strain and stress in
 // the frame of the material table (crystal frame for ROT, sample otherwise).
@@ -127,8 +175,8 @@ __device__ __forceinline__ void variant_terms(TP tab, const float (&sig_m)[6], c
 
 // HK: the interpolation h (PF_H_LINEAR or PF_H_QUINTIC) as a constant, so
 // the linear case carries no polynomial.
-template <int V, bool ROT, bool AC, int HK>
-__device__ __forceinline__ void eval_voxel(const KArgs& a, const LaneTab& xt, const float* tabs, const float (&e)[6],
+template <int V, bool ROT, bool AC, int HK, class TT>
+__device__ __forceinline__ void eval_voxel(const KArgs& a, const TT& xt, const float* tabs, const float (&e)[6],
                                            const float (&et)[V], const float (&ep)[6], int g, VoxelOut& o,
                                            float (&work)[V], float (&quad)[V]) {
   if constexpr (ROT) {
@@ -158,6 +206,74 @@ __device__ __forceinline__ void eval_voxel(const KArgs& a, const LaneTab& xt, co
   }
 }
 
+#if PF_XTAB_SCALAR
+// variant_terms for the two voxels of a sample, the crystal table read with
+// scalar loads block by block (see smem_after).
+template <int V>
+__device__ __forceinline__ void variant_terms_pair(ctab_t xtab, const VoxelOut (&vo)[2], float (&work)[2][V],
+                                                   float (&quad)[2][V]) {
+  float gg[2][21];
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+#pragma unroll
+      for (int j = i; j < 6; ++j) gg[v][sym6(i, j)] = (i == j ? 1.f : 2.f) * vo[v].gam_m[i] * vo[v].gam_m[j];
+  ctab_t t = smem_after(xtab + 21 * (V + 1), gg[1][20]);
+#pragma unroll
+  for (int v = 0; v < 2; ++v)
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const ctab_t e0q = t + 6 * q;
+      const float* sm = vo[v].sig_m;
+      work[v][q] = sm[0] * e0q[0] + sm[1] * e0q[1] + sm[2] * e0q[2] + 2.f * (sm[3] * e0q[3] + sm[4] * e0q[4] + sm[5] * e0q[5]);
+    }
+  float dep = work[1][V - 1];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    t = smem_after(xtab + 21 * (q + 1), dep);
+    float acc[2] = {0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 21; ++k) {
+#pragma unroll
+      for (int v = 0; v < 2; ++v) acc[v] += t[k] * gg[v][k];
+      if (k == 10) dep = acc[1];
+    }
+    quad[0][q] = acc[0];
+    quad[1][q] = acc[1];
+  }
+}
+#endif
+
+// Both voxels of a packed sample: with the rotation form and scalar table
+// loads the two share every table read.
+// R: the grain rotations of the two voxels (rotation form), loaded by the
+// caller together with the sample.
+template <int V, bool ROT, bool AC, int HK, class TT>
+__device__ __forceinline__ void eval_pair(const KArgs& a, const TT& xt, const float* tabs, const float (&e)[2][6],
+                                          const float (&et)[2][V], const float (&ep)[2][6], const int (&g)[2],
+                                          const float (&R)[2][9], VoxelOut (&vo)[2], float (&work)[2][V],
+                                          float (&quad)[2][V]) {
+#if PF_XTAB_SCALAR
+  if constexpr (ROT) {
+    MatR<V> m[2];
+    constitutive_rot_pair<V>(kernarg_xtab(), HK, e, et, ep, R, m);
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        vo[v].sig[c] = m[v].sig[c];
+        vo[v].sig_m[c] = m[v].sig_c[c];
+        vo[v].gam_m[c] = m[v].gam_c[c];
+      }
+    if constexpr (AC) variant_terms_pair<V>(kernarg_xtab(), vo, work, quad);
+    return;
+  }
+#endif
+#pragma unroll
+  for (int v = 0; v < 2; ++v) eval_voxel<V, ROT, AC, HK>(a, xt, tabs, e[v], et[v], ep[v], g[v], vo[v], work[v], quad[v]);
+}
+
 // Chemical force of variant q: 2A f_q sum_{b != q} f_b (f_b - f_q), b over
 // the other variants and the matrix f_M = 1 - sum f.
 template <int V>
@@ -182,7 +298,11 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   if (st->st.done) return;
   const ctab_t C0 = (ctab_t)(a.ref + (size_t)inst * kRefStride);
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
+#if PF_XTAB_SCALAR
+  const LaneTab xt{};
+#else
   const LaneTab xt = ROT ? load_lanetab(a.xtab, 21 + 27 * V) : LaneTab{};
+#endif
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
@@ -193,34 +313,45 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
 #pragma unroll
   for (int c = 0; c < 6; ++c) shift[c] = mean_shift(a, st, c);
   float fsum[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // this thread's voxels, then FP64
+  GidPack<E> gids;
+  gids.load(a, rbase, t, T);
 #pragma unroll 1
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
     Sample<V> s;
-    load_sample<V>(a, valid, vs, rbase + 2 * k, s);
-    extrapolate_strain(a, valid, vs, rbase + 2 * k, s.e);
+    load_sample<V>(a, vs, (uint32_t)(rbase + 2 * k), s);
+    gids.get(m, s.g0, s.g1);
+    float R[2][9];
+    if constexpr (ROT && PF_XTAB_SCALAR) {
+      load_rotation(a, s.g0, R[0]);
+      load_rotation(a, s.g1, R[1]);
+    }
+    extrapolate_strain(a, vs, (uint32_t)(rbase + 2 * k), s.e);
     float o[2][6];
+    float e[2][6], ep[2][6], et[2][V];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      float e[6], ep[6], et[V];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        e[c] = (half ? s.e[c].y : s.e[c].x) + shift[c];
-        ep[c] = half ? s.p[c].y : s.p[c].x;
+        e[half][c] = (half ? s.e[c].y : s.e[c].x) + shift[c];
+        ep[half][c] = half ? s.p[c].y : s.p[c].x;
       }
 #pragma unroll
-      for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
-      VoxelOut vo;
-      float work[V], quad[V];
-      eval_voxel<V, ROT, false, HK>(a, xt, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
+      for (int q = 0; q < V; ++q) et[half][q] = half ? s.h[q].y : s.h[q].x;
+    }
+    VoxelOut vo[2];
+    float work[2][V], quad[2][V];
+    eval_pair<V, ROT, false, HK>(a, xt, tabs, e, et, ep, {s.g0, s.g1}, R, vo, work, quad);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
       float ge[6], c0e[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) ge[c] = c < 3 ? e[c] : 2.f * e[c];
+      for (int c = 0; c < 6; ++c) ge[c] = c < 3 ? e[half][c] : 2.f * e[half][c];
       symv6(C0, ge, c0e);
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        o[half][c] = vo.sig[c] - c0e[c];
-        if (valid) fsum[c] += vo.sig[c];
+        o[half][c] = vo[half].sig[c] - c0e[c];
+        if (valid) fsum[c] += vo[half].sig[c];
       }
     }
 #pragma unroll
@@ -254,7 +385,11 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   const int rpi = a.nz * a.ny;
   const int inst = blockIdx.x * ROWS / rpi;
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
+#if PF_XTAB_SCALAR
+  const LaneTab xt{};
+#else
   const LaneTab xt = ROT ? load_lanetab(a.xtab, 21 + 27 * V) : LaneTab{};
+#endif
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
@@ -265,26 +400,42 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
 #pragma unroll
   for (int q = 0; q < kQac; ++q) facc[q] = 0.f;
   float mn = 3.0e38f, mx = -3.0e38f;
+  GidPack<E> gids;
+  gids.load(a, rbase, t, T);
 #pragma unroll 1
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
     const int x0 = 2 * k;
     Sample<V> s;
-    load_sample<V>(a, valid, vs, rbase + x0, s);
+    load_sample<V>(a, vs, (uint32_t)(rbase + x0), s);
+    gids.get(m, s.g0, s.g1);
+    float R[2][9];
+    if constexpr (ROT && PF_XTAB_SCALAR) {
+      load_rotation(a, s.g0, R[0]);
+      load_rotation(a, s.g1, R[1]);
+    }
     float o[2][V];
+    float e2[2][6], ep2[2][6], et2[2][V];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-      float e[6], ep[6], et[V];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        e[c] = half ? s.e[c].y : s.e[c].x;
-        ep[c] = half ? s.p[c].y : s.p[c].x;
+        e2[half][c] = half ? s.e[c].y : s.e[c].x;
+        ep2[half][c] = half ? s.p[c].y : s.p[c].x;
       }
 #pragma unroll
-      for (int q = 0; q < V; ++q) et[q] = half ? s.h[q].y : s.h[q].x;
-      VoxelOut vo;
-      float work[V], quad[V];
-      eval_voxel<V, ROT, true, HK>(a, xt, tabs, e, et, ep, half ? s.g1 : s.g0, vo, work, quad);
+      for (int q = 0; q < V; ++q) et2[half][q] = half ? s.h[q].y : s.h[q].x;
+    }
+    VoxelOut vo2[2];
+    float work2[2][V], quad2[2][V];
+    eval_pair<V, ROT, true, HK>(a, xt, tabs, e2, et2, ep2, {s.g0, s.g1}, R, vo2, work2, quad2);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      const float (&e)[6] = e2[half];
+      const float (&et)[V] = et2[half];
+      const VoxelOut& vo = vo2[half];
+      const float (&work)[V] = work2[half];
+      const float (&quad)[V] = quad2[half];
       float fm = 1.f;
 #pragma unroll
       for (int q = 0; q < V; ++q) fm -= et[q];
