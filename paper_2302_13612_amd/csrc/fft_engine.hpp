@@ -142,12 +142,70 @@ __device__ __forceinline__ float2 twiddle(const float2* __restrict__ tw, int idx
   return DIR > 0 ? w : cconj(w);
 }
 
-// One Stockham stage. NS = product of the radices of earlier stages.
-// FIRST: inputs from registers; LAST: outputs to registers. Every LDS write
-// phase sits between two block barriers, so callers may reuse the buffer.
-template <int N, class P, int R, int NS, int DIR, bool FIRST, bool LAST, class View>
-__device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& lds, int t,
-                                               const float2* __restrict__ tw) {
+// Radix list of a plan as constants.
+template <class R> struct RadixInfo;
+template <int... Rs>
+struct RadixInfo<Radices<Rs...>> {
+  static constexpr int n = sizeof...(Rs);
+  static constexpr int r[n] = {Rs...};
+};
+
+// Per-thread twiddles of every stage of plan P in direction DIR. They depend
+// only on the thread index, so a thread that transforms several pencils
+// loads them once from the table and keeps them in registers (each stage of
+// a pencil would otherwise wait on its table loads behind a barrier).
+template <int N, class P, int DIR>
+struct TwCache {
+  using RI = RadixInfo<typename P::R>;
+  static constexpr int ns(int s) {
+    int v = 1;
+    for (int i = 0; i < s; ++i) v *= RI::r[i];
+    return v;
+  }
+  // first twiddle of stage s (stage 0 needs none)
+  static constexpr int offset(int s) {
+    int v = 0;
+    for (int i = 1; i < s; ++i) v += (P::E / RI::r[i]) * (RI::r[i] - 1);
+    return v;
+  }
+  static constexpr int count = offset(RI::n);
+  float2 w[count > 0 ? count : 1];
+
+  template <int SI>
+  __device__ __forceinline__ void load_stages(const float2* __restrict__ tw, int t) {
+    if constexpr (SI < RI::n) {
+      constexpr int R = RI::r[SI], NS = ns(SI), NB = P::E / R, T = N / P::E;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int k = (t + T * q) % NS;
+#pragma unroll
+        for (int r = 1; r < R; ++r) w[offset(SI) + q * (R - 1) + r - 1] = twiddle<DIR>(tw, r * k * (N / (NS * R)));
+      }
+      load_stages<SI + 1>(tw, t);
+    }
+  }
+  __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) { load_stages<1>(tw, t); }
+};
+
+// Twiddle r of butterfly q of stage SI (R, NS): from the table, or from a
+// thread's cache.
+template <int N, class P, int R, int NS, int SI, int DIR>
+__device__ __forceinline__ float2 stage_twiddle(const float2* __restrict__ tw, int t, int q, int r) {
+  constexpr int T = N / P::E;
+  const int k = (t + T * q) % NS;
+  return twiddle<DIR>(tw, r * k * (N / (NS * R)));
+}
+template <int N, class P, int R, int NS, int SI, int DIR>
+__device__ __forceinline__ float2 stage_twiddle(const TwCache<N, P, DIR>& c, int, int q, int r) {
+  return c.w[TwCache<N, P, DIR>::offset(SI) + q * (R - 1) + r - 1];
+}
+
+// One Stockham stage. NS = product of the radices of earlier stages, SI =
+// stage index. FIRST: inputs from registers; LAST: outputs to registers.
+// Every LDS write phase sits between two block barriers, so callers may
+// reuse the buffer. TW: the twiddle table (const float2*) or a TwCache.
+template <int N, class P, int R, int NS, int SI, int DIR, bool FIRST, bool LAST, class View, class TW>
+__device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& lds, int t, const TW& tw) {
   constexpr int E = P::E;
   constexpr int T = N / E;
   constexpr int NB = E / R;  // butterflies per thread
@@ -162,10 +220,9 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& ld
       else a[q * R + r] = lds.read(j + r * (N / R));
     }
     if constexpr (!FIRST) {
-      const int k = j % NS;
 #pragma unroll
       for (int r = 1; r < R; ++r)
-        a[q * R + r] = cmul(a[q * R + r], twiddle<DIR>(tw, r * k * (N / (NS * R))));
+        a[q * R + r] = cmul(a[q * R + r], stage_twiddle<N, P, R, NS, SI, DIR>(tw, t, q, r));
     }
     dft<R, DIR>(&a[q * R]);
   }
@@ -187,21 +244,20 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& ld
   }
 }
 
-template <int N, class P, int NS, int DIR, bool FIRST, class View, int R0, int... Rest>
-__device__ __forceinline__ void run_stages(float2 (&v)[P::E], const View& lds, int t,
-                                           const float2* __restrict__ tw, Radices<R0, Rest...>) {
+template <int N, class P, int NS, int SI, int DIR, bool FIRST, class View, class TW, int R0, int... Rest>
+__device__ __forceinline__ void run_stages(float2 (&v)[P::E], const View& lds, int t, const TW& tw,
+                                           Radices<R0, Rest...>) {
   constexpr bool LAST = sizeof...(Rest) == 0;
-  stockham_stage<N, P, R0, NS, DIR, FIRST, LAST>(v, lds, t, tw);
-  if constexpr (!LAST) run_stages<N, P, NS * R0, DIR, false>(v, lds, t, tw, Radices<Rest...>{});
+  stockham_stage<N, P, R0, NS, SI, DIR, FIRST, LAST>(v, lds, t, tw);
+  if constexpr (!LAST) run_stages<N, P, NS * R0, SI + 1, DIR, false>(v, lds, t, tw, Radices<Rest...>{});
 }
 
 // Transform the pencil held in v (thread t owns elements t + T*m, T = N/E)
 // in place with plan P. All threads of the block must call it together (it
-// contains barriers).
-template <int N, int DIR, class P = Plan<N>, class View>
-__device__ __forceinline__ void fft_pencil(float2 (&v)[P::E], const View& lds, int t,
-                                           const float2* __restrict__ tw) {
-  run_stages<N, P, 1, DIR, true>(v, lds, t, tw, typename P::R{});
+// contains barriers). tw: the twiddle table or the thread's TwCache.
+template <int N, int DIR, class P = Plan<N>, class View, class TW>
+__device__ __forceinline__ void fft_pencil(float2 (&v)[P::E], const View& lds, int t, const TW& tw) {
+  run_stages<N, P, 1, 0, DIR, true>(v, lds, t, tw, typename P::R{});
 }
 
 }  // namespace pft

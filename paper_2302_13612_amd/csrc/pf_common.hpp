@@ -323,15 +323,30 @@ __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* l
   }
 }
 
+// Twiddles a thread uses on every row of an x pass: those of the
+// half-length FFT in direction DIR and the split factors W_N^k of its own
+// k = t + T m (taken as stored; the inverse conjugates them where used).
+// Loaded once per kernel, they keep the row transforms free of table loads.
+template <int M, int DIR>
+struct XTw {
+  TwCache<M, XPlan<M>, DIR> fft;
+  float2 split[XPlan<M>::E];
+  __device__ __forceinline__ void load(const KArgs& a, int t) {
+    constexpr int E = XPlan<M>::E, T = M / E;
+    fft.load(a.tw_xh, t);
+#pragma unroll
+    for (int m = 0; m < E; ++m) split[m] = a.tw_x[t + T * m];
+  }
+};
+
 // Forward of one staged row: v (packed real pairs) -> FFT -> split into the
 // nx/2+1 coefficients stored at dst. ldsrow is this row's exchange buffer.
 template <int M>
 __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
-                                        float2* __restrict__ dst, const float2* __restrict__ tw_m,
-                                        const float2* __restrict__ tw_n) {
+                                        float2* __restrict__ dst, const XTw<M, 1>& tw) {
   constexpr int E = XPlan<M>::E, T = M / E;
   RowView view{ldsrow};
-  fft_pencil<M, 1, XPlan<M>>(v, view, t, tw_m);
+  fft_pencil<M, 1, XPlan<M>>(v, view, t, tw.fft);
   __syncthreads();
 #pragma unroll
   for (int m = 0; m < E; ++m) view.write(t + T * m, v[m]);
@@ -344,7 +359,7 @@ __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow
     const float2 ev = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y - zm.y));
     const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
     const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);
-    const float2 X = cadd(ev, cmul(tw_n[k], od));
+    const float2 X = cadd(ev, cmul(tw.split[m], od));
     if (valid) dst[k] = X;
   }
   if (t == 0 && valid) dst[M] = make_float2(v[0].x - v[0].y, 0.f);
@@ -372,8 +387,7 @@ __device__ __forceinline__ void c2r_fetch(RowFetch<M>& f, int t, bool valid, con
 
 template <int M>
 __device__ __forceinline__ void c2r_from_regs(float2 (&v)[XPlan<M>::E], const RowFetch<M>& f, float2* ldsrow,
-                                              int t, const float2* __restrict__ tw_m,
-                                              const float2* __restrict__ tw_n) {
+                                              int t, const XTw<M, -1>& tw) {
   constexpr int E = XPlan<M>::E, T = M / E;
   RowView view{ldsrow};
   __syncthreads();
@@ -392,20 +406,18 @@ __device__ __forceinline__ void c2r_from_regs(float2 (&v)[XPlan<M>::E], const Ro
     }
     // Z = (X_k + conj X_{M-k}) + i W_N^{-k} (X_k - conj X_{M-k})
     const float2 ev = make_float2(X.x + Xm.x, X.y - Xm.y);
-    const float2 od = cmul(make_float2(X.x - Xm.x, X.y + Xm.y), cconj(tw_n[k]));
+    const float2 od = cmul(make_float2(X.x - Xm.x, X.y + Xm.y), cconj(tw.split[m]));
     v[m] = make_float2(ev.x - od.y, ev.y + od.x);
   }
-  fft_pencil<M, -1, XPlan<M>>(v, view, t, tw_m);
+  fft_pencil<M, -1, XPlan<M>>(v, view, t, tw.fft);
 }
 
 template <int M>
 __device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
-                                        const float2* __restrict__ srow,
-                                        const float2* __restrict__ tw_m,
-                                        const float2* __restrict__ tw_n) {
+                                        const float2* __restrict__ srow, const XTw<M, -1>& tw) {
   RowFetch<M> f;
   c2r_fetch<M>(f, t, valid, srow);
-  c2r_from_regs<M>(v, f, ldsrow, t, tw_m, tw_n);
+  c2r_from_regs<M>(v, f, ldsrow, t, tw);
 }
 
 // Per-voxel material table of grain g, always read through the constant

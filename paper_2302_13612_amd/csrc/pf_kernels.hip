@@ -42,6 +42,8 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   // is transformed
   RowFetch<M> cur, nxt;
   c2r_fetch<M>(cur, t, valid, a.spec + roff);
+  XTw<M, -1> tw;
+  tw.load(a, t);
   float2 old_c[E], old_n[E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
     const float shift = (float)(st->ebar_cur[c] - st->ebar_base[c]);
     const float w = c < 3 ? 1.f : 2.f;
     float2 v[E];
-    c2r_from_regs<M>(v, cur, lds + p * LROW, t, a.tw_xh, a.tw_x);
+    c2r_from_regs<M>(v, cur, lds + p * LROW, t, tw);
     float dsum = 0.f, nsum = 0.f;
     if (valid) {
 #pragma unroll
@@ -112,11 +114,13 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   double bad[1] = {0.0};
   RowFetch<M> cur, nxt;
   c2r_fetch<M>(cur, t, valid, a.spec + roff);
+  XTw<M, -1> tw;
+  tw.load(a, t);
 #pragma unroll 1
   for (int q = 0; q < a.nv; ++q) {
     if (q + 1 < a.nv) c2r_fetch<M>(nxt, t, valid, a.spec + (q + 1) * cs + roff);
     float2 v[E];
-    c2r_from_regs<M>(v, cur, lds + p * LROW, t, a.tw_xh, a.tw_x);
+    c2r_from_regs<M>(v, cur, lds + p * LROW, t, tw);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -167,9 +171,10 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, floa
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
   const size_t cs = (size_t)nrows * a.sh;
+  XTw<M, -1> tw;
+  tw.load(a, t);
   float2 v[E];
-  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.sh, a.tw_xh,
-             a.tw_x);
+  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.sh, tw);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -598,10 +603,12 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_resid(const KArgs a, const 
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
   const size_t cs = (size_t)nrows * a.sh;
   float mx = 0.f;
+  XTw<M, -1> tw;
+  tw.load(a, t);
 #pragma unroll 1
   for (int q = 0; q < a.nv; ++q) {
     float2 v[E];
-    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + (size_t)(valid ? row : 0) * a.sh, a.tw_xh, a.tw_x);
+    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + (size_t)(valid ? row : 0) * a.sh, tw);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {

@@ -360,13 +360,15 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   }
   const size_t cs = (size_t)nrows * a.sh;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+  XTw<M, 1> tw;
+  tw.load(a, t);
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
     float2* slab = stage + (c * ROWS + p) * LROW;
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + c * cs, a.tw_xh, a.tw_x);
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, tw);
   }
   double ssum[6];
 #pragma unroll
@@ -482,13 +484,15 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   }
   const size_t cs = (size_t)nrows * a.sh;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+  XTw<M, 1> tw;
+  tw.load(a, t);
 #pragma unroll 1
   for (int q = 0; q < V; ++q) {
     float2* slab = stage + (q * ROWS + p) * LROW;
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + q * cs, a.tw_xh, a.tw_x);
+    r2c_one<M>(v, slab, t, valid, dst + q * cs, tw);
   }
   double acc[kQac];
 #pragma unroll
@@ -564,13 +568,15 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int r
   }
   const size_t cs = (size_t)nrows * a.sh;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+  XTw<M, 1> tw;
+  tw.load(a, t);
 #pragma unroll 1
   for (int c = 0; c < 2 * V; ++c) {
     float2* slab = stage + (c * ROWS + p) * LROW;
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + c * cs, a.tw_xh, a.tw_x);
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, tw);
   }
   double acc[kQac];
 #pragma unroll
