@@ -185,6 +185,13 @@ struct TwCache {
     }
   }
   __device__ __forceinline__ void load(const float2* __restrict__ tw, int t) { load_stages<1>(tw, t); }
+  // the same thread's twiddles for the opposite direction (conjugates)
+  __device__ __forceinline__ TwCache<N, P, -DIR> conj() const {
+    TwCache<N, P, -DIR> c;
+#pragma unroll
+    for (int i = 0; i < (count > 0 ? count : 1); ++i) c.w[i] = cconj(w[i]);
+    return c;
+  }
 };
 
 // Twiddle r of butterfly q of stage SI (R, NS): from the table, or from a

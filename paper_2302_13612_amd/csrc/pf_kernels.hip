@@ -338,9 +338,11 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 #pragma unroll
     for (int m = 0; m < E; ++m)
       v[c][m] = valid ? col[c * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+  TwCache<N, Plan<N>, 1> twf;
+  twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<N, 1>(v[c], view, t, a.tw_z);
+  for (int c = 0; c < 6; ++c) fft_pencil<N, 1>(v[c], view, t, twf);
   const int kxv = valid ? kx : 0;
   float xi[3] = {(float)kxv / (float)a.nx, (float)signed_k(ky, a.ny) / (float)a.ny, 0.f};
   float K0[6], K1[6], K2[6];
@@ -359,8 +361,9 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][m] = tau[c];
   }
+  const TwCache<N, Plan<N>, -1> twi = twf.conj();
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<N, -1>(v[c], view, t, a.tw_z);
+  for (int c = 0; c < 6; ++c) fft_pencil<N, -1>(v[c], view, t, twi);
   if (valid) {
 #pragma unroll
     for (int c = 0; c < 6; ++c)
@@ -387,8 +390,10 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+  TwCache<N, Plan<N>, 1> twf;
+  twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
-  fft_pencil<N, 1>(v, view, t, a.tw_z);
+  fft_pencil<N, 1>(v, view, t, twf);
   const int sy = signed_k(ky, a.ny);
   const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
@@ -406,7 +411,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
     v[m] = cscale(v[m], a.inv_ntot);
   }
   if (mode == 0) {
-    fft_pencil<N, -1>(v, view, t, a.tw_z);
+    fft_pencil<N, -1>(v, view, t, twf.conj());
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
@@ -431,7 +436,9 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
-  fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, a.tw_z);
+  TwCache<N, Plan<N>, DIR> tw;
+  tw.load(a.tw_z, t);
+  fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, tw);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
@@ -485,11 +492,13 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
       th[q][m] = valid ? col[q * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
       rh[q][m] = valid ? col[(V + q) * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
     }
+  TwCache<N, Plan<N>, 1> twf;
+  twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    fft_pencil<N, 1>(th[q], view, t, a.tw_z);
-    fft_pencil<N, 1>(rh[q], view, t, a.tw_z);
+    fft_pencil<N, 1>(th[q], view, t, twf);
+    fft_pencil<N, 1>(rh[q], view, t, twf);
   }
   const int kxv = valid ? kx : 0;
   const int sy = signed_k(ky, a.ny);
@@ -576,8 +585,9 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
       th[q][m] = cscale(nv, a.inv_ntot);
     }
   }
+  const TwCache<N, Plan<N>, -1> twi = twf.conj();
 #pragma unroll
-  for (int q = 0; q < V; ++q) fft_pencil<N, -1>(th[q], view, t, a.tw_z);
+  for (int q = 0; q < V; ++q) fft_pencil<N, -1>(th[q], view, t, twi);
   if (valid) {
 #pragma unroll
     for (int q = 0; q < V; ++q)
