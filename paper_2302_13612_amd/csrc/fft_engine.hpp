@@ -117,23 +117,38 @@ template <> struct XPlan<64>  { static constexpr int E = 4; using R = Radices<4,
 template <> struct XPlan<128> { static constexpr int E = 4; using R = Radices<4, 4, 4, 2>; };
 
 // ------------------------------------------------------------ LDS views
+// Orders the LDS accesses of one wavefront's lanes: the compiler moves no
+// memory operation across it, and the LDS unit executes a wavefront's
+// operations in issue order, so what any lane wrote before it is what every
+// lane of the same wavefront reads after it.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // One pencil of a row-major tile, padded by one element every 16 to break
-// the stride-R bank conflicts of the scatter phases.
+// the stride-R bank conflicts of the scatter phases. A row is transformed
+// by threads of one wavefront (T divides 64 and rows are contiguous thread
+// ranges), so its exchanges need only wavefront order, no block barrier.
 struct RowView {
   float2* base;
   __device__ __forceinline__ static int pad(int e) { return e + (e >> 4); }
   __device__ __forceinline__ float2 read(int e) const { return base[pad(e)]; }
   __device__ __forceinline__ void write(int e, float2 v) const { base[pad(e)] = v; }
+  __device__ __forceinline__ static void sync() { wave_sync(); }
   __host__ __device__ static constexpr int padded(int n) { return n + (n >> 4); }
 };
 
 // One column of a column-interleaved tile: element e of column c at
-// base[e * C + c]; the C columns of a wavefront segment are contiguous.
+// base[e * C + c]; the C columns of a wavefront segment are contiguous. A
+// column's threads span the block's wavefronts: exchanges need a barrier.
 template <int C>
 struct ColView {
   float2* base;
   __device__ __forceinline__ float2 read(int e) const { return base[e * C]; }
   __device__ __forceinline__ void write(int e, float2 v) const { base[e * C] = v; }
+  __device__ __forceinline__ static void sync() { __syncthreads(); }
 };
 
 template <int DIR>
@@ -209,7 +224,7 @@ __device__ __forceinline__ float2 stage_twiddle(const TwCache<N, P, DIR>& c, int
 
 // One Stockham stage. NS = product of the radices of earlier stages, SI =
 // stage index. FIRST: inputs from registers; LAST: outputs to registers.
-// Every LDS write phase sits between two block barriers, so callers may
+// Every LDS write phase sits between two syncs of the view, so callers may
 // reuse the buffer. TW: the twiddle table (const float2*) or a TwCache.
 template <int N, class P, int R, int NS, int SI, int DIR, bool FIRST, bool LAST, class View, class TW>
 __device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& lds, int t, const TW& tw) {
@@ -239,7 +254,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& ld
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q + r * NB] = a[q * R + r];
   } else {
-    __syncthreads();
+    View::sync();
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int j = t + T * q;
@@ -247,7 +262,7 @@ __device__ __forceinline__ void stockham_stage(float2 (&v)[P::E], const View& ld
 #pragma unroll
       for (int r = 0; r < R; ++r) lds.write(base + r * NS, a[q * R + r]);
     }
-    __syncthreads();
+    View::sync();
   }
 }
 
@@ -260,8 +275,8 @@ __device__ __forceinline__ void run_stages(float2 (&v)[P::E], const View& lds, i
 }
 
 // Transform the pencil held in v (thread t owns elements t + T*m, T = N/E)
-// in place with plan P. All threads of the block must call it together (it
-// contains barriers). tw: the twiddle table or the thread's TwCache.
+// in place with plan P. All threads that share the view's sync (the
+// wavefront of a row, the block of a column tile) must call it together. tw: the twiddle table or the thread's TwCache.
 template <int N, int DIR, class P = Plan<N>, class View, class TW>
 __device__ __forceinline__ void fft_pencil(float2 (&v)[P::E], const View& lds, int t, const TW& tw) {
   run_stages<N, P, 1, 0, DIR, true>(v, lds, t, tw, typename P::R{});

@@ -287,6 +287,10 @@ __device__ __forceinline__ void load_rotation(const KArgs& a, int g, float (&R)[
 }
 
 // ----------------------------------------------------------- x pass parts
+// Rows of the x passes are exchanged with wavefront order only (RowView).
+template <int M>
+constexpr bool row_in_wave() { return 64 % (M / XPlan<M>::E) == 0; }
+
 // Threads per x-pass block for half-length M (smaller for the radix-3 rows so
 // the staging slabs stay within 64 KiB of LDS).
 template <int M>
@@ -299,14 +303,15 @@ __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* l
                                          const float2* __restrict__ tw_m,
                                          const float2* __restrict__ tw_n) {
   constexpr int E = XPlan<M>::E, T = M / E;
+  static_assert(row_in_wave<M>(), "the threads of a row must lie in one wavefront");
   RowView view{ldsrow};
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     fft_pencil<M, 1, XPlan<M>>(v[c], view, t, tw_m);
-    __syncthreads();
+    view.sync();
 #pragma unroll
     for (int m = 0; m < E; ++m) view.write(t + T * m, v[c][m]);
-    __syncthreads();
+    view.sync();
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int k = t + T * m;
@@ -329,6 +334,7 @@ __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* l
 // Loaded once per kernel, they keep the row transforms free of table loads.
 template <int M, int DIR>
 struct XTw {
+  static_assert(row_in_wave<M>(), "the threads of a row must lie in one wavefront");
   TwCache<M, XPlan<M>, DIR> fft;
   float2 split[XPlan<M>::E];
   __device__ __forceinline__ void load(const KArgs& a, int t) {
@@ -347,10 +353,10 @@ __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow
   constexpr int E = XPlan<M>::E, T = M / E;
   RowView view{ldsrow};
   fft_pencil<M, 1, XPlan<M>>(v, view, t, tw.fft);
-  __syncthreads();
+  view.sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) view.write(t + T * m, v[m]);
-  __syncthreads();
+  view.sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
@@ -390,11 +396,11 @@ __device__ __forceinline__ void c2r_from_regs(float2 (&v)[XPlan<M>::E], const Ro
                                               int t, const XTw<M, -1>& tw) {
   constexpr int E = XPlan<M>::E, T = M / E;
   RowView view{ldsrow};
-  __syncthreads();
+  view.sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) view.write(t + T * m, f.x[m]);
   if (t == 0) view.write(M, f.last);
-  __syncthreads();
+  view.sync();
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int k = t + T * m;
