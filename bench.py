@@ -37,9 +37,14 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# first fixed-point iteration of a step: the forward and the inverse x pass
-# each read three more strain fields (the cubic extrapolated warm start)
-EXTRAPOLATION_BYTES_PER_VOXEL = {"ms_x_forward": 72, "ms_x_inverse": 72}
+# first fixed-point iteration of a step: the forward x pass reads three more
+# strain fields (the cubic extrapolated warm start) and stores the
+# extrapolated iterate, which the inverse pass reads in place of the strain
+EXTRAPOLATION_BYTES_PER_VOXEL = {"ms_x_forward": 96}
+# stages of a polycrystal step; the dominant one is timed in the timed region
+STAGES = ("ms_x_forward", "ms_y_forward", "ms_z_green", "ms_y_inverse", "ms_x_inverse",
+          "ac_x_forward", "ac_y_forward", "ac_z_update", "ac_y_inverse", "ac_x_inverse")
+DOMINANT = "ms_x_forward"
 
 
 def sources_digest():
@@ -390,7 +395,7 @@ def main():
     ap.add_argument("--eval-instances", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-3, help="acceptance residual of the learned stepper")
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64)
@@ -403,11 +408,18 @@ def main():
         sys.exit(2)
     args.steps_given = args.steps is not None
     if args.workload == "rve-batch":
+        if args.warmup is None:
+            args.warmup = 3
         return bench_rve_batch(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    # polycrystal: steps 11-110 of the 1000-step run (10 warm-up steps, then
+    # 100 timed); the fixed-point iteration count per step falls as the run
+    # settles, so a short window early in the run is not representative
     if args.steps is None:
-        args.steps = 20
+        args.steps = 100
+    if args.warmup is None:
+        args.warmup = 10
 
     import torch
     from paper_2302_13612_amd import binding, inputs
@@ -442,8 +454,10 @@ def main():
     for _ in range(max(0, args.warmup - 1)):
         solver.step(1, cfg["eps_bar"], cfg["sig_bar"])
     torch.cuda.synchronize()
+    # The timed steps carry HIP events around the launches of the dominant
+    # stage only (events around every launch cost a few per cent of the step).
     log(f"timing {args.steps} steps")
-    solver.profile(True)
+    solver.profile(True, only=DOMINANT)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     solver.step(args.steps, cfg["eps_bar"], cfg["sig_bar"])
@@ -454,24 +468,35 @@ def main():
     stats = solver.stats()
     value = n ** 3 * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
-    log(f"{ms_step:.3f} ms/step, {value:.3e} voxel-updates/s, ms_iters {stats['ms_iters']}")
+    n_iter = prof[DOMINANT][0]  # one launch of each fixed-point stage per iteration
+    log(f"{ms_step:.3f} ms/step, {value:.3e} voxel-updates/s, {n_iter / args.steps:.2f} fixed-point "
+        f"iterations per step (last step {stats['ms_iters']})")
 
     V = cfg["n_var"]
-    rows = []
-    total_ms = sum(v[1] for v in prof.values())
     nvox = n ** 3
-    for name, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
-        # algorithmic bytes of all launches: per-launch bytes, plus the warm
-        # start's extra reads once per timed step (every timed step extrapolates)
-        b_all = kernel_bytes(name, n, n, n, V, True) * cnt
-        b_all += EXTRAPOLATION_BYTES_PER_VOXEL.get(name, 0) * nvox * args.steps
-        avg = ms / cnt
-        gbs = b_all / (ms * 1e-3) / 1e9 if b_all else 0.0
-        rows.append((name, cnt, avg, gbs, b_all / cnt))
-        log(f"  {name:22s} {cnt:5d} x {avg * 1e3:9.1f} us  {100 * ms / total_ms:5.1f}%  "
+
+    def stage_bytes(name, cnt, steps):
+        # per-launch bytes, plus the warm start's extra traffic once per step
+        return kernel_bytes(name, n, n, n, V, True) * cnt + EXTRAPOLATION_BYTES_PER_VOXEL.get(name, 0) * nvox * steps
+
+    cnt, ms = prof[DOMINANT]
+    b_dom = stage_bytes(DOMINANT, cnt, args.steps)
+    dom = (DOMINANT, cnt, ms / cnt, b_dom / (ms * 1e-3) / 1e9, b_dom / cnt)
+    step_bytes = sum(stage_bytes(nm, n_iter if nm.startswith("ms_") else args.steps, args.steps)
+                     for nm in STAGES) / args.steps
+    # per-stage breakdown (stderr only): a few more steps with every launch timed
+    nprof = min(5, args.steps)
+    solver.profile(True)
+    solver.step(nprof, cfg["eps_bar"], cfg["sig_bar"])
+    allp = solver.profile_read()
+    solver.profile(False)
+    total_ms = sum(v[1] for v in allp.values())
+    log(f"per-stage times over {nprof} further steps:")
+    for name, (c2, m2) in sorted(allp.items(), key=lambda kv: -kv[1][1]):
+        b = stage_bytes(name, c2, nprof)
+        gbs = b / (m2 * 1e-3) / 1e9 if b else 0.0
+        log(f"  {name:22s} {c2:5d} x {m2 / c2 * 1e3:9.1f} us  {100 * m2 / total_ms:5.1f}%  "
             f"{gbs:8.1f} GB/s ({100 * gbs / HBM_PEAK_GBS:5.1f}% of HBM)")
-    dom = rows[0]
-    step_bytes = sum(r[4] * r[1] for r in rows) / args.steps
     roofline = {
         "bound": "hbm",
         "kernel": dom[0],
@@ -503,6 +528,8 @@ def main():
                         f"RMS 2e-3, uniaxial -5e-3, fixed-point tol 1e-6",
             "grid": [n, n, n], "n_var": V, "n_grains": 64,
             "ms_iters_last_step": stats["ms_iters"],
+            "fixed_point_iters_per_step": round(n_iter / args.steps, 3),
+            "timed_steps": f"{args.warmup + 1}-{args.warmup + args.steps} of the run",
         },
         "roofline": roofline,
     }

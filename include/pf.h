@@ -186,6 +186,9 @@ int pf_fft(pf_ctx *ctx, int32_t direction, int32_t ncomp, float *real, void *spe
 int pf_profile_enable(pf_ctx *ctx, int32_t on);
 int pf_profile_read(pf_ctx *ctx, int32_t max_n, char (*names)[64],
                     int64_t *counts, double *total_ms, int32_t *n);
+/* Time only the launches of the named stage (e.g. "ms_x_forward"); NULL or
+ * "" times every launch. The name is copied. */
+int pf_profile_select(pf_ctx *ctx, const char *name);
 
 int pf_destroy(pf_ctx *ctx);
 const char *pf_last_error(const pf_ctx *ctx);

@@ -88,6 +88,7 @@ def load():
     lib.pf_profile_enable.argtypes = [vp, i32]
     lib.pf_profile_read.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
+    lib.pf_profile_select.argtypes = [vp, ctypes.c_char_p]
     lib.pf_destroy.argtypes = [vp]
     lib.pf_last_error.argtypes = [vp]
     lib.pf_last_error.restype = ctypes.c_char_p
@@ -100,7 +101,8 @@ def load():
     lib.pf_batch_stats.argtypes = [vp, i32, ctypes.POINTER(PfStats)]
     lib.pf_batch_size.argtypes = [vp]
     for name in ("pf_workspace_size", "pf_init", "pf_step", "pf_fields", "pf_stats_get", "pf_fft",
-                 "pf_profile_enable", "pf_profile_read", "pf_destroy", "pf_mg_twin_tables",
+                 "pf_profile_enable", "pf_profile_read", "pf_profile_select", "pf_destroy",
+                 "pf_mg_twin_tables",
                  "pf_batch_workspace_size", "pf_batch_init", "pf_batch_step", "pf_batch_fields",
                  "pf_batch_stats", "pf_batch_size"):
         getattr(lib, name).restype = ctypes.c_int
@@ -282,7 +284,10 @@ class Solver:
         self._check(self.lib.pf_fft(self.ctx, -1, nc, real.data_ptr(), spec.data_ptr()), "pf_fft")
         return real
 
-    def profile(self, on=True):
+    def profile(self, on=True, only=None):
+        """Per-launch HIP-event timing on (reset) or off; only: time just the
+        launches of that stage name."""
+        self._check(self.lib.pf_profile_select(self.ctx, only.encode() if only else None), "pf_profile_select")
         self._check(self.lib.pf_profile_enable(self.ctx, 1 if on else 0), "pf_profile_enable")
 
     def profile_read(self):
@@ -422,9 +427,7 @@ class BatchSolver:
         self._check(self.lib.pf_batch_stats(self.ctx, int(inst), ctypes.byref(s)), "pf_batch_stats")
         return _stats_dict(s, self.n_var)
 
-    def profile(self, on=True):
-        self._check(self.lib.pf_profile_enable(self.ctx, 1 if on else 0), "pf_profile_enable")
-
+    profile = Solver.profile
     profile_read = Solver.profile_read
 
     def close(self):

@@ -331,6 +331,7 @@ struct pf_ctx {
   bool capturing;
   // profiling
   bool prof_on;
+  std::string prof_only;  // time only the launches of this stage ("" = all)
   std::vector<ProfEntry> prof;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::string> prof_names;
@@ -364,7 +365,7 @@ hipEvent_t get_event(pf_ctx* c) {
 template <class F>
 int launch(pf_ctx* c, hipStream_t s, const char* name, F&& f) {
   ProfEntry pe;
-  const bool prof = c->prof_on && !c->capturing;
+  const bool prof = c->prof_on && !c->capturing && (c->prof_only.empty() || c->prof_only == name);
   if (prof) {
     pe.name = name;
     pe.start = get_event(c);
@@ -1144,6 +1145,12 @@ int pf_profile_enable(pf_ctx* c, int32_t on) {
   c->prof_counts.clear();
   c->prof_ms.clear();
   c->prof_on = on != 0;
+  return PF_OK;
+}
+
+int pf_profile_select(pf_ctx* c, const char* name) {
+  if (!c) return PF_EINVAL;
+  c->prof_only = name ? name : "";
   return PF_OK;
 }
 

@@ -85,7 +85,9 @@ struct KArgs {
   // fields
   float* eta;                 // [nv][ninst][nz][ny][nx]
   float* eps;                 // [6][ninst][nz][ny][nx] strain the iterate is formed from
-  float* eps_out;             // where the inverse pass writes the new iterate
+  float* eps_out;             // where the inverse pass writes the new iterate; with
+                              // iter_mode != 0 the forward pass first stores the
+                              // extrapolated iterate there (the inverse pass's old value)
   const float* eps_h1;        // converged strain of the step before (iter_mode >= 1)
   const float* eps_h2;        // of the one before that (iter_mode >= 2)
   const float* eps_h3;        // and of the one before that (iter_mode 3)

@@ -44,17 +44,20 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   c2r_fetch<M>(cur, t, valid, a.spec + roff);
   XTw<M, -1> tw;
   tw.load(a, t);
+  // the iterate this iteration started from: the stored strain, or on the
+  // first iteration of a step the extrapolated one the forward pass wrote
+  const float* prev = a.iter_mode != 0 ? a.eps_out : a.eps;
   float2 old_c[E], old_n[E];
 #pragma unroll
   for (int m = 0; m < E; ++m)
-    old_c[m] = valid ? *reinterpret_cast<const float2*>(a.eps + rbase + 2 * (t + T * m)) : make_float2(0.f, 0.f);
+    old_c[m] = valid ? *reinterpret_cast<const float2*>(prev + rbase + 2 * (t + T * m)) : make_float2(0.f, 0.f);
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
     if (c + 1 < 6) {
       c2r_fetch<M>(nxt, t, valid, a.spec + (c + 1) * cs + roff);
 #pragma unroll
       for (int m = 0; m < E; ++m)
-        old_n[m] = valid ? *reinterpret_cast<const float2*>(a.eps + (c + 1) * vs + rbase + 2 * (t + T * m))
+        old_n[m] = valid ? *reinterpret_cast<const float2*>(prev + (c + 1) * vs + rbase + 2 * (t + T * m))
                          : make_float2(0.f, 0.f);
     }
     const float shift = (float)(st->ebar_cur[c] - st->ebar_base[c]);
@@ -66,25 +69,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const size_t off = c * vs + rbase + 2 * (t + T * m);
-        float2 old = old_c[m];
-        if (a.iter_mode >= 1) {
-          const float2 p1 = *reinterpret_cast<const float2*>(a.eps_h1 + off);
-          if (a.iter_mode == 1) {
-            old = make_float2(2.f * old.x - p1.x, 2.f * old.y - p1.y);
-          } else {
-            const float2 p2 = *reinterpret_cast<const float2*>(a.eps_h2 + off);
-            if (a.iter_mode == 2) {
-              old = make_float2(3.f * (old.x - p1.x) + p2.x, 3.f * (old.y - p1.y) + p2.y);
-            } else {
-              const float2 p3 = *reinterpret_cast<const float2*>(a.eps_h3 + off);
-              old = make_float2(4.f * (old.x + p2.x) - 6.f * p1.x - p3.x, 4.f * (old.y + p2.y) - 6.f * p1.y - p3.y);
-            }
-          }
-        }
+        const float2 old = old_c[m];
         const float dx0 = v[m].x - (old.x + shift), dx1 = v[m].y - (old.y + shift);
         dsum += dx0 * dx0 + dx1 * dx1;
         nsum += v[m].x * v[m].x + v[m].y * v[m].y;
-        // the output may be the oldest field (h2 or h3): read above, same element
+        // on a first iteration the output is the field read above as the old iterate
         *reinterpret_cast<float2*>(a.eps_out + off) = v[m];
       }
     }

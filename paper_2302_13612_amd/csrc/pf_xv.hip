@@ -327,6 +327,13 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
       load_rotation(a, s.g1, R[1]);
     }
     extrapolate_strain(a, vs, (uint32_t)(rbase + 2 * k), s.e);
+    if (a.iter_mode != 0 && valid) {
+      // the extrapolated first iterate, kept for the inverse pass's residual
+      // (eps_out may be the oldest history field: read above, same element)
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        *reinterpret_cast<float2*>(a.eps_out + c * vs + rbase + 2 * k) = s.e[c];
+    }
     float o[2][6];
     float e[2][6], ep[2][6], et[2][V];
 #pragma unroll
