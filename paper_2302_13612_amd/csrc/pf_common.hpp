@@ -11,9 +11,11 @@ namespace pft {
 typedef const __attribute__((address_space(4))) float* ctab_t;
 
 // -------------------------------------------------------------- reductions
-template <int Q>
+// NW: the most wavefronts a calling block has (its LDS scratch is sized by
+// it; the x passes' staging leaves little LDS to spare at three blocks/CU).
+template <int Q, int NW = 16>
 __device__ __forceinline__ void block_sum(double (&v)[Q], double* __restrict__ out) {
-  __shared__ double red[16][Q];
+  __shared__ double red[NW][Q];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll
@@ -32,8 +34,9 @@ __device__ __forceinline__ void block_sum(double (&v)[Q], double* __restrict__ o
   __syncthreads();
 }
 
+template <int NW = 16>
 __device__ __forceinline__ void block_minmax(float mn, float mx, float* __restrict__ out) {
-  __shared__ float red[16][2];
+  __shared__ float red[NW][2];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
 #pragma unroll
     for (int m = 0; m < E; ++m) old_c[m] = old_n[m];
   }
-  block_sum<2>(acc, a.part_res + (size_t)blockIdx.x * kQres);
+  block_sum<2, xthreads<M>() / 64>(acc, a.part_res + (size_t)blockIdx.x * kQres);
 }
 
 // Phase-field update, inverse: new order parameters, count of non-finite values.
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
     }
     cur = nxt;
   }
-  block_sum<1>(bad, a.part_res + (size_t)blockIdx.x * kQres);
+  block_sum<1, xthreads<M>() / 64>(bad, a.part_res + (size_t)blockIdx.x * kQres);
 }
 
 // Plain transforms of caller fields (checking the passes).

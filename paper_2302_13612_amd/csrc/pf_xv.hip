@@ -380,7 +380,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   double ssum[6];
 #pragma unroll
   for (int c = 0; c < 6; ++c) ssum[c] = (double)fsum[c];
-  block_sum<6>(ssum, a.part_ms + (size_t)blockIdx.x * kQms);
+  block_sum<6, xthreads<M>() / 64>(ssum, a.part_ms + (size_t)blockIdx.x * kQms);
 }
 
 // Phase-field update, forward: driving forces and the explicit right-hand
@@ -504,8 +504,8 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   double acc[kQac];
 #pragma unroll
   for (int q = 0; q < kQac; ++q) acc[q] = (double)facc[q];
-  block_sum<kQac>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
-  block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
+  block_sum<kQac, xthreads<M>() / 64>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
+  block_minmax<xthreads<M>() / 64>(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
 
 
@@ -591,8 +591,8 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int r
   acc[0] = (double)facc[0];
 #pragma unroll
   for (int q = 0; q < V; ++q) acc[14 + q] = (double)facc[1 + q];
-  block_sum<kQac>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
-  block_minmax(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
+  block_sum<kQac, xthreads<M>() / 64>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
+  block_minmax<xthreads<M>() / 64>(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
 #endif
 }  // namespace pft
