@@ -167,3 +167,27 @@ def mg_tables(rotations, variant_ids, C_hex=MG_HEX_PA, gamma=GAMMA_TW,
             C_var[g, a] = rotate4(C_tw, R)
             eps0[g, a] = rotate2(twin_eigenstrain(m, s, gamma), R)
     return C_grain, C_var, eps0
+
+
+# Table 5: gradient coefficient c2 along the twin-plane normal and along the
+# shear direction (N = J/m).
+C2_NORMAL = 2.81e-7
+C2_SHEAR = 2.81e-6
+
+
+def twin_gradient_tensors(rotations, variant_ids, c2n=C2_NORMAL, c2s=C2_SHEAR, c2t=None,
+                          c_over_a=C_OVER_A):
+    """Anisotropic gradient tensors K_a = c2n m m + c2s s s + c2t t t of the
+    given variants (t = m x s; the paper gives no value along t, read as
+    c2n), turned to the sample frame: (G, V, 3, 3)."""
+    c2t = c2n if c2t is None else c2t
+    rotations = np.asarray(rotations, float).reshape(-1, 3, 3)
+    systems = twin_systems(c_over_a)
+    out = np.empty((rotations.shape[0], len(variant_ids), 3, 3))
+    for g in range(rotations.shape[0]):
+        for a, vid in enumerate(variant_ids):
+            m, s = systems[vid]
+            t = np.cross(m, s)
+            K = c2n * np.outer(m, m) + c2s * np.outer(s, s) + c2t * np.outer(t, t)
+            out[g, a] = rotate2(K, rotations[g])
+    return out

@@ -33,7 +33,7 @@ from scipy.special import erf
 
 from . import spectral
 from .mech import ms_solve, voigt6_to_tensor
-from .phasefield import chemical_force, mechanical_force
+from .phasefield import chemical_force, gradient_symbol, mechanical_force
 
 N_COND = 7
 
@@ -117,7 +117,8 @@ def conditioning(eps0_sample6, eps_bar_xx, gamma_tw=0.129, strain_scale=5e-3):
 
 def variational_derivative(prob, eta, load, eps_p6=None):
     """dF/df = chem - 2 kappa lap f - mech for eta (V, nz, ny, nx), with the
-    equilibrium of eta solved from a uniform start."""
+    equilibrium of eta solved from a uniform start (with gradient tensors
+    K_a, -2 div(K_a grad f_a) in place of -2 kappa lap f_a)."""
     shape = prob.shape
     C_grain, C_var, eps0 = prob.tables
     eps_p = np.zeros(shape + (3, 3)) if eps_p6 is None else voigt6_to_tensor(eps_p6)
@@ -127,10 +128,12 @@ def variational_derivative(prob, eta, load, eps_p6=None):
                                             load, prob.ms_tol, prob.ms_max_iter, prob.h_kind)
     chem = chemical_force(eta, prob.A)
     mech = mechanical_force(eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
-    xi = spectral.wavevectors(shape, prob.dx)
-    xi2 = (xi ** 2).sum(axis=-1)
-    lap = np.stack([spectral.irfft3(-xi2 * spectral.rfft3(eta[a]), shape) for a in range(eta.shape[0])])
-    return chem - 2.0 * prob.kappa * lap - mech
+    kv = getattr(prob, "kappa_var", None)
+    grad_force = np.stack([
+        spectral.irfft3(2.0 * gradient_symbol(shape, prob.dx, prob.kappa, None if kv is None else kv[a]) *
+                        spectral.rfft3(eta[a]), shape)
+        for a in range(eta.shape[0])])
+    return chem + grad_force - mech
 
 
 def macro_residual(prob, eta_prev, eta_pred, n_steps, load, eps_p6=None):

@@ -29,6 +29,14 @@ Readings (stated once here, used below):
 * No clipping of f.
 * Gradient energy reported as kappa sum_a |grad f_a|^2 through Parseval with
   the -|xi|^2 Laplacian symbol (equal to eq. (14) for one variant).
+* Anisotropic gradient energy (Table 5 lists c2 along the twin-plane normal
+  and along the shear direction): optionally each variant carries a
+  symmetric tensor K_a (sample frame, J/m) and the gradient term becomes
+  grad f_a . K_a . grad f_a, so its force is -2 div(K_a grad f_a) and its
+  Fourier symbol xi . K_a . xi replaces kappa |xi|^2. K_a = kappa I is the
+  isotropic case. K_a is constant in space: one grain (a polycrystal would
+  need a spatially varying K, which the spectral implicit step does not
+  solve exactly).
 """
 
 import numpy as np
@@ -83,29 +91,54 @@ def double_well_density(eta, A):
     return A * g
 
 
-def gradient_energy(eta, kappa, dx):
-    """kappa sum_a int |grad f_a|^2 dV by Parseval with the |xi|^2 symbol."""
-    shape = eta.shape[1:]
+def gradient_symbol(shape, dx, kappa, K=None):
+    """Fourier symbol of the gradient energy density on the half spectrum:
+    kappa |xi|^2, or xi . K . xi for a tensor K (3, 3) indexed (x, y, z).
+
+    Reading: the cross terms K_ij xi_i xi_j (i != j) are odd in xi_i, and on an
+    even axis the Nyquist index stands for both +N/2 and -N/2; a component at
+    its Nyquist index therefore enters the diagonal term K_ii xi_i^2 only (the
+    mean over the two signs), which keeps the symbol even and the step real."""
     xi = spectral.wavevectors(shape, dx)
-    xi2 = (xi ** 2).sum(axis=-1)
+    if K is None:
+        return kappa * (xi ** 2).sum(axis=-1)
+    K = np.asarray(K, dtype=np.float64)
+    nz, ny, nx = shape
+    xc = xi.copy()
+    if nx % 2 == 0:
+        xc[:, :, nx // 2, 0] = 0.0
+    if ny % 2 == 0:
+        xc[:, ny // 2, :, 1] = 0.0
+    if nz % 2 == 0:
+        xc[nz // 2, :, :, 2] = 0.0
+    diag = sum(K[i, i] * xi[..., i] ** 2 for i in range(3))
+    cross = sum(K[i, j] * xc[..., i] * xc[..., j] for i in range(3) for j in range(3) if i != j)
+    return diag + cross
+
+
+def gradient_energy(eta, kappa, dx, kappa_var=None):
+    """sum_a int grad f_a . K_a . grad f_a dV (K_a = kappa I unless kappa_var
+    gives the (V, 3, 3) tensors) by Parseval."""
+    shape = eta.shape[1:]
     w = spectral.half_spectrum_weights(shape)
     ntot = np.prod(shape)
     dV = dx ** 3
     total = 0.0
     for a in range(eta.shape[0]):
+        q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
         F = spectral.rfft3(eta[a], workers=-1)
-        total += (w * xi2 * np.abs(F) ** 2).sum() * dV / ntot
-    return kappa * total
+        total += (w * q * np.abs(F) ** 2).sum() * dV / ntot
+    return total
 
 
-def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx):
-    """f^{n+1} = IFFT[ FFT(f^n - L dt (chem - mech)) / (1 + 2 L dt kappa |xi|^2) ]."""
+def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx, kappa_var=None):
+    """f_a^{n+1} = IFFT[ FFT(f_a^n - L dt (chem_a - mech_a)) / (1 + 2 L dt q_a(xi)) ]
+    with q_a the gradient symbol (kappa |xi|^2, or xi . K_a . xi)."""
     shape = eta.shape[1:]
-    xi = spectral.wavevectors(shape, dx)
-    xi2 = (xi ** 2).sum(axis=-1)
-    denom = 1.0 + 2.0 * L * dt * kappa * xi2
     out = np.empty_like(eta)
     for a in range(eta.shape[0]):
+        q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
+        denom = 1.0 + 2.0 * L * dt * q
         rhs = eta[a] - L * dt * (chem[a] - mech[a])
         out[a] = spectral.irfft3(spectral.rfft3(rhs, workers=-1) / denom, shape, workers=-1)
     return out
@@ -116,14 +149,20 @@ class Problem:
 
     tables = (C_grain, C_var, eps0) as returned by crystal.mg_tables.
     C0: reference stiffness (3,3,3,3) for the fixed point.
+    kappa_var: optional (V, 3, 3) gradient tensors (one grain only).
     """
 
     def __init__(self, shape, dx, tables, A, kappa, L, dt, C0, gid=None,
-                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200):
+                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200, kappa_var=None):
         self.shape = tuple(shape)
         self.dx = float(dx)
         self.tables = tables
         self.A, self.kappa, self.L, self.dt = float(A), float(kappa), float(L), float(dt)
+        if kappa_var is not None:
+            if gid is not None and len(np.unique(gid)) > 1:
+                raise ValueError("an anisotropic gradient energy needs one grain")
+            kappa_var = np.asarray(kappa_var, dtype=np.float64)
+        self.kappa_var = kappa_var
         self.gid = None if gid is None else np.asarray(gid, dtype=np.int64)
         self.h_kind = h_kind
         self.ms_tol, self.ms_max_iter = ms_tol, ms_max_iter
@@ -164,11 +203,11 @@ def step(prob, state, eps_p6, load):
         load, prob.ms_tol, prob.ms_max_iter, prob.h_kind)
     chem = chemical_force(state.eta, prob.A)
     mech = mechanical_force(state.eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
-    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx)
+    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var)
     dV = prob.dx ** 3
     stats = {
         "G_dw": float(double_well_density(state.eta, prob.A).sum() * dV),
-        "G_gd": float(gradient_energy(state.eta, prob.kappa, prob.dx)),
+        "G_gd": float(gradient_energy(state.eta, prob.kappa, prob.dx, prob.kappa_var)),
         "G_me": float(0.5 * np.einsum("...ij,...ij->...", eps_el, sigma).sum() * dV),
         "sig_mean": tensor_to_voigt6(sigma.mean(axis=(0, 1, 2))),
         "eps_mean": tensor_to_voigt6(eps.mean(axis=(0, 1, 2))),
@@ -194,5 +233,5 @@ def reference_stiffness_average(C_grain, C_var):
 
 
 __all__ = ["chemical_force", "mechanical_force", "double_well_density",
-           "gradient_energy", "allen_cahn_update", "Problem", "State", "step",
+           "gradient_symbol", "gradient_energy", "allen_cahn_update", "Problem", "State", "step",
            "h_interp", "reference_stiffness_average", "stress_voigt6"]
