@@ -275,10 +275,9 @@ __device__ __forceinline__ void green_apply(const KArgs& a, const DevState* st, 
   const float A11 = K[0] * K[5] - K[2] * K[2];
   const float A12 = K[1] * K[2] - K[0] * K[4];
   const float A22 = K[0] * K[3] - K[1] * K[1];
-  const float rdet = 1.f / (K[0] * A00 + K[1] * A01 + K[2] * A02);
-  const float Nm[3][3] = {{A00 * rdet, A01 * rdet, A02 * rdet},
-                          {A01 * rdet, A11 * rdet, A12 * rdet},
-                          {A02 * rdet, A12 * rdet, A22 * rdet}};
+  // K^{-1} = adj(K) / det: the adjugate here, 1/det folded into the scale
+  const float rdet = fast_rcp(K[0] * A00 + K[1] * A01 + K[2] * A02);
+  const float Nm[3][3] = {{A00, A01, A02}, {A01, A11, A12}, {A02, A12, A22}};
   // t = tau xi (tau symmetric, Voigt xx yy zz yz xz xy)
   float2 tv[3];
   tv[0] = make_float2(tau[0].x * xi[0] + tau[5].x * xi[1] + tau[4].x * xi[2],
@@ -293,10 +292,10 @@ __device__ __forceinline__ void green_apply(const KArgs& a, const DevState* st, 
     u[i] = make_float2(Nm[i][0] * tv[0].x + Nm[i][1] * tv[1].x + Nm[i][2] * tv[2].x,
                        Nm[i][0] * tv[0].y + Nm[i][1] * tv[1].y + Nm[i][2] * tv[2].y);
   // eps = -sym(xi (x) u) / N
-  const float h = -0.5f * s;
-  tau[0] = cscale(u[0], -s * xi[0]);
-  tau[1] = cscale(u[1], -s * xi[1]);
-  tau[2] = cscale(u[2], -s * xi[2]);
+  const float g = -s * rdet, h = 0.5f * g;
+  tau[0] = cscale(u[0], g * xi[0]);
+  tau[1] = cscale(u[1], g * xi[1]);
+  tau[2] = cscale(u[2], g * xi[2]);
   tau[3] = make_float2(h * (xi[1] * u[2].x + xi[2] * u[1].x), h * (xi[1] * u[2].y + xi[2] * u[1].y));
   tau[4] = make_float2(h * (xi[0] * u[2].x + xi[2] * u[0].x), h * (xi[0] * u[2].y + xi[2] * u[0].y));
   tau[5] = make_float2(h * (xi[0] * u[1].x + xi[1] * u[0].x), h * (xi[0] * u[1].y + xi[1] * u[0].y));
@@ -334,12 +333,13 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
   for (int c = 0; c < 6; ++c) fft_pencil<N, 1>(v[c], view, t, twf);
   const int kxv = valid ? kx : 0;
   float xi[3] = {(float)kxv / (float)a.nx, (float)signed_k(ky, a.ny) / (float)a.ny, 0.f};
+  const float inz = 1.f / (float)a.nz;
   float K0[6], K1[6], K2[6];
   acoustic_parts(ref, xi[0], xi[1], K0, K1, K2);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = t + T * m;
-    xi[2] = (float)signed_k(kz, a.nz) / (float)a.nz;
+    xi[2] = (float)signed_k(kz, a.nz) * inz;
     float K[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) K[e] = K0[e] + xi[2] * (K1[e] + xi[2] * K2[e]);
@@ -386,19 +386,20 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const int sy = signed_k(ky, a.ny);
   const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
-  double en[kQgd] = {0.0, 0.0, 0.0};
+  const float gx = (float)a.gx * fx + (float)a.gy * fy, gz = (float)a.gz;
+  float e0 = 0.f;  // this thread's Parseval terms, then FP64
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int sz = signed_k(t + T * m, a.nz);
     const float fz = (float)sz * (float)sz;
     if (mode == 0) {
       const float den = 1.f + a.ax * fx + a.ay * fy + a.az * fz;
-      v[m] = cscale(v[m], 1.f / den);
+      v[m] = cscale(v[m], fast_rcp(den));
     }
-    const double x2 = a.gx * fx + a.gy * fy + a.gz * fz;
-    if (valid) en[0] += wgt * x2 * ((double)v[m].x * v[m].x + (double)v[m].y * v[m].y);
+    e0 += (gx + gz * fz) * (v[m].x * v[m].x + v[m].y * v[m].y);
     v[m] = cscale(v[m], a.inv_ntot);
   }
+  double en[kQgd] = {valid ? wgt * (double)e0 : 0.0, 0.0, 0.0};
   if (mode == 0) {
     fft_pencil<N, -1>(v, view, t, twf.conj());
     if (valid) {
@@ -509,12 +510,14 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
   const ctab_t W = kt + 21 + 6 * kMaxVar;
   const float fx = (float)kxv * (float)kxv, fy = (float)sy * (float)sy;
   const double wgt = (kxv == 0 || kxv == a.nx / 2) ? 1.0 : 2.0;
-  double en[kQgd] = {0.0, 0.0, 0.0};
+  const float inz = 1.f / (float)a.nz;
+  const float gxy = (float)a.gx * fx + (float)a.gy * fy, gz = (float)a.gz;
+  float ef[kQgd] = {0.f, 0.f, 0.f};  // this thread's terms, then FP64
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kz = t + T * m;
     const int sz = signed_k(kz, a.nz);
-    const float xi2 = (float)sz / (float)a.nz;
+    const float xi2 = (float)sz * inz;
     const float fz = (float)sz * (float)sz;
     float2 y[V];  // sum_b B_ab f_hat_b
 #pragma unroll
@@ -530,7 +533,7 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
       const float A11 = K[0] * K[5] - K[2] * K[2];
       const float A12 = K[1] * K[2] - K[0] * K[4];
       const float A22 = K[0] * K[3] - K[1] * K[1];
-      const float rdet = 1.f / (K[0] * A00 + K[1] * A01 + K[2] * A02);
+      const float rdet = fast_rcp(K[0] * A00 + K[1] * A01 + K[2] * A02);
       float u[V][3], nu[V][3];
 #pragma unroll
       for (int q = 0; q < V; ++q) {
@@ -548,24 +551,22 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
           y[q].x += b * th[r][m].x;
           y[q].y += b * th[r][m].y;
         }
-      if (valid && mode == 0) {
-        double e2 = 0.0;
+      if (mode == 0) {
 #pragma unroll
-        for (int q = 0; q < V; ++q) e2 += (double)th[q][m].x * y[q].x + (double)th[q][m].y * y[q].y;
-        en[1] += wgt * e2;
+        for (int q = 0; q < V; ++q) ef[1] += th[q][m].x * y[q].x + th[q][m].y * y[q].y;
       }
     }
     const float den = 1.f + a.ax * fx + a.ay * fy + a.az * fz;
-    const double x2 = a.gx * fx + a.gy * fy + a.gz * fz;
+    const float rden = fast_rcp(den);
+    const float x2 = gxy + gz * fz;
 #pragma unroll
     for (int q = 0; q < V; ++q) {
-      if (mode == 0 && valid)
-        en[2] += wgt * x2 * ((double)th[q][m].x * th[q][m].x + (double)th[q][m].y * th[q][m].y);
+      if (mode == 0) ef[2] += x2 * (th[q][m].x * th[q][m].x + th[q][m].y * th[q][m].y);
       float2 nv;
       if (mode == 0) {
-        nv = make_float2((rh[q][m].x - a.LDt * y[q].x) / den, (rh[q][m].y - a.LDt * y[q].y) / den);
+        nv = make_float2((rh[q][m].x - a.LDt * y[q].x) * rden, (rh[q][m].y - a.LDt * y[q].y) * rden);
         if (dc && valid) nv = make_float2(rh[q][m].x + (float)a.state[inst].kh_drive[q], 0.f);
-        if (valid) en[0] += wgt * x2 * ((double)nv.x * nv.x + (double)nv.y * nv.y);
+        ef[0] += x2 * (nv.x * nv.x + nv.y * nv.y);
       } else {
         const float g = den - 1.f;
         nv = make_float2(rh[q][m].x + g * th[q][m].x + a.LDt * y[q].x, rh[q][m].y + g * th[q][m].y + a.LDt * y[q].y);
@@ -583,7 +584,12 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
 #pragma unroll
       for (int m = 0; m < E; ++m) col[q * cs + (size_t)(t + T * m) * zs] = th[q][m];
   }
-  if (mode == 0) block_sum<kQgd>(en, a.part_gd + (size_t)lb * kQgd);
+  if (mode == 0) {
+    double en[kQgd];
+#pragma unroll
+    for (int q = 0; q < kQgd; ++q) en[q] = valid ? wgt * (double)ef[q] : 0.0;
+    block_sum<kQgd>(en, a.part_gd + (size_t)lb * kQgd);
+  }
 }
 
 // Residual of a macro step, inverse x pass: r = f~ - prev + S g with g the
