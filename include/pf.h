@@ -129,6 +129,19 @@ typedef struct {
                               and C_ref equal to it needs exactly one       */
   uint32_t bc_stress_mask; /* bit i set: mean stress component i prescribed,
                               clear: mean strain component i prescribed     */
+  const double *kappa_var; /* optional host [n_var][6]: anisotropic gradient
+                              energy, one symmetric tensor K_a per variant
+                              (tensor-Voigt xx yy zz yz xz xy, J/m, sample
+                              frame) in place of kappa I: the gradient term
+                              of f_a is grad f_a . K_a . grad f_a and its
+                              implicit symbol xi . K_a . xi (Table 5 gives c2
+                              along the twin-plane normal and the shear
+                              direction; pf_mg_twin_gradient builds K_a). A
+                              component at its Nyquist index enters only the
+                              diagonal term. NULL: isotropic kappa. Needs
+                              n_grains == 1 (PF_EUNSUPPORTED otherwise: a
+                              spatially varying K is not solved exactly by
+                              the spectral implicit step). Copied at init.  */
 } pf_problem;
 
 /* Load of one pf_step call. */
@@ -289,6 +302,18 @@ int pf_mg_twin_tables(const double C_hex[5], double c_over_a, double gamma_tw,
                       int32_t n_grains, const double *rotations,
                       int32_t n_var, const int32_t *variant_ids,
                       double *C_grain, double *C_var, double *eps0);
+
+/* Host helper: anisotropic gradient tensors of Mg tension-twin variants,
+ * K_a = c2n m m + c2s s s + c2t t t (m the twin-plane normal, s the shear
+ * direction, t = m x s; Table 5 gives c2n = 2.81e-7 N and c2s = 2.81e-6 N,
+ * nothing along t), turned to the sample frame by the rotations
+ * [n_grains][3][3]. Output kappa_var [n_grains][n_var][6] (tensor-Voigt),
+ * host memory, caller-owned. PF_EINVAL on a bad variant id or a negative
+ * coefficient. */
+int pf_mg_twin_gradient(double c_over_a, double c2n, double c2s, double c2t,
+                        int32_t n_grains, const double *rotations,
+                        int32_t n_var, const int32_t *variant_ids,
+                        double *kappa_var);
 
 #ifdef __cplusplus
 }

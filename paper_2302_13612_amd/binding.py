@@ -42,7 +42,18 @@ class PfProblem(ctypes.Structure):
         ("ms_tol", ctypes.c_double),
         ("ms_max_iter", ctypes.c_int32),
         ("bc_stress_mask", ctypes.c_uint32),
+        ("kappa_var", _dp),
     ]
+
+
+def _kappa_var_voigt(kappa_var, V):
+    """(V, 3, 3) or (V, 6) gradient tensors -> contiguous (V, 6) tensor-Voigt."""
+    k = np.asarray(kappa_var, dtype=np.float64)
+    if k.shape == (V, 3, 3):
+        k = np.stack([k[:, 0, 0], k[:, 1, 1], k[:, 2, 2], k[:, 1, 2], k[:, 0, 2], k[:, 0, 1]], axis=1)
+    if k.shape != (V, 6):
+        raise ValueError("kappa_var must be (n_var, 3, 3) or (n_var, 6)")
+    return np.ascontiguousarray(k)
 
 
 class PfLoad(ctypes.Structure):
@@ -94,6 +105,8 @@ def load():
     lib.pf_last_error.restype = ctypes.c_char_p
     lib.pf_mg_twin_tables.argtypes = [_dp, ctypes.c_double, ctypes.c_double, i32, _dp, i32,
                                       ctypes.POINTER(i32), _dp, _dp, _dp]
+    lib.pf_mg_twin_gradient.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        i32, _dp, i32, ctypes.POINTER(i32), _dp]
     lib.pf_batch_workspace_size.argtypes = [ctypes.POINTER(PfProblem), i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pf_batch_init.argtypes = [ctypes.POINTER(PfProblem), i32, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     lib.pf_batch_step.argtypes = [vp, i32, ctypes.POINTER(PfLoad)]
@@ -102,7 +115,7 @@ def load():
     lib.pf_batch_size.argtypes = [vp]
     for name in ("pf_workspace_size", "pf_init", "pf_step", "pf_fields", "pf_stats_get", "pf_fft",
                  "pf_profile_enable", "pf_profile_read", "pf_profile_select", "pf_destroy",
-                 "pf_mg_twin_tables",
+                 "pf_mg_twin_tables", "pf_mg_twin_gradient",
                  "pf_batch_workspace_size", "pf_batch_init", "pf_batch_step", "pf_batch_fields",
                  "pf_batch_stats", "pf_batch_size"):
         getattr(lib, name).restype = ctypes.c_int
@@ -138,6 +151,20 @@ def mg_twin_tables(rotations, variant_ids, C_hex=(59.4e9, 25.6e9, 21.4e9, 61.6e9
     return Cg, Cv, e0
 
 
+def mg_twin_gradient(rotations, variant_ids, c2n=2.81e-7, c2s=2.81e-6, c2t=None, c_over_a=1.633):
+    """Sample-frame anisotropic gradient tensors (G, V, 6) computed by the
+    library (c2t defaults to c2n)."""
+    lib = load()
+    R = np.ascontiguousarray(np.asarray(rotations, dtype=np.float64).reshape(-1, 3, 3))
+    G, V = R.shape[0], len(variant_ids)
+    ids = (ctypes.c_int32 * V)(*[int(v) for v in variant_ids])
+    out = np.zeros((G, V, 6))
+    rc = lib.pf_mg_twin_gradient(c_over_a, c2n, c2s, c2n if c2t is None else c2t, G, _ptr(R), V, ids, _ptr(out))
+    if rc != PF_OK:
+        raise PfError(rc, "pf_mg_twin_gradient")
+    return out
+
+
 def stress_mask_bits(mask):
     return int(sum(1 << i for i, m in enumerate(mask) if m))
 
@@ -169,10 +196,12 @@ class Solver:
     (G,V,6). C_ref: 6x6 numpy or None for the mean of all stiffnesses.
     rotations: optional (G,3,3) crystal->sample rotations; then the tables
     hold one crystal-frame material (leading dimension 1) shared by all grains.
+    kappa_var: optional (V,3,3) or (V,6) anisotropic gradient tensors (sample
+    frame; one grain only).
     """
 
     def __init__(self, eta0, dx, A, kappa, L, dt, tables, stress_mask, gid=None, C_ref=None,
-                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None):
+                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None, kappa_var=None):
         import torch
         self.lib = load()
         self.torch = torch
@@ -218,6 +247,12 @@ class Solver:
         p.ms_tol = ms_tol
         p.ms_max_iter = ms_max_iter
         p.bc_stress_mask = stress_mask_bits(stress_mask)
+        if kappa_var is not None:
+            kv = _kappa_var_voigt(kappa_var, V)
+            self._keep.append(kv)
+            p.kappa_var = _ptr(kv)
+        else:
+            p.kappa_var = None
         nbytes = ctypes.c_size_t()
         rc = self.lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(nbytes))
         if rc != PF_OK:
@@ -321,6 +356,8 @@ class BatchSolver:
                 crystal frame when "rotation" is given
       rotation  optional (3,3) crystal->sample rotation
       C_ref     optional 6x6 reference medium (default: the mean stiffness)
+      kappa_var optional (V,3,3) or (V,6) anisotropic gradient tensors
+                (sample frame)
     The shared parameters are keyword arguments as for Solver.
     """
 
@@ -372,6 +409,12 @@ class BatchSolver:
             p.ms_tol = ms_tol
             p.ms_max_iter = ms_max_iter
             p.bc_stress_mask = stress_mask_bits(stress_mask)
+            if inst.get("kappa_var") is not None:
+                kv = _kappa_var_voigt(inst["kappa_var"], V)
+                self._keep.append(kv)
+                p.kappa_var = _ptr(kv)
+            else:
+                p.kappa_var = None
             self.shapes.append((nz, ny, nx))
         nbytes = ctypes.c_size_t()
         rc = self.lib.pf_batch_workspace_size(probs, n, ctypes.byref(nbytes))

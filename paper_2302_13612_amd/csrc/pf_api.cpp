@@ -39,7 +39,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
 // Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
-  size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, tw;
+  size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, gk, tw;
   size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
@@ -82,6 +82,7 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.loads = take(sizeof(double) * 12 * (size_t)ninst);
   L.kh = take(sizeof(float) * pft::kKhStride * (size_t)ninst);
   L.khd = take(sizeof(double) * pft::kKhdStride * (size_t)ninst);
+  L.gk = take(sizeof(float) * pft::kGkStride * (size_t)ninst);
   L.tw = take(sizeof(float) * 2 * (size_t)(nx / 2 + nx + ny + nz));
   L.part_ms = take(sizeof(double) * xb * pft::kQms);
   L.part_res = take(sizeof(double) * xb * pft::kQres);
@@ -165,6 +166,8 @@ struct InstanceHost {
   double bss[36];
   float kh[pft::kKhStride];
   double khd[pft::kKhdStride];
+  float gk[pft::kGkStride]; // gradient-energy coefficients (see kGkStride)
+  bool aniso;               // kappa_var given
   bool one_iteration;       // one stiffness everywhere, equal to the reference
   bool homogeneous;         // one stiffness everywhere (spectral path possible)
 };
@@ -216,6 +219,26 @@ int prepare_instance(const pf_problem* p, InstanceHost& h, std::string& why) {
   if (rotated)
     for (int g = 0; g < G; ++g)
       for (int k = 0; k < 9; ++k) h.rot[12 * g + k] = (float)p->grain_rot[9 * g + k];
+  // gradient energy: D_ij = 2 L dt K_ij c_i c_j and G_ij = K_ij c_i c_j with
+  // c_i = 2 pi / (n_i dx), K = kappa I unless kappa_var gives K_a
+  {
+    const double tp = 2.0 * M_PI / p->dx;
+    const double c[3] = {tp / p->nx, tp / p->ny, tp / p->nz};
+    const double f = 2.0 * p->L * p->dt;
+    std::memset(h.gk, 0, sizeof(h.gk));
+    h.aniso = p->kappa_var != nullptr;
+    for (int q = 0; q < nv; ++q) {
+      double K[6] = {p->kappa, p->kappa, p->kappa, 0.0, 0.0, 0.0};
+      if (h.aniso)
+        for (int k = 0; k < 6; ++k) K[k] = p->kappa_var[6 * q + k];
+      const double g[6] = {K[0] * c[0] * c[0], K[1] * c[1] * c[1], K[2] * c[2] * c[2],
+                           2.0 * K[3] * c[1] * c[2], 2.0 * K[4] * c[0] * c[2], 2.0 * K[5] * c[0] * c[1]};
+      for (int k = 0; k < 6; ++k) {
+        h.gk[12 * q + k] = (float)(f * g[k]);
+        h.gk[12 * q + 6 + k] = (float)g[k];
+      }
+    }
+  }
   // reference medium
   double C0[36];
   if (p->C_ref_auto) {
@@ -406,6 +429,18 @@ int validate(const pf_problem* p, std::string& why) {
   if (p->ms_max_iter < 1) { why = "ms_max_iter must be >= 1"; return PF_EINVAL; }
   if (!(p->ms_tol >= 0)) { why = "ms_tol must be >= 0"; return PF_EINVAL; }
   if (p->bc_stress_mask > 63u) { why = "bc_stress_mask has bits above 5"; return PF_EINVAL; }
+  if (p->kappa_var) {
+    for (int q = 0; q < p->n_var; ++q) {
+      const double* K = p->kappa_var + 6 * q;
+      for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(K[k])) { why = "kappa_var must be finite"; return PF_EINVAL; }
+      if (K[0] < 0 || K[1] < 0 || K[2] < 0) { why = "kappa_var diagonal must be >= 0"; return PF_EINVAL; }
+    }
+    if (p->n_grains != 1) {
+      why = "an anisotropic gradient energy (kappa_var) needs one grain";
+      return PF_EUNSUPPORTED;
+    }
+  }
   return PF_OK;
 }
 
@@ -789,6 +824,9 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.loads = reinterpret_cast<double*>(ws + L.loads);
     a.kh = reinterpret_cast<float*>(ws + L.kh);
     a.khd = reinterpret_cast<double*>(ws + L.khd);
+    bool aniso = false;
+    for (int m : g.members) aniso = aniso || hosts[m].aniso;
+    a.gk = aniso ? reinterpret_cast<float*>(ws + L.gk) : nullptr;
     // one grain: its rotated table serves every voxel (no per-voxel rotation)
     const bool rotated = pg.grain_rot != nullptr;
     a.rot = (rotated && G > 1) ? reinterpret_cast<float*>(ws + L.rot) : nullptr;
@@ -817,7 +855,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.save_stress = 0;
 
     // per-instance tables, stacked
-    std::vector<float> tab, ref, kh;
+    std::vector<float> tab, ref, kh, gk;
     std::vector<double> bss, khd;
     for (int m : g.members) {
       const InstanceHost& h = hosts[m];
@@ -826,6 +864,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
       kh.insert(kh.end(), h.kh, h.kh + pft::kKhStride);
       bss.insert(bss.end(), h.bss, h.bss + 36);
       khd.insert(khd.end(), h.khd, h.khd + pft::kKhdStride);
+      gk.insert(gk.end(), h.gk, h.gk + pft::kGkStride);
     }
     std::vector<float> twh(2 * (size_t)(g.nx / 2 + g.nx + g.ny + g.nz));
     twiddles(g.nx / 2, twh.data());
@@ -845,6 +884,8 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     if ((e = h2d(a.kh, kh.data(), kh.size() * sizeof(float))) != hipSuccess) return bail(e, "spectral tables");
     if ((e = h2d(a.bss, bss.data(), bss.size() * sizeof(double))) != hipSuccess) return bail(e, "mixed condition");
     if ((e = h2d(a.khd, khd.data(), khd.size() * sizeof(double))) != hipSuccess) return bail(e, "spectral tables");
+    if (a.gk && (e = h2d(a.gk, gk.data(), gk.size() * sizeof(float))) != hipSuccess)
+      return bail(e, "gradient tables");
     if ((e = h2d(tw, twh.data(), twh.size() * sizeof(float))) != hipSuccess) return bail(e, "twiddles");
     if ((e = h2d(a.state, st0.data(), st0.size() * sizeof(DevState))) != hipSuccess) return bail(e, "state");
     // the host vectors above are pageable: the copies complete before return
@@ -1096,7 +1137,8 @@ int pf_batch_stats(pf_ctx* c, int32_t inst, pf_stats* out) {
     out->eps_mean[k] = st.stats[8 + k] / ntot;
   }
   for (int q = 0; q < c->nv; ++q) out->eta_mean[q] = st.stats[14 + q] / ntot;
-  out->G_gd = c->kappa * st.stats[pft::kQac] * dV / ntot;
+  // with gradient tables the sums already carry K (isotropic: kappa |xi|^2)
+  out->G_gd = (g.args.gk ? 1.0 : c->kappa) * st.stats[pft::kQac] * dV / ntot;
   out->eta_min = st.stats[pft::kQac + 1];
   out->eta_max = st.stats[pft::kQac + 2];
   out->ms_iters = st.st.iters;

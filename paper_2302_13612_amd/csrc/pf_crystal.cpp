@@ -97,6 +97,27 @@ void pf_rotate_voigt(const double* Cv, const double* R9, double* out) {
   rotate_voigt(Cv, R, out);
 }
 
+namespace {
+// Unit plane normal m and shear direction s of variant vid (crystal frame,
+// a = 1): m from the plane indices on the reciprocal basis, s from the
+// direction indices on the direct one.
+void variant_axes(double c_over_a, int vid, V3& m, V3& s) {
+  const V3 a1{{std::sqrt(3.0) / 2.0, -0.5, 0.0}}, a2{{0.0, 1.0, 0.0}}, cc{{0.0, 0.0, c_over_a}};
+  const V3 a3{{-(a1.v[0] + a2.v[0]), -(a1.v[1] + a2.v[1]), 0.0}};
+  const double vol = dot(a1, cross(a2, cc));
+  V3 b1 = cross(a2, cc), b2 = cross(cc, a1), b3 = cross(a1, a2);
+  for (int k = 0; k < 3; ++k) {
+    b1.v[k] /= vol;
+    b2.v[k] /= vol;
+    b3.v[k] /= vol;
+  }
+  const int* pl = kVariants[vid][0];
+  const int* dr = kVariants[vid][1];
+  m = unit(axpy(pl[0], b1, axpy(pl[1], b2, axpy(pl[3], b3, V3{{0, 0, 0}}))));
+  s = unit(axpy(dr[0], a1, axpy(dr[1], a2, axpy(dr[2], a3, axpy(dr[3], cc, V3{{0, 0, 0}})))));
+}
+}  // namespace
+
 extern "C" int pf_mg_twin_tables(const double C_hex[5], double c_over_a, double gamma_tw, int32_t n_grains,
                                  const double* rotations, int32_t n_var, const int32_t* variant_ids,
                                  double* C_grain, double* C_var, double* eps0) {
@@ -113,26 +134,14 @@ extern "C" int pf_mg_twin_tables(const double C_hex[5], double c_over_a, double 
   Ch[2] = Ch[12] = Ch[8] = Ch[13] = C13;
   Ch[21] = Ch[28] = C44;
   Ch[35] = 0.5 * (C11 - C12);
-  // hexagonal basis (a = 1) and its reciprocal
-  const V3 a1{{std::sqrt(3.0) / 2.0, -0.5, 0.0}}, a2{{0.0, 1.0, 0.0}}, cc{{0.0, 0.0, c_over_a}};
-  const V3 a3{{-(a1.v[0] + a2.v[0]), -(a1.v[1] + a2.v[1]), 0.0}};
-  const double vol = dot(a1, cross(a2, cc));
-  V3 b1 = cross(a2, cc), b2 = cross(cc, a1), b3 = cross(a1, a2);
-  for (int k = 0; k < 3; ++k) {
-    b1.v[k] /= vol;
-    b2.v[k] /= vol;
-    b3.v[k] /= vol;
-  }
   for (int g = 0; g < n_grains; ++g) {
     double R[3][3];
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) R[i][j] = rotations[9 * g + 3 * i + j];
     rotate_voigt(Ch, R, C_grain + 36 * g);
     for (int q = 0; q < n_var; ++q) {
-      const int* pl = kVariants[variant_ids[q]][0];
-      const int* dr = kVariants[variant_ids[q]][1];
-      const V3 m = unit(axpy(pl[0], b1, axpy(pl[1], b2, axpy(pl[3], b3, V3{{0, 0, 0}}))));
-      const V3 s = unit(axpy(dr[0], a1, axpy(dr[1], a2, axpy(dr[2], a3, axpy(dr[3], cc, V3{{0, 0, 0}})))));
+      V3 m, s;
+      variant_axes(c_over_a, variant_ids[q], m, s);
       double Q[3][3], Ctw[36];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) Q[i][j] = 2.0 * m.v[i] * m.v[j] - (i == j ? 1.0 : 0.0);
@@ -152,6 +161,40 @@ extern "C" int pf_mg_twin_tables(const double C_hex[5], double c_over_a, double 
       double* o = eps0 + 6 * ((size_t)g * n_var + q);
       o[0] = er[0][0]; o[1] = er[1][1]; o[2] = er[2][2];
       o[3] = er[1][2]; o[4] = er[0][2]; o[5] = er[0][1];
+    }
+  }
+  return PF_OK;
+}
+
+extern "C" int pf_mg_twin_gradient(double c_over_a, double c2n, double c2s, double c2t, int32_t n_grains,
+                                   const double* rotations, int32_t n_var, const int32_t* variant_ids,
+                                   double* kappa_var) {
+  if (!rotations || !variant_ids || !kappa_var) return PF_EINVAL;
+  if (n_grains < 1 || n_var < 1 || n_var > 6 || !(c_over_a > 0)) return PF_EINVAL;
+  if (!(c2n >= 0) || !(c2s >= 0) || !(c2t >= 0)) return PF_EINVAL;
+  for (int q = 0; q < n_var; ++q)
+    if (variant_ids[q] < 0 || variant_ids[q] > 5) return PF_EINVAL;
+  for (int g = 0; g < n_grains; ++g) {
+    const double* R = rotations + 9 * g;
+    for (int q = 0; q < n_var; ++q) {
+      V3 m, s;
+      variant_axes(c_over_a, variant_ids[q], m, s);
+      const V3 t = cross(m, s);
+      // sample-frame axes R m, R s, R t
+      V3 ms{}, ss{}, ts{};
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) {
+          ms.v[i] += R[3 * i + k] * m.v[k];
+          ss.v[i] += R[3 * i + k] * s.v[k];
+          ts.v[i] += R[3 * i + k] * t.v[k];
+        }
+      double K[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          K[i][j] = c2n * ms.v[i] * ms.v[j] + c2s * ss.v[i] * ss.v[j] + c2t * ts.v[i] * ts.v[j];
+      double* o = kappa_var + 6 * ((size_t)g * n_var + q);
+      o[0] = K[0][0]; o[1] = K[1][1]; o[2] = K[2][2];
+      o[3] = K[1][2]; o[4] = K[0][2]; o[5] = K[0][1];
     }
   }
   return PF_OK;

@@ -58,6 +58,10 @@ constexpr int kRefStride = 21 + 36;
 // stress-controlled block embedded in 6x6 (36), eps0_a (6 per variant).
 constexpr int kKhStride = 21 + 6 * kMaxVar + kMaxVar * kMaxVar;
 constexpr int kKhdStride = 36 + 36 + 6 * kMaxVar;
+// anisotropic gradient energy, per instance and variant: 6 coefficients of
+// the semi-implicit denominator 1 + sum D k k and 6 of the energy symbol
+// sum G k k over integer wave numbers (xx yy zz, then doubled yz xz xy)
+constexpr int kGkStride = 12 * kMaxVar;
 constexpr int kKhMaxVar = 3;       // variants handled by the spectral path (2 V <= 6 spectra)
 
 // Everything a kernel needs, passed by value. A context holds ninst
@@ -81,6 +85,7 @@ struct KArgs {
   int tab_inst;               // table stride between instances (n_grains * tab_stride)
   const float* kh;            // [ninst][kKhStride] or null
   const double* khd;          // [ninst][kKhdStride] or null
+  const float* gk;            // [ninst][kGkStride] or null (isotropic kappa)
   uint32_t stress_mask;
   // fields
   float* eta;                 // [nv][ninst][nz][ny][nx]

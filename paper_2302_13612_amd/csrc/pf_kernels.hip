@@ -200,6 +200,42 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_y(const KArgs a
 // Signed index of coefficient k on an axis of length n (Nyquist -> -n/2).
 __device__ __forceinline__ int signed_k(int k, int n) { return k < n / 2 ? k : k - n; }
 
+// Gradient-energy symbols of one column (kx, ky) of variant q as quadratics
+// in the z wave number: the semi-implicit denominator 1 + 2 L dt xi.K.xi and
+// the Parseval symbol (kappa |xi|^2 up to the host's kappa factor, or
+// xi.K.xi from the instance's tables). A wave number at its Nyquist index
+// enters the diagonal terms only (the cross terms are odd in it).
+// GK: the tables are given (a.gk); otherwise the isotropic per-axis factors.
+template <bool GK>
+struct GradSym {
+  float d0, d1, d2;  // den - 1 = d0 + d1 kcz + d2 kz^2
+  float g0, g1, g2;  // symbol  = g0 + g1 kcz + g2 kz^2
+  GradSym() = default;
+  __device__ __forceinline__ GradSym(const KArgs& a, int inst, int q, int kx, int sy) {
+    const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
+    if constexpr (!GK) {
+      d0 = a.ax * fx + a.ay * fy, d1 = 0.f, d2 = a.az;
+      g0 = (float)a.gx * fx + (float)a.gy * fy, g1 = 0.f, g2 = (float)a.gz;
+      return;
+    }
+    const ctab_t t = (ctab_t)(a.gk + (size_t)inst * kGkStride + 12 * q);
+    const float cx = kx == a.nx / 2 ? 0.f : (float)kx, cy = 2 * sy == -a.ny ? 0.f : (float)sy;
+    d0 = t[0] * fx + t[1] * fy + t[5] * cx * cy, d1 = t[3] * cy + t[4] * cx, d2 = t[2];
+    g0 = t[6] * fx + t[7] * fy + t[11] * cx * cy, g1 = t[9] * cy + t[10] * cx, g2 = t[8];
+  }
+  // cz: the z wave number for the cross terms (0 at the Nyquist index)
+  __device__ __forceinline__ float den(float cz, float fz) const {
+    if constexpr (GK) return 1.f + d0 + cz * d1 + d2 * fz;
+    return 1.f + d0 + d2 * fz;
+  }
+  __device__ __forceinline__ float sym(float cz, float fz) const {
+    if constexpr (GK) return g0 + cz * g1 + g2 * fz;
+    return g0 + g2 * fz;
+  }
+};
+
+__device__ __forceinline__ float cross_k(int sz, int n) { return 2 * sz == -n ? 0.f : (float)sz; }
+
 // Logical block index that gives consecutive ids to the blocks the hardware
 // deals to one XCD (blocks go round-robin to the 8 XCDs), so neighbouring
 // column tiles that share 128-byte lines run under the same L2.
@@ -365,7 +401,7 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 // transform, semi-implicit divide by 1 + 2 L dt kappa |xi|^2 (and 1/N),
 // Parseval sum of |xi|^2 |f_hat|^2 of the new state, inverse transform.
 // mode 1: Parseval sum of the unmodified spectrum only, nothing stored.
-template <int N>
+template <int N, bool GK>
 __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArgs a, int mode) {
   constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
   __shared__ float2 lds[N * C];
@@ -384,19 +420,15 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const ColView<C> view{lds + cc};
   fft_pencil<N, 1>(v, view, t, twf);
   const int sy = signed_k(ky, a.ny);
-  const float fx = (float)kx * (float)kx, fy = (float)sy * (float)sy;
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
-  const float gx = (float)a.gx * fx + (float)a.gy * fy, gz = (float)a.gz;
+  const GradSym<GK> gs(a, inst, q, kx, sy);
   float e0 = 0.f;  // this thread's Parseval terms, then FP64
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int sz = signed_k(t + T * m, a.nz);
-    const float fz = (float)sz * (float)sz;
-    if (mode == 0) {
-      const float den = 1.f + a.ax * fx + a.ay * fy + a.az * fz;
-      v[m] = cscale(v[m], fast_rcp(den));
-    }
-    e0 += (gx + gz * fz) * (v[m].x * v[m].x + v[m].y * v[m].y);
+    const float fz = (float)sz * (float)sz, cz = cross_k(sz, a.nz);
+    if (mode == 0) v[m] = cscale(v[m], fast_rcp(gs.den(cz, fz)));
+    e0 += gs.sym(cz, fz) * (v[m].x * v[m].x + v[m].y * v[m].y);
     v[m] = cscale(v[m], a.inv_ntot);
   }
   double en[kQgd] = {valid ? wgt * (double)e0 : 0.0, 0.0, 0.0};
@@ -455,7 +487,7 @@ __host__ __device__ constexpr int kh_tile() { return V == 1 ? kColTile : kZmsTil
 // L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
 __device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk);
 
-template <int N, int V>
+template <int N, int V, bool GK>
 __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode, int nblk_x) {
   constexpr int E = Plan<N>::E, T = N / E, C = kh_tile<V>();
   __shared__ float2 lds[N * C];
@@ -511,7 +543,9 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
   const float fx = (float)kxv * (float)kxv, fy = (float)sy * (float)sy;
   const double wgt = (kxv == 0 || kxv == a.nx / 2) ? 1.0 : 2.0;
   const float inz = 1.f / (float)a.nz;
-  const float gxy = (float)a.gx * fx + (float)a.gy * fy, gz = (float)a.gz;
+  GradSym<GK> gsq[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) gsq[q] = GradSym<GK>(a, inst, q, kxv, sy);
   float ef[kQgd] = {0.f, 0.f, 0.f};  // this thread's terms, then FP64
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -556,11 +590,12 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
         for (int q = 0; q < V; ++q) ef[1] += th[q][m].x * y[q].x + th[q][m].y * y[q].y;
       }
     }
-    const float den = 1.f + a.ax * fx + a.ay * fy + a.az * fz;
-    const float rden = fast_rcp(den);
-    const float x2 = gxy + gz * fz;
+    const float cz = cross_k(sz, a.nz);
 #pragma unroll
     for (int q = 0; q < V; ++q) {
+      const float den = gsq[q].den(cz, fz);
+      const float rden = fast_rcp(den);
+      const float x2 = gsq[q].sym(cz, fz);
       if (mode == 0) ef[2] += x2 * (th[q][m].x * th[q][m].x + th[q][m].y * th[q][m].y);
       float2 nv;
       if (mode == 0) {
@@ -999,7 +1034,11 @@ hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
 
 hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
   const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, a.nv);
-  PF_SWITCH_N(a.nz, (k_z_ac<N><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  if (a.gk) {
+    PF_SWITCH_N(a.nz, (k_z_ac<N, true><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  } else {
+    PF_SWITCH_N(a.nz, (k_z_ac<N, false><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  }
   return hipGetLastError();
 }
 
@@ -1031,23 +1070,28 @@ hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream
 }
 
 
-hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s) {
+template <bool GK>
+hipError_t kh_z_update_t(const KArgs& a, int mode, hipStream_t s) {
   switch (a.nv) {
     case 1: {
       const dim3 grid(((a.nh + kColTile - 1) / kColTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 1><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 1, GK><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
     } break;
     case 2: {
       const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 2><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 2, GK><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
     } break;
     case 3: {
       const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 3><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
+      PF_SWITCH_N(a.nz, (k_z_kh<N, 3, GK><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
     } break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s) {
+  return a.gk ? kh_z_update_t<true>(a, mode, s) : kh_z_update_t<false>(a, mode, s);
 }
 
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s) {

@@ -32,8 +32,13 @@ def oracle_problem(cfg, tol=1e-10):
     if cfg["homogeneous"]:
         tabs = (tabs[0], np.broadcast_to(tabs[0][:, None], tabs[1].shape).copy(), tabs[2])
     C0 = opf.reference_stiffness_average(tabs[0], tabs[1])
+    kv = None
+    if cfg.get("aniso"):
+        # the oracle's own gradient tensors (one grain)
+        kv = cr.twin_gradient_tensors(np.asarray(cfg["rotations"])[:1], cfg["variant_ids"], **cfg["aniso"])[0]
     return opf.Problem(cfg["shape"], cfg["dx"], tabs, cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], C0,
-                       gid=cfg["gid"], h_kind=cfg.get("h_kind", "linear"), ms_tol=tol, ms_max_iter=300)
+                       gid=cfg["gid"], h_kind=cfg.get("h_kind", "linear"), ms_tol=tol, ms_max_iter=300,
+                       kappa_var=kv)
 
 
 def oracle_run(cfg, steps, tol=1e-10):
@@ -67,9 +72,13 @@ def gpu_solver(cfg, device="cuda", rotation_form=True):
     eta0 = torch.from_numpy(np.ascontiguousarray(cfg["eta0"])).to(device)
     gid = None if cfg["gid"] is None else torch.from_numpy(np.ascontiguousarray(cfg["gid"])).to(device)
     h_kind = binding.PF_H_QUINTIC if cfg.get("h_kind") == "quintic" else binding.PF_H_LINEAR
+    kv = None
+    if cfg.get("aniso"):
+        # the library's own gradient tensors (one grain, sample frame)
+        kv = binding.mg_twin_gradient(np.asarray(cfg["rotations"])[:1], cfg["variant_ids"], **cfg["aniso"])[0]
     solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
                             cfg["stress_mask"], gid=gid, h_kind=h_kind, ms_tol=cfg["ms_tol"],
-                            ms_max_iter=cfg["ms_max_iter"], rotations=rotations)
+                            ms_max_iter=cfg["ms_max_iter"], rotations=rotations, kappa_var=kv)
     epsp = None if cfg["eps_p"] is None else torch.from_numpy(np.ascontiguousarray(cfg["eps_p"])).to(device)
     return solver, epsp
 
@@ -113,18 +122,22 @@ def batch_instance_cfg(batch, i, variant=None):
     return cfg
 
 
-def gpu_batch(batch, idx, variants, device="cuda", **kw):
+def gpu_batch(batch, idx, variants, device="cuda", aniso=None, **kw):
     """BatchSolver over instances idx of a batch recipe (library tables in
-    the crystal frame, turned by each instance's rotation)."""
+    the crystal frame, turned by each instance's rotation). aniso: optional
+    per-instance dicts (c2n, c2s, c2t) or None entries for the gradient
+    tensors."""
     import torch
     from paper_2302_13612_amd import binding
     insts = []
-    for i, v in zip(idx, variants):
+    for k, (i, v) in enumerate(zip(idx, variants)):
         inst = batch["instances"][i]
         Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], [v])
         Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
-        insts.append(dict(eta0=torch.from_numpy(inst["eta0"]).to(device), tables=(Cg, Cv, e0),
-                          rotation=inst["rotation"]))
+        d = dict(eta0=torch.from_numpy(inst["eta0"]).to(device), tables=(Cg, Cv, e0), rotation=inst["rotation"])
+        if aniso is not None and aniso[k]:
+            d["kappa_var"] = binding.mg_twin_gradient(inst["rotation"][None], [v], **aniso[k])[0]
+        insts.append(d)
     return binding.BatchSolver(insts, batch["dx"], batch["A"], batch["kappa"], batch["L"], batch["dt"],
                                batch["stress_mask"], ms_tol=batch["ms_tol"], ms_max_iter=batch["ms_max_iter"],
                                **kw)

@@ -71,3 +71,61 @@ def test_mg_tables_match_oracle(seed):
 def test_mg_tables_reject_bad_variant():
     with pytest.raises(binding.PfError):
         binding.mg_twin_tables(np.eye(3)[None], [6])
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_mg_gradient_tensors_match_oracle(seed):
+    rng = inputs.rng_for(seed)
+    R = inputs.random_rotations(3, rng)
+    ids = [0, 1, 4]
+    K = binding.mg_twin_gradient(R, ids, c2n=2.81e-7, c2s=2.81e-6, c2t=1.3e-7)
+    oK = cr.twin_gradient_tensors(R, ids, c2n=2.81e-7, c2s=2.81e-6, c2t=1.3e-7)
+    for g in range(3):
+        for a in range(3):
+            ref = oK[g, a]
+            np.testing.assert_allclose(K[g, a], [ref[0, 0], ref[1, 1], ref[2, 2], ref[1, 2], ref[0, 2], ref[0, 1]],
+                                       rtol=0, atol=1e-20)
+
+
+def valid_problem(lib, n_grains=1, keep=None):
+    """A problem that passes validation (pointers are only checked, never read
+    before the validation fails)."""
+    keep = keep if keep is not None else []
+    Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None].repeat(n_grains, 0), [0])
+    keep += [Cg, Cv, e0]
+    p = binding.PfProblem()
+    p.nx = p.ny = p.nz = 32
+    p.dx, p.n_var, p.A, p.kappa, p.L, p.dt = 5e-8, 1, 1e7, 1e-9, 1.2e-5, 2e-4
+    p.n_grains = n_grains
+    p.C_grain, p.C_var, p.eps0 = binding._ptr(Cg), binding._ptr(Cv), binding._ptr(e0)
+    p.grain_id = 0x1000 if n_grains > 1 else None
+    p.eta0 = 0x2000
+    p.C_ref_auto, p.ms_tol, p.ms_max_iter = 1, 1e-6, 10
+    return p
+
+
+def test_anisotropic_gradient_needs_one_grain():
+    lib = binding.load()
+    keep = []
+    p = valid_problem(lib, n_grains=2, keep=keep)
+    kv = np.ascontiguousarray(np.array([[1e-9, 2e-9, 3e-9, 1e-10, 0.0, 0.0]]))
+    p.kappa_var = binding._ptr(kv)
+    ctx = ctypes.c_void_p()
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
+    assert not ctx.value
+    kv[0, 0] = -1.0                             # negative diagonal
+    p.n_grains = 1
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EINVAL
+
+
+def test_batch_voxel_limit_of_one_size():
+    lib = binding.load()
+    keep = []
+    n = 64                                      # 64 x 256^3 = 2^30 voxels: one too many
+    probs = (binding.PfProblem * n)()
+    for i in range(n):
+        probs[i] = valid_problem(lib, keep=keep)
+        probs[i].nx = probs[i].ny = probs[i].nz = 256
+    size = ctypes.c_size_t()
+    assert lib.pf_batch_workspace_size(probs, n, ctypes.byref(size)) == binding.PF_EINVAL
+    assert lib.pf_batch_workspace_size(probs, n - 1, ctypes.byref(size)) == binding.PF_OK
