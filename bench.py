@@ -45,6 +45,8 @@ EXTRAPOLATION_BYTES_PER_VOXEL = {"ms_x_forward": 96}
 STAGES = ("ms_x_forward", "ms_y_forward", "ms_z_green", "ms_y_inverse", "ms_x_inverse",
           "ac_x_forward", "ac_y_forward", "ac_z_update", "ac_y_inverse", "ac_x_inverse")
 DOMINANT = "ms_x_forward"
+# Table 5: gradient coefficient c2 along the twin-plane normal / shear direction
+C2N, C2S = 2.81e-7, 2.81e-6
 
 
 def sources_digest():
@@ -152,7 +154,7 @@ def kh_bytes(name, groups, V=1):
     return tot
 
 
-def oracle_rve_baseline(batch, variants, sizes_count):
+def oracle_rve_baseline(batch, variants, sizes_count, aniso=False):
     """Oracle per-step time of one instance of each size, extrapolated to the
     batch (sum over instances of the per-size time)."""
     from oracle import crystal as cr
@@ -164,8 +166,10 @@ def oracle_rve_baseline(batch, variants, sizes_count):
         Cg, Cv, e0 = cr.mg_tables(inst["rotation"][None], [variants[i]])
         Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
         C0 = opf.reference_stiffness_average(Cg, Cv)
+        kv = cr.twin_gradient_tensors(inst["rotation"][None], [variants[i]], c2n=C2N, c2s=C2S)[0] if aniso else None
         prob = opf.Problem(inst["shape"], batch["dx"], (Cg, Cv, e0), batch["A"], batch["kappa"], batch["L"],
-                           batch["dt"], C0, ms_tol=batch["ms_tol"], ms_max_iter=batch["ms_max_iter"])
+                           batch["dt"], C0, ms_tol=batch["ms_tol"], ms_max_iter=batch["ms_max_iter"],
+                           kappa_var=kv)
         st = opf.State.initial(inst["eta0"].astype(np.float64), np.zeros(6))
         ld = dict(eps_bar=inst["eps_bar"], sig_bar=batch["sig_bar"], stress_mask=batch["stress_mask"])
         opf.step(prob, st, None, ld)  # warm (plans, caches)
@@ -201,8 +205,12 @@ def bench_rve_batch(args):
     for inst, v in zip(insts, variants):
         Cg, Cv, e0 = binding.mg_twin_tables(np.eye(3)[None], [v])
         Cv = np.broadcast_to(Cg[:, None], Cv.shape).copy()
-        specs.append(dict(eta0=torch.from_numpy(inst["eta0"]).to(dev), tables=(Cg, Cv, e0),
-                          rotation=inst["rotation"]))
+        sp = dict(eta0=torch.from_numpy(inst["eta0"]).to(dev), tables=(Cg, Cv, e0), rotation=inst["rotation"])
+        if args.aniso:
+            # gradient tensors of Table 5 (c2 along the normal and the shear
+            # direction of the instance's variant), sample frame
+            sp["kappa_var"] = binding.mg_twin_gradient(inst["rotation"][None], [v], c2n=C2N, c2s=C2S)[0]
+        specs.append(sp)
     offs = np.cumsum([0] + [inst["eta0"].size for inst in insts])
     nvox = int(offs[-1])
     log(f"batch of {nb} instances, {nvox / 1e6:.1f} M voxels")
@@ -262,14 +270,17 @@ def bench_rve_batch(args):
                                                      "kh_y_inverse", "kh_x_inverse"))
     ms_step = 1e3 * elapsed / steps
     out = {
-        "metric": "PF-FFT voxel-updates/s, batch of 256 RVEs (edges 32-96), graph replay",
+        "metric": "PF-FFT voxel-updates/s, batch of 256 RVEs (edges 32-96), graph replay" +
+                  (", anisotropic gradient energy" if args.aniso else ""),
         "value": value, "unit": "voxel-updates/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"rve-batch: {nb} single-crystal cubes, " +
                                ", ".join(f"{n}^3 x{c}" for n, c in groups) +
                                f", 1 variant, homogeneous stiffness, {nsnap} snapshots of eta",
-                   "voxels": nvox, "path": "homogeneous spectral"},
+                   "voxels": nvox, "path": "homogeneous spectral",
+                   "gradient_energy": (f"anisotropic per variant, c2 {C2N:g} (normal) / {C2S:g} (shear) N"
+                                       if args.aniso else f"isotropic, kappa {batch['kappa']:g} J/m")},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(dom[3], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(dom[3] / HBM_PEAK_GBS, 4), "traffic": None,
                      "bytes_per_step": kh_bytes(dom[0], groups),
@@ -279,7 +290,7 @@ def bench_rve_batch(args):
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one step per size)")
-        out["cpu_baseline"] = oracle_rve_baseline(batch, variants, sizes_count)
+        out["cpu_baseline"] = oracle_rve_baseline(batch, variants, sizes_count, aniso=args.aniso)
     print(json.dumps(out), flush=True)
 
 
@@ -399,6 +410,8 @@ def main():
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=64)
+    ap.add_argument("--aniso", action="store_true",
+                    help="rve-batch: anisotropic gradient energy of Table 5 for every instance")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
