@@ -206,6 +206,51 @@ int pf_profile_select(pf_ctx *ctx, const char *name);
 int pf_destroy(pf_ctx *ctx);
 const char *pf_last_error(const pf_ctx *ctx);
 
+/* FE <-> FFT mapping by nearest Gauss point (the mapping of Sec. 3 that
+ * Sec. 5 compares with interpolation and keeps; Table 1 starts each step by
+ * mapping the finite-element data to the FFT cells and ends by mapping the
+ * volume fractions back). The Gauss points seed a Voronoi tessellation of
+ * the grid: every cell takes the data of the point nearest to its centre,
+ * every point takes the mean over the cells of its domain (the cell that
+ * contains it, clamped to the grid, when the domain holds no cell centre).
+ * Cell (i, j, k), x fastest, has its centre at ((i+1/2) dx, (j+1/2) dx,
+ * (k+1/2) dx) in the frame of the points; distances are Euclidean and not
+ * periodic; the squared distance is (px-cx)^2 + (py-cy)^2 + (pz-cz)^2 in
+ * FP64, summed in that order without fused multiply-adds, and ties go to the
+ * lower point index, so the map is exact and reproducible. Any grid with
+ * nx, ny, nz >= 1 and fewer than 2^31 cells; 1 <= n_points <= 2^28.
+ * All arrays are device memory owned by the caller; work goes on the given
+ * HIP stream (NULL = default). */
+
+/* Workspace bytes for n_points and up to ncomp (1..64) transferred values. */
+int pf_vmap_workspace_size(int32_t n_points, int32_t ncomp, size_t *bytes);
+
+/* Nearest point of every cell: points [n_points][3] (m, FP64), out
+ * cell_point [nz][ny][nx] point indices. Waits on the stream once (the
+ * bounding box sizes the bins); PF_EINVAL on a non-finite coordinate,
+ * PF_ENOMEM if ws_bytes is short. The workspace is scratch. */
+int pf_vmap_build(int32_t nx, int32_t ny, int32_t nz, double dx,
+                  int32_t n_points, const double *points,
+                  void *workspace, size_t ws_bytes, void *hip_stream,
+                  int32_t *cell_point);
+
+/* Point data to the cells: cell_values[c][cell] =
+ * point_values[c][cell_point[cell]] for ncomp components (FP32). */
+int pf_vmap_to_cells(int64_t n_cells, const int32_t *cell_point,
+                     int32_t n_points, int32_t ncomp,
+                     const float *point_values, float *cell_values,
+                     void *hip_stream);
+
+/* Cell data back to the points: the mean over each point's domain (FP64
+ * sums; their order is not fixed, so the last bit of a mean may vary), or
+ * its containing cell. cell_values [ncomp][nz][ny][nx], point_values
+ * [ncomp][n_points]; points as for pf_vmap_build. */
+int pf_vmap_to_points(int32_t nx, int32_t ny, int32_t nz, double dx,
+                      const int32_t *cell_point, int32_t n_points,
+                      const double *points, int32_t ncomp,
+                      const float *cell_values, float *point_values,
+                      void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Batches of independent instances (see "Batches" above). The single-instance
  * calls are these with n_inst = 1; pf_step, pf_fields and pf_stats_get act on
  * instance 0 of a one-instance context only.

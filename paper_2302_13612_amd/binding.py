@@ -100,6 +100,11 @@ def load():
     lib.pf_profile_read.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     lib.pf_profile_select.argtypes = [vp, ctypes.c_char_p]
+    lib.pf_vmap_workspace_size.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pf_vmap_build.argtypes = [i32, i32, i32, ctypes.c_double, i32, vp, vp, ctypes.c_size_t, vp, vp]
+    lib.pf_vmap_to_cells.argtypes = [ctypes.c_int64, vp, i32, i32, vp, vp, vp]
+    lib.pf_vmap_to_points.argtypes = [i32, i32, i32, ctypes.c_double, vp, i32, vp, i32, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
     lib.pf_destroy.argtypes = [vp]
     lib.pf_last_error.argtypes = [vp]
     lib.pf_last_error.restype = ctypes.c_char_p
@@ -115,7 +120,8 @@ def load():
     lib.pf_batch_size.argtypes = [vp]
     for name in ("pf_workspace_size", "pf_init", "pf_step", "pf_fields", "pf_stats_get", "pf_fft",
                  "pf_profile_enable", "pf_profile_read", "pf_profile_select", "pf_destroy",
-                 "pf_mg_twin_tables", "pf_mg_twin_gradient",
+                 "pf_mg_twin_tables", "pf_mg_twin_gradient", "pf_vmap_workspace_size", "pf_vmap_build",
+                 "pf_vmap_to_cells", "pf_vmap_to_points",
                  "pf_batch_workspace_size", "pf_batch_init", "pf_batch_step", "pf_batch_fields",
                  "pf_batch_stats", "pf_batch_size"):
         getattr(lib, name).restype = ctypes.c_int
@@ -595,3 +601,70 @@ class Fno:
             self.close()
         except Exception:
             pass
+
+
+class VoronoiMap:
+    """FE <-> FFT mapping by nearest Gauss point on the current torch stream.
+
+    points: torch float64 CUDA tensor (n_points, 3) in metres; shape (nz, ny,
+    nx) and dx of the grid (cell centres at (i + 1/2) dx). cell_point holds
+    the nearest point of every cell (int32, (nz, ny, nx)).
+    """
+
+    def __init__(self, points, shape, dx, ncomp_max=6):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        if points.dtype != torch.float64 or not points.is_cuda or points.dim() != 2 or points.shape[1] != 3:
+            raise ValueError("points must be a float64 CUDA tensor (n, 3)")
+        self.points = points.contiguous()
+        self.n = points.shape[0]
+        self.shape = tuple(int(v) for v in shape)
+        self.dx = float(dx)
+        self.ncomp_max = ncomp_max
+        nbytes = ctypes.c_size_t()
+        rc = self.lib.pf_vmap_workspace_size(self.n, ncomp_max, ctypes.byref(nbytes))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_vmap_workspace_size")
+        dev = points.device
+        self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        self.cell_point = torch.empty(self.shape, dtype=torch.int32, device=dev)
+        self.stream = torch.cuda.current_stream(dev)
+        self.build()
+
+    def build(self):
+        nz, ny, nx = self.shape
+        rc = self.lib.pf_vmap_build(nx, ny, nz, self.dx, self.n, self.points.data_ptr(), self.workspace.data_ptr(),
+                                    self.workspace.numel(), ctypes.c_void_p(self.stream.cuda_stream),
+                                    self.cell_point.data_ptr())
+        if rc != PF_OK:
+            raise PfError(rc, "pf_vmap_build")
+
+    def to_cells(self, point_values, out=None):
+        """(ncomp, n_points) float32 -> (ncomp, nz, ny, nx)."""
+        torch = self.torch
+        pv = point_values.contiguous()
+        if pv.dtype != torch.float32 or pv.dim() != 2 or pv.shape[1] != self.n:
+            raise ValueError("point_values must be float32 (ncomp, n_points)")
+        out = torch.empty((pv.shape[0],) + self.shape, dtype=torch.float32, device=pv.device) if out is None else out
+        rc = self.lib.pf_vmap_to_cells(self.cell_point.numel(), self.cell_point.data_ptr(), self.n, pv.shape[0],
+                                       pv.data_ptr(), out.data_ptr(), ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_vmap_to_cells")
+        return out
+
+    def to_points(self, cell_values, out=None):
+        """(ncomp, nz, ny, nx) float32 -> (ncomp, n_points)."""
+        torch = self.torch
+        cv = cell_values.contiguous()
+        if cv.dtype != torch.float32 or tuple(cv.shape[1:]) != self.shape or cv.shape[0] > self.ncomp_max:
+            raise ValueError("cell_values must be float32 (ncomp <= ncomp_max, nz, ny, nx)")
+        out = torch.empty((cv.shape[0], self.n), dtype=torch.float32, device=cv.device) if out is None else out
+        nz, ny, nx = self.shape
+        rc = self.lib.pf_vmap_to_points(nx, ny, nz, self.dx, self.cell_point.data_ptr(), self.n,
+                                        self.points.data_ptr(), cv.shape[0], cv.data_ptr(), out.data_ptr(),
+                                        self.workspace.data_ptr(), self.workspace.numel(),
+                                        ctypes.c_void_p(self.stream.cuda_stream))
+        if rc != PF_OK:
+            raise PfError(rc, "pf_vmap_to_points")
+        return out

@@ -289,3 +289,42 @@ def rve_batch(n_inst=256, seed=4, sizes=(32, 48, 64, 96), radius=4.0, max_nuclei
         steps=steps, save_every=save_every, sig_bar=np.zeros(6),
         stress_mask=np.array([False, True, True, True, True, True]),
         ms_tol=1e-6, ms_max_iter=1, **MG_PARAMS)
+
+
+def pillar_gauss_points(shape, dx, pad=4, elem=2.5, jitter=0.2, seed=8):
+    """Gauss points of a hexahedral finite-element mesh of a micro-pillar
+    inside the FFT box (the box extends beyond the body by `pad` cells on
+    every side, as the paper's pad layer does): elements of about `elem` cells
+    per edge on a lattice whose interior nodes are jittered by up to
+    `jitter` of an element edge, 2x2x2 Gauss points per element at the
+    reference coordinates +-1/sqrt(3) mapped trilinearly. Returns (n, 3)
+    float64 coordinates in metres (x, y, z), cell (i, j, k) centred at
+    ((i + 1/2) dx, ...)."""
+    rng = rng_for(seed)
+    nz, ny, nx = shape
+    lo = np.array([pad, pad, pad], dtype=np.float64) * dx
+    hi = np.array([nx - pad, ny - pad, nz - pad], dtype=np.float64) * dx
+    ne = np.maximum(1, np.round((hi - lo) / (elem * dx)).astype(int))
+    axes = [np.linspace(lo[d], hi[d], ne[d] + 1) for d in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    nodes = np.stack([X, Y, Z], axis=-1)
+    h = (hi - lo) / ne
+    inner = np.zeros(nodes.shape[:3], dtype=bool)
+    inner[1:-1, 1:-1, 1:-1] = True
+    nodes[inner] += rng.uniform(-jitter, jitter, size=(inner.sum(), 3)) * h
+    g = 1.0 / np.sqrt(3.0)
+    pts = []
+    for a in (-g, g):
+        for b in (-g, g):
+            for c in (-g, g):
+                # trilinear map of the reference point (a, b, c) in every element
+                xi = np.array([(1 - a) / 2, (1 + a) / 2])
+                eta = np.array([(1 - b) / 2, (1 + b) / 2])
+                zeta = np.array([(1 - c) / 2, (1 + c) / 2])
+                p = 0.0
+                for u in range(2):
+                    for v in range(2):
+                        for w in range(2):
+                            p = p + xi[u] * eta[v] * zeta[w] * nodes[u:u + ne[0], v:v + ne[1], w:w + ne[2]]
+                pts.append(p.reshape(-1, 3))
+    return np.concatenate(pts, axis=0)
