@@ -398,10 +398,87 @@ def bench_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_vmap(args):
+    """FE <-> FFT coupling transfer of the paper's loop (Sec. 3, Table 1):
+    a pillar mesh's Gauss points inside the 128 x 128 x 256 box with a pad
+    layer; per coupling step the plastic strain (6 components) goes to the
+    cells and the volume fraction back to the points."""
+    import torch
+    from paper_2302_13612_amd import binding, inputs
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dx = 5e-8
+    shape = (256, 128, 128)
+    ncell = int(np.prod(shape))
+    pts = inputs.pillar_gauss_points(shape, dx, elem=4.0)
+    npts = pts.shape[0]
+    log(f"pillar mesh: {npts} Gauss points, grid {shape}")
+    pts_d = torch.from_numpy(pts).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vm = binding.VoronoiMap(pts_d, shape, dx)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    rng = np.random.default_rng(0)
+    pv = torch.from_numpy(rng.normal(size=(6, npts)).astype(np.float32)).to(dev)
+    cv = torch.empty((6,) + shape, dtype=torch.float32, device=dev)
+    eta = torch.from_numpy(rng.random((1,) + shape, dtype=np.float32)).to(dev)
+    back = torch.empty((1, npts), dtype=torch.float32, device=dev)
+    steps = args.steps if args.steps_given else 50
+    for _ in range(3):
+        vm.to_cells(pv, out=cv)
+        vm.to_points(eta, out=back)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        ev[k][0].record()
+        vm.to_cells(pv, out=cv)
+        ev[k][1].record()
+        vm.to_points(eta, out=back)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    t_cells = sum(a.elapsed_time(b) for a, b in ev) / steps * 1e-3
+    value = ncell * steps / elapsed
+    # algorithmic bytes of the gather: the point index and 6 values per cell,
+    # the point values once
+    b_cells = ncell * (4 + 6 * 4) + npts * 6 * 4
+    log(f"build {t_build * 1e3:.1f} ms; {1e3 * elapsed / steps:.3f} ms per coupling step, {value:.3e} cells/s; "
+        f"to_cells {t_cells * 1e6:.1f} us")
+    out = {
+        "metric": "FE<->FFT mapping cells/s (nearest Gauss point, 6 components in, 1 back)",
+        "value": value, "unit": "cells/s", "n_gpus": 1, "steps": steps, "warmup": 3,
+        "ms_per_step": 1e3 * elapsed / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 values, f64 coordinates", "data": "synthetic",
+        "config": {"workload": f"vmap: pillar hex mesh (elements of 4 cells, 2x2x2 Gauss points, jittered nodes), "
+                               f"{npts} points, grid {shape[2]}x{shape[1]}x{shape[0]}, pad 4 cells",
+                   "build_ms": round(t_build * 1e3, 2)},
+        "roofline": {"bound": "hbm", "kernel": "vmap_to_cells", "achieved": round(b_cells / t_cells / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(b_cells / t_cells / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": b_cells, "avg_launch_us": round(t_cells * 1e6, 1)},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import mapping as om
+        sample = rng.choice(ncell, size=400, replace=False)
+        cen = om.cell_centres(shape, dx).reshape(-1, 3)[sample]
+        t0 = time.perf_counter()
+        for c in cen:
+            d2 = (pts[:, 0] - c[0]) ** 2
+            d2 = d2 + (pts[:, 1] - c[1]) ** 2
+            d2 = d2 + (pts[:, 2] - c[2]) ** 2
+            int(np.argmin(d2))
+        dt = time.perf_counter() - t0
+        cores, model = cpu_info()
+        out["cpu_baseline"] = {"value": 400 / dt, "unit": "cells/s", "cores": cores, "kind": "oracle",
+                               "sample": f"brute-force nearest point of 400 sampled cells over all {npts} points "
+                                         f"({dt:.1f} s on {model}); the transfers themselves not timed"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("polycrystal", "rve-batch", "surrogate"), default="polycrystal")
+    ap.add_argument("--workload", choices=("polycrystal", "rve-batch", "surrogate", "vmap"), default="polycrystal")
     ap.add_argument("--train-seconds", type=float, default=240.0)
     ap.add_argument("--eval-instances", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-3, help="acceptance residual of the learned stepper")
@@ -426,6 +503,8 @@ def main():
         return bench_rve_batch(args)
     if args.workload == "surrogate":
         return bench_surrogate(args)
+    if args.workload == "vmap":
+        return bench_vmap(args)
     # polycrystal: steps 11-110 of the 1000-step run (10 warm-up steps, then
     # 100 timed); the fixed-point iteration count per step falls as the run
     # settles, so a short window early in the run is not representative

@@ -222,13 +222,17 @@ const char *pf_last_error(const pf_ctx *ctx);
  * All arrays are device memory owned by the caller; work goes on the given
  * HIP stream (NULL = default). */
 
-/* Workspace bytes for n_points and up to ncomp (1..64) transferred values. */
-int pf_vmap_workspace_size(int32_t n_points, int32_t ncomp, size_t *bytes);
+/* Workspace bytes for a grid and n_points. The workspace holds scratch of
+ * the build and then each point's list of cells, which pf_vmap_to_points
+ * reads: keep it, unchanged, between the two. */
+int pf_vmap_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t n_points,
+                           size_t *bytes);
 
 /* Nearest point of every cell: points [n_points][3] (m, FP64), out
- * cell_point [nz][ny][nx] point indices. Waits on the stream once (the
- * bounding box sizes the bins); PF_EINVAL on a non-finite coordinate,
- * PF_ENOMEM if ws_bytes is short. The workspace is scratch. */
+ * cell_point [nz][ny][nx] point indices; also fills the workspace's per-
+ * point cell lists. Waits on the stream once (the bounding box sizes the
+ * bins); PF_EINVAL on a non-finite coordinate, PF_ENOMEM if ws_bytes is
+ * short. */
 int pf_vmap_build(int32_t nx, int32_t ny, int32_t nz, double dx,
                   int32_t n_points, const double *points,
                   void *workspace, size_t ws_bytes, void *hip_stream,
@@ -242,14 +246,15 @@ int pf_vmap_to_cells(int64_t n_cells, const int32_t *cell_point,
                      void *hip_stream);
 
 /* Cell data back to the points: the mean over each point's domain (FP64
- * sums; their order is not fixed, so the last bit of a mean may vary), or
- * its containing cell. cell_values [ncomp][nz][ny][nx], point_values
- * [ncomp][n_points]; points as for pf_vmap_build. */
+ * sum in ascending cell order, then one division, rounded to FP32: exact
+ * and reproducible), or the cell that contains the point. cell_values
+ * [ncomp][nz][ny][nx], point_values [ncomp][n_points]; cell_point, points
+ * and the workspace as left by pf_vmap_build. */
 int pf_vmap_to_points(int32_t nx, int32_t ny, int32_t nz, double dx,
                       const int32_t *cell_point, int32_t n_points,
                       const double *points, int32_t ncomp,
                       const float *cell_values, float *point_values,
-                      void *workspace, size_t ws_bytes, void *hip_stream);
+                      const void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* Batches of independent instances (see "Batches" above). The single-instance
  * calls are these with n_inst = 1; pf_step, pf_fields and pf_stats_get act on

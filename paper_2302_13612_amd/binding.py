@@ -100,7 +100,7 @@ def load():
     lib.pf_profile_read.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     lib.pf_profile_select.argtypes = [vp, ctypes.c_char_p]
-    lib.pf_vmap_workspace_size.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.pf_vmap_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pf_vmap_build.argtypes = [i32, i32, i32, ctypes.c_double, i32, vp, vp, ctypes.c_size_t, vp, vp]
     lib.pf_vmap_to_cells.argtypes = [ctypes.c_int64, vp, i32, i32, vp, vp, vp]
     lib.pf_vmap_to_points.argtypes = [i32, i32, i32, ctypes.c_double, vp, i32, vp, i32, vp, vp, vp,
@@ -611,7 +611,7 @@ class VoronoiMap:
     the nearest point of every cell (int32, (nz, ny, nx)).
     """
 
-    def __init__(self, points, shape, dx, ncomp_max=6):
+    def __init__(self, points, shape, dx):
         import torch
         self.lib = load()
         self.torch = torch
@@ -621,9 +621,9 @@ class VoronoiMap:
         self.n = points.shape[0]
         self.shape = tuple(int(v) for v in shape)
         self.dx = float(dx)
-        self.ncomp_max = ncomp_max
         nbytes = ctypes.c_size_t()
-        rc = self.lib.pf_vmap_workspace_size(self.n, ncomp_max, ctypes.byref(nbytes))
+        nz, ny, nx = self.shape
+        rc = self.lib.pf_vmap_workspace_size(nx, ny, nz, self.n, ctypes.byref(nbytes))
         if rc != PF_OK:
             raise PfError(rc, "pf_vmap_workspace_size")
         dev = points.device
@@ -657,8 +657,8 @@ class VoronoiMap:
         """(ncomp, nz, ny, nx) float32 -> (ncomp, n_points)."""
         torch = self.torch
         cv = cell_values.contiguous()
-        if cv.dtype != torch.float32 or tuple(cv.shape[1:]) != self.shape or cv.shape[0] > self.ncomp_max:
-            raise ValueError("cell_values must be float32 (ncomp <= ncomp_max, nz, ny, nx)")
+        if cv.dtype != torch.float32 or tuple(cv.shape[1:]) != self.shape:
+            raise ValueError("cell_values must be float32 (ncomp, nz, ny, nx)")
         out = torch.empty((cv.shape[0], self.n), dtype=torch.float32, device=cv.device) if out is None else out
         nz, ny, nx = self.shape
         rc = self.lib.pf_vmap_to_points(nx, ny, nz, self.dx, self.cell_point.data_ptr(), self.n,

@@ -10,6 +10,7 @@
 // can hold a point as near as the best one found. Ties go to the lower point
 // index, so the result does not depend on the order inside a bin.
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 #include <climits>
 #include <cmath>
 #include <cstdint>
@@ -32,26 +33,45 @@ struct SortedPoint {
 
 constexpr int kThreads = 256;
 
-// Workspace: [bbox 8 doubles][counts nbins_max][offsets nbins_max + 1]
-// [fill nbins_max][sorted points][per-point sums (ncomp + 1) doubles].
+// Workspace: [bbox 8 doubles][counts][offsets nbins_max + 1][fill nbins_max]
+// [sorted points][point offsets n_points + 1][cell iota n_cells][sorted keys
+// n_cells][cell lists n_cells][library scratch]. The point offsets and the
+// cell lists (each point's cells, ascending) stay valid from pf_vmap_build
+// to pf_vmap_to_points.
 inline size_t align256(size_t n) { return (n + 255) / 256 * 256; }
 inline int64_t max_bins(int32_t n_points) { return 2 * (int64_t)n_points + 64; }
+inline int key_bits(int32_t n_points) {
+  int b = 1;
+  while (b < 31 && ((int64_t)1 << b) < n_points) ++b;
+  return b;
+}
 
 struct WsLayout {
-  size_t bbox, counts, offsets, fill, sorted, sums, total;
+  size_t bbox, counts, offsets, fill, sorted, poff, iota, keys, plist, temp, temp_bytes, total;
 };
 
-inline WsLayout ws_layout(int32_t n_points, int32_t ncomp) {
+inline WsLayout ws_layout(int64_t n_cells, int32_t n_points) {
   WsLayout w{};
   const int64_t nb = max_bins(n_points);
+  const int64_t ncount = (nb > n_points ? nb : n_points) + 1;
+  size_t t1 = 0, t2 = 0, t3 = 0;
+  hipcub::DeviceScan::ExclusiveSum(nullptr, t1, (int*)nullptr, (int*)nullptr, (int)(nb + 1));
+  hipcub::DeviceScan::ExclusiveSum(nullptr, t2, (int*)nullptr, (int*)nullptr, n_points + 1);
+  hipcub::DeviceRadixSort::SortPairs(nullptr, t3, (const unsigned*)nullptr, (unsigned*)nullptr, (const int*)nullptr,
+                                     (int*)nullptr, (int)n_cells, 0, key_bits(n_points));
+  w.temp_bytes = t1 > t2 ? (t1 > t3 ? t1 : t3) : (t2 > t3 ? t2 : t3);
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   w.bbox = take(8 * sizeof(double));
-  w.counts = take(sizeof(int) * nb);
+  w.counts = take(sizeof(int) * ncount);
   w.offsets = take(sizeof(int) * (nb + 1));
   w.fill = take(sizeof(int) * nb);
   w.sorted = take(sizeof(SortedPoint) * (size_t)n_points);
-  w.sums = take(sizeof(double) * (size_t)(ncomp + 1) * n_points);
+  w.poff = take(sizeof(int) * ((size_t)n_points + 1));
+  w.iota = take(sizeof(int) * (size_t)n_cells);
+  w.keys = take(sizeof(int) * (size_t)n_cells);
+  w.plist = take(sizeof(int) * (size_t)n_cells);
+  w.temp = take(w.temp_bytes);
   w.total = off;
   return w;
 }
@@ -121,33 +141,6 @@ __global__ void k_count(const double* __restrict__ pts, int n, const BinGrid g, 
   if (i >= n) return;
   const double* p = pts + 3 * (size_t)i;
   atomicAdd(&counts[bin_of(g, p[0], p[1], p[2])], 1);
-}
-
-// Exclusive scan of the bin counts (one block; each thread a contiguous chunk).
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, int nbins, int* __restrict__ offsets) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x, T = blockDim.x;
-  const int chunk = (nbins + T - 1) / T;
-  const int b0 = t * chunk, b1 = min(nbins, b0 + chunk);
-  int s = 0;
-  for (int b = b0; b < b1; ++b) s += counts[b];
-  part[t] = s;
-  __syncthreads();
-  if (t == 0) {
-    int acc = 0;
-    for (int k = 0; k < T; ++k) {
-      const int v = part[k];
-      part[k] = acc;
-      acc += v;
-    }
-    offsets[nbins] = acc;
-  }
-  __syncthreads();
-  int acc = part[t];
-  for (int b = b0; b < b1; ++b) {
-    offsets[b] = acc;
-    acc += counts[b];
-  }
 }
 
 __global__ void k_scatter(const double* __restrict__ pts, int n, const BinGrid g, const int* __restrict__ offsets,
@@ -232,32 +225,37 @@ __global__ void k_to_cells(int64_t ncell, const int32_t* __restrict__ cp, int np
   for (int c = 0; c < ncomp; ++c) cv[c * ncell + cell] = pv[(int64_t)c * npts + p];
 }
 
-__global__ void k_zero_double(double* __restrict__ p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
-
-// Per-point sums over the domains: [ncomp][npts] values, then [npts] counts.
-__global__ void k_accumulate(int64_t ncell, const int32_t* __restrict__ cp, int npts, int ncomp,
-                             const float* __restrict__ cv, double* __restrict__ sums) {
+// Per-point cell lists: a stable radix sort of (point, cell) pairs taken in
+// ascending cell order leaves each point's cells ascending, so every sum
+// over a domain runs in cell order; the counts give the row offsets.
+__global__ void k_cell_count(int64_t ncell, const int32_t* __restrict__ cp, int* __restrict__ pcount) {
   const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= ncell) return;
-  const int p = cp[cell];
-  for (int c = 0; c < ncomp; ++c) unsafeAtomicAdd(&sums[(int64_t)c * npts + p], (double)cv[c * ncell + cell]);
-  unsafeAtomicAdd(&sums[(int64_t)ncomp * npts + p], 1.0);
+  if (cell < ncell) atomicAdd(&pcount[cp[cell]], 1);
 }
 
-__global__ void k_finish(int npts, int ncomp, const double* __restrict__ sums, const double* __restrict__ pts,
-                         int nx, int ny, int nz, double dx, int64_t ncell, const float* __restrict__ cv,
-                         float* __restrict__ pv) {
+__global__ void k_iota(int64_t n, int* __restrict__ v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (int)i;
+}
+
+// Mean over each point's domain: FP64 sum in ascending cell order, one
+// division; an empty domain takes the cell that contains the point.
+__global__ void k_to_points(int npts, int ncomp, const int* __restrict__ poff, const int* __restrict__ plist,
+                            const double* __restrict__ pts, int nx, int ny, int nz, double dx, int64_t ncell,
+                            const float* __restrict__ cv, float* __restrict__ pv) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npts) return;
-  const double cnt = sums[(int64_t)ncomp * npts + p];
-  if (cnt > 0.0) {
-    for (int c = 0; c < ncomp; ++c) pv[(int64_t)c * npts + p] = (float)(sums[(int64_t)c * npts + p] / cnt);
+  const int b = poff[p], e = poff[p + 1];
+  if (e > b) {
+    const double cnt = (double)(e - b);
+    for (int c = 0; c < ncomp; ++c) {
+      const float* v = cv + c * ncell;
+      double s = 0.0;
+      for (int k = b; k < e; ++k) s += (double)v[plist[k]];
+      pv[(int64_t)c * npts + p] = (float)(s / cnt);
+    }
     return;
   }
-  // empty domain: the cell containing the point, clamped to the grid
   const double* q = pts + 3 * (size_t)p;
   const int n[3] = {nx, ny, nz};
   int64_t ix[3];
@@ -285,9 +283,9 @@ int hip_rc(hipError_t e) { return e == hipSuccess ? PF_OK : PF_EDEVICE; }
 
 extern "C" {
 
-int pf_vmap_workspace_size(int32_t n_points, int32_t ncomp, size_t* bytes) {
-  if (!bytes || n_points < 1 || n_points > (1 << 28) || ncomp < 1 || ncomp > 64) return PF_EINVAL;
-  *bytes = ws_layout(n_points, ncomp).total;
+int pf_vmap_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t n_points, size_t* bytes) {
+  if (!bytes || !grid_ok(nx, ny, nz, 1.0) || n_points < 1 || n_points > (1 << 28)) return PF_EINVAL;
+  *bytes = ws_layout((int64_t)nx * ny * nz, n_points).total;
   return PF_OK;
 }
 
@@ -295,7 +293,8 @@ int pf_vmap_build(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t n_point
                   void* workspace, size_t ws_bytes, void* hip_stream, int32_t* cell_point) {
   if (!grid_ok(nx, ny, nz, dx) || n_points < 1 || n_points > (1 << 28) || !points || !workspace || !cell_point)
     return PF_EINVAL;
-  const WsLayout w = ws_layout(n_points, 1);
+  const int64_t ncell = (int64_t)nx * ny * nz;
+  const WsLayout w = ws_layout(ncell, n_points);
   if (ws_bytes < w.total) return PF_ENOMEM;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   char* ws = static_cast<char*>(workspace);
@@ -338,13 +337,30 @@ int pf_vmap_build(int32_t nx, int32_t ny, int32_t nz, double dx, int32_t n_point
   int* offsets = reinterpret_cast<int*>(ws + w.offsets);
   int* fill = reinterpret_cast<int*>(ws + w.fill);
   SortedPoint* sorted = reinterpret_cast<SortedPoint*>(ws + w.sorted);
-  k_zero_int<<<blocks(g.nbins), kThreads, 0, s>>>(counts, g.nbins);
+  void* temp = ws + w.temp;
+  size_t tb = w.temp_bytes;
+  k_zero_int<<<blocks(g.nbins + 1), kThreads, 0, s>>>(counts, g.nbins + 1);
   k_zero_int<<<blocks(g.nbins), kThreads, 0, s>>>(fill, g.nbins);
   k_count<<<blocks(n_points), kThreads, 0, s>>>(points, n_points, g, counts);
-  k_scan<<<1, 1024, 0, s>>>(counts, g.nbins, offsets);
+  if ((e = hipcub::DeviceScan::ExclusiveSum(temp, tb, counts, offsets, g.nbins + 1, s)) != hipSuccess)
+    return PF_EDEVICE;
   k_scatter<<<blocks(n_points), kThreads, 0, s>>>(points, n_points, g, offsets, fill, sorted);
-  const int64_t ncell = (int64_t)nx * ny * nz;
   k_search<<<blocks(ncell), kThreads, 0, s>>>(g, offsets, sorted, nx, ny, nz, dx, cell_point);
+  // each point's cells, ascending
+  int* poff = reinterpret_cast<int*>(ws + w.poff);
+  int* iota = reinterpret_cast<int*>(ws + w.iota);
+  unsigned* keys = reinterpret_cast<unsigned*>(ws + w.keys);
+  int* plist = reinterpret_cast<int*>(ws + w.plist);
+  k_zero_int<<<blocks(n_points + 1), kThreads, 0, s>>>(counts, n_points + 1);
+  k_cell_count<<<blocks(ncell), kThreads, 0, s>>>(ncell, cell_point, counts);
+  tb = w.temp_bytes;
+  if ((e = hipcub::DeviceScan::ExclusiveSum(temp, tb, counts, poff, n_points + 1, s)) != hipSuccess)
+    return PF_EDEVICE;
+  k_iota<<<blocks(ncell), kThreads, 0, s>>>(ncell, iota);
+  tb = w.temp_bytes;
+  if ((e = hipcub::DeviceRadixSort::SortPairs(temp, tb, reinterpret_cast<const unsigned*>(cell_point), keys,
+                                              iota, plist, (int)ncell, 0, key_bits(n_points), s)) != hipSuccess)
+    return PF_EDEVICE;
   return hip_rc(hipGetLastError());
 }
 
@@ -358,20 +374,19 @@ int pf_vmap_to_cells(int64_t n_cells, const int32_t* cell_point, int32_t n_point
 
 int pf_vmap_to_points(int32_t nx, int32_t ny, int32_t nz, double dx, const int32_t* cell_point, int32_t n_points,
                       const double* points, int32_t ncomp, const float* cell_values, float* point_values,
-                      void* workspace, size_t ws_bytes, void* hip_stream) {
-  if (!grid_ok(nx, ny, nz, dx) || n_points < 1 || n_points > (1 << 28) || ncomp < 1 || ncomp > 64 ||
-      !cell_point || !points || !cell_values || !point_values || !workspace)
+                      const void* workspace, size_t ws_bytes, void* hip_stream) {
+  if (!grid_ok(nx, ny, nz, dx) || n_points < 1 || n_points > (1 << 28) || ncomp < 1 || !cell_point || !points ||
+      !cell_values || !point_values || !workspace)
     return PF_EINVAL;
-  const WsLayout w = ws_layout(n_points, ncomp);
+  const int64_t ncell = (int64_t)nx * ny * nz;
+  const WsLayout w = ws_layout(ncell, n_points);
   if (ws_bytes < w.total) return PF_ENOMEM;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  double* sums = reinterpret_cast<double*>(static_cast<char*>(workspace) + w.sums);
-  const int64_t ncell = (int64_t)nx * ny * nz;
-  const int64_t nsum = (int64_t)(ncomp + 1) * n_points;
-  k_zero_double<<<blocks(nsum), kThreads, 0, s>>>(sums, nsum);
-  k_accumulate<<<blocks(ncell), kThreads, 0, s>>>(ncell, cell_point, n_points, ncomp, cell_values, sums);
-  k_finish<<<blocks(n_points), kThreads, 0, s>>>(n_points, ncomp, sums, points, nx, ny, nz, dx, ncell, cell_values,
-                                                 point_values);
+  const char* ws = static_cast<const char*>(workspace);
+  const int* poff = reinterpret_cast<const int*>(ws + w.poff);
+  const int* plist = reinterpret_cast<const int*>(ws + w.plist);
+  k_to_points<<<blocks(n_points), kThreads, 0, s>>>(n_points, ncomp, poff, plist, points, nx, ny, nz, dx, ncell,
+                                                    cell_values, point_values);
   return hip_rc(hipGetLastError());
 }
 
