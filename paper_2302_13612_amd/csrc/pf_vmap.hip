@@ -217,12 +217,25 @@ __global__ __launch_bounds__(kThreads) void k_search(const BinGrid g, const int*
 }
 
 // ---------------------------------------------------------------- transfer
+// Four consecutive cells per thread: one 16-byte index load, the point
+// values gathered (they stay in L2), one 16-byte store per component.
+// vec: the host found ncell a multiple of 4 and both arrays 16-byte aligned.
 __global__ void k_to_cells(int64_t ncell, const int32_t* __restrict__ cp, int npts, int ncomp,
-                           const float* __restrict__ pv, float* __restrict__ cv) {
-  const int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= ncell) return;
-  const int p = cp[cell];
-  for (int c = 0; c < ncomp; ++c) cv[c * ncell + cell] = pv[(int64_t)c * npts + p];
+                           const float* __restrict__ pv, float* __restrict__ cv, int vec) {
+  const int64_t c0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+  if (c0 >= ncell) return;
+  if (vec) {
+    const int4 p = *reinterpret_cast<const int4*>(cp + c0);
+    for (int c = 0; c < ncomp; ++c) {
+      const float* v = pv + (int64_t)c * npts;
+      *reinterpret_cast<float4*>(cv + c * ncell + c0) = make_float4(v[p.x], v[p.y], v[p.z], v[p.w]);
+    }
+    return;
+  }
+  for (int64_t cell = c0; cell < c0 + 4 && cell < ncell; ++cell) {
+    const int p = cp[cell];
+    for (int c = 0; c < ncomp; ++c) cv[c * ncell + cell] = pv[(int64_t)c * npts + p];
+  }
 }
 
 // Per-point cell lists: a stable radix sort of (point, cell) pairs taken in
@@ -368,7 +381,10 @@ int pf_vmap_to_cells(int64_t n_cells, const int32_t* cell_point, int32_t n_point
                      const float* point_values, float* cell_values, void* hip_stream) {
   if (n_cells < 1 || n_points < 1 || ncomp < 1 || !cell_point || !point_values || !cell_values) return PF_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  k_to_cells<<<blocks(n_cells), kThreads, 0, s>>>(n_cells, cell_point, n_points, ncomp, point_values, cell_values);
+  const int vec = (n_cells % 4 == 0) && reinterpret_cast<uintptr_t>(cell_point) % 16 == 0 &&
+                  reinterpret_cast<uintptr_t>(cell_values) % 16 == 0;
+  k_to_cells<<<blocks((n_cells + 3) / 4), kThreads, 0, s>>>(n_cells, cell_point, n_points, ncomp, point_values,
+                                                              cell_values, vec);
   return hip_rc(hipGetLastError());
 }
 

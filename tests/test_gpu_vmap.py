@@ -118,3 +118,23 @@ def test_few_points_own_a_large_grid():
     lists come from a stable radix sort, not a per-list sort)."""
     pts = np.array([[10.0, 100.0, 64.0], [120.0, 20.0, 5.0], [60.0, 60.0, 120.0]])
     check(pts, (128, 128, 128), 1.0, "three points, 128^3", ncomp=2)
+
+
+def test_to_cells_unaligned_and_ragged():
+    """The gather's vector path needs 16-byte aligned arrays and a cell count
+    divisible by 4; other arrays take the scalar path, with the same result."""
+    import torch
+    rng = np.random.default_rng(6)
+    shape, dx = (5, 6, 7), 1.0                  # 210 cells: not a multiple of 4
+    pts = rng.uniform(0, 7, size=(40, 3))
+    vm = binding.VoronoiMap(torch.from_numpy(pts).cuda(), shape, dx)
+    pv = torch.from_numpy(rng.normal(size=(2, 40)).astype(np.float32)).cuda()
+    expect = om.to_cells(om.voronoi_cells(pts, shape, dx), pv.cpu().numpy())
+    np.testing.assert_array_equal(vm.to_cells(pv).cpu().numpy(), expect)
+    shape2 = (4, 6, 8)                          # 192 cells, then an output offset by one float
+    vm2 = binding.VoronoiMap(torch.from_numpy(pts).cuda(), shape2, dx)
+    buf = torch.empty(2 * 192 + 1, dtype=torch.float32, device="cuda")
+    out = buf[1:].view((2,) + shape2)
+    vm2.to_cells(pv, out=out)
+    expect2 = om.to_cells(om.voronoi_cells(pts, shape2, dx), pv.cpu().numpy())
+    np.testing.assert_array_equal(out.cpu().numpy(), expect2)
