@@ -37,6 +37,14 @@ Readings (stated once here, used below):
   isotropic case. K_a is constant in space: one grain (a polycrystal would
   need a spatially varying K, which the spectral implicit step does not
   solve exactly).
+* Variable mobility (Sec. 4: a pad layer of very low mobility around the
+  specimen suppresses the flux into it, a Neumann-like condition): optionally
+  a relative mobility m(x) in [0, 1] with L(x) = L m(x). The gradient term is
+  split with a constant implicit mobility L (the largest):
+  (f^{n+1} - f^n)/dt = L G(f^{n+1}) + L (m - 1) G(f^n) - L m (chem - mech)(f^n),
+  G(f) = 2 div(K grad f); for a constant m the amplification of a mode,
+  (1 + 2 L dt (1 - m) q) / (1 + 2 L dt q), lies in [0, 1] for every m in
+  [0, 1]. m = 1 is the plain step, m = 0 leaves f unchanged.
 """
 
 import numpy as np
@@ -131,15 +139,26 @@ def gradient_energy(eta, kappa, dx, kappa_var=None):
     return total
 
 
-def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx, kappa_var=None):
+def gradient_force(f, q, shape):
+    """G(f) = 2 div(K grad f) of one field through its symbol q: -2 q f_hat."""
+    return spectral.irfft3(-2.0 * q * spectral.rfft3(f, workers=-1), shape, workers=-1)
+
+
+def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx, kappa_var=None, mobility=None):
     """f_a^{n+1} = IFFT[ FFT(f_a^n - L dt (chem_a - mech_a)) / (1 + 2 L dt q_a(xi)) ]
-    with q_a the gradient symbol (kappa |xi|^2, or xi . K_a . xi)."""
+    with q_a the gradient symbol (kappa |xi|^2, or xi . K_a . xi); with a
+    relative mobility m the right-hand side is f_a^n - L dt m (chem_a - mech_a)
+    + L dt (m - 1) G(f_a^n)."""
     shape = eta.shape[1:]
     out = np.empty_like(eta)
     for a in range(eta.shape[0]):
         q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
         denom = 1.0 + 2.0 * L * dt * q
-        rhs = eta[a] - L * dt * (chem[a] - mech[a])
+        if mobility is None:
+            rhs = eta[a] - L * dt * (chem[a] - mech[a])
+        else:
+            rhs = eta[a] - L * dt * mobility * (chem[a] - mech[a]) + \
+                L * dt * (mobility - 1.0) * gradient_force(eta[a], q, shape)
         out[a] = spectral.irfft3(spectral.rfft3(rhs, workers=-1) / denom, shape, workers=-1)
     return out
 
@@ -150,10 +169,11 @@ class Problem:
     tables = (C_grain, C_var, eps0) as returned by crystal.mg_tables.
     C0: reference stiffness (3,3,3,3) for the fixed point.
     kappa_var: optional (V, 3, 3) gradient tensors (one grain only).
+    mobility: optional (nz, ny, nx) relative mobility in [0, 1].
     """
 
     def __init__(self, shape, dx, tables, A, kappa, L, dt, C0, gid=None,
-                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200, kappa_var=None):
+                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200, kappa_var=None, mobility=None):
         self.shape = tuple(shape)
         self.dx = float(dx)
         self.tables = tables
@@ -163,6 +183,11 @@ class Problem:
                 raise ValueError("an anisotropic gradient energy needs one grain")
             kappa_var = np.asarray(kappa_var, dtype=np.float64)
         self.kappa_var = kappa_var
+        if mobility is not None:
+            mobility = np.asarray(mobility, dtype=np.float64)
+            if mobility.shape != self.shape or mobility.min() < 0 or mobility.max() > 1:
+                raise ValueError("mobility must be (nz, ny, nx) with values in [0, 1]")
+        self.mobility = mobility
         self.gid = None if gid is None else np.asarray(gid, dtype=np.int64)
         self.h_kind = h_kind
         self.ms_tol, self.ms_max_iter = ms_tol, ms_max_iter
@@ -203,7 +228,8 @@ def step(prob, state, eps_p6, load):
         load, prob.ms_tol, prob.ms_max_iter, prob.h_kind)
     chem = chemical_force(state.eta, prob.A)
     mech = mechanical_force(state.eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
-    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var)
+    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var,
+                                getattr(prob, "mobility", None))
     dV = prob.dx ** 3
     stats = {
         "G_dw": float(double_well_density(state.eta, prob.A).sum() * dV),
