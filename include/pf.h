@@ -142,6 +142,17 @@ typedef struct {
                               n_grains == 1 (PF_EUNSUPPORTED otherwise: a
                               spatially varying K is not solved exactly by
                               the spectral implicit step). Copied at init.  */
+  const float *mobility;   /* optional device [nz][ny][nx]: relative mobility
+                              m in [0, 1] of each cell, L(x) = L m (the pad
+                              layer of very low mobility around a specimen,
+                              Sec. 4). The gradient term is split with L
+                              implicit and L (m - 1) explicit, stable for any
+                              m in [0, 1] (values outside are the caller's
+                              responsibility); m = 1 is the plain step, m = 0
+                              freezes f. Steps take the generic path. Needs a
+                              one-instance context (PF_EUNSUPPORTED in a
+                              batch); not for pf_macro_residual. Must stay
+                              valid until pf_destroy. NULL: m = 1.         */
 } pf_problem;
 
 /* Load of one pf_step call. */

@@ -43,6 +43,7 @@ class PfProblem(ctypes.Structure):
         ("ms_max_iter", ctypes.c_int32),
         ("bc_stress_mask", ctypes.c_uint32),
         ("kappa_var", _dp),
+        ("mobility", ctypes.c_void_p),
     ]
 
 
@@ -203,11 +204,13 @@ class Solver:
     rotations: optional (G,3,3) crystal->sample rotations; then the tables
     hold one crystal-frame material (leading dimension 1) shared by all grains.
     kappa_var: optional (V,3,3) or (V,6) anisotropic gradient tensors (sample
-    frame; one grain only).
+    frame; one grain only). mobility: optional float32 CUDA tensor (nz, ny, nx)
+    of relative mobilities in [0, 1].
     """
 
     def __init__(self, eta0, dx, A, kappa, L, dt, tables, stress_mask, gid=None, C_ref=None,
-                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None, kappa_var=None):
+                 h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None, kappa_var=None,
+                 mobility=None):
         import torch
         self.lib = load()
         self.torch = torch
@@ -259,6 +262,14 @@ class Solver:
             p.kappa_var = _ptr(kv)
         else:
             p.kappa_var = None
+        if mobility is not None:
+            if mobility.dtype != torch.float32 or not mobility.is_cuda or tuple(mobility.shape) != (nz, ny, nx):
+                raise ValueError("mobility must be a float32 CUDA tensor (nz, ny, nx)")
+            mobility = mobility.contiguous()
+            self._keep.append(mobility)
+            p.mobility = mobility.data_ptr()
+        else:
+            p.mobility = None
         nbytes = ctypes.c_size_t()
         rc = self.lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(nbytes))
         if rc != PF_OK:

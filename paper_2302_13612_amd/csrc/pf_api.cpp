@@ -40,6 +40,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
   size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, gk, tw;
+  size_t lapf;  // gradient force of the state (with a mobility field), else 0
   size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
@@ -55,7 +56,9 @@ int spec_stride(int nx) { return (nx / 2 + 1 + 15) / 16 * 16; }
 
 // ninst instances of one size; own_epsp: the group keeps its own stacked
 // plastic strain (batches), else the caller's buffer is used in place.
-Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool own_epsp) {
+// mobile: a mobility field is given (the state's gradient force is kept and
+// the spectra hold 2 nv components).
+Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool own_epsp, bool mobile) {
   Layout L{};
   const size_t nvox = (size_t)nx * ny * nz * ninst;
   const size_t nspec = (size_t)spec_stride(nx) * ny * nz * ninst;
@@ -73,7 +76,8 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.eps_prev3 = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
   L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
-  L.spec = take(sizeof(float) * 2 * nspec * 6);
+  L.spec = take(sizeof(float) * 2 * nspec * (mobile && 2 * nv > 6 ? 2 * nv : 6));
+  L.lapf = mobile ? take(sizeof(float) * nvox * nv) : 0;
   L.tab_stride = tab_stride_for(nv);
   L.tables = take(sizeof(float) * (size_t)L.tab_stride * G * ninst);
   L.rot = take(sizeof(float) * 12 * (size_t)G);
@@ -325,6 +329,8 @@ struct Group {
   bool strain_valid;     // the strain field describes the current state
   int64_t hist;          // consecutive fixed-point steps with a valid strain history
   bool own_epsp, epsp_given;
+  bool mobile;           // a mobility field (one instance): generic path only
+  bool lap_valid;        // the kept gradient force matches the order parameters
   std::vector<int> members;
   float* ring[4];        // strain fields: ring[cur] the latest converged one, then
   int cur;               // ring[cur - 1], ring[cur - 2], ring[cur - 3] those of the steps before
@@ -465,6 +471,11 @@ int validate_batch(const pf_problem* probs, int n, std::string& why) {
     }
   }
   if (n == 1) return PF_OK;
+  for (int i = 0; i < n; ++i)
+    if (probs[i].mobility) {
+      why = "a mobility field needs a one-instance context";
+      return PF_EUNSUPPORTED;
+    }
   const pf_problem& p0 = probs[0];
   for (int i = 0; i < n; ++i) {
     const pf_problem& p = probs[i];
@@ -499,7 +510,9 @@ std::vector<Group> plan_groups(const pf_problem* probs, int n) {
   for (auto& g : gs) {
     g.ninst = (int)g.members.size();
     g.own_epsp = n > 1;
-    g.L = make_layout(g.nx, g.ny, g.nz, probs[0].n_var, probs[g.members[0]].n_grains, g.ninst, g.own_epsp);
+    g.mobile = probs[g.members[0]].mobility != nullptr;
+    g.L = make_layout(g.nx, g.ny, g.nz, probs[0].n_var, probs[g.members[0]].n_grains, g.ninst, g.own_epsp,
+                      g.mobile);
     g.base = off;
     off += g.L.total;
   }
@@ -548,7 +561,7 @@ int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
   PF_TRY(launch(c, s, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
   PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
   PF_TRY(launch(c, s, "ac_z_update", [&] { return pfl::ac_z_update(a, 0, s); }));
-  PF_TRY(launch(c, s, "ac_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
+  PF_TRY(launch(c, s, "ac_y_inverse", [&] { return pfl::y_pass(a, a.lapf ? 2 * a.nv : a.nv, -1, s); }));
   PF_TRY(launch(c, s, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
   PF_TRY(launch(c, s, "ac_finalize", [&] { return pfl::ac_finalize(a, 0, s); }));
   return PF_OK;
@@ -673,6 +686,20 @@ int refresh_gradient_energy(pf_ctx* c, const Group& g) {
   PF_TRY(launch(c, s, "init_y", [&] { return pfl::y_pass(a, c->nv, 1, s); }));
   PF_TRY(launch(c, s, "init_z", [&] { return pfl::ac_z_update(a, 1, s); }));
   PF_TRY(launch(c, s, "init_fin", [&] { return pfl::ac_finalize(a, 1, s); }));
+  return PF_OK;
+}
+
+// The gradient force 2 div(K grad f) of the current order parameters, which
+// a step with a mobility field reads (each such step leaves that of its new
+// state); needed after init and after the order parameters were replaced.
+int refresh_gradient_force(pf_ctx* c, const Group& g) {
+  const KArgs& a = g.args;
+  hipStream_t s = c->stream;
+  PF_TRY(launch(c, s, "lap_x", [&] { return pfl::raw_x_forward(a, a.eta, c->nv, s); }));
+  PF_TRY(launch(c, s, "lap_y", [&] { return pfl::y_pass(a, c->nv, 1, s); }));
+  PF_TRY(launch(c, s, "lap_z", [&] { return pfl::ac_z_update(a, 2, s); }));
+  PF_TRY(launch(c, s, "lap_y_inverse", [&] { return pfl::y_pass(a, c->nv, -1, s); }));
+  PF_TRY(launch(c, s, "lap_x_inverse", [&] { return pfl::raw_x_inverse(a, a.lapf, c->nv, 1.f, s); }));
   return PF_OK;
 }
 
@@ -827,6 +854,10 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     bool aniso = false;
     for (int m : g.members) aniso = aniso || hosts[m].aniso;
     a.gk = aniso ? reinterpret_cast<float*>(ws + L.gk) : nullptr;
+    a.mob = g.mobile ? pg.mobility : nullptr;
+    a.lapf = g.mobile ? reinterpret_cast<float*>(ws + L.lapf) : nullptr;
+    a.gscale = (float)(aniso ? 2.0 : 2.0 * p0.kappa);
+    g.lap_valid = false;
     // one grain: its rotated table serves every voxel (no per-voxel rotation)
     const bool rotated = pg.grain_rot != nullptr;
     a.rot = (rotated && G > 1) ? reinterpret_cast<float*>(ws + L.rot) : nullptr;
@@ -953,7 +984,11 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
   for (size_t k = 0; k < c->groups.size(); ++k) {
     Group& g = c->groups[k];
     g.args.save_stress = save_stress ? 1 : 0;
-    use_kh[k] = g.homogeneous && !g.epsp_given && !save_stress && !force_fp;
+    use_kh[k] = g.homogeneous && !g.epsp_given && !save_stress && !force_fp && !g.mobile;
+    if (g.mobile && !g.lap_valid && n_steps > 0) {
+      PF_TRY(refresh_gradient_force(c, g));
+      g.lap_valid = true;
+    }
     if (!use_kh[k] && !g.one_iteration) graphable = false;
     char buf[64];
     snprintf(buf, sizeof(buf), "%d:%p;", (int)use_kh[k], (const void*)g.args.epsp);
@@ -1108,7 +1143,10 @@ int pf_batch_fields(pf_ctx* c, int32_t inst, int32_t which, int32_t set, float* 
                        : hipMemcpyAsync(ext, slot, g.nvox * sizeof(float), hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "pf_fields");
   }
-  if (set && which == PF_FIELD_ETA) PF_TRY(refresh_gradient_energy(c, g));
+  if (set && which == PF_FIELD_ETA) {
+    PF_TRY(refresh_gradient_energy(c, g));
+    g.lap_valid = false;
+  }
   return PF_OK;
 }
 
@@ -1259,8 +1297,9 @@ int pf_macro_residual(pf_ctx* c, const float* eta_prev, int32_t n_steps, const p
   if (!eta_prev || !load || !rho || n_steps < 1) return fail(c, PF_EINVAL, "pf_macro_residual: bad arguments");
   if (c->n_inst != 1) return fail(c, PF_EUNSUPPORTED, "pf_macro_residual: single-instance contexts only");
   Group& g = c->groups[0];
-  if (!g.homogeneous || g.epsp_given)
-    return fail(c, PF_EUNSUPPORTED, "pf_macro_residual: needs one stiffness, linear h, n_var <= 3, no plastic strain");
+  if (!g.homogeneous || g.epsp_given || g.mobile)
+    return fail(c, PF_EUNSUPPORTED,
+                "pf_macro_residual: needs one stiffness, linear h, n_var <= 3, no plastic strain, uniform mobility");
   PF_TRY(upload_loads(c, load));
   const KArgs& a = g.args;
   hipStream_t s = c->stream;
@@ -1482,6 +1521,7 @@ int pf_fno_advance(pf_fno* f, int32_t n_calls, int32_t steps_per_call, const dou
       c->steps += steps_per_call;
       g.hist = 0;
       g.strain_valid = false;
+      g.lap_valid = false;
       PF_TRY(refresh_gradient_energy(c, g));
     } else {
       rep->rejected += 1;

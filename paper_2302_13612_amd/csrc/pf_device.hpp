@@ -86,6 +86,9 @@ struct KArgs {
   const float* kh;            // [ninst][kKhStride] or null
   const double* khd;          // [ninst][kKhdStride] or null
   const float* gk;            // [ninst][kGkStride] or null (isotropic kappa)
+  const float* mob;           // [nz][ny][nx] relative mobility, or null (uniform)
+  float* lapf;                // [nv][nz][ny][nx] 2 div(K grad f) of the state (with mob)
+  float gscale;               // 2 kappa (isotropic symbol) or 2 (tables carry K)
   uint32_t stress_mask;
   // fields
   float* eta;                 // [nv][ninst][nz][ny][nx]
@@ -139,7 +142,8 @@ hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t ms_z_green(const KArgs& a, hipStream_t s);
 hipError_t ms_x_inverse(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward(const KArgs& a, hipStream_t s);
-hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);  // mode 0 update, 1 energy only
+// mode 0 update, 1 energy only, 2 gradient force 2 div(K grad f) in place
+hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);

@@ -105,17 +105,21 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   c2r_fetch<M>(cur, t, valid, a.spec + roff);
   XTw<M, -1> tw;
   tw.load(a, t);
+  // components 0..nv-1: the new f; with a mobility field also nv..2nv-1:
+  // the gradient force of the new f, kept for the next step
+  const int nc = a.lapf ? 2 * a.nv : a.nv;
 #pragma unroll 1
-  for (int q = 0; q < a.nv; ++q) {
-    if (q + 1 < a.nv) c2r_fetch<M>(nxt, t, valid, a.spec + (q + 1) * cs + roff);
+  for (int q = 0; q < nc; ++q) {
+    if (q + 1 < nc) c2r_fetch<M>(nxt, t, valid, a.spec + (q + 1) * cs + roff);
     float2 v[E];
     c2r_from_regs<M>(v, cur, lds + p * LROW, t, tw);
     if (valid) {
+      float* dst = q < a.nv ? a.eta + q * vs : a.lapf + (q - a.nv) * vs;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int x0 = 2 * (t + T * m);
-        if (!isfinite(v[m].x) || !isfinite(v[m].y)) bad[0] += 1.0;
-        *reinterpret_cast<float2*>(a.eta + q * vs + rbase + x0) = v[m];
+        if (q < a.nv && (!isfinite(v[m].x) || !isfinite(v[m].y))) bad[0] += 1.0;
+        *reinterpret_cast<float2*>(dst + rbase + x0) = v[m];
       }
     }
     cur = nxt;
@@ -422,14 +426,20 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const int sy = signed_k(ky, a.ny);
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
   const GradSym<GK> gs(a, inst, q, kx, sy);
+  // the gradient force G = 2 div(K grad f) = -gscale sym f_hat of the new
+  // state (with a mobility field) or of the given one (mode 2)
+  const bool want_g = mode == 2 || (mode == 0 && a.lapf != nullptr);
+  float2 g[E];
   float e0 = 0.f;  // this thread's Parseval terms, then FP64
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int sz = signed_k(t + T * m, a.nz);
     const float fz = (float)sz * (float)sz, cz = cross_k(sz, a.nz);
     if (mode == 0) v[m] = cscale(v[m], fast_rcp(gs.den(cz, fz)));
-    e0 += gs.sym(cz, fz) * (v[m].x * v[m].x + v[m].y * v[m].y);
+    const float sym = gs.sym(cz, fz);
+    e0 += sym * (v[m].x * v[m].x + v[m].y * v[m].y);
     v[m] = cscale(v[m], a.inv_ntot);
+    g[m] = want_g ? cscale(v[m], -a.gscale * sym) : make_float2(0.f, 0.f);
   }
   double en[kQgd] = {valid ? wgt * (double)e0 : 0.0, 0.0, 0.0};
   if (mode == 0) {
@@ -437,6 +447,14 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
+    }
+  }
+  if (want_g) {
+    fft_pencil<N, -1>(g, view, t, twf.conj());
+    float2* gcol = mode == 2 ? col : col + (size_t)a.nv * cs;
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) gcol[(size_t)(t + T * m) * zs] = g[m];
     }
   }
   // partials ordered [inst][variant][ky][tile] so each instance's are contiguous

@@ -465,6 +465,15 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
         const float mech = dh_of(et[q], HK) * (work[q] - 0.5f * quad[q]);
         o[half][q] = et[q] - a.LDt * (chem_force<V>(a.A, et, fm, q) - mech);
       }
+      if (a.mob) {
+        // relative mobility m: the local forces scaled by m, the gradient
+        // term's explicit part L dt (m - 1) G(f^n) (the implicit part uses L)
+        const size_t vox = rbase + x0 + half;
+        const float mb = a.mob[vox];
+#pragma unroll
+        for (int q = 0; q < V; ++q)
+          o[half][q] = et[q] + mb * (o[half][q] - et[q]) + a.LDt * (mb - 1.f) * a.lapf[q * vs + vox];
+      }
       if (valid) {
         facc[0] += fdw;
         facc[1] += 0.5f * fme;

@@ -328,3 +328,12 @@ def pillar_gauss_points(shape, dx, pad=4, elem=2.5, jitter=0.2, seed=8):
                             p = p + xi[u] * eta[v] * zeta[w] * nodes[u:u + ne[0], v:v + ne[1], w:w + ne[2]]
                 pts.append(p.reshape(-1, 3))
     return np.concatenate(pts, axis=0)
+
+
+def pad_mobility(shape, pad=4, m_pad=1e-3):
+    """Relative mobility of a specimen inside a pad layer of `pad` cells on
+    every side (Sec. 4: very low mobility in the pad): 1 inside, m_pad in the
+    pad. float32 (nz, ny, nx)."""
+    m = np.full(shape, m_pad, dtype=np.float32)
+    m[pad:shape[0] - pad, pad:shape[1] - pad, pad:shape[2] - pad] = 1.0
+    return m

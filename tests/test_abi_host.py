@@ -129,3 +129,17 @@ def test_batch_voxel_limit_of_one_size():
     size = ctypes.c_size_t()
     assert lib.pf_batch_workspace_size(probs, n, ctypes.byref(size)) == binding.PF_EINVAL
     assert lib.pf_batch_workspace_size(probs, n - 1, ctypes.byref(size)) == binding.PF_OK
+
+
+def test_mobility_needs_a_one_instance_context():
+    lib = binding.load()
+    keep = []
+    probs = (binding.PfProblem * 2)()
+    for i in range(2):
+        probs[i] = valid_problem(lib, keep=keep)
+    probs[1].mobility = 0x3000
+    size = ctypes.c_size_t()
+    assert lib.pf_batch_workspace_size(probs, 2, ctypes.byref(size)) == binding.PF_EINVAL
+    ctx = ctypes.c_void_p()
+    assert lib.pf_batch_init(probs, 2, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
+    assert not ctx.value
