@@ -45,6 +45,21 @@ Readings (stated once here, used below):
   G(f) = 2 div(K grad f); for a constant m the amplification of a mode,
   (1 + 2 L dt (1 - m) q) / (1 + 2 L dt q), lies in [0, 1] for every m in
   [0, 1]. m = 1 is the plain step, m = 0 leaves f unchanged.
+* The paper's iterated scheme (Table 1 with eqs. (19)-(20)): the fixed point
+  i solves f^i/dt - c3 c2 [sum_{b != a} f_b^{i-1}] lap f^i + r^i = 0 with the
+  nonlinear terms of r at f^{i-1} and the mechanical ones held at f^n (the
+  elastic strain is constant during the phase-field solve, Sec. 2.3). With
+  f_M = 1 - sum f the coefficient is 2 L kappa (1 - f_a^{i-1}); splitting it
+  as the constant 2 L kappa implicit plus the rest explicit, the explicit
+  rest cancels the cross-gradient term of r exactly, so an iterate is
+  f^i = [f^n - L dt (chem(f^{i-1}) - mech(f^n))] / (1 + 2 L dt q): the plain
+  step re-evaluated with the latest chemical force (a Picard iteration
+  converging to backward Euler). The guess f^0 is f^n, so the first iterate
+  is the plain step, and the change max |f^i - f^{i-1}| is tested after every
+  solve, the first included. All variants are iterated together (Jacobi);
+  a per-variant sweep has the same fixed point. The conservation loop j
+  holds by construction; the subdomains k are a memory device of the
+  paper's CPU code and are one domain here.
 """
 
 import numpy as np
@@ -163,6 +178,26 @@ def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx, kappa_var=None, mobilit
     return out
 
 
+def picard_iterate(eta0, prev, mech, prob, mobility=None):
+    """One iterate of the paper's fixed point: the update from f^n (eta0)
+    with the chemical force of the previous iterate (see the module notes).
+    With a mobility field the explicit gradient remainder is the one of the
+    previous iterate."""
+    shape = eta0.shape[1:]
+    chem = chemical_force(prev, prob.A)
+    out = np.empty_like(eta0)
+    for a in range(eta0.shape[0]):
+        q = gradient_symbol(shape, prob.dx, prob.kappa, None if prob.kappa_var is None else prob.kappa_var[a])
+        denom = 1.0 + 2.0 * prob.L * prob.dt * q
+        if mobility is None:
+            rhs = eta0[a] - prob.L * prob.dt * (chem[a] - mech[a])
+        else:
+            rhs = eta0[a] - prob.L * prob.dt * mobility * (chem[a] - mech[a]) + \
+                prob.L * prob.dt * (mobility - 1.0) * gradient_force(prev[a], q, shape)
+        out[a] = spectral.irfft3(spectral.rfft3(rhs, workers=-1) / denom, shape, workers=-1)
+    return out
+
+
 class Problem:
     """Everything fixed over a run (the analogue of the library's problem).
 
@@ -170,10 +205,13 @@ class Problem:
     C0: reference stiffness (3,3,3,3) for the fixed point.
     kappa_var: optional (V, 3, 3) gradient tensors (one grain only).
     mobility: optional (nz, ny, nx) relative mobility in [0, 1].
+    pf_tol, pf_max_iter: the paper's fixed point i over the phase-field update
+    (pf_max_iter = 1: the plain semi-implicit step).
     """
 
     def __init__(self, shape, dx, tables, A, kappa, L, dt, C0, gid=None,
-                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200, kappa_var=None, mobility=None):
+                 h_kind="linear", ms_tol=1e-12, ms_max_iter=200, kappa_var=None, mobility=None,
+                 pf_tol=1e-12, pf_max_iter=1):
         self.shape = tuple(shape)
         self.dx = float(dx)
         self.tables = tables
@@ -188,6 +226,7 @@ class Problem:
             if mobility.shape != self.shape or mobility.min() < 0 or mobility.max() > 1:
                 raise ValueError("mobility must be (nz, ny, nx) with values in [0, 1]")
         self.mobility = mobility
+        self.pf_tol, self.pf_max_iter = float(pf_tol), int(pf_max_iter)
         self.gid = None if gid is None else np.asarray(gid, dtype=np.int64)
         self.h_kind = h_kind
         self.ms_tol, self.ms_max_iter = ms_tol, ms_max_iter
@@ -228,8 +267,18 @@ def step(prob, state, eps_p6, load):
         load, prob.ms_tol, prob.ms_max_iter, prob.h_kind)
     chem = chemical_force(state.eta, prob.A)
     mech = mechanical_force(state.eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
-    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var,
-                                getattr(prob, "mobility", None))
+    mob = getattr(prob, "mobility", None)
+    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var, mob)
+    # the paper's fixed point i: the guess is f^n, each solve re-evaluates the
+    # chemical force at the latest iterate, stop when max |f^i - f^{i-1}| <= tol
+    pf_max = max(1, getattr(prob, "pf_max_iter", 1))
+    pf_iters = 1
+    pf_change = float(np.abs(eta_new - state.eta).max()) if eta_new.size else 0.0
+    while pf_iters < pf_max and pf_change > prob.pf_tol:
+        prev = eta_new
+        eta_new = picard_iterate(state.eta, prev, mech, prob, mob)
+        pf_iters += 1
+        pf_change = float(np.abs(eta_new - prev).max())
     dV = prob.dx ** 3
     stats = {
         "G_dw": float(double_well_density(state.eta, prob.A).sum() * dV),
@@ -240,6 +289,9 @@ def step(prob, state, eps_p6, load):
         "eta_mean": state.eta.mean(axis=(1, 2, 3)),
         "ms_iters": iters,
         "ms_residual": res,
+        "pf_iters": pf_iters,
+        "pf_change": pf_change,
+        "pf_converged": pf_max == 1 or pf_change <= prob.pf_tol,
     }
     stats["G"] = stats["G_dw"] + stats["G_gd"] + stats["G_me"]
     return State(eta_new, eps, ebar), stats, sigma

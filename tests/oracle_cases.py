@@ -27,11 +27,13 @@ def tables(rotations, variant_ids, homogeneous=False, no_eigenstrain=False):
 
 
 def problem(shape, tabs, dx=5e-8, A=1e7, kappa=1e-9, L=1.2e-5, dt=2e-4, gid=None,
-            C0=None, h_kind="linear", tol=1e-12, max_iter=500, kappa_var=None, mobility=None):
+            C0=None, h_kind="linear", tol=1e-12, max_iter=500, kappa_var=None, mobility=None,
+            pf_tol=1e-12, pf_max_iter=1):
     if C0 is None:
         C0 = pf.reference_stiffness_average(tabs[0], tabs[1])
     return pf.Problem(shape, dx, tabs, A, kappa, L, dt, C0, gid=gid, h_kind=h_kind,
-                      ms_tol=tol, ms_max_iter=max_iter, kappa_var=kappa_var, mobility=mobility)
+                      ms_tol=tol, ms_max_iter=max_iter, kappa_var=kappa_var, mobility=mobility,
+                      pf_tol=pf_tol, pf_max_iter=pf_max_iter)
 
 
 def load(eps_bar=None, sig_bar=None, stress_mask=None):
