@@ -153,6 +153,21 @@ typedef struct {
                               one-instance context (PF_EUNSUPPORTED in a
                               batch); not for pf_macro_residual. Must stay
                               valid until pf_destroy. NULL: m = 1.         */
+  double pf_tol;           /* ERR_f of Table 1 (see pf_max_iter)            */
+  int32_t pf_max_iter;     /* solves of the fixed point i of Table 1 per step
+                              (eqs. (19)-(20)): the guess is f^n, each further
+                              solve re-evaluates the chemical (double-well)
+                              force at the latest iterate with the gradient
+                              term implicit and the mechanical force that of
+                              f^n; the step ends when max |f^i - f^{i-1}| <=
+                              pf_tol, checked after every solve (one stream
+                              wait each), else PF_ENOCONV after pf_max_iter
+                              solves, f left at the last iterate. 0 or 1: one
+                              solve, the plain semi-implicit step. > 1 needs
+                              a one-instance context (PF_EUNSUPPORTED in a
+                              batch) and takes the generic path. With
+                              f_M = 1 - sum f the conservation check of
+                              Table 1 holds identically.                    */
 } pf_problem;
 
 /* Load of one pf_step call. */
@@ -175,6 +190,10 @@ typedef struct {
   double eta_min, eta_max; /* over all variants and voxels                  */
   int32_t ms_iters;        /* fixed-point iterations of the last step       */
   double ms_residual;      /* last relative strain change                   */
+  int32_t pf_iters;        /* solves of the update in the last step (1
+                              unless pf_max_iter > 1)                       */
+  double pf_change;        /* max |f^i - f^{i-1}| of its last solve (0
+                              unless pf_max_iter > 1)                       */
 } pf_stats;
 
 /* Workspace bytes for a problem (only the sizes, n_var and n_grains are read). */

@@ -44,6 +44,8 @@ class PfProblem(ctypes.Structure):
         ("bc_stress_mask", ctypes.c_uint32),
         ("kappa_var", _dp),
         ("mobility", ctypes.c_void_p),
+        ("pf_tol", ctypes.c_double),
+        ("pf_max_iter", ctypes.c_int32),
     ]
 
 
@@ -76,6 +78,8 @@ class PfStats(ctypes.Structure):
         ("eta_min", ctypes.c_double), ("eta_max", ctypes.c_double),
         ("ms_iters", ctypes.c_int32),
         ("ms_residual", ctypes.c_double),
+        ("pf_iters", ctypes.c_int32),
+        ("pf_change", ctypes.c_double),
     ]
 
 
@@ -192,6 +196,7 @@ def _stats_dict(s, n_var):
         "eta_mean": np.array(s.eta_mean[:n_var]),
         "eta_min": s.eta_min, "eta_max": s.eta_max,
         "ms_iters": s.ms_iters, "ms_residual": s.ms_residual,
+        "pf_iters": s.pf_iters, "pf_change": s.pf_change,
     }
 
 
@@ -205,12 +210,13 @@ class Solver:
     hold one crystal-frame material (leading dimension 1) shared by all grains.
     kappa_var: optional (V,3,3) or (V,6) anisotropic gradient tensors (sample
     frame; one grain only). mobility: optional float32 CUDA tensor (nz, ny, nx)
-    of relative mobilities in [0, 1].
+    of relative mobilities in [0, 1]. pf_max_iter > 1: the fixed point over the
+    update (Table 1), stopping at max |f^i - f^{i-1}| <= pf_tol.
     """
 
     def __init__(self, eta0, dx, A, kappa, L, dt, tables, stress_mask, gid=None, C_ref=None,
                  h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None, kappa_var=None,
-                 mobility=None):
+                 mobility=None, pf_tol=1e-6, pf_max_iter=1):
         import torch
         self.lib = load()
         self.torch = torch
@@ -270,6 +276,8 @@ class Solver:
             p.mobility = mobility.data_ptr()
         else:
             p.mobility = None
+        p.pf_tol = pf_tol
+        p.pf_max_iter = pf_max_iter
         nbytes = ctypes.c_size_t()
         rc = self.lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(nbytes))
         if rc != PF_OK:

@@ -41,6 +41,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 struct Layout {
   size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, gk, tw;
   size_t lapf;  // gradient force of the state (with a mobility field), else 0
+  size_t pf_base, part_pc;  // fixed point over the update (pf_max_iter > 1), else 0
   size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
@@ -57,8 +58,10 @@ int spec_stride(int nx) { return (nx / 2 + 1 + 15) / 16 * 16; }
 // ninst instances of one size; own_epsp: the group keeps its own stacked
 // plastic strain (batches), else the caller's buffer is used in place.
 // mobile: a mobility field is given (the state's gradient force is kept and
-// the spectra hold 2 nv components).
-Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool own_epsp, bool mobile) {
+// the spectra hold 2 nv components). picard: a fixed point over the update
+// (the step's fixed base of the right-hand side and the per-block changes).
+Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool own_epsp, bool mobile,
+                   bool picard) {
   Layout L{};
   const size_t nvox = (size_t)nx * ny * nz * ninst;
   const size_t nspec = (size_t)spec_stride(nx) * ny * nz * ninst;
@@ -78,6 +81,8 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
   L.spec = take(sizeof(float) * 2 * nspec * (mobile && 2 * nv > 6 ? 2 * nv : 6));
   L.lapf = mobile ? take(sizeof(float) * nvox * nv) : 0;
+  L.pf_base = picard ? take(sizeof(float) * nvox * nv) : 0;
+  L.part_pc = picard ? take(sizeof(float) * xb * 2) : 0;
   L.tab_stride = tab_stride_for(nv);
   L.tables = take(sizeof(float) * (size_t)L.tab_stride * G * ninst);
   L.rot = take(sizeof(float) * 12 * (size_t)G);
@@ -331,6 +336,8 @@ struct Group {
   bool own_epsp, epsp_given;
   bool mobile;           // a mobility field (one instance): generic path only
   bool lap_valid;        // the kept gradient force matches the order parameters
+  int pf_max_iter;       // solves of the update's fixed point per step (1: plain step)
+  double pf_tol;         // its stopping threshold on max |f^i - f^{i-1}|
   std::vector<int> members;
   float* ring[4];        // strain fields: ring[cur] the latest converged one, then
   int cur;               // ring[cur - 1], ring[cur - 2], ring[cur - 3] those of the steps before
@@ -434,6 +441,11 @@ int validate(const pf_problem* p, std::string& why) {
   if (p->h_kind != PF_H_LINEAR && p->h_kind != PF_H_QUINTIC) { why = "bad h_kind"; return PF_EINVAL; }
   if (p->ms_max_iter < 1) { why = "ms_max_iter must be >= 1"; return PF_EINVAL; }
   if (!(p->ms_tol >= 0)) { why = "ms_tol must be >= 0"; return PF_EINVAL; }
+  if (p->pf_max_iter < 0) { why = "pf_max_iter must be >= 0"; return PF_EINVAL; }
+  if (p->pf_max_iter > 1 && !(p->pf_tol >= 0 && std::isfinite(p->pf_tol))) {
+    why = "pf_tol must be finite and >= 0";
+    return PF_EINVAL;
+  }
   if (p->bc_stress_mask > 63u) { why = "bc_stress_mask has bits above 5"; return PF_EINVAL; }
   if (p->kappa_var) {
     for (int q = 0; q < p->n_var; ++q) {
@@ -471,11 +483,16 @@ int validate_batch(const pf_problem* probs, int n, std::string& why) {
     }
   }
   if (n == 1) return PF_OK;
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (probs[i].mobility) {
       why = "a mobility field needs a one-instance context";
       return PF_EUNSUPPORTED;
     }
+    if (probs[i].pf_max_iter > 1) {
+      why = "a fixed point over the update (pf_max_iter > 1) needs a one-instance context";
+      return PF_EUNSUPPORTED;
+    }
+  }
   const pf_problem& p0 = probs[0];
   for (int i = 0; i < n; ++i) {
     const pf_problem& p = probs[i];
@@ -511,8 +528,10 @@ std::vector<Group> plan_groups(const pf_problem* probs, int n) {
     g.ninst = (int)g.members.size();
     g.own_epsp = n > 1;
     g.mobile = probs[g.members[0]].mobility != nullptr;
+    g.pf_max_iter = std::max(1, (int)probs[g.members[0]].pf_max_iter);
+    g.pf_tol = probs[g.members[0]].pf_tol;
     g.L = make_layout(g.nx, g.ny, g.nz, probs[0].n_var, probs[g.members[0]].n_grains, g.ninst, g.own_epsp,
-                      g.mobile);
+                      g.mobile, g.pf_max_iter > 1);
     g.base = off;
     off += g.L.total;
   }
@@ -556,13 +575,33 @@ int ms_iteration(pf_ctx* c, const KArgs& a, hipStream_t s) {
   return PF_OK;
 }
 
+// The update of a step. With pf_max_iter > 1 it is the fixed point i of
+// Table 1 (eqs. (19)-(20)): the guess is f^n, every further solve takes the
+// chemical force of the latest iterate (pc_x_forward) while the gradient
+// term stays implicit and the mechanical force stays that of f^n; after each
+// solve the host reads max |f^i - f^{i-1}| and stops at pf_tol.
 int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
   const KArgs& a = g.args;
   PF_TRY(launch(c, s, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
-  PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
-  PF_TRY(launch(c, s, "ac_z_update", [&] { return pfl::ac_z_update(a, 0, s); }));
-  PF_TRY(launch(c, s, "ac_y_inverse", [&] { return pfl::y_pass(a, a.lapf ? 2 * a.nv : a.nv, -1, s); }));
-  PF_TRY(launch(c, s, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
+  for (int it = 1;; ++it) {
+    PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
+    PF_TRY(launch(c, s, "ac_z_update", [&] { return pfl::ac_z_update(a, 0, s); }));
+    PF_TRY(launch(c, s, "ac_y_inverse", [&] { return pfl::y_pass(a, a.lapf ? 2 * a.nv : a.nv, -1, s); }));
+    PF_TRY(launch(c, s, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
+    if (g.pf_max_iter <= 1) break;
+    PF_TRY(launch(c, s, "pc_finalize", [&] { return pfl::pc_finalize(a, it, s); }));
+    PF_TRY(read_status(c));
+    const size_t b = status_base(c, (size_t)(&g - c->groups.data()));
+    const double change = c->host_status[b].pf_change;
+    if (change <= g.pf_tol) break;
+    if (it == g.pf_max_iter) {
+      char buf[160];
+      snprintf(buf, sizeof(buf), "phase-field fixed point not converged after %d solves (change %.3e)", it,
+               change);
+      return fail(c, PF_ENOCONV, buf);
+    }
+    PF_TRY(launch(c, s, "pc_x_forward", [&] { return pfl::pc_x_forward(a, s); }));
+  }
   PF_TRY(launch(c, s, "ac_finalize", [&] { return pfl::ac_finalize(a, 0, s); }));
   return PF_OK;
 }
@@ -856,6 +895,8 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.gk = aniso ? reinterpret_cast<float*>(ws + L.gk) : nullptr;
     a.mob = g.mobile ? pg.mobility : nullptr;
     a.lapf = g.mobile ? reinterpret_cast<float*>(ws + L.lapf) : nullptr;
+    a.pf_base = g.pf_max_iter > 1 ? reinterpret_cast<float*>(ws + L.pf_base) : nullptr;
+    a.part_pc = g.pf_max_iter > 1 ? reinterpret_cast<float*>(ws + L.part_pc) : nullptr;
     a.gscale = (float)(aniso ? 2.0 : 2.0 * p0.kappa);
     g.lap_valid = false;
     // one grain: its rotated table serves every voxel (no per-voxel rotation)
@@ -984,12 +1025,12 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
   for (size_t k = 0; k < c->groups.size(); ++k) {
     Group& g = c->groups[k];
     g.args.save_stress = save_stress ? 1 : 0;
-    use_kh[k] = g.homogeneous && !g.epsp_given && !save_stress && !force_fp && !g.mobile;
+    use_kh[k] = g.homogeneous && !g.epsp_given && !save_stress && !force_fp && !g.mobile && g.pf_max_iter <= 1;
     if (g.mobile && !g.lap_valid && n_steps > 0) {
       PF_TRY(refresh_gradient_force(c, g));
       g.lap_valid = true;
     }
-    if (!use_kh[k] && !g.one_iteration) graphable = false;
+    if (!use_kh[k] && (!g.one_iteration || g.pf_max_iter > 1)) graphable = false;
     char buf[64];
     snprintf(buf, sizeof(buf), "%d:%p;", (int)use_kh[k], (const void*)g.args.epsp);
     key += buf;
@@ -1181,6 +1222,8 @@ int pf_batch_stats(pf_ctx* c, int32_t inst, pf_stats* out) {
   out->eta_max = st.stats[pft::kQac + 2];
   out->ms_iters = st.st.iters;
   out->ms_residual = st.st.residual;
+  out->pf_iters = g.pf_max_iter > 1 ? st.st.pf_iters : 1;
+  out->pf_change = g.pf_max_iter > 1 ? st.st.pf_change : 0.0;
   if (st.st.nonfinite) return fail(c, PF_ENONFINITE, "non-finite order parameter");
   return PF_OK;
 }

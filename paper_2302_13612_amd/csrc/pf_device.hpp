@@ -26,6 +26,9 @@ struct Status {
   int32_t done;
   int32_t nonfinite;
   int32_t pad;
+  double pf_change;   // max |f^i - f^{i-1}| of the last solve of the update's fixed point
+  int32_t pf_iters;   // solves of that fixed point in the last step
+  int32_t pf_pad;
 };
 
 // Device-resident state of a context (FP64 scalars).
@@ -89,6 +92,9 @@ struct KArgs {
   const float* mob;           // [nz][ny][nx] relative mobility, or null (uniform)
   float* lapf;                // [nv][nz][ny][nx] 2 div(K grad f) of the state (with mob)
   float gscale;               // 2 kappa (isotropic symbol) or 2 (tables carry K)
+  float* pf_base;             // [nv][nz][ny][nx] f^n + L dt m mech of the step, kept for
+                              // the fixed point over the update, or null (one solve)
+  float* part_pc;             // per-block (0, max |f^i - f^{i-1}|) of that fixed point
   uint32_t stress_mask;
   // fields
   float* eta;                 // [nv][ninst][nz][ny][nx]
@@ -145,6 +151,11 @@ hipError_t ac_x_forward(const KArgs& a, hipStream_t s);
 // mode 0 update, 1 energy only, 2 gradient force 2 div(K grad f) in place
 hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s);
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
+// Fixed point over the update: the right-hand side of a further solve from
+// the kept base and the chemical force of the latest iterate, R2C in x; and
+// the per-instance max change of a solve into Status (solve number it).
+hipError_t pc_x_forward(const KArgs& a, hipStream_t s);
+hipError_t pc_finalize(const KArgs& a, int it, hipStream_t s);
 hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s);  // 0 step, 1 init, 2 spectral path
@@ -168,6 +179,12 @@ hipError_t ac_x_forward_v3(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v4(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v5(const KArgs& a, hipStream_t s);
 hipError_t ac_x_forward_v6(const KArgs& a, hipStream_t s);
+hipError_t pc_x_forward_v1(const KArgs& a, hipStream_t s);
+hipError_t pc_x_forward_v2(const KArgs& a, hipStream_t s);
+hipError_t pc_x_forward_v3(const KArgs& a, hipStream_t s);
+hipError_t pc_x_forward_v4(const KArgs& a, hipStream_t s);
+hipError_t pc_x_forward_v5(const KArgs& a, hipStream_t s);
+hipError_t pc_x_forward_v6(const KArgs& a, hipStream_t s);
 hipError_t kh_x_forward_v1(const KArgs& a, int resid, hipStream_t s);
 hipError_t kh_x_forward_v2(const KArgs& a, int resid, hipStream_t s);
 hipError_t kh_x_forward_v3(const KArgs& a, int resid, hipStream_t s);

@@ -86,7 +86,9 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   block_sum<2, xthreads<M>() / 64>(acc, a.part_res + (size_t)blockIdx.x * kQres);
 }
 
-// Phase-field update, inverse: new order parameters, count of non-finite values.
+// Phase-field update, inverse: new order parameters, count of non-finite
+// values; with a fixed point over the update also the per-block max change
+// max |f^i - f^{i-1}| against the values overwritten.
 template <int M>
 __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   const size_t cs = (size_t)nrows * a.sh;
   const size_t roff = (size_t)(valid ? row : 0) * a.sh;
   double bad[1] = {0.0};
+  float dmax = 0.f;
   RowFetch<M> cur, nxt;
   c2r_fetch<M>(cur, t, valid, a.spec + roff);
   XTw<M, -1> tw;
@@ -115,6 +118,14 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
     c2r_from_regs<M>(v, cur, lds + p * LROW, t, tw);
     if (valid) {
       float* dst = q < a.nv ? a.eta + q * vs : a.lapf + (q - a.nv) * vs;
+      if (a.part_pc && q < a.nv) {
+        float2 old[E];
+#pragma unroll
+        for (int m = 0; m < E; ++m) old[m] = *reinterpret_cast<const float2*>(dst + rbase + 2 * (t + T * m));
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+          dmax = fmaxf(dmax, fmaxf(fabsf(v[m].x - old[m].x), fabsf(v[m].y - old[m].y)));
+      }
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int x0 = 2 * (t + T * m);
@@ -125,6 +136,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
     cur = nxt;
   }
   block_sum<1, xthreads<M>() / 64>(bad, a.part_res + (size_t)blockIdx.x * kQres);
+  if (a.part_pc) block_minmax<xthreads<M>() / 64>(0.f, dmax, a.part_pc + 2 * (size_t)blockIdx.x);
 }
 
 // Plain transforms of caller fields (checking the passes).
@@ -917,6 +929,20 @@ __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int 
 
 __global__ __launch_bounds__(1024) void k_resid_fin(const KArgs a, int nblk) { resid_fin(a, blockIdx.x, nblk); }
 
+// Fixed point over the update: max change of solve number it over the
+// instance's blocks.
+__global__ __launch_bounds__(1024) void k_fin_pc(const KArgs a, int nblk, int it) {
+  __shared__ float mm[2];
+  const float* pm = a.part_pc + 2 * (size_t)blockIdx.x * nblk;
+  float mx = 0.f;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) mx = fmaxf(mx, pm[2 * b + 1]);
+  block_minmax(0.f, mx, mm);
+  if (threadIdx.x == 0) {
+    a.state[blockIdx.x].st.pf_change = mm[1];
+    a.state[blockIdx.x].st.pf_iters = it;
+  }
+}
+
 }  // namespace pft
 
 // ====================================================================== host
@@ -1063,6 +1089,23 @@ hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));
   PF_SWITCH_M(a.nx, (k_x_inv_ac<M><<<grid, xthreads<M>(), 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t pc_x_forward(const KArgs& a, hipStream_t s) {
+  switch (a.nv) {
+    case 1: return pc_x_forward_v1(a, s);
+    case 2: return pc_x_forward_v2(a, s);
+    case 3: return pc_x_forward_v3(a, s);
+    case 4: return pc_x_forward_v4(a, s);
+    case 5: return pc_x_forward_v5(a, s);
+    case 6: return pc_x_forward_v6(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t pc_finalize(const KArgs& a, int it, hipStream_t s) {
+  k_fin_pc<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a), it);
   return hipGetLastError();
 }
 

@@ -385,7 +385,8 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
 
 // Phase-field update, forward: driving forces and the explicit right-hand
 // side RHS_a = f_a - L dt (chem_a - mech_a) of every voxel, FP64 energy and
-// mean sums, extrema of f; R2C of the V right-hand sides.
+// mean sums, extrema of f; R2C of the V right-hand sides. With a fixed point
+// over the update the part that stays fixed, f_a + L dt m mech_a, is kept.
 template <int M, int V, bool ROT, int HK>
 __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(PF_XWAVES))) void k_x_fwd_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
@@ -437,6 +438,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
     }
     VoxelOut vo2[2];
     float work2[2][V], quad2[2][V];
+    float bs[2][V];  // L dt m mech_a
     eval_pair<V, ROT, true, HK>(a, xt, tabs, e2, et2, ep2, {s.g0, s.g1}, R, vo2, work2, quad2);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -464,6 +466,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
         // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
         const float mech = dh_of(et[q], HK) * (work[q] - 0.5f * quad[q]);
         o[half][q] = et[q] - a.LDt * (chem_force<V>(a.A, et, fm, q) - mech);
+        bs[half][q] = a.LDt * mech;
       }
       if (a.mob) {
         // relative mobility m: the local forces scaled by m, the gradient
@@ -471,8 +474,10 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
         const size_t vox = rbase + x0 + half;
         const float mb = a.mob[vox];
 #pragma unroll
-        for (int q = 0; q < V; ++q)
+        for (int q = 0; q < V; ++q) {
           o[half][q] = et[q] + mb * (o[half][q] - et[q]) + a.LDt * (mb - 1.f) * a.lapf[q * vs + vox];
+          bs[half][q] *= mb;
+        }
       }
       if (valid) {
         facc[0] += fdw;
@@ -493,6 +498,12 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
           for (int c = 0; c < 6; ++c) a.sig[c * vs + rbase + x0 + half] = vo.sig[c];
         }
       }
+    }
+    if (a.pf_base && valid) {
+#pragma unroll
+      for (int q = 0; q < V; ++q)
+        *reinterpret_cast<float2*>(a.pf_base + q * vs + rbase + x0) =
+            make_float2(s.h[q].x + bs[0][q], s.h[q].y + bs[1][q]);
     }
 #pragma unroll
     for (int q = 0; q < V; ++q)
@@ -517,6 +528,73 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   block_minmax<xthreads<M>() / 64>(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
 
+
+// Fixed point over the update, forward pass of a further solve: the
+// right-hand side b_a - L dt m chem_a(f^{i-1}) (+ L dt (m - 1) G(f^{i-1})
+// with a mobility field) from the kept base b_a = f^n_a + L dt m mech_a,
+// R2C of the V components. The reductions of the step stay those of its
+// first pass.
+template <int M, int V>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_pc(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 stage[V * ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.ninst * a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+#pragma unroll 1
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    const size_t vox = rbase + 2 * k;
+    float2 f[V], b[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      f[q] = *reinterpret_cast<const float2*>(a.eta + q * vs + vox);
+      b[q] = *reinterpret_cast<const float2*>(a.pf_base + q * vs + vox);
+    }
+    float o[2][V];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      float et[V];
+      float fm = 1.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        et[q] = half ? f[q].y : f[q].x;
+        fm -= et[q];
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) o[half][q] = (half ? b[q].y : b[q].x) - a.LDt * chem_force<V>(a.A, et, fm, q);
+    }
+    if (a.mob) {
+      const float2 mb = *reinterpret_cast<const float2*>(a.mob + vox);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        const float2 g = *reinterpret_cast<const float2*>(a.lapf + q * vs + vox);
+        const float b0 = b[q].x, b1 = b[q].y;
+        o[0][q] = b0 + mb.x * (o[0][q] - b0) + a.LDt * (mb.x - 1.f) * g.x;
+        o[1][q] = b1 + mb.y * (o[1][q] - b1) + a.LDt * (mb.y - 1.f) * g.y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q)
+      stage[(q * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][q], o[1][q]);
+  }
+  const size_t cs = (size_t)nrows * a.sh;
+  float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+  XTw<M, 1> tw;
+  tw.load(a, t);
+#pragma unroll 1
+  for (int q = 0; q < V; ++q) {
+    float2* slab = stage + (q * ROWS + p) * LROW;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
+    r2c_one<M>(v, slab, t, valid, dst + q * cs, tw);
+  }
+}
 
 #if PF_NV <= 3
 // Homogeneous spectral path, forward: R2C of f_a (components 0..V-1) and of
@@ -653,6 +731,12 @@ hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, int resid, hipStream_t 
 
 hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
   PF_LAUNCH_X(k_x_fwd_ac);
+  return hipGetLastError();
+}
+
+hipError_t PF_CAT(pc_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_pc<M, PF_NV><<<grid, xthreads<M>(), 0, s>>>(a)));
   return hipGetLastError();
 }
 

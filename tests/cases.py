@@ -38,7 +38,8 @@ def oracle_problem(cfg, tol=1e-10):
         kv = cr.twin_gradient_tensors(np.asarray(cfg["rotations"])[:1], cfg["variant_ids"], **cfg["aniso"])[0]
     return opf.Problem(cfg["shape"], cfg["dx"], tabs, cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], C0,
                        gid=cfg["gid"], h_kind=cfg.get("h_kind", "linear"), ms_tol=tol, ms_max_iter=300,
-                       kappa_var=kv, mobility=cfg.get("mobility"))
+                       kappa_var=kv, mobility=cfg.get("mobility"),
+                       pf_tol=cfg.get("pf_tol_oracle", 1e-12), pf_max_iter=cfg.get("pf_max_iter", 1))
 
 
 def oracle_run(cfg, steps, tol=1e-10):
@@ -81,7 +82,8 @@ def gpu_solver(cfg, device="cuda", rotation_form=True):
         mob = torch.from_numpy(np.ascontiguousarray(cfg["mobility"], dtype=np.float32)).to(device)
     solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
                             cfg["stress_mask"], gid=gid, h_kind=h_kind, ms_tol=cfg["ms_tol"],
-                            ms_max_iter=cfg["ms_max_iter"], rotations=rotations, kappa_var=kv, mobility=mob)
+                            ms_max_iter=cfg["ms_max_iter"], rotations=rotations, kappa_var=kv, mobility=mob,
+                            pf_tol=cfg.get("pf_tol", 1e-6), pf_max_iter=cfg.get("pf_max_iter", 1))
     epsp = None if cfg["eps_p"] is None else torch.from_numpy(np.ascontiguousarray(cfg["eps_p"])).to(device)
     return solver, epsp
 

@@ -143,3 +143,29 @@ def test_mobility_needs_a_one_instance_context():
     ctx = ctypes.c_void_p()
     assert lib.pf_batch_init(probs, 2, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
     assert not ctx.value
+
+
+def test_update_fixed_point_arguments():
+    lib = binding.load()
+    keep = []
+    probs = (binding.PfProblem * 2)()
+    for i in range(2):
+        probs[i] = valid_problem(lib, keep=keep)
+    size = ctypes.c_size_t()
+    # a fixed point over the update needs a one-instance context
+    probs[1].pf_max_iter, probs[1].pf_tol = 5, 1e-6
+    ctx = ctypes.c_void_p()
+    assert lib.pf_batch_init(probs, 2, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
+    assert not ctx.value
+    # and takes its base and change partials from the workspace
+    one = valid_problem(lib, keep=keep)
+    assert lib.pf_workspace_size(ctypes.byref(one), ctypes.byref(size)) == binding.PF_OK
+    plain = size.value
+    one.pf_max_iter, one.pf_tol = 5, 1e-6
+    assert lib.pf_workspace_size(ctypes.byref(one), ctypes.byref(size)) == binding.PF_OK
+    assert size.value > plain + 4 * one.nx * one.ny * one.nz * one.n_var
+    for bad in ((-1, 1e-6), (3, -1.0), (3, float("nan")), (3, float("inf"))):
+        one.pf_max_iter, one.pf_tol = bad
+        assert lib.pf_init(ctypes.byref(one), None, 0, None, ctypes.byref(ctx)) == binding.PF_EINVAL, bad
+    one.pf_max_iter, one.pf_tol = 1, float("nan")   # one solve: the threshold is not read
+    assert lib.pf_workspace_size(ctypes.byref(one), ctypes.byref(size)) == binding.PF_OK

@@ -1,0 +1,101 @@
+"""GPU: the fixed point i over the phase-field update (Table 1, eqs. (19)-(20):
+each further solve takes the chemical force of the latest iterate, the
+gradient term stays implicit, the mechanical force stays that of f^n; stop at
+max |f^i - f^{i-1}| <= ERR_f) through the C ABI against the FP64 oracle
+iterated to 1e-12. Cases: the lamellae with the parent/twin contrast (the
+equilibrium iterates too), a six-variant polycrystal, two variants in a pad of
+zero mobility, and the sphere at three times its step (where the plain step
+runs away and the iterated one stays bounded). The library stops at 1e-6
+(1e-5 for the sphere, whose contraction is slow); bars as for the plain step:
+order parameter max-abs <= 1e-4, stress rel-L2 <= 1e-5. Also: a threshold met
+at the first solve gives the plain step bit for bit, and a fixed point that
+cannot meet its threshold reports PF_ENOCONV.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2302_13612_amd import binding, inputs
+from tests import cases
+from tests.test_gpu_batch import check_stats, multivariant_cfg
+
+pytestmark = pytest.mark.gpu
+
+ETA_TOL = 1e-4
+SIG_TOL = 1e-5
+
+
+def log(msg):
+    print(msg, flush=True)
+
+
+def compare(cfg, steps, label, stress=True):
+    log(f"\n[picard] {label} shape={cfg['shape']} n_var={cfg['n_var']} steps={steps}")
+    solver, eta_g, sig_g = cases.gpu_run(cfg, steps, save_stress_last=stress)
+    st_g = solver.stats()
+    eta_o, sig_o, stats_o = cases.oracle_run(cfg, steps)
+    d = np.abs(eta_g - eta_o).max()
+    msg = (f"  eta max-abs {d:.2e}  solves {st_g['pf_iters']} (oracle {stats_o[-1]['pf_iters']}) "
+           f"change {st_g['pf_change']:.1e}  ms_iters {st_g['ms_iters']}")
+    if stress:
+        r = cases.stress_rel_l2(sig_g, sig_o)
+        msg += f"  stress rel-L2 {r:.2e}"
+        assert r <= SIG_TOL
+    log(msg)
+    assert all(s["pf_converged"] for s in stats_o)
+    assert np.isfinite(eta_g).all()
+    assert d <= ETA_TOL
+    assert st_g["pf_iters"] > 2 and st_g["pf_change"] <= cfg["pf_tol"]
+    check_stats(st_g, stats_o[-1], np.abs(sig_o).max())
+    solver.close()
+    return eta_g
+
+
+def iterated(cfg, tol=1e-6):
+    return dict(cfg, pf_max_iter=200, pf_tol=tol, pf_tol_oracle=1e-12)
+
+
+def test_lamellae_iterated():
+    cfg = iterated(dict(cases.small_lamellae(), ms_tol=1e-6, ms_max_iter=60))
+    compare(cfg, 4, "lamellae 64x32x32 with contrast")
+
+
+def test_polycrystal_six_variants_iterated():
+    cfg = cases.small_polycrystal()
+    compare(iterated(dict(cfg, dt=2 * cfg["dt"])), 2, "polycrystal 32^3, 6 variants, 2 dt")
+
+
+def test_two_variants_in_a_pad_iterated():
+    cfg = multivariant_cfg(2)
+    cfg = dict(cfg, dt=5 * cfg["dt"], mobility=inputs.pad_mobility(cfg["shape"], pad=3, m_pad=0.0),
+               ms_tol=1e-6, ms_max_iter=60)
+    compare(iterated(cfg), 6, "2 variants 32^3, m_pad 0, 5 dt", stress=False)
+
+
+def test_sphere_at_three_steps_stays_bounded():
+    cfg = inputs.single_crystal_sphere()
+    cfg = iterated(dict(cfg, dt=3 * cfg["dt"]), tol=1e-5)
+    eta_g = compare(cfg, 5, "sphere 32^3, 3 dt")
+    assert -0.5 < eta_g.min() and eta_g.max() < 1.5
+
+
+def test_threshold_met_at_once_is_the_plain_step():
+    cfg = cases.small_lamellae()
+    _, plain, _ = cases.gpu_run(cfg, 3, save_stress_last=False)
+    solver, once, _ = cases.gpu_run(dict(cfg, pf_max_iter=5, pf_tol=1.0), 3, save_stress_last=False)
+    st = solver.stats()
+    solver.close()
+    log(f"\n[picard] tol 1: solves {st['pf_iters']}, max diff to the plain run {np.abs(once - plain).max():.1e}")
+    assert st["pf_iters"] == 1
+    np.testing.assert_array_equal(once, plain)
+
+
+def test_unmet_threshold_reports_enoconv():
+    cfg = dict(cases.small_lamellae(), pf_max_iter=2, pf_tol=0.0)
+    solver, epsp = cases.gpu_solver(cfg)
+    e, s = cases.loads(cfg, 0)
+    with pytest.raises(binding.PfError) as ei:
+        solver.step(1, e, s, eps_p=epsp)
+    solver.close()
+    log(f"\n[picard] tol 0: {ei.value}")
+    assert ei.value.code == binding.PF_ENOCONV
