@@ -94,6 +94,12 @@ def kernel_bytes(name, nx, ny, nz, V, multigrain, save_stress=False):
         "ac_z_update": 2 * V * 8 * nspec,
         "ac_y_inverse": 2 * V * 8 * nspec,
         "ac_x_inverse": V * 8 * nspec + V * 4 * nvox,
+        # fixed point over the update: the base f^n + L dt m mech kept by the
+        # first forward pass, the order parameter and base read by a further
+        # one, the overwritten values read by the inverse pass (max change)
+        "ac_x_forward+base": fields_in + V * 8 * nspec + V * 4 * nvox,
+        "pc_x_forward": 2 * V * 4 * nvox + V * 8 * nspec,
+        "ac_x_inverse+change": V * 8 * nspec + 2 * V * 4 * nvox,
     }
     return table.get(name, 0)
 
@@ -111,7 +117,7 @@ def cpu_info():
     return cores, model
 
 
-def cpu_baseline(n=64, steps=1):
+def cpu_baseline(n=64, steps=1, pf_max_iter=1, pf_tol=1e-6):
     """The FP64 oracle, as it stands, on the same recipe at n^3 (a bounded
     sample of the workload), in voxel-updates/s."""
     from oracle import crystal as cr
@@ -121,7 +127,8 @@ def cpu_baseline(n=64, steps=1):
     tabs = cr.mg_tables(cfg["rotations"], cfg["variant_ids"])
     C0 = opf.reference_stiffness_average(tabs[0], tabs[1])
     prob = opf.Problem(cfg["shape"], cfg["dx"], tabs, cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], C0,
-                       gid=cfg["gid"], ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"])
+                       gid=cfg["gid"], ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"],
+                       pf_tol=pf_tol, pf_max_iter=pf_max_iter)
     st = opf.State.initial(cfg["eta0"].astype(np.float64), np.zeros(6))
     epsp = cfg["eps_p"].astype(np.float64)
     ld = dict(eps_bar=cfg["eps_bar"], sig_bar=cfg["sig_bar"], stress_mask=cfg["stress_mask"])
@@ -133,7 +140,9 @@ def cpu_baseline(n=64, steps=1):
     return {
         "value": n ** 3 * steps / dt, "unit": "voxel-updates/s", "cores": cores, "kind": "oracle",
         "sample": f"{steps} oracle step(s) of the same polycrystal recipe at {n}^3 (64 grains, 6 variants, "
-                  f"fixed-point tol {cfg['ms_tol']:g}, {stats['ms_iters']} iterations), {dt:.1f} s on {model}",
+                  f"fixed-point tol {cfg['ms_tol']:g}, {stats['ms_iters']} iterations"
+                  + (f", update fixed point tol {pf_tol:g}, {stats['pf_iters']} solves" if pf_max_iter > 1 else "")
+                  + f"), {dt:.1f} s on {model}",
     }
 
 
@@ -544,6 +553,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=64)
     ap.add_argument("--aniso", action="store_true",
                     help="rve-batch: anisotropic gradient energy of Table 5 for every instance")
+    ap.add_argument("--pf-max-iter", type=int, default=1,
+                    help="polycrystal: solves of the fixed point over the update per step (Table 1; 1: plain step)")
+    ap.add_argument("--pf-tol", type=float, default=1e-6, help="its threshold on max |f^i - f^{i-1}|")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -596,8 +608,12 @@ def main():
     epsp = torch.from_numpy(cfg["eps_p"]).to(dev)
     solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
                             cfg["stress_mask"], gid=gid, ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"],
-                            rotations=cfg["rotations"])
+                            rotations=cfg["rotations"], pf_tol=args.pf_tol, pf_max_iter=args.pf_max_iter)
     del eta0
+    iterated = args.pf_max_iter > 1
+    # with the fixed point over the update its further forward passes are
+    # timed (they and the update's passes dominate the step)
+    dominant = "pc_x_forward" if iterated else DOMINANT
     log("warmup")
     solver.step(1, cfg["eps_bar"], cfg["sig_bar"], eps_p=epsp)
     for _ in range(max(0, args.warmup - 1)):
@@ -606,10 +622,17 @@ def main():
     # The timed steps carry HIP events around the launches of the dominant
     # stage only (events around every launch cost a few per cent of the step).
     log(f"timing {args.steps} steps")
-    solver.profile(True, only=DOMINANT)
+    solver.profile(True, only=dominant)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    solver.step(args.steps, cfg["eps_bar"], cfg["sig_bar"])
+    if iterated:
+        # one call per step: every step's statistics carry its solve count
+        solves = 0
+        for _ in range(args.steps):
+            solver.step(1, cfg["eps_bar"], cfg["sig_bar"])
+            solves += solver.stats()["pf_iters"]
+    else:
+        solver.step(args.steps, cfg["eps_bar"], cfg["sig_bar"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     prof = solver.profile_read()
@@ -617,20 +640,26 @@ def main():
     stats = solver.stats()
     value = n ** 3 * args.steps / elapsed
     ms_step = 1e3 * elapsed / args.steps
-    n_iter = prof[DOMINANT][0]  # one launch of each fixed-point stage per iteration
-    log(f"{ms_step:.3f} ms/step, {value:.3e} voxel-updates/s, {n_iter / args.steps:.2f} fixed-point "
-        f"iterations per step (last step {stats['ms_iters']})")
+    n_iter = prof[dominant][0]  # one launch of each fixed-point stage per iteration
+    if iterated:
+        log(f"{ms_step:.3f} ms/step, {value:.3e} voxel-updates/s, {solves / args.steps:.2f} update solves per "
+            f"step (last step {stats['pf_iters']}, equilibrium iterations {stats['ms_iters']})")
+    else:
+        log(f"{ms_step:.3f} ms/step, {value:.3e} voxel-updates/s, {n_iter / args.steps:.2f} fixed-point "
+            f"iterations per step (last step {stats['ms_iters']})")
 
     V = cfg["n_var"]
     nvox = n ** 3
 
     def stage_bytes(name, cnt, steps):
         # per-launch bytes, plus the warm start's extra traffic once per step
+        if iterated and name in ("ac_x_forward", "ac_x_inverse"):
+            name += "+base" if name == "ac_x_forward" else "+change"
         return kernel_bytes(name, n, n, n, V, True) * cnt + EXTRAPOLATION_BYTES_PER_VOXEL.get(name, 0) * nvox * steps
 
-    cnt, ms = prof[DOMINANT]
-    b_dom = stage_bytes(DOMINANT, cnt, args.steps)
-    dom = (DOMINANT, cnt, ms / cnt, b_dom / (ms * 1e-3) / 1e9, b_dom / cnt)
+    cnt, ms = prof[dominant]
+    b_dom = stage_bytes(dominant, cnt, args.steps)
+    dom = (dominant, cnt, ms / cnt, b_dom / (ms * 1e-3) / 1e9, b_dom / cnt)
     step_bytes = sum(stage_bytes(nm, n_iter if nm.startswith("ms_") else args.steps, args.steps)
                      for nm in STAGES) / args.steps
     # per-stage breakdown (stderr only): a few more steps with every launch timed
@@ -639,6 +668,9 @@ def main():
     solver.step(nprof, cfg["eps_bar"], cfg["sig_bar"])
     allp = solver.profile_read()
     solver.profile(False)
+    if iterated:
+        # bytes of a step from the launches each stage made in those steps
+        step_bytes = sum(stage_bytes(nm, c2, nprof) for nm, (c2, _) in allp.items()) / nprof
     total_ms = sum(v[1] for v in allp.values())
     log(f"per-stage times over {nprof} further steps:")
     for name, (c2, m2) in sorted(allp.items(), key=lambda kv: -kv[1][1]):
@@ -656,6 +688,7 @@ def main():
         "traffic": measured_traffic(dom[0]),
         "bytes_per_launch": round(dom[4]),
         "avg_launch_us": round(dom[2] * 1e3, 1),
+        "launches": dom[1],
         "step_algorithmic_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
@@ -674,7 +707,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"polycrystal {n}^3, 64 Voronoi grains, 6 twin variants, GRF plastic strain "
-                        f"RMS 2e-3, uniaxial -5e-3, fixed-point tol 1e-6",
+                        f"RMS 2e-3, uniaxial -5e-3, fixed-point tol 1e-6"
+                        + (f", update iterated to max change {args.pf_tol:g} (Table 1)" if iterated else ""),
             "grid": [n, n, n], "n_var": V, "n_grains": 64,
             "ms_iters_last_step": stats["ms_iters"],
             "fixed_point_iters_per_step": round(n_iter / args.steps, 3),
@@ -682,10 +716,14 @@ def main():
         },
         "roofline": roofline,
     }
+    if iterated:
+        out["metric"] = METRIC + ", update iterated (Table 1)"
+        out["config"]["update_solves_per_step"] = round(solves / args.steps, 3)
+        out["config"]["pf_max_iter"] = args.pf_max_iter
     solver.close()
     if not args.no_cpu_baseline:
         log(f"cpu baseline (oracle at {args.cpu_n}^3)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, pf_max_iter=args.pf_max_iter, pf_tol=args.pf_tol)
         log(f"cpu baseline {out['cpu_baseline']['value']:.3e} voxel-updates/s")
     print(json.dumps(out), flush=True)
 

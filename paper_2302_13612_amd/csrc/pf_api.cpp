@@ -393,7 +393,9 @@ hipEvent_t get_event(pf_ctx* c) {
     return e;
   }
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  // timing-only events: no system-scope fence when they are recorded (the
+  // fence writes back the caches and stretches the timed launch)
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 

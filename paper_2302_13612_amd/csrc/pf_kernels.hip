@@ -736,7 +736,23 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
   double acc[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+  // U blocks' partials are loaded before they are added (same order of
+  // addition), so a thread waits on memory nblk / (U blockDim) times
+  constexpr int U = Q >= 16 ? 1 : (Q >= 6 ? 4 : 8);
+  const int step = blockDim.x;
+  int b = threadIdx.x;
+  for (; b + (U - 1) * step < nblk; b += U * step) {
+    double v[U][Q];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) v[u][q] = part[(size_t)(b + u * step) * Q + q];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) acc[q] += v[u][q];
+  }
+  for (; b < nblk; b += step)
 #pragma unroll
     for (int q = 0; q < Q; ++q) acc[q] += part[(size_t)b * Q + q];
   block_sum<Q>(acc, res);
@@ -815,6 +831,7 @@ __device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, 
   __shared__ float mm[2];
   const float* pm = a.part_mm + 2 * (size_t)inst * nblk_x;
   float mn = 3.0e38f, mx = -3.0e38f;
+#pragma unroll 4
   for (int b = threadIdx.x; b < nblk_x; b += blockDim.x) {
     mn = fminf(mn, pm[2 * b]);
     mx = fmaxf(mx, pm[2 * b + 1]);

@@ -386,8 +386,9 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
 // Phase-field update, forward: driving forces and the explicit right-hand
 // side RHS_a = f_a - L dt (chem_a - mech_a) of every voxel, FP64 energy and
 // mean sums, extrema of f; R2C of the V right-hand sides. With a fixed point
-// over the update the part that stays fixed, f_a + L dt m mech_a, is kept.
-template <int M, int V, bool ROT, int HK>
+// over the update (PB) the part that stays fixed, f_a + L dt m mech_a, is
+// kept (a separate instantiation: the store costs registers).
+template <int M, int V, bool ROT, int HK, bool PB>
 __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(PF_XWAVES))) void k_x_fwd_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
@@ -438,7 +439,6 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
     }
     VoxelOut vo2[2];
     float work2[2][V], quad2[2][V];
-    float bs[2][V];  // L dt m mech_a
     eval_pair<V, ROT, true, HK>(a, xt, tabs, e2, et2, ep2, {s.g0, s.g1}, R, vo2, work2, quad2);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -466,7 +466,11 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
         // mech_a = h'(f_a) [sigma : eps0_a - 1/2 eps_el : dC_a : eps_el]
         const float mech = dh_of(et[q], HK) * (work[q] - 0.5f * quad[q]);
         o[half][q] = et[q] - a.LDt * (chem_force<V>(a.A, et, fm, q) - mech);
-        bs[half][q] = a.LDt * mech;
+        if (PB && valid) {
+          const size_t vox = rbase + x0 + half;
+          const float mb = a.mob ? a.mob[vox] : 1.f;
+          a.pf_base[q * vs + vox] = et[q] + mb * a.LDt * mech;
+        }
       }
       if (a.mob) {
         // relative mobility m: the local forces scaled by m, the gradient
@@ -474,10 +478,8 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
         const size_t vox = rbase + x0 + half;
         const float mb = a.mob[vox];
 #pragma unroll
-        for (int q = 0; q < V; ++q) {
+        for (int q = 0; q < V; ++q)
           o[half][q] = et[q] + mb * (o[half][q] - et[q]) + a.LDt * (mb - 1.f) * a.lapf[q * vs + vox];
-          bs[half][q] *= mb;
-        }
       }
       if (valid) {
         facc[0] += fdw;
@@ -498,12 +500,6 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
           for (int c = 0; c < 6; ++c) a.sig[c * vs + rbase + x0 + half] = vo.sig[c];
         }
       }
-    }
-    if (a.pf_base && valid) {
-#pragma unroll
-      for (int q = 0; q < V; ++q)
-        *reinterpret_cast<float2*>(a.pf_base + q * vs + rbase + x0) =
-            make_float2(s.h[q].x + bs[0][q], s.h[q].y + bs[1][q]);
     }
 #pragma unroll
     for (int q = 0; q < V; ++q)
@@ -701,19 +697,19 @@ using namespace pft;
     default: return hipErrorInvalidValue;              \
   }
 
-#define PF_LAUNCH_X(KERNEL)                                                                    \
-  do {                                                                                         \
-    const dim3 grid(x_blocks(a));                                                              \
-    const bool q = a.h_kind == 1;                                                              \
-    if (a.rot && q) {                                                                          \
-      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, true, 1><<<grid, xthreads<M>(), 0, s>>>(a)));   \
-    } else if (a.rot) {                                                                        \
-      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, true, 0><<<grid, xthreads<M>(), 0, s>>>(a)));   \
-    } else if (q) {                                                                            \
-      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, false, 1><<<grid, xthreads<M>(), 0, s>>>(a)));  \
-    } else {                                                                                   \
-      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, false, 0><<<grid, xthreads<M>(), 0, s>>>(a)));  \
-    }                                                                                          \
+#define PF_LAUNCH_X(KERNEL, ...)                                                                    \
+  do {                                                                                              \
+    const dim3 grid(x_blocks(a));                                                                   \
+    const bool q = a.h_kind == 1;                                                                   \
+    if (a.rot && q) {                                                                               \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, true, 1 __VA_ARGS__><<<grid, xthreads<M>(), 0, s>>>(a)));   \
+    } else if (a.rot) {                                                                             \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, true, 0 __VA_ARGS__><<<grid, xthreads<M>(), 0, s>>>(a)));   \
+    } else if (q) {                                                                                 \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, false, 1 __VA_ARGS__><<<grid, xthreads<M>(), 0, s>>>(a)));  \
+    } else {                                                                                        \
+      PF_SWITCH_M_LOCAL(a.nx, (KERNEL<M, PF_NV, false, 0 __VA_ARGS__><<<grid, xthreads<M>(), 0, s>>>(a)));  \
+    }                                                                                               \
   } while (0)
 
 hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
@@ -730,7 +726,11 @@ hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, int resid, hipStream_t 
 #endif
 
 hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
-  PF_LAUNCH_X(k_x_fwd_ac);
+  if (a.pf_base) {
+    PF_LAUNCH_X(k_x_fwd_ac, , true);
+  } else {
+    PF_LAUNCH_X(k_x_fwd_ac, , false);
+  }
   return hipGetLastError();
 }
 
