@@ -104,6 +104,25 @@ def kernel_bytes(name, nx, ny, nz, V, multigrain, save_stress=False):
     return table.get(name, 0)
 
 
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (bytes read + written per second) of a
+    1 GiB buffer: the bandwidth a plain streaming kernel reaches on this
+    device, reported beside the datasheet peak."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    s = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(s)
+    e1.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    return gbs
+
+
 def cpu_info():
     cores = len(os.sched_getaffinity(0))
     model = "unknown"
@@ -692,6 +711,10 @@ def main():
         "step_algorithmic_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
+    copy_gbs = copy_bandwidth(torch, dev)
+    roofline["copy_GBs"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(dom[3] / copy_gbs, 4)
+    log(f"device copy {copy_gbs:.0f} GB/s; {dom[0]} at {100 * dom[3] / copy_gbs:.1f}% of it")
     out = {
         "metric": METRIC,
         "value": value,
@@ -712,6 +735,7 @@ def main():
             "grid": [n, n, n], "n_var": V, "n_grains": 64,
             "ms_iters_last_step": stats["ms_iters"],
             "fixed_point_iters_per_step": round(n_iter / args.steps, 3),
+            "variant_updates_per_s": value * V,
             "timed_steps": f"{args.warmup + 1}-{args.warmup + args.steps} of the run",
         },
         "roofline": roofline,

@@ -417,7 +417,9 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 // transform, semi-implicit divide by 1 + 2 L dt kappa |xi|^2 (and 1/N),
 // Parseval sum of |xi|^2 |f_hat|^2 of the new state, inverse transform.
 // mode 1: Parseval sum of the unmodified spectrum only, nothing stored.
-template <int N, bool GK>
+// WG: the gradient force may be wanted (a mobility field, or mode 2); without
+// it the kernel holds one pencil less.
+template <int N, bool GK, bool WG>
 __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArgs a, int mode) {
   constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
   __shared__ float2 lds[N * C];
@@ -440,7 +442,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   const GradSym<GK> gs(a, inst, q, kx, sy);
   // the gradient force G = 2 div(K grad f) = -gscale sym f_hat of the new
   // state (with a mobility field) or of the given one (mode 2)
-  const bool want_g = mode == 2 || (mode == 0 && a.lapf != nullptr);
+  const bool want_g = WG && (mode == 2 || (mode == 0 && a.lapf != nullptr));
   float2 g[E];
   float e0 = 0.f;  // this thread's Parseval terms, then FP64
 #pragma unroll
@@ -515,7 +517,7 @@ __host__ __device__ constexpr int kh_tile() { return V == 1 ? kColTile : kZmsTil
 // mode 1: instead of the update, L dt dF/df of the state whose transforms
 // are in components 0..V-1 (f_hat) and V..2V-1 (L dt chem_hat):
 // L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
-__device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk);
+__device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk, double* scratch);
 
 template <int N, int V, bool GK>
 __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode, int nblk_x) {
@@ -526,7 +528,8 @@ __global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const 
   const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
   if (tile == 0 && ky == 0) {
     // this block holds xi = 0: the mean fields of the instance first
-    kh_begin_mean(a, inst, nblk_x);
+    // the pass's LDS (N C float2 >= blockDim doubles) is free until the transforms
+    kh_begin_mean(a, inst, nblk_x, reinterpret_cast<double*>(lds));
     __syncthreads();
   }
   const ctab_t kt = (ctab_t)(a.kh + (size_t)inst * kKhStride);
@@ -728,34 +731,41 @@ __global__ void k_step_begin(const KArgs a) {
 }
 
 // -------------------------------------------------------------- finalizes
-// Deterministic sum over nblk blocks of Q partials: each thread sums a fixed
-// strided subset in block order, then a fixed-shape tree.
+// Deterministic sum over nblk blocks of Q partials ([nblk][Q], FP64). The
+// block reads the array as one flat run with a stride S that is a multiple
+// of Q, so a thread always meets the same quantity (q = thread mod Q) and
+// every load is coalesced; sixteen loads are in flight per thread. The
+// per-thread sums of a quantity are then added by a fixed pairwise tree in
+// LDS. scratch: blockDim.x doubles of LDS.
 template <int Q>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nblk, double (&out)[Q]) {
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int nblk, double (&out)[Q],
+                                             double* scratch) {
   __shared__ double res[Q];
-  double acc[Q];
+  const int t = threadIdx.x;
+  const int S = (int)(blockDim.x / Q) * Q;
+  const int total = nblk * Q;
+  double acc = 0.0;
+  if (t < S) {
+    int i = t;
+    for (; i + 15 * S < total; i += 16 * S) {
+      double v[16];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) acc[q] = 0.0;
-  // U blocks' partials are loaded before they are added (same order of
-  // addition), so a thread waits on memory nblk / (U blockDim) times
-  constexpr int U = Q >= 16 ? 1 : (Q >= 6 ? 4 : 8);
-  const int step = blockDim.x;
-  int b = threadIdx.x;
-  for (; b + (U - 1) * step < nblk; b += U * step) {
-    double v[U][Q];
+      for (int u = 0; u < 16; ++u) v[u] = part[i + u * S];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < Q; ++q) v[u][q] = part[(size_t)(b + u * step) * Q + q];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < Q; ++q) acc[q] += v[u][q];
+      for (int u = 0; u < 16; ++u) acc += v[u];
+    }
+    for (; i < total; i += S) acc += part[i];
   }
-  for (; b < nblk; b += step)
-#pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] += part[(size_t)b * Q + q];
-  block_sum<Q>(acc, res);
+  scratch[t] = acc;
+  __syncthreads();
+  // entry t holds quantity t % Q, term j = t / Q of S / Q
+  const int nt = S / Q, j = t / Q;
+  for (int h = 1; h < nt; h *= 2) {
+    if (t < S && j % (2 * h) == 0 && j + h < nt) scratch[t] += scratch[t + h * Q];
+    __syncthreads();
+  }
+  if (t < Q) res[t] = scratch[t];
+  __syncthreads();
 #pragma unroll
   for (int q = 0; q < Q; ++q) out[q] = res[q];
   __syncthreads();
@@ -774,10 +784,10 @@ __host__ __device__ inline int z_partials_inst(const KArgs& a, int mode) {
 
 // Mixed condition after the forward x pass of an iteration: the mean strain
 // of the next iterate.
-__device__ inline void fin_ms(const KArgs& a, int inst, int nblk) {
+__device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratch) {
   DevState* st = a.state + inst;
   double s[kQms];
-  sum_partials<kQms>(a.part_ms + (size_t)inst * nblk * kQms, nblk, s);
+  sum_partials<kQms>(a.part_ms + (size_t)inst * nblk * kQms, nblk, s, scratch);
   if (threadIdx.x != 0) return;
   const double* Bss = a.bss + 36 * (size_t)inst;
   const double ntot = (double)a.nx * a.ny * a.nz;
@@ -796,10 +806,10 @@ __device__ inline void fin_ms(const KArgs& a, int inst, int nblk) {
 }
 
 // Convergence test after the inverse x pass of an iteration.
-__device__ inline void fin_res(const KArgs& a, int inst, int nblk) {
+__device__ inline void fin_res(const KArgs& a, int inst, int nblk, double* scratch) {
   DevState* st = a.state + inst;
   double s[kQres];
-  sum_partials<kQres>(a.part_res + (size_t)inst * nblk * kQres, nblk, s);
+  sum_partials<kQres>(a.part_res + (size_t)inst * nblk * kQres, nblk, s, scratch);
   if (threadIdx.x != 0) return;
   const double r = s[1] > 0.0 ? sqrt(s[0] / s[1]) : (s[0] > 0.0 ? 1.0e300 : 0.0);
   st->st.residual = r;
@@ -816,18 +826,18 @@ __device__ inline void fin_res(const KArgs& a, int inst, int nblk) {
 // the new state. mode 0: fixed-point path; 1: only the gradient sum of the
 // initial state; 2: homogeneous spectral path (stress, strain and the
 // mean-field elastic energy from the mean kernel).
-__device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, int mode) {
+__device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, int mode, double* scratch) {
   DevState* st = a.state + inst;
   double gd[kQgd];
-  sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd);
+  sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd, scratch);
   if (mode == 1) {
     if (threadIdx.x == 0) st->gd_cur = gd[0];
     return;
   }
   double s[kQac];
-  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, s);
+  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, s, scratch);
   double bad[kQres];
-  sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad);
+  sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad, scratch);
   __shared__ float mm[2];
   const float* pm = a.part_mm + 2 * (size_t)inst * nblk_x;
   float mn = 3.0e38f, mx = -3.0e38f;
@@ -864,9 +874,9 @@ __device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, 
 // <sigma> = C : (<eps> - sum_a <f_a> eps0_a); the mean elastic force
 // <sigma> : eps0_a (added to the xi = 0 coefficient by the z pass) and the
 // mean-field part of the elastic energy.
-__device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk) {
+__device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk, double* scratch) {
   double s[kQac];
-  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk * kQac, nblk, s);
+  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk * kQac, nblk, s, scratch);
   if (threadIdx.x != 0) return;
   DevState* st = a.state + inst;
   const double* ld = a.loads + 12 * (size_t)inst;
@@ -878,31 +888,44 @@ __device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk) {
   st->st.iters = 0;
   const double* kd = a.khd + (size_t)inst * kKhdStride;
   const double ntot = (double)a.nx * a.ny * a.nz;
+  // every array below is indexed by constants only (fully unrolled loops),
+  // so it stays in registers
   double es[6] = {0, 0, 0, 0, 0, 0};
-  for (int r = 0; r < a.nv; ++r) {
+#pragma unroll
+  for (int r = 0; r < kMaxVar; ++r) {
+    if (r >= a.nv) break;
     const double fr = s[14 + r] / ntot;
+#pragma unroll
     for (int c = 0; c < 6; ++c) es[c] += fr * kd[72 + 6 * r + c];
   }
   double d[6], rs[6];
+#pragma unroll
   for (int c = 0; c < 6; ++c) d[c] = ((a.stress_mask >> c) & 1u) ? 0.0 : ld[c] - es[c];
+#pragma unroll
   for (int i = 0; i < 6; ++i) {
     double acc = ld[6 + i];
+#pragma unroll
     for (int j = 0; j < 6; ++j) acc -= kd[6 * i + j] * d[j];
     rs[i] = acc;
   }
+#pragma unroll
   for (int i = 0; i < 6; ++i)
     if ((a.stress_mask >> i) & 1u) {
       double acc = 0.0;
+#pragma unroll
       for (int j = 0; j < 6; ++j)
         if ((a.stress_mask >> j) & 1u) acc += kd[36 + 6 * i + j] * rs[j];
       d[i] = acc;
     }
   double sg[6], e2 = 0.0;
+#pragma unroll
   for (int i = 0; i < 6; ++i) {
     double acc = 0.0;
+#pragma unroll
     for (int j = 0; j < 6; ++j) acc += kd[6 * i + j] * d[j];
     sg[i] = acc;
   }
+#pragma unroll
   for (int c = 0; c < 6; ++c) {
     st->mean_kh[c] = ntot * sg[c];
     st->mean_kh[6 + c] = ntot * (d[c] + es[c]);
@@ -930,17 +953,20 @@ __device__ inline void resid_fin(const KArgs& a, int inst, int nblk) {
 // block of the x passes needs a device-scope fence in every block, which on
 // this multi-L2 part writes back the L2 and costs far more than a launch.)
 __global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
+  __shared__ double scratch[1024];
   if (a.state[blockIdx.x].st.done) return;
-  fin_ms(a, blockIdx.x, nblk);
+  fin_ms(a, blockIdx.x, nblk, scratch);
 }
 
 __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
+  __shared__ double scratch[1024];
   if (a.state[blockIdx.x].st.done) return;
-  fin_res(a, blockIdx.x, nblk);
+  fin_res(a, blockIdx.x, nblk, scratch);
 }
 
 __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int mode) {
-  fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode);
+  __shared__ double scratch[1024];
+  fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode, scratch);
 }
 
 
@@ -1095,10 +1121,15 @@ hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
 
 hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
   const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, a.nv);
-  if (a.gk) {
-    PF_SWITCH_N(a.nz, (k_z_ac<N, true><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  const bool wg = mode == 2 || a.lapf != nullptr;
+  if (a.gk && wg) {
+    PF_SWITCH_N(a.nz, (k_z_ac<N, true, true><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  } else if (a.gk) {
+    PF_SWITCH_N(a.nz, (k_z_ac<N, true, false><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+  } else if (wg) {
+    PF_SWITCH_N(a.nz, (k_z_ac<N, false, true><<<grid, col_block<N>(), 0, s>>>(a, mode)));
   } else {
-    PF_SWITCH_N(a.nz, (k_z_ac<N, false><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+    PF_SWITCH_N(a.nz, (k_z_ac<N, false, false><<<grid, col_block<N>(), 0, s>>>(a, mode)));
   }
   return hipGetLastError();
 }
