@@ -38,8 +38,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   const size_t cs = (size_t)nrows * a.sh;
   const size_t roff = (size_t)(valid ? row : 0) * a.sh;
   double acc[2] = {0.0, 0.0};
-  // component c+1's spectral row and old strain are fetched while component c
-  // is transformed
+  // component c+1's spectral row is fetched while component c is transformed
   RowFetch<M> cur, nxt;
   c2r_fetch<M>(cur, t, valid, a.spec + roff);
   XTw<M, -1> tw;
@@ -47,19 +46,16 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   // the iterate this iteration started from: the stored strain, or on the
   // first iteration of a step the extrapolated one the forward pass wrote
   const float* prev = a.iter_mode != 0 ? a.eps_out : a.eps;
-  float2 old_c[E], old_n[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m)
-    old_c[m] = valid ? *reinterpret_cast<const float2*>(prev + rbase + 2 * (t + T * m)) : make_float2(0.f, 0.f);
+  float2 old_c[E];
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
-    if (c + 1 < 6) {
-      c2r_fetch<M>(nxt, t, valid, a.spec + (c + 1) * cs + roff);
+    if (c + 1 < 6) c2r_fetch<M>(nxt, t, valid, a.spec + (c + 1) * cs + roff);
+    // this component's old iterate, in flight while its row is transformed
+    // (fetching it one component ahead costs registers and gains nothing)
 #pragma unroll
-      for (int m = 0; m < E; ++m)
-        old_n[m] = valid ? *reinterpret_cast<const float2*>(prev + (c + 1) * vs + rbase + 2 * (t + T * m))
-                         : make_float2(0.f, 0.f);
-    }
+    for (int m = 0; m < E; ++m)
+      old_c[m] = valid ? *reinterpret_cast<const float2*>(prev + c * vs + rbase + 2 * (t + T * m))
+                       : make_float2(0.f, 0.f);
     const float shift = (float)(st->ebar_cur[c] - st->ebar_base[c]);
     const float w = c < 3 ? 1.f : 2.f;
     float2 v[E];
@@ -80,8 +76,6 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
     acc[0] += (double)(w * dsum);
     acc[1] += (double)(w * nsum);
     cur = nxt;
-#pragma unroll
-    for (int m = 0; m < E; ++m) old_c[m] = old_n[m];
   }
   block_sum<2, xthreads<M>() / 64>(acc, a.part_res + (size_t)blockIdx.x * kQres);
 }
