@@ -4,7 +4,8 @@ gradient term stays implicit, the mechanical force stays that of f^n; stop at
 max |f^i - f^{i-1}| <= ERR_f) through the C ABI against the FP64 oracle
 iterated to 1e-12. Cases: the lamellae with the parent/twin contrast (the
 equilibrium iterates too), a six-variant polycrystal, two variants in a pad of
-zero mobility, and the sphere at three times its step (where the plain step
+zero mobility, the anisotropic gradient energy of Table 5, quintic h on a
+radix-3 grid, and the sphere at three times its step (where the plain step
 runs away and the iterated one stays bounded). The library stops at 1e-6
 (1e-5 for the sphere, whose contraction is slow); bars as for the plain step:
 order parameter max-abs <= 1e-4, stress rel-L2 <= 1e-5. Also: a threshold met
@@ -77,6 +78,18 @@ def test_sphere_at_three_steps_stays_bounded():
     cfg = iterated(dict(cfg, dt=3 * cfg["dt"]), tol=1e-5)
     eta_g = compare(cfg, 5, "sphere 32^3, 3 dt")
     assert -0.5 < eta_g.min() and eta_g.max() < 1.5
+
+
+def test_anisotropic_gradient_iterated():
+    # Table 5's c2 along the twin-plane normal and the shear direction
+    cfg = dict(cases.small_lamellae(), aniso=dict(c2n=2.81e-7, c2s=2.81e-6), ms_tol=1e-6, ms_max_iter=60)
+    compare(iterated(dict(cfg, dt=2 * cfg["dt"])), 4, "lamellae 64x32x32, anisotropic c2, 2 dt")
+
+
+def test_quintic_two_variants_radix3_iterated():
+    cfg = cases.small_polycrystal(shape=(32, 64, 48), n_grains=5, seed=11, n_var=2)
+    cfg["h_kind"] = "quintic"
+    compare(iterated(dict(cfg, dt=2 * cfg["dt"])), 3, "polycrystal 32x64x48, 2 variants, quintic h, 2 dt")
 
 
 def test_threshold_met_at_once_is_the_plain_step():
