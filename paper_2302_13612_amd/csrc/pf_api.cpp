@@ -568,7 +568,6 @@ size_t status_base(pf_ctx* c, size_t gi) {
 
 int ms_iteration(pf_ctx* c, const KArgs& a, hipStream_t s) {
   PF_TRY(launch(c, s, "ms_x_forward", [&] { return pfl::ms_x_forward(a, s); }));
-  PF_TRY(launch(c, s, "ms_finalize_mean", [&] { return pfl::ms_finalize_mean(a, s); }));
   PF_TRY(launch(c, s, "ms_y_forward", [&] { return pfl::y_pass(a, 6, 1, s); }));
   PF_TRY(launch(c, s, "ms_z_green", [&] { return pfl::ms_z_green(a, s); }));
   PF_TRY(launch(c, s, "ms_y_inverse", [&] { return pfl::y_pass(a, 6, -1, s); }));

@@ -156,7 +156,6 @@ hipError_t ac_x_inverse(const KArgs& a, hipStream_t s);
 // the per-instance max change of a solve into Status (solve number it).
 hipError_t pc_x_forward(const KArgs& a, hipStream_t s);
 hipError_t pc_finalize(const KArgs& a, int it, hipStream_t s);
-hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s);
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s);
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s);  // 0 step, 1 init, 2 spectral path
 // 0 update, 1 L dt dF/df; the block owning xi = 0 of an instance first takes

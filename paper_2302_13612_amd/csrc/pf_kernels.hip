@@ -290,12 +290,13 @@ __device__ __forceinline__ bool ambiguous_nyquist(const KArgs& a, int kx, int ky
   return (nqx || nqy || nqz) && (otx || oty || otz);
 }
 
-__device__ __forceinline__ void green_apply(const KArgs& a, const DevState* st, ctab_t S0, int kx, int ky,
+// ebar: the mean strain of the next iterate (read at xi = 0 only)
+__device__ __forceinline__ void green_apply(const KArgs& a, const double* ebar, ctab_t S0, int kx, int ky,
                                             int kz, const float (&xi)[3], const float (&K)[6],
                                             float2 (&tau)[6]) {
   if (kx == 0 && ky == 0 && kz == 0) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) tau[c] = make_float2((float)st->ebar_next[c], 0.f);
+    for (int c = 0; c < 6; ++c) tau[c] = make_float2((float)ebar[c], 0.f);
     return;
   }
   const float s = a.inv_ntot;
@@ -347,18 +348,29 @@ __device__ __forceinline__ void green_apply(const KArgs& a, const DevState* st, 
   tau[5] = make_float2(h * (xi[0] * u[1].x + xi[1] * u[0].x), h * (xi[0] * u[1].y + xi[1] * u[0].y));
 }
 
+__device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratch, double* ebar_out);
+
 // z pass of the fixed point: forward z transform of the six polarisation
 // components, Green's operator, inverse z transform. 1D grid of
 // (column tile, ky) blocks in XCD-aware order; tiles of kZmsTile columns.
+// The block holding xi = 0 of an instance first applies the mixed condition
+// (the mean strain of the next iterate from the stress sums of the forward
+// x pass, nblk_x blocks), so no separate launch sits between the passes.
 template <int N>
-__global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a) {
+__global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a, int nblk_x) {
   constexpr int E = Plan<N>::E, T = N / E, C = kZmsTile;
   __shared__ float2 lds[N * C];
+  __shared__ double ebar[6];
   const int ntile = (a.nh + C - 1) / C;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
   const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
   const DevState* st = a.state + inst;
   if (st->st.done) return;
+  if (tile == 0 && ky == 0) {
+    // the pass's LDS (N C float2 >= blockDim doubles) is free until the transforms
+    fin_ms(a, inst, nblk_x, reinterpret_cast<double*>(lds), ebar);
+    __syncthreads();
+  }
   const ctab_t ref = (ctab_t)(a.ref + (size_t)inst * kRefStride);
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = tile * C + cc;
@@ -392,7 +404,7 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
     float2 tau[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) tau[c] = v[c][m];
-    green_apply(a, st, ref + 21, kxv, ky, kz, xi, K, tau);
+    green_apply(a, ebar, ref + 21, kxv, ky, kz, xi, K, tau);
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][m] = tau[c];
   }
@@ -777,8 +789,8 @@ __host__ __device__ inline int z_partials_inst(const KArgs& a, int mode) {
 }
 
 // Mixed condition after the forward x pass of an iteration: the mean strain
-// of the next iterate.
-__device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratch) {
+// of the next iterate, into the state and into ebar_out (LDS of the caller).
+__device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratch, double* ebar_out) {
   DevState* st = a.state + inst;
   double s[kQms];
   sum_partials<kQms>(a.part_ms + (size_t)inst * nblk * kQms, nblk, s, scratch);
@@ -786,16 +798,22 @@ __device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratc
   const double* Bss = a.bss + 36 * (size_t)inst;
   const double ntot = (double)a.nx * a.ny * a.nz;
   double r[6];
+#pragma unroll
   for (int c = 0; c < 6; ++c) r[c] = s[c] / ntot - st->sig_target[c];
+#pragma unroll
   for (int i = 0; i < 6; ++i) {
+    double e;
     if ((a.stress_mask >> i) & 1u) {
       double d = 0.0;
+#pragma unroll
       for (int j = 0; j < 6; ++j)
         if ((a.stress_mask >> j) & 1u) d += Bss[6 * i + j] * r[j];
-      st->ebar_next[i] = st->ebar_cur[i] - d;
+      e = st->ebar_cur[i] - d;
     } else {
-      st->ebar_next[i] = st->eps_target[i];
+      e = st->eps_target[i];
     }
+    st->ebar_next[i] = e;
+    ebar_out[i] = e;
   }
 }
 
@@ -946,12 +964,6 @@ __device__ inline void resid_fin(const KArgs& a, int inst, int nblk) {
 // One-block-per-instance finalize kernels. (Folding them into the last
 // block of the x passes needs a device-scope fence in every block, which on
 // this multi-L2 part writes back the L2 and costs far more than a launch.)
-__global__ __launch_bounds__(1024) void k_fin_ms(const KArgs a, int nblk) {
-  __shared__ double scratch[1024];
-  if (a.state[blockIdx.x].st.done) return;
-  fin_ms(a, blockIdx.x, nblk, scratch);
-}
-
 __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
   __shared__ double scratch[1024];
   if (a.state[blockIdx.x].st.done) return;
@@ -1077,11 +1089,6 @@ hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t ms_finalize_mean(const KArgs& a, hipStream_t s) {
-  k_fin_ms<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
-  return hipGetLastError();
-}
-
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
   k_fin_res<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a));
   return hipGetLastError();
@@ -1090,7 +1097,7 @@ hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
 
 hipError_t ms_z_green(const KArgs& a, hipStream_t s) {
   const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-  PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a)));
+  PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, x_blocks_inst(a))));
   return hipGetLastError();
 }
 
