@@ -838,18 +838,52 @@ __device__ inline void fin_res(const KArgs& a, int inst, int nblk, double* scrat
 // the new state. mode 0: fixed-point path; 1: only the gradient sum of the
 // initial state; 2: homogeneous spectral path (stress, strain and the
 // mean-field elastic energy from the mean kernel).
-__device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, int mode, double* scratch) {
+// The four reductions run in four blocks of one launch (part 0: gradient
+// sums, 1: energies and means, 2: non-finite count, 3: extrema); each writes
+// its own fields of the state.
+__device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, int mode, int part,
+                              double* scratch) {
   DevState* st = a.state + inst;
-  double gd[kQgd];
-  sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd, scratch);
-  if (mode == 1) {
-    if (threadIdx.x == 0) st->gd_cur = gd[0];
+  if (part == 0) {
+    double gd[kQgd];
+    sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd, scratch);
+    if (threadIdx.x != 0) return;
+    if (mode == 1) {
+      st->gd_cur = gd[0];
+      return;
+    }
+    st->stats[kQac] = st->gd_cur;  // the starting state's
+    if (mode == 2) {
+      const double ntot = (double)a.nx * a.ny * a.nz;
+      st->stats[kQac] = gd[2];  // the starting state's, from the spectral z pass
+      st->stats[1] = st->mean_kh[12] + 0.5 * gd[1] / ntot;
+      for (int c = 0; c < 6; ++c) {
+        st->stats[2 + c] = st->mean_kh[c];
+        st->stats[8 + c] = st->mean_kh[6 + c];
+      }
+      st->st.iters = 1;
+      st->st.residual = 0.0;
+      st->st.done = 1;
+    }
+    st->gd_cur = gd[0];
     return;
   }
-  double s[kQac];
-  sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, s, scratch);
-  double bad[kQres];
-  sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad, scratch);
+  if (mode == 1) return;
+  if (part == 1) {
+    double sm[kQac];
+    sum_partials<kQac>(a.part_ac + (size_t)inst * nblk_x * kQac, nblk_x, sm, scratch);
+    if (threadIdx.x != 0) return;
+    // on the spectral path stress, strain and elastic energy come from part 0
+    for (int q = 0; q < kQac; ++q)
+      if (mode != 2 || q == 0 || q >= 14) st->stats[q] = sm[q];
+    return;
+  }
+  if (part == 2) {
+    double bad[kQres];
+    sum_partials<kQres>(a.part_res + (size_t)inst * nblk_x * kQres, nblk_x, bad, scratch);
+    if (threadIdx.x == 0 && bad[0] > 0.0) st->st.nonfinite = 1;
+    return;
+  }
   __shared__ float mm[2];
   const float* pm = a.part_mm + 2 * (size_t)inst * nblk_x;
   float mn = 3.0e38f, mx = -3.0e38f;
@@ -860,24 +894,8 @@ __device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, 
   }
   block_minmax(mn, mx, mm);
   if (threadIdx.x != 0) return;
-  for (int q = 0; q < kQac; ++q) st->stats[q] = s[q];
-  st->stats[kQac] = st->gd_cur;
-  if (mode == 2) {
-    const double ntot = (double)a.nx * a.ny * a.nz;
-    st->stats[kQac] = gd[2];  // the starting state's, from the spectral z pass
-    st->stats[1] = st->mean_kh[12] + 0.5 * gd[1] / ntot;
-    for (int c = 0; c < 6; ++c) {
-      st->stats[2 + c] = st->mean_kh[c];
-      st->stats[8 + c] = st->mean_kh[6 + c];
-    }
-    st->st.iters = 1;
-    st->st.residual = 0.0;
-    st->st.done = 1;
-  }
   st->stats[kQac + 1] = mm[0];
   st->stats[kQac + 2] = mm[1];
-  st->gd_cur = gd[0];
-  if (bad[0] > 0.0) st->st.nonfinite = 1;
 }
 
 // Homogeneous spectral path after its forward x pass: the step's load and
@@ -972,7 +990,7 @@ __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
 
 __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int mode) {
   __shared__ double scratch[1024];
-  fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode, scratch);
+  fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode, blockIdx.y, scratch);
 }
 
 
@@ -1159,7 +1177,7 @@ hipError_t pc_finalize(const KArgs& a, int it, hipStream_t s) {
 }
 
 hipError_t ac_finalize(const KArgs& a, int mode, hipStream_t s) {
-  k_fin_ac<<<a.ninst, 1024, 0, s>>>(a, x_blocks_inst(a), z_partials_inst(a, mode), mode);
+  k_fin_ac<<<dim3(a.ninst, mode == 1 ? 1 : 4), 1024, 0, s>>>(a, x_blocks_inst(a), z_partials_inst(a, mode), mode);
   return hipGetLastError();
 }
 
