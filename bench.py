@@ -247,6 +247,14 @@ def bench_rve_batch(args):
     eta0_all = [sp["eta0"] for sp in specs]
     del specs
     log(f"workspace {bs.workspace.numel() / 2**30:.2f} GiB")
+    plans, timed, tune_ms = {}, 0, 0.0
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        timed = bs.autotune(cache=args.tune_cache)
+        tune_ms = 1e3 * (time.perf_counter() - t0)
+        for i, inst in enumerate(insts):
+            plans.setdefault(str(inst["shape"][0]), list(bs.plan(i)))
+        log(f"autotuned {timed} size groups in {tune_ms:.0f} ms: tiles (y, z) {plans}")
     eb = np.stack([inst["eps_bar"] for inst in insts])
     steps = args.steps if args.steps_given else batch["steps"]
     every = batch["save_every"]
@@ -307,6 +315,7 @@ def bench_rve_batch(args):
                                ", ".join(f"{n}^3 x{c}" for n, c in groups) +
                                f", 1 variant, homogeneous stiffness, {nsnap} snapshots of eta",
                    "voxels": nvox, "path": "homogeneous spectral",
+                   "plans": plans, "groups_timed": timed, "tune_ms": round(tune_ms, 1),
                    "gradient_energy": (f"anisotropic per variant, c2 {C2N:g} (normal) / {C2S:g} (shear) N"
                                        if args.aniso else f"isotropic, kappa {batch['kappa']:g} J/m")},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(dom[3], 1), "peak": HBM_PEAK_GBS,
@@ -575,6 +584,8 @@ def main():
     ap.add_argument("--pf-max-iter", type=int, default=1,
                     help="polycrystal: solves of the fixed point over the update per step (Table 1; 1: plain step)")
     ap.add_argument("--pf-tol", type=float, default=1e-6, help="its threshold on max |f^i - f^{i-1}|")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch tiles (no autotuning)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (one JSON object per line)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -629,6 +640,11 @@ def main():
                             cfg["stress_mask"], gid=gid, ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"],
                             rotations=cfg["rotations"], pf_tol=args.pf_tol, pf_max_iter=args.pf_max_iter)
     del eta0
+    plan = None
+    if not args.no_tune:
+        solver.autotune(cache=args.tune_cache)
+        plan = list(solver.plan())
+        log(f"autotuned tiles (y, z): {plan}")
     iterated = args.pf_max_iter > 1
     # with the fixed point over the update its further forward passes are
     # timed (they and the update's passes dominate the step)
@@ -737,6 +753,7 @@ def main():
             "fixed_point_iters_per_step": round(n_iter / args.steps, 3),
             "variant_updates_per_s": value * V,
             "timed_steps": f"{args.warmup + 1}-{args.warmup + args.steps} of the run",
+            "plan": plan,
         },
         "roofline": roofline,
     }

@@ -223,6 +223,26 @@ int pf_stats_get(pf_ctx *ctx, pf_stats *out);
  * spec is overwritten. ncomp in 1..6. */
 int pf_fft(pf_ctx *ctx, int32_t direction, int32_t ncomp, float *real, void *spec);
 
+/* Autotuner (launch plans of a batched launch picked by timing on the device,
+ * for uneven RVE sizes): for every group of same-size instances, the column
+ * tile of the y passes (8 or 16 columns per block) and, for groups that can
+ * take the homogeneous spectral path, of its z pass, each candidate timed on
+ * the group's own spectral buffer (zeroed first; it holds nothing between
+ * steps; the instances' state is kept). The tile changes no arithmetic: a
+ * tuned context computes bit for bit what an untuned one does. cache_path
+ * (may be NULL): a text file of one JSON object per line, keyed by the
+ * device's architecture name and compute-unit count and by the group's grid,
+ * instance count, n_var and path; an entry found there is applied without
+ * timing (unless flags has PF_TUNE_RETIME) and each timed group is appended.
+ * Synchronises the stream; not during graph capture; call between steps.
+ * *n_timed (may be NULL) receives the number of groups timed. */
+#define PF_TUNE_RETIME 1u
+int pf_autotune(pf_ctx *ctx, const char *cache_path, uint32_t flags, int32_t *n_timed);
+
+/* Plan of the group holding instance inst: *ytile the y-pass tile, *ztile the
+ * spectral z-pass tile (0 if the group never takes that path). */
+int pf_batch_plan(pf_ctx *ctx, int32_t inst, int32_t *ytile, int32_t *ztile);
+
 /* Per-kernel timing with HIP events on the context's stream: enable (1) or
  * disable (0) and reset; read returns up to max_n entries of name, launch
  * count and total milliseconds, the number of entries in *n. */

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpftwin.so")
 
 PF_OK, PF_EINVAL, PF_ENOMEM, PF_EDEVICE, PF_ENOCONV, PF_ENONFINITE, PF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+PF_TUNE_RETIME = 1
 ERROR_NAMES = {PF_EINVAL: "PF_EINVAL", PF_ENOMEM: "PF_ENOMEM", PF_EDEVICE: "PF_EDEVICE",
                PF_ENOCONV: "PF_ENOCONV", PF_ENONFINITE: "PF_ENONFINITE",
                PF_EUNSUPPORTED: "PF_EUNSUPPORTED"}
@@ -105,6 +106,8 @@ def load():
     lib.pf_profile_read.argtypes = [vp, i32, vp, ctypes.POINTER(ctypes.c_int64),
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     lib.pf_profile_select.argtypes = [vp, ctypes.c_char_p]
+    lib.pf_autotune.argtypes = [vp, ctypes.c_char_p, u32, ctypes.POINTER(i32)]
+    lib.pf_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pf_vmap_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pf_vmap_build.argtypes = [i32, i32, i32, ctypes.c_double, i32, vp, vp, ctypes.c_size_t, vp, vp]
     lib.pf_vmap_to_cells.argtypes = [ctypes.c_int64, vp, i32, i32, vp, vp, vp]
@@ -198,6 +201,19 @@ def _stats_dict(s, n_var):
         "ms_iters": s.ms_iters, "ms_residual": s.ms_residual,
         "pf_iters": s.pf_iters, "pf_change": s.pf_change,
     }
+
+
+def _autotune(obj, cache, retime):
+    n = ctypes.c_int32()
+    path = None if cache is None else os.fspath(cache).encode()
+    obj._check(obj.lib.pf_autotune(obj.ctx, path, PF_TUNE_RETIME if retime else 0, ctypes.byref(n)), "pf_autotune")
+    return n.value
+
+
+def _plan(obj, inst):
+    y, z = ctypes.c_int32(), ctypes.c_int32()
+    obj._check(obj.lib.pf_batch_plan(obj.ctx, inst, ctypes.byref(y), ctypes.byref(z)), "pf_batch_plan")
+    return y.value, z.value
 
 
 class Solver:
@@ -360,6 +376,15 @@ class Solver:
                     "pf_profile_read")
         return {names[i].value.decode(): (counts[i], tot[i]) for i in range(min(n.value, maxn))}
 
+    def autotune(self, cache=None, retime=False):
+        """Pick the launch tiles by timing (see pf_autotune); returns the
+        number of groups timed (0 when the cache held the plan)."""
+        return _autotune(self, cache, retime)
+
+    def plan(self):
+        """(y-pass tile, spectral z-pass tile or 0)."""
+        return _plan(self, 0)
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.pf_destroy(self.ctx)
@@ -497,6 +522,15 @@ class BatchSolver:
 
     profile = Solver.profile
     profile_read = Solver.profile_read
+
+    def autotune(self, cache=None, retime=False):
+        """Pick each size group's launch tiles by timing (see pf_autotune);
+        returns the number of groups timed."""
+        return _autotune(self, cache, retime)
+
+    def plan(self, inst):
+        """(y-pass tile, spectral z-pass tile or 0) of the instance's group."""
+        return _plan(self, inst)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -15,6 +15,7 @@
 // captured once in a HIP graph and replayed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -42,6 +43,7 @@ struct Layout {
   size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, gk, tw;
   size_t lapf;  // gradient force of the state (with a mobility field), else 0
   size_t pf_base, part_pc;  // fixed point over the update (pf_max_iter > 1), else 0
+  size_t spec_bytes;        // size of the spectral buffer
   size_t part_ms, part_res, part_ac, part_mm, part_gd, state, total;
   int tab_stride;
 };
@@ -79,7 +81,8 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.eps_prev3 = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
   L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
-  L.spec = take(sizeof(float) * 2 * nspec * (mobile && 2 * nv > 6 ? 2 * nv : 6));
+  L.spec_bytes = sizeof(float) * 2 * nspec * (mobile && 2 * nv > 6 ? 2 * nv : 6);
+  L.spec = take(L.spec_bytes);
   L.lapf = mobile ? take(sizeof(float) * nvox * nv) : 0;
   L.pf_base = picard ? take(sizeof(float) * nvox * nv) : 0;
   L.part_pc = picard ? take(sizeof(float) * xb * 2) : 0;
@@ -1254,6 +1257,175 @@ int pf_fft(pf_ctx* c, int32_t direction, int32_t ncomp, float* real, void* spec)
     PF_TRY(launch(c, s, "fft_x_inverse",
                   [&] { return pfl::raw_x_inverse(a, real, ncomp, (float)(1.0 / (double)g.nvox), s); }));
   }
+  return PF_OK;
+}
+
+// ---------------------------------------------------------------- autotuner
+// Per size group: the column tile (8 or 16 columns per block) of the y passes
+// and of the spectral path's z pass, picked by timing the candidates on the
+// group's own spectral buffer (zeroed first: it holds nothing between steps)
+// and kept in the context; optionally cached as one JSON object per line.
+}  // extern "C"
+
+namespace {
+
+struct TuneKey {
+  char dev[128];
+  int cus, nx, ny, nz, ninst, nv, spectral;
+};
+
+// an entry as written, and the same fields as read back
+const char* kTuneOut =
+    "{\"device\":\"%s\",\"cus\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"ninst\":%d,\"nv\":%d,"
+    "\"spectral\":%d,\"ytile\":%d,\"ztile\":%d";
+const char* kTuneIn =
+    "{\"device\":\"%127[^\"]\",\"cus\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"ninst\":%d,\"nv\":%d,"
+    "\"spectral\":%d,\"ytile\":%d,\"ztile\":%d";
+
+bool same_key(const TuneKey& a, const TuneKey& b) {
+  return std::strcmp(a.dev, b.dev) == 0 && a.cus == b.cus && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz &&
+         a.ninst == b.ninst && a.nv == b.nv && a.spectral == b.spectral;
+}
+
+// last entry of the cache for key (entries are appended), or false
+bool tune_cache_read(const char* path, const TuneKey& key, int& ytile, int& ztile) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool hit = false;
+  while (std::fgets(line, sizeof(line), f)) {
+    TuneKey k{};
+    int y = 0, z = 0;
+    if (std::sscanf(line, kTuneIn, k.dev, &k.cus, &k.nx, &k.ny, &k.nz, &k.ninst, &k.nv, &k.spectral, &y, &z) == 10 &&
+        same_key(k, key) && (y == 8 || y == 16) && (z == 0 || z == 8 || z == 16)) {
+      ytile = y;
+      ztile = z;
+      hit = true;
+    }
+  }
+  std::fclose(f);
+  return hit;
+}
+
+// us: the candidates' times, (y, z) = (8, 8), (16, 8), (8, 16), (16, 16) in that
+// order (the first two only without the spectral path)
+bool tune_cache_append(const char* path, const TuneKey& k, int ytile, int ztile, const double* us, int ncand) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return false;
+  std::fprintf(f, kTuneOut, k.dev, k.cus, k.nx, k.ny, k.nz, k.ninst, k.nv, k.spectral, ytile, ztile);
+  std::fprintf(f, ",\"us\":[");
+  for (int i = 0; i < ncand; ++i) std::fprintf(f, i ? ",%.2f" : "%.2f", us[i]);
+  std::fprintf(f, "]}\n");
+  const bool ok = std::ferror(f) == 0;
+  return std::fclose(f) == 0 && ok;
+}
+
+// average duration (us) of reps calls of f on stream s, after one warm-up call
+template <class F>
+int time_us(pf_ctx* c, hipStream_t s, int reps, F&& f, double& us) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = f();
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = f();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (e != hipSuccess) return hip_fail(c, e, "autotune timing");
+  us = 1e3 * ms / reps;
+  return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_autotune(pf_ctx* c, const char* cache_path, uint32_t flags, int32_t* n_timed) {
+  if (!c) return PF_EINVAL;
+  if (c->capturing) return fail(c, PF_EINVAL, "pf_autotune: not during capture");
+  hipStream_t s = c->stream;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(c, e, "autotune sync");
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if ((e = hipGetDevice(&dev)) != hipSuccess || (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+    return hip_fail(c, e, "autotune device");
+  int timed = 0;
+  constexpr int kReps = 10;
+  const int cand[2] = {8, 16};
+  for (auto& g : c->groups) {
+    TuneKey key{};
+    std::snprintf(key.dev, sizeof(key.dev), "%s", prop.gcnArchName);
+    key.cus = prop.multiProcessorCount;
+    key.nx = g.nx; key.ny = g.ny; key.nz = g.nz; key.ninst = g.ninst; key.nv = c->nv;
+    key.spectral = (g.homogeneous && !g.mobile && g.pf_max_iter <= 1) ? 1 : 0;
+    int ytile = 0, ztile = 0;
+    if (cache_path && !(flags & PF_TUNE_RETIME) && tune_cache_read(cache_path, key, ytile, ztile)) {
+      g.args.ytile = ytile;
+      g.args.ztile_kh = ztile;
+      continue;
+    }
+    // the state of every instance is kept: the spectral z pass writes per-step fields
+    std::vector<DevState> saved(g.ninst);
+    if ((e = hipMemcpyAsync(saved.data(), g.args.state, sizeof(DevState) * g.ninst, hipMemcpyDeviceToHost, s)) !=
+            hipSuccess ||
+        (e = hipMemsetAsync(g.args.spec, 0, g.L.spec_bytes, s)) != hipSuccess)
+      return hip_fail(c, e, "autotune setup");
+    // Each candidate plan is timed as the sequence the step runs: on the
+    // spectral path y forward (2V components), z pass, y inverse (V), every
+    // pair of tiles; in the fixed point y forward and inverse of six
+    // components. Candidates alternate over two rounds; the best time counts.
+    const int ncand = key.spectral ? 4 : 2;
+    double us_best[4] = {1e30, 1e30, 1e30, 1e30};
+    for (int round = 0; round < 2; ++round)
+      for (int k = 0; k < ncand; ++k) {
+        KArgs a = g.args;
+        a.ytile = cand[k & 1];
+        a.ztile_kh = cand[k >> 1];
+        a.skip_done = 0;
+        double us = 0.0;
+        PF_TRY(time_us(c, s, kReps, [&] {
+          if (!key.spectral) {
+            hipError_t r = pfl::y_pass(a, 6, 1, s);
+            return r == hipSuccess ? pfl::y_pass(a, 6, -1, s) : r;
+          }
+          hipError_t r = pfl::y_pass(a, 2 * c->nv, 1, s);
+          if (r == hipSuccess) r = pfl::kh_z_update(a, 1, s);
+          return r == hipSuccess ? pfl::y_pass(a, c->nv, -1, s) : r;
+        }, us));
+        us_best[k] = std::min(us_best[k], us);
+      }
+    int best = 0;
+    for (int k = 1; k < ncand; ++k)
+      if (us_best[k] < us_best[best]) best = k;
+    ytile = cand[best & 1];
+    ztile = key.spectral ? cand[best >> 1] : 0;
+    if ((e = hipMemcpyAsync(g.args.state, saved.data(), sizeof(DevState) * g.ninst, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(c, e, "autotune restore");
+    g.args.ytile = ytile;
+    g.args.ztile_kh = ztile;
+    ++timed;
+    if (cache_path && !tune_cache_append(cache_path, key, ytile, ztile, us_best, ncand))
+      return fail(c, PF_EINVAL, std::string("pf_autotune: cannot write the cache ") + cache_path);
+  }
+  drop_graph(c);  // launches of a captured step carry the old tiles
+  if (n_timed) *n_timed = timed;
+  return PF_OK;
+}
+
+int pf_batch_plan(pf_ctx* c, int32_t inst, int32_t* ytile, int32_t* ztile) {
+  if (!c || !ytile || !ztile) return PF_EINVAL;
+  PF_TRY(check_instance(c, inst));
+  const Group& g = c->groups[c->where[inst].first];
+  *ytile = g.args.ytile ? g.args.ytile : 16;
+  const bool spectral = g.homogeneous && !g.mobile && g.pf_max_iter <= 1;
+  *ztile = !spectral ? 0 : (g.args.ztile_kh ? g.args.ztile_kh : (c->nv == 1 ? 16 : 8));
   return PF_OK;
 }
 

@@ -127,6 +127,9 @@ struct KArgs {
   DevState* state;            // [ninst]
   int save_stress;
   int skip_done;              // y pass: skip instances whose fixed point has converged
+  int ytile;                  // columns per block of the y passes (8 or 16; 0: 16)
+  int ztile_kh;               // columns per block of the spectral path's z pass (8 or 16;
+                              // 0: 16 for one variant, else 8)
 };
 
 // Packed upper-triangle index of a symmetric 6x6 matrix.

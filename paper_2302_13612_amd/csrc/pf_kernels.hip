@@ -184,10 +184,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, floa
 }
 
 // ------------------------------------------------------------ y and z passes
-// y: columns of kColTile consecutive kx at one z, in place. grid (tiles, nz, ncomp).
-template <int N, int DIR>
-__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_y(const KArgs a) {
-  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+// y: columns of C consecutive kx at one z, in place. grid (tiles, nz, ncomp).
+// C (8 or 16) is the group's tuned tile.
+template <int N, int DIR, int C>
+__global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_y(const KArgs a) {
+  constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[N * C];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
@@ -519,15 +520,19 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
 // and the fluctuation part of the elastic energy.
 template <int V>
 __host__ __device__ constexpr int kh_tile() { return V == 1 ? kColTile : kZmsTile; }
+// the tile the spectral z pass runs with: the group's tuned one, else the default
+__host__ __device__ inline int kh_tile_of(const KArgs& a) {
+  return a.ztile_kh ? a.ztile_kh : (a.nv == 1 ? kColTile : kZmsTile);
+}
 
 // mode 1: instead of the update, L dt dF/df of the state whose transforms
 // are in components 0..V-1 (f_hat) and V..2V-1 (L dt chem_hat):
 // L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
 __device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk, double* scratch);
 
-template <int N, int V, bool GK>
-__global__ __launch_bounds__(kh_tile<V>() * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode, int nblk_x) {
-  constexpr int E = Plan<N>::E, T = N / E, C = kh_tile<V>();
+template <int N, int V, bool GK, int C>
+__global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode, int nblk_x) {
+  constexpr int E = Plan<N>::E, T = N / E;
   __shared__ float2 lds[N * C];
   const int ntile = (a.nh + C - 1) / C;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -782,7 +787,7 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 // one variant, else 8).
 __host__ __device__ inline int z_partials_inst(const KArgs& a, int mode) {
   if (mode == 2) {
-    const int C = a.nv == 1 ? kColTile : kZmsTile;
+    const int C = kh_tile_of(a);
     return ((a.nh + C - 1) / C) * a.ny;
   }
   return ((a.nh + kColTile - 1) / kColTile) * a.ny * a.nv;
@@ -1097,14 +1102,19 @@ hipError_t ms_x_forward(const KArgs& a, hipStream_t s) {
 }
 
 
-hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.nz * a.ninst, ncomp);
+template <int C>
+static hipError_t y_pass_t(const KArgs& a, int ncomp, int dir, hipStream_t s) {
+  const dim3 grid((a.nh + C - 1) / C, a.nz * a.ninst, ncomp);
   if (dir > 0) {
-    PF_SWITCH_N(a.ny, (k_y<N, 1><<<grid, col_block<N>(), 0, s>>>(a)));
+    PF_SWITCH_N(a.ny, (k_y<N, 1, C><<<grid, dim3(C * (N / Plan<N>::E)), 0, s>>>(a)));
   } else {
-    PF_SWITCH_N(a.ny, (k_y<N, -1><<<grid, col_block<N>(), 0, s>>>(a)));
+    PF_SWITCH_N(a.ny, (k_y<N, -1, C><<<grid, dim3(C * (N / Plan<N>::E)), 0, s>>>(a)));
   }
   return hipGetLastError();
+}
+
+hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
+  return a.ytile == 8 ? y_pass_t<8>(a, ncomp, dir, s) : y_pass_t<kColTile>(a, ncomp, dir, s);
 }
 
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
@@ -1198,24 +1208,26 @@ hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream
 }
 
 
+template <bool GK, int V, int C>
+static hipError_t kh_z_launch(const KArgs& a, int mode, hipStream_t s) {
+  const dim3 grid(((a.nh + C - 1) / C) * a.ny * a.ninst);
+  PF_SWITCH_N(a.nz, (k_z_kh<N, V, GK, C><<<grid, dim3(C * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
+  return hipGetLastError();
+}
+
+template <bool GK, int V>
+static hipError_t kh_z_tile(const KArgs& a, int mode, hipStream_t s) {
+  return kh_tile_of(a) == 8 ? kh_z_launch<GK, V, 8>(a, mode, s) : kh_z_launch<GK, V, 16>(a, mode, s);
+}
+
 template <bool GK>
 hipError_t kh_z_update_t(const KArgs& a, int mode, hipStream_t s) {
   switch (a.nv) {
-    case 1: {
-      const dim3 grid(((a.nh + kColTile - 1) / kColTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 1, GK><<<grid, dim3(kColTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
-    } break;
-    case 2: {
-      const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 2, GK><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
-    } break;
-    case 3: {
-      const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-      PF_SWITCH_N(a.nz, (k_z_kh<N, 3, GK><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
-    } break;
-    default: return hipErrorInvalidValue;
+    case 1: return kh_z_tile<GK, 1>(a, mode, s);
+    case 2: return kh_z_tile<GK, 2>(a, mode, s);
+    case 3: return kh_z_tile<GK, 3>(a, mode, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s) {

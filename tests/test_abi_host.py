@@ -169,3 +169,11 @@ def test_update_fixed_point_arguments():
         assert lib.pf_init(ctypes.byref(one), None, 0, None, ctypes.byref(ctx)) == binding.PF_EINVAL, bad
     one.pf_max_iter, one.pf_tol = 1, float("nan")   # one solve: the threshold is not read
     assert lib.pf_workspace_size(ctypes.byref(one), ctypes.byref(size)) == binding.PF_OK
+
+
+def test_autotune_arguments():
+    lib = binding.load()
+    n = ctypes.c_int32()
+    assert lib.pf_autotune(None, None, 0, ctypes.byref(n)) == binding.PF_EINVAL
+    y, z = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.pf_batch_plan(None, 0, ctypes.byref(y), ctypes.byref(z)) == binding.PF_EINVAL
