@@ -108,6 +108,76 @@ def forward(params, eta, cond):
     return eta + project(params, v)
 
 
+def gelu_grad(x):
+    """d GELU / dx = Phi(x) + x phi(x)."""
+    return 0.5 * (1.0 + erf(x / np.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / np.sqrt(2.0 * np.pi)
+
+
+def spectral_conv_adjoint(dy, R, v):
+    """Gradients through K v = irfftn(embed(R sub(rfftn(v)))) for the output
+    gradient dy (C_out, nz, ny, nx): returns (dv, dR) with dR holding
+    dL/dRe R + i dL/dIm R. Written out from the real-pair derivatives of the
+    transforms: an output mode's gradient is c(kx)/N rfftn(dy) (c = 1 on the
+    kx = 0 plane, 2 elsewhere among the kept kx), dR = that times conj of the
+    input's kept modes, and dv is the same convolution with R^H."""
+    C, nz, ny, nx = v.shape
+    m = R.shape[-1]
+    ntot = nz * ny * nx
+    iz, iy = kept_index(nz, m), kept_index(ny, m)
+    cx = np.where(np.arange(m) == 0, 1.0, 2.0)
+    G = np.fft.rfftn(dy, axes=(1, 2, 3))[:, iz][:, :, iy][..., :m] * (cx / ntot)   # (C_out, 2m, 2m, m)
+    S = np.fft.rfftn(v, axes=(1, 2, 3))[:, iz][:, :, iy][..., :m]                  # (C_in, 2m, 2m, m)
+    dR = G[:, None] * np.conj(S)[None, :]
+    GS = np.einsum("oizyx,ozyx->izyx", np.conj(R), G)
+    emb = np.zeros((C, nz, ny, nx // 2 + 1), dtype=complex)
+    emb[np.ix_(np.arange(C), iz, iy, np.arange(m))] = GS
+    # dv(x) = sum over kept modes Re[GS e^{+i theta}] = N irfftn(GS / c)
+    dv = np.fft.irfftn(emb / np.concatenate([cx, np.full(nx // 2 + 1 - m, 1.0)]), s=(nz, ny, nx),
+                       axes=(1, 2, 3)) * ntot
+    return dv, dR
+
+
+def backward(params, eta, cond, g_out):
+    """Gradients of L = sum_x g_out(x) f~(x) with respect to every parameter,
+    by the chain rule through the forward pass above (hand-written, FP64).
+    Returns a dict shaped like params; R's entry is dL/dRe R + i dL/dIm R."""
+    eta = np.asarray(eta, dtype=np.float64)
+    g_out = np.asarray(g_out, dtype=np.float64)
+    n_layers = params["W"].shape[0]
+    vs = [lift(params, eta, cond)]
+    us = []
+    for l in range(n_layers):
+        W, b, R = params["W"][l], params["b"][l], params["R"][l]
+        u = np.einsum("oi,izyx->ozyx", W, vs[-1]) + b[:, None, None, None] + spectral_conv(vs[-1], R)
+        us.append(u)
+        vs.append(gelu(u))
+    zh = np.einsum("hi,izyx->hzyx", params["Q1"], vs[-1]) + params["q1"][:, None, None, None]
+    h = gelu(zh)
+    gr = {}
+    gr["q2"] = np.array([g_out.sum()])
+    gr["Q2"] = np.einsum("zyx,hzyx->h", g_out, h)[None, :]
+    dzh = params["Q2"][0][:, None, None, None] * g_out[None] * gelu_grad(zh)
+    gr["Q1"] = np.einsum("hzyx,izyx->hi", dzh, vs[-1])
+    gr["q1"] = dzh.sum(axis=(1, 2, 3))
+    dv = np.einsum("hi,hzyx->izyx", params["Q1"], dzh)
+    gW, gb, gR = [], [], []
+    for l in reversed(range(n_layers)):
+        du = dv * gelu_grad(us[l])
+        gW.append(np.einsum("ozyx,izyx->oi", du, vs[l]))
+        gb.append(du.sum(axis=(1, 2, 3)))
+        dv_spec, dR = spectral_conv_adjoint(du, params["R"][l], vs[l])
+        gR.append(dR)
+        dv = np.einsum("oi,ozyx->izyx", params["W"][l], du) + dv_spec
+    gr["W"] = np.stack(gW[::-1])
+    gr["b"] = np.stack(gb[::-1])
+    gr["R"] = np.stack(gR[::-1])
+    c = np.asarray(cond, dtype=np.float64)
+    dsum = dv.sum(axis=(1, 2, 3))
+    gr["P"] = np.concatenate([np.einsum("czyx,zyx->c", dv, eta)[:, None], dsum[:, None] * c[None, :]], axis=1)
+    gr["p"] = dsum
+    return gr
+
+
 def conditioning(eps0_sample6, eps_bar_xx, gamma_tw=0.129, strain_scale=5e-3):
     """The constant input channels: eps0 (tensor-Voigt, sample frame) / gamma_tw
     and the applied strain / strain_scale."""
