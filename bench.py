@@ -590,8 +590,9 @@ def main():
                     help="run one 256 MiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition is "
-              "described in DESIGN.md but not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU decomposition "
+              "(z slabs with one all-to-all per 3D transform, FP64 all-reduces for the means) is not built.",
+              file=sys.stderr)
         sys.exit(2)
     args.steps_given = args.steps is not None
     if args.workload == "rve-batch":
