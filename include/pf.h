@@ -12,11 +12,11 @@
  *   2. the driving forces of eq. (17): double well (eq. (13)), gradient
  *      (eq. (14)) and elastic (eq. (15)) terms;
  *   3. the linearised semi-implicit update of eqs. (19)-(20), solved in
- *      Fourier space (Table 1, steps 5-9):
+ *      Fourier space (Table 1):
  *      f^{n+1} = IFFT[FFT(f^n - L dt (chem - mech)) / (1 + 2 L dt kappa |xi|^2)];
  *   4. FP64 reductions: energies (eq. (12)), mean stress and strain, mean f.
  * The plastic strain eps_p is the per-voxel input handed over by the crystal
- * plasticity side (Table 1, steps 1-2); f goes back to it (Table 1, step 12).
+ * plasticity side, and f goes back to it (Table 1).
  *
  * Conventions
  *   Grid fields are float32, component-major, [comp][z][y][x] with x

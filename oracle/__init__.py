@@ -19,7 +19,7 @@ coupling crystal plasticity and phase field models"):
                   stiffness of eq. (5)).
 * ``phasefield``- driving forces of eq. (17), the linearised semi-implicit
                   update of eqs. (19)-(20) solved in Fourier space
-                  (Table 1, steps 5-9), energies of eqs. (12)-(15).
+                  (Table 1), energies of eqs. (12)-(15).
 
 Where the paper is silent or garbled the reading taken is stated in the
 docstring of the function that depends on it.

@@ -8,7 +8,7 @@ Free energy, eq. (12): G = G_dw + G_gd + G_me, with
 * the stored elastic energy of eq. (15), 1/2 eps_el : C(x) : eps_el.
 
 Evolution: eq. (16)/(17), linearised per eqs. (19)-(20) with the Laplacian
-implicit and the rest explicit, solved in Fourier space (Table 1, steps 5-9).
+implicit and the rest explicit, solved in Fourier space (Table 1).
 
 Readings (stated once here, used below):
 * Symbols: A = c1, kappa = c2, and the mobility maps as c3 -> 2L on the
@@ -21,9 +21,10 @@ Readings (stated once here, used below):
 * Mechanical force: mech_a = h'(f_a) [sigma : eps0_a
   - 1/2 eps_el : (C_twin^a - C_g) : eps_el]; eq. (17) prints C_twin^a, the
   derivative of eq. (5) gives the difference (C_twin^a - C_matrix).
-* One pass per variant per step: with f_M = 1 - sum f the implicit
-  coefficient is constant, so the fixed point i of Table 1 converges in one
-  solve; eq. (18) holds by construction, so the loop j is empty.
+* One solve per step by default: with f_M = 1 - sum f the implicit
+  coefficient of the converged equation is constant, and the step takes the
+  nonlinear force at f^n (the fixed point i of Table 1 is the option below);
+  eq. (18) holds by construction, so the loop j is empty.
 * Mechanics solved at f^n (the paper also holds the strain fixed during the
   phase-field solve, Sec. 2.2).
 * No clipping of f.

@@ -1,7 +1,7 @@
 """Fourier-space conventions and the Green's operator (oracle, test only).
 
-Table 1, step 8, and Sec. 3 solve the linearised phase-field equation "in FFT
-space" on a periodic regular grid (Sec. 4.2). The paper states no
+Table 1 and Sec. 3 solve the linearised phase-field equation in Fourier space
+on a periodic regular grid (Sec. 4.2). The paper states no
 normalisation or wavevector convention; the readings used here:
 
 * fields are stored [z][y][x]; the real-to-complex transform halves x, so a

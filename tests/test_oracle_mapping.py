@@ -1,5 +1,5 @@
-"""Pins of the oracle's FE <-> FFT mapping by nearest Gauss point (Sec. 3,
-Table 1's last step; compared with interpolation in Sec. 5).
+"""Pins of the oracle's FE <-> FFT mapping by nearest Gauss point (Sec. 3 and
+Table 1; compared with interpolation in Sec. 5).
 
 * Points placed at cell centres own those cells (distance 0).
 * Two points on a line along x split the grid at their bisector; a cell

@@ -1,6 +1,6 @@
 """Pins of the oracle's FFT conventions and Green's operator.
 
-FFT conventions (the paper solves in "FFT space", Table 1 step 8, and is
+FFT conventions (the paper solves in Fourier space, Table 1, and is
 silent on normalisation) are pinned against a naive DFT written out; the
 Green's operator (textbook Moulinec-Suquet / Mura; the paper has none) is
 pinned by the projection identity, the isotropic closed form and the
