@@ -341,8 +341,10 @@ def bench_surrogate(args):
     torch.cuda.set_device(dev)
     train_batch = inputs.rve_batch()
     trajs, conds = surrogate.generate_trajectories(binding, torch, train_batch, dev, log=log)
-    model = surrogate.make_model(torch).to(dev)
+    native = args.train_conv == "native"
+    model = surrogate.make_model(torch, native=native).to(dev)
     info = surrogate.train(torch, model, trajs, conds, seconds=args.train_seconds, log=log)
+    info["spectral_conv"] = "library kernels (pf_specconv)" if native else "torch.fft"
     del trajs
     torch.cuda.empty_cache()
     params = surrogate.to_params(model)
@@ -574,6 +576,8 @@ def main():
     ap.add_argument("--train-seconds", type=float, default=240.0)
     ap.add_argument("--eval-instances", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-3, help="acceptance residual of the learned stepper")
+    ap.add_argument("--train-conv", choices=("native", "torch"), default="native",
+                    help="surrogate training: spectral convolution in the library's kernels or in torch.fft")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")

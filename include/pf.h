@@ -239,6 +239,31 @@ int pf_fft(pf_ctx *ctx, int32_t direction, int32_t ncomp, float *real, void *spe
 #define PF_TUNE_RETIME 1u
 int pf_autotune(pf_ctx *ctx, const char *cache_path, uint32_t flags, int32_t *n_timed);
 
+/* Spectral convolution of the learned stepper for training (the layers
+ * v_l = GELU(W v + b + K v) of a Fourier neural operator; K v keeps 2m x 2m x m
+ * modes: kx < m, ky and kz in [0, m) u [n - m, n), positive then negative).
+ * Batches of B samples with C channels, channel-first FP32 device arrays:
+ * v, y, dy, dv [B][C][nz][ny][nx]; S, M, G [B][C][2m][2m][m] complex64
+ * (re, im interleaved); R, dR [C][C][2m][2m][m] complex64, [out][in][kz'][ky'][kx].
+ *   forward:  S = kept modes of rfftn(v), M = R S per mode,
+ *             y = irfftn(M placed on the kept modes) = K v;
+ *   backward: G = c(kx)/N kept modes of rfftn(dy) (c = 1 on kx = 0, else 2),
+ *             dR = sum_b G conj(S) (dL/dRe R + i dL/dIm R for L with
+ *             dL/dy = dy), M = R^H G, dv = sum over kept modes
+ *             Re[M e^{+i k.x}] (= dL/dv), given S from the forward call.
+ * Sizes: 1 <= B <= 64, 1 <= C <= 256, axes 4..256, 2m < nx, 2m <= ny, nz.
+ * work: pf_specconv_workspace_size bytes of device memory. Enqueued on
+ * hip_stream (NULL: the null stream); PF_EINVAL for bad sizes or NULL
+ * pointers, PF_ENOMEM for a short work buffer. */
+int pf_specconv_workspace_size(int32_t B, int32_t C, int32_t nx, int32_t ny, int32_t nz, int32_t m,
+                               size_t *bytes);
+int pf_specconv_forward(int32_t B, int32_t C, int32_t nx, int32_t ny, int32_t nz, int32_t m,
+                        const float *v, const float *R, float *S, float *M, float *y, void *work,
+                        size_t work_bytes, void *hip_stream);
+int pf_specconv_backward(int32_t B, int32_t C, int32_t nx, int32_t ny, int32_t nz, int32_t m,
+                         const float *dy, const float *R, const float *S, float *G, float *M, float *dv,
+                         float *dR, void *work, size_t work_bytes, void *hip_stream);
+
 /* Plan of the group holding instance inst: *ytile the y-pass tile, *ztile the
  * spectral z-pass tile (0 if the group never takes that path). */
 int pf_batch_plan(pf_ctx *ctx, int32_t inst, int32_t *ytile, int32_t *ztile);

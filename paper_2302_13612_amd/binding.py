@@ -107,6 +107,10 @@ def load():
                                     ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32)]
     lib.pf_profile_select.argtypes = [vp, ctypes.c_char_p]
     lib.pf_autotune.argtypes = [vp, ctypes.c_char_p, u32, ctypes.POINTER(i32)]
+    sz = ctypes.c_size_t
+    lib.pf_specconv_workspace_size.argtypes = [i32] * 6 + [ctypes.POINTER(sz)]
+    lib.pf_specconv_forward.argtypes = [i32] * 6 + [vp] * 6 + [sz, vp]
+    lib.pf_specconv_backward.argtypes = [i32] * 6 + [vp] * 8 + [sz, vp]
     lib.pf_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pf_vmap_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pf_vmap_build.argtypes = [i32, i32, i32, ctypes.c_double, i32, vp, vp, ctypes.c_size_t, vp, vp]
@@ -721,3 +725,76 @@ class VoronoiMap:
         if rc != PF_OK:
             raise PfError(rc, "pf_vmap_to_points")
         return out
+
+
+def spectral_conv(v, R, m):
+    """K v of a Fourier layer through the library's training kernels, with
+    their backward pass: v (B, C, nz, ny, nx) float32 CUDA, R the layer's
+    (C, C, 2m, 2m, m, 2) float32 (real, imaginary) weights. Differentiable in
+    v and R (pf_specconv_forward / pf_specconv_backward)."""
+    return _spectral_conv_fn().apply(v, R, m)
+
+
+_SPEC_FN = None
+
+
+def _spectral_conv_fn():
+    global _SPEC_FN
+    if _SPEC_FN is not None:
+        return _SPEC_FN
+    import torch
+
+    def dims(v, m):
+        B, C, nz, ny, nx = v.shape
+        return [int(B), int(C), int(nx), int(ny), int(nz), int(m)]
+
+    def work_for(lib, d, dev):
+        n = ctypes.c_size_t()
+        rc = lib.pf_specconv_workspace_size(*d, ctypes.byref(n))
+        if rc != PF_OK:
+            raise PfError(rc, f"pf_specconv_workspace_size{tuple(d)}")
+        return torch.empty(n.value, dtype=torch.uint8, device=dev), n.value
+
+    class SpectralConv(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, v, R, m):
+            lib = load()
+            if v.dtype != torch.float32 or R.dtype != torch.float32 or not v.is_cuda or not R.is_cuda:
+                raise ValueError("spectral_conv needs float32 CUDA tensors")
+            v, R = v.contiguous(), R.contiguous()
+            d = dims(v, m)
+            B, C = d[0], d[1]
+            work, nbytes = work_for(lib, d, v.device)
+            S = torch.empty((B, C, 2 * m, 2 * m, m, 2), dtype=torch.float32, device=v.device)
+            M = torch.empty_like(S)
+            y = torch.empty_like(v)
+            stream = torch.cuda.current_stream(v.device).cuda_stream
+            rc = lib.pf_specconv_forward(*d, v.data_ptr(), R.data_ptr(), S.data_ptr(), M.data_ptr(), y.data_ptr(),
+                                         work.data_ptr(), nbytes, ctypes.c_void_p(stream))
+            if rc != PF_OK:
+                raise PfError(rc, "pf_specconv_forward")
+            ctx.save_for_backward(R, S)
+            ctx.m = m
+            return y
+
+        @staticmethod
+        def backward(ctx, dy):
+            lib = load()
+            R, S = ctx.saved_tensors
+            dy = dy.contiguous()
+            d = dims(dy, ctx.m)
+            work, nbytes = work_for(lib, d, dy.device)
+            G = torch.empty_like(S)
+            M = torch.empty_like(S)
+            dv = torch.empty_like(dy)
+            dR = torch.empty_like(R)
+            stream = torch.cuda.current_stream(dy.device).cuda_stream
+            rc = lib.pf_specconv_backward(*d, dy.data_ptr(), R.data_ptr(), S.data_ptr(), G.data_ptr(),
+                                          M.data_ptr(), dv.data_ptr(), dR.data_ptr(), work.data_ptr(), nbytes,
+                                          ctypes.c_void_p(stream))
+            if rc != PF_OK:
+                raise PfError(rc, "pf_specconv_backward")
+            return dv, dR, None
+
+    _SPEC_FN = SpectralConv
+    return _SPEC_FN

@@ -3,7 +3,9 @@
 Training is an off-line procedure beside the stepping path: trajectories of
 the batched ensemble (single-crystal cubes of edge 32-96, one twin variant
 each, homogeneous stiffness) come from the library's batched spectral path;
-the network is fitted with PyTorch autograd in FP32 on the GPU; the weights
+the network is fitted in FP32 on the GPU, the spectral convolution of every
+layer (forward and backward) in the library's training kernels
+(pf_specconv_*) and the pointwise parts by PyTorch autograd; the weights
 are then handed to the library (pf_fno_init), whose forward pass, acceptance
 residual and fallback run in HIP.
 
@@ -66,7 +68,10 @@ def generate_trajectories(binding, torch, batch, device, log=print):
     return trajs, conds
 
 
-def make_model(torch, width=32, modes=12, hidden=128, n_layers=4, n_cond=7, seed=0):
+def make_model(torch, width=32, modes=12, hidden=128, n_layers=4, n_cond=7, seed=0, native=False):
+    """The training model. native: the spectral convolution of every layer
+    (forward and backward) runs in the library's kernels (binding.spectral_conv);
+    otherwise in torch.fft."""
     nn = torch.nn
     F = torch.nn.functional
 
@@ -99,13 +104,17 @@ def make_model(torch, width=32, modes=12, hidden=128, n_layers=4, n_cond=7, seed
             v = self.P[:, 0].view(1, -1, 1, 1, 1) * eta[:, None] + const[:, :, None, None, None]
             iz, iy = kept(nz, m, eta.device), kept(ny, m, eta.device)
             for l in range(self.W.shape[0]):
-                Vh = torch.fft.rfftn(v, dim=(2, 3, 4))
-                sub = Vh[:, :, iz][:, :, :, iy][..., :m]
-                Rc = torch.view_as_complex(self.R[l])
-                out_sub = torch.einsum("bizyx,oizyx->bozyx", sub, Rc)
-                spec = torch.zeros((B, Rc.shape[0], nz, ny, nx // 2 + 1), dtype=Vh.dtype, device=eta.device)
-                spec[:, :, iz[:, None], iy[None, :], :m] = out_sub
-                kv = torch.fft.irfftn(spec, s=(nz, ny, nx), dim=(2, 3, 4))
+                if native:
+                    from . import binding
+                    kv = binding.spectral_conv(v, self.R[l], m)
+                else:
+                    Vh = torch.fft.rfftn(v, dim=(2, 3, 4))
+                    sub = Vh[:, :, iz][:, :, :, iy][..., :m]
+                    Rc = torch.view_as_complex(self.R[l])
+                    out_sub = torch.einsum("bizyx,oizyx->bozyx", sub, Rc)
+                    spec = torch.zeros((B, Rc.shape[0], nz, ny, nx // 2 + 1), dtype=Vh.dtype, device=eta.device)
+                    spec[:, :, iz[:, None], iy[None, :], :m] = out_sub
+                    kv = torch.fft.irfftn(spec, s=(nz, ny, nx), dim=(2, 3, 4))
                 local = torch.einsum("oi,bizyx->bozyx", self.W[l], v) + self.b[l].view(1, -1, 1, 1, 1)
                 v = F.gelu(local + kv)
             h = F.gelu(torch.einsum("hi,bizyx->bhzyx", self.Q1, v) + self.q1.view(1, -1, 1, 1, 1))

@@ -177,3 +177,15 @@ def test_autotune_arguments():
     assert lib.pf_autotune(None, None, 0, ctypes.byref(n)) == binding.PF_EINVAL
     y, z = ctypes.c_int32(), ctypes.c_int32()
     assert lib.pf_batch_plan(None, 0, ctypes.byref(y), ctypes.byref(z)) == binding.PF_EINVAL
+
+
+def test_specconv_sizes():
+    lib = binding.load()
+    n = ctypes.c_size_t()
+    assert lib.pf_specconv_workspace_size(2, 32, 128, 128, 128, 12, ctypes.byref(n)) == binding.PF_OK
+    assert n.value >= 8 * (2 * 32 * 128 * 128 * 12 + 2 * 32 * 128 * 24 * 12)
+    for bad in ((0, 32, 128, 128, 128, 12), (2, 32, 24, 128, 128, 12), (2, 32, 128, 20, 128, 12),
+                (2, 32, 512, 128, 128, 12), (2, 32, 128, 128, 128, 0)):
+        assert lib.pf_specconv_workspace_size(*bad, ctypes.byref(n)) == binding.PF_EINVAL, bad
+    assert lib.pf_specconv_forward(2, 4, 16, 16, 16, 3, None, None, None, None, None, None, 0, None) == \
+        binding.PF_EINVAL

@@ -24,9 +24,10 @@ def test_torch_model_matches_oracle_forward():
     np.testing.assert_array_equal(back["R"], p["R"])
 
 
-def _grad_case(torch, device, dtype, seed=3):
+def _grad_case(torch, device, dtype, seed=3, native=False):
     p = ofno.init_params(width=8, modes=3, hidden=10, n_layers=2, seed=seed, scale_spec=0.2)
-    model = surrogate.make_model(torch, width=8, modes=3, hidden=10, n_layers=2).to(device=device, dtype=dtype)
+    model = surrogate.make_model(torch, width=8, modes=3, hidden=10, n_layers=2, native=native)
+    model = model.to(device=device, dtype=dtype)
     surrogate.load_params(model, p, torch)
     rng = np.random.default_rng(seed + 1)
     eta = rng.random((16, 12, 10))
