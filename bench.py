@@ -341,14 +341,21 @@ def bench_surrogate(args):
     torch.cuda.set_device(dev)
     train_batch = inputs.rve_batch()
     trajs, conds = surrogate.generate_trajectories(binding, torch, train_batch, dev, log=log)
-    native = args.train_conv == "native"
-    model = surrogate.make_model(torch, native=native).to(dev)
-    info = surrogate.train(torch, model, trajs, conds, seconds=args.train_seconds, log=log)
-    info["spectral_conv"] = "library kernels (pf_specconv)" if native else "torch.fft"
-    del trajs
+    model = surrogate.make_model(torch, native=args.trainer == "autograd").to(dev)
+    if args.trainer == "native":
+        # the same initial weights, trained by the library's kernels alone
+        trainer = surrogate.NativeTrainer(torch, binding, surrogate.to_params(model), dev)
+        info = surrogate.train_native(torch, trainer, trajs, conds, seconds=args.train_seconds, log=log)
+        params = trainer.params()
+        del trainer
+    else:
+        info = surrogate.train(torch, model, trajs, conds, seconds=args.train_seconds, log=log)
+        params = surrogate.to_params(model)
+    info["trainer"] = {"native": "library kernels (forward, backward, Adam)",
+                       "autograd": "PyTorch autograd, spectral convolution in library kernels",
+                       "torch": "PyTorch autograd with torch.fft"}[args.trainer]
+    del trajs, model
     torch.cuda.empty_cache()
-    params = surrogate.to_params(model)
-    del model
     held = inputs.rve_batch(n_inst=args.eval_instances, seed=99, sizes=(128,))
     calls, per = held["steps"] // 16, 16
     results = []
@@ -576,8 +583,9 @@ def main():
     ap.add_argument("--train-seconds", type=float, default=240.0)
     ap.add_argument("--eval-instances", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-3, help="acceptance residual of the learned stepper")
-    ap.add_argument("--train-conv", choices=("native", "torch"), default="native",
-                    help="surrogate training: spectral convolution in the library's kernels or in torch.fft")
+    ap.add_argument("--trainer", choices=("native", "autograd", "torch"), default="native",
+                    help="surrogate training: the library's kernels alone; PyTorch autograd with the library's "
+                         "spectral convolution; or PyTorch autograd with torch.fft")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")

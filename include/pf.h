@@ -264,6 +264,48 @@ int pf_specconv_backward(int32_t B, int32_t C, int32_t nx, int32_t ny, int32_t n
                          const float *dy, const float *R, const float *S, float *G, float *M, float *dv,
                          float *dR, void *work, size_t work_bytes, void *hip_stream);
 
+/* Pointwise parts of the learned stepper's training and its optimiser (FP32,
+ * channel-first device arrays [B][channels][nvox], nvox = nz ny nx; C in
+ * {4, 8, 16, 32, 64}, H <= 128; the network of the stepper: v_0 = P [f, c] + p
+ * with 7 conditioning values c per sample, v_l = GELU(u_l), u_l = W_l v + b_l
+ * + K_l v, f~ = f + Q2 GELU(Q1 v_L + q1) + q2). Parameters as the stepper
+ * holds them: P [C][8], W [C][C] (out, in), Q1 [H][C], Q2 [H]. All enqueued on
+ * stream (NULL: the null stream); PF_EINVAL for bad sizes or NULL pointers.
+ *   pf_nt_lift:            v0 = P [f, cond] + p
+ *   pf_nt_layer_forward:   u = W v + bias + kv, vout = GELU(u)
+ *   pf_nt_project_forward: z = Q1 v + q1 (kept), out = f + Q2 GELU(z) + q2
+ *   pf_nt_project_backward: for the loss sum of (out - target)^2 times
+ *       scale / 2, g = scale (out - target), dz = g Q2 GELU'(z), hg = GELU(z),
+ *       dv = Q1^T dz
+ *   pf_nt_gelu_backward:   du = dvout GELU'(u) over n values
+ *   pf_nt_layer_input_grad: dv = W^T du + dvs
+ *   pf_nt_outer_sum:       out[a][c] (+)= sum over samples and voxels of
+ *       X[b][a][i] Y[b][c][i] (Y NULL: 1), a < MA, c < MC; work of
+ *       pf_nt_outer_workspace bytes (per-chunk partials, added in a fixed order)
+ *   pf_nt_cond_grad:       dP[c][1 + j] = sum_b dK[b][c] cond[b][j],
+ *       dp[c] = sum_b dK[b][c] (dK: per-sample channel sums of dv0)
+ *   pf_nt_adam:            Adam with bias correction, step >= 1 */
+int pf_nt_lift(int32_t B, int32_t C, int64_t nvox, const float *P, const float *p, const float *f,
+               const float *cond, float *v0, void *stream);
+int pf_nt_layer_forward(int32_t B, int32_t C, int64_t nvox, const float *W, const float *bias,
+                        const float *v, const float *kv, float *u, float *vout, void *stream);
+int pf_nt_project_forward(int32_t B, int32_t C, int32_t H, int64_t nvox, const float *Q1,
+                          const float *q1, const float *Q2, float q2, const float *v, const float *f,
+                          float *z, float *out, void *stream);
+int pf_nt_project_backward(int32_t B, int32_t C, int32_t H, int64_t nvox, const float *Q1,
+                           const float *Q2, const float *z, const float *out, const float *target,
+                           float scale, float *g, float *dz, float *hg, float *dv, void *stream);
+int pf_nt_gelu_backward(int64_t n, const float *dvout, const float *u, float *du, void *stream);
+int pf_nt_layer_input_grad(int32_t B, int32_t C, int64_t nvox, const float *W, const float *du,
+                           const float *dvs, float *dv, void *stream);
+int pf_nt_outer_workspace(int32_t B, int32_t MA, int32_t MC, int64_t nvox, size_t *bytes);
+int pf_nt_outer_sum(int32_t B, int32_t MA, int32_t MC, int64_t nvox, const float *X, const float *Y,
+                    float *out, int32_t accumulate, float *work, size_t work_bytes, void *stream);
+int pf_nt_cond_grad(int32_t B, int32_t C, const float *dK, const float *cond, float *dP, float *dp,
+                    void *stream);
+int pf_nt_adam(int64_t n, float *w, const float *g, float *m, float *v, float lr, float beta1,
+               float beta2, float eps, int32_t step, void *stream);
+
 /* Plan of the group holding instance inst: *ytile the y-pass tile, *ztile the
  * spectral z-pass tile (0 if the group never takes that path). */
 int pf_batch_plan(pf_ctx *ctx, int32_t inst, int32_t *ytile, int32_t *ztile);

@@ -111,6 +111,17 @@ def load():
     lib.pf_specconv_workspace_size.argtypes = [i32] * 6 + [ctypes.POINTER(sz)]
     lib.pf_specconv_forward.argtypes = [i32] * 6 + [vp] * 6 + [sz, vp]
     lib.pf_specconv_backward.argtypes = [i32] * 6 + [vp] * 8 + [sz, vp]
+    i64, f32 = ctypes.c_int64, ctypes.c_float
+    lib.pf_nt_lift.argtypes = [i32, i32, i64] + [vp] * 6
+    lib.pf_nt_layer_forward.argtypes = [i32, i32, i64] + [vp] * 7
+    lib.pf_nt_project_forward.argtypes = [i32, i32, i32, i64, vp, vp, vp, f32, vp, vp, vp, vp, vp]
+    lib.pf_nt_project_backward.argtypes = [i32, i32, i32, i64, vp, vp, vp, vp, vp, f32, vp, vp, vp, vp, vp]
+    lib.pf_nt_gelu_backward.argtypes = [i64, vp, vp, vp, vp]
+    lib.pf_nt_layer_input_grad.argtypes = [i32, i32, i64] + [vp] * 5
+    lib.pf_nt_outer_workspace.argtypes = [i32, i32, i32, i64, ctypes.POINTER(sz)]
+    lib.pf_nt_outer_sum.argtypes = [i32, i32, i32, i64, vp, vp, vp, i32, vp, sz, vp]
+    lib.pf_nt_cond_grad.argtypes = [i32, i32] + [vp] * 5
+    lib.pf_nt_adam.argtypes = [i64, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
     lib.pf_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pf_vmap_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pf_vmap_build.argtypes = [i32, i32, i32, ctypes.c_double, i32, vp, vp, ctypes.c_size_t, vp, vp]

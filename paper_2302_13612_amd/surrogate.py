@@ -16,6 +16,7 @@ v <- GELU(W v + b + K v) with 12 kept modes per signed axis, projection
 / gamma_tw, applied strain / 5e-3).
 """
 
+import ctypes
 import time
 
 import numpy as np
@@ -141,6 +142,41 @@ def load_params(model, params, torch):
         model.R.copy_(torch.as_tensor(np.stack([R.real, R.imag], axis=-1)))
 
 
+def train_native(torch, trainer, trajs, conds, seconds=240.0, lr=2e-3, batch_size=4, seed=0, log=print):
+    """The schedule of train() (mini-batches of one instance size, pairs of
+    snapshots k, k + 1, cosine-decayed rate, wall-clock budget) with a
+    NativeTrainer: every forward, backward and Adam kernel is the library's."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    dev = trajs[0].device
+    by_size = {}
+    for i, tr in enumerate(trajs):
+        by_size.setdefault(tuple(tr.shape[1:]), []).append(i)
+    cond_t = torch.as_tensor(conds, dtype=torch.float32, device=dev)
+    t0 = time.perf_counter()
+    it, hist = 0, []
+    while True:
+        el = time.perf_counter() - t0
+        if el > seconds:
+            break
+        rate = lr * 0.5 * (1 + np.cos(np.pi * min(1.0, el / seconds)))
+        shape = list(by_size)[rng.integers(len(by_size))]
+        members = by_size[shape]
+        pick = [(members[rng.integers(len(members))], int(rng.integers(trajs[0].shape[0] - 1)))
+                for _ in range(batch_size)]
+        x = torch.stack([trajs[i][k] for i, k in pick])
+        y = torch.stack([trajs[i][k + 1] for i, k in pick])
+        c = cond_t[[i for i, _ in pick]].contiguous()
+        _, loss = trainer.gradients(x, c, y)
+        trainer.adam(rate)
+        hist.append(loss)
+        it += 1
+        if it % 200 == 0:
+            log(f"  iter {it} ({el:.0f} s) loss {np.mean(hist[-200:]):.3e}")
+    log(f"trained {it} iterations in {time.perf_counter() - t0:.0f} s (library kernels), "
+        f"last loss {np.mean(hist[-50:]):.3e}")
+    return {"iterations": it, "final_loss": float(np.mean(hist[-50:])) if hist else None}
+
+
 def train(torch, model, trajs, conds, seconds=240.0, lr=2e-3, batch_size=4, seed=0, log=print):
     """Adam on MSE of the macro-step increment, pairs (snapshot k, k+1) of
     every instance, mini-batches of one instance size, cosine-decayed rate,
@@ -180,3 +216,141 @@ def train(torch, model, trajs, conds, seconds=240.0, lr=2e-3, batch_size=4, seed
     log(f"trained {it} iterations in {time.perf_counter() - t0:.0f} s, last loss {np.mean(hist[-50:]):.3e}")
     del pairs
     return {"iterations": it, "final_loss": float(np.mean(hist[-50:])) if hist else None}
+
+
+class NativeTrainer:
+    """Training of the stepper in the library's kernels alone: forward and
+    backward of the lift, the Fourier layers (spectral convolution:
+    pf_specconv_*, pointwise part: pf_nt_layer_*), the projection and the
+    mean-square loss, weight gradients as outer sums over samples and voxels
+    (pf_nt_outer_sum), Adam (pf_nt_adam). PyTorch holds the device memory and
+    orders nothing: every call goes on the current stream.
+
+    params: float64 numpy dict as the checker's init_params / to_params
+    (R complex); mini-batches of one grid size, eta (B, nz, ny, nx) and the
+    target float32 CUDA, cond (B, 7) float32 CUDA."""
+
+    KEYS = ("P", "p", "W", "b", "R", "Q1", "q1", "Q2", "q2")
+
+    def __init__(self, torch, binding, params, device):
+        self.t, self.bd, self.lib = torch, binding, binding.load()
+        self.dev = torch.device(device)
+        f32 = dict(dtype=torch.float32, device=self.dev)
+        R = np.asarray(params["R"])
+        self.w = {k: torch.as_tensor(np.asarray(params[k], dtype=np.float64), **f32).contiguous()
+                  for k in self.KEYS if k != "R"}
+        self.w["R"] = torch.as_tensor(np.stack([R.real, R.imag], axis=-1), **f32).contiguous()
+        self.w["q2"] = self.w["q2"].reshape(1)
+        self.w["Q2"] = self.w["Q2"].reshape(-1)
+        self.g = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        self.m1 = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        self.m2 = {k: torch.zeros_like(v) for k, v in self.w.items()}
+        self.C = self.w["W"].shape[1]
+        self.L = self.w["W"].shape[0]
+        self.H = self.w["Q1"].shape[0]
+        self.m = self.w["R"].shape[-2]
+        self.steps = 0
+
+    def _ok(self, rc, what):
+        if rc != 0:
+            raise self.bd.PfError(rc, what)
+
+    def _stream(self):
+        return ctypes.c_void_p(self.t.cuda.current_stream(self.dev).cuda_stream)
+
+    def _outer(self, B, MA, MC, nvox, X, Y, out):
+        n = ctypes.c_size_t()
+        self._ok(self.lib.pf_nt_outer_workspace(B, MA, MC, nvox, ctypes.byref(n)), "pf_nt_outer_workspace")
+        if getattr(self, "_ow", None) is None or self._ow.numel() * 4 < n.value:
+            self._ow = self.t.empty((n.value + 3) // 4, dtype=self.t.float32, device=self.dev)
+        self._ok(self.lib.pf_nt_outer_sum(B, MA, MC, nvox, X.data_ptr(), Y.data_ptr() if Y is not None else None,
+                                          out.data_ptr(), 0, self._ow.data_ptr(), self._ow.numel() * 4,
+                                          self._stream()), "pf_nt_outer_sum")
+
+    def gradients(self, eta, cond, target):
+        """Forward pass, loss mean((f~ - target)^2) and every parameter
+        gradient into self.g; returns (prediction, loss)."""
+        t, lib, w, st = self.t, self.lib, self.w, self._stream()
+        B, nz, ny, nx = eta.shape
+        nvox = nz * ny * nx
+        C, H, L, m = self.C, self.H, self.L, self.m
+        eta, cond, target = eta.contiguous(), cond.contiguous(), target.contiguous()
+        f32 = dict(dtype=t.float32, device=self.dev)
+        v = [t.empty((B, C, nz, ny, nx), **f32) for _ in range(L + 1)]
+        u = [t.empty((B, C, nz, ny, nx), **f32) for _ in range(L)]
+        S = [t.empty((B, C, 2 * m, 2 * m, m, 2), **f32) for _ in range(L)]
+        Mb = t.empty((B, C, 2 * m, 2 * m, m, 2), **f32)
+        kv = t.empty((B, C, nz, ny, nx), **f32)
+        d = [B, C, nx, ny, nz, m]
+        n = ctypes.c_size_t()
+        self._ok(lib.pf_specconv_workspace_size(*d, ctypes.byref(n)), "pf_specconv_workspace_size")
+        work = t.empty(n.value, dtype=t.uint8, device=self.dev)
+        self._ok(lib.pf_nt_lift(B, C, nvox, w["P"].data_ptr(), w["p"].data_ptr(), eta.data_ptr(), cond.data_ptr(),
+                                v[0].data_ptr(), st), "pf_nt_lift")
+        for l in range(L):
+            self._ok(lib.pf_specconv_forward(*d, v[l].data_ptr(), w["R"][l].data_ptr(), S[l].data_ptr(),
+                                             Mb.data_ptr(), kv.data_ptr(), work.data_ptr(), n.value, st),
+                     "pf_specconv_forward")
+            self._ok(lib.pf_nt_layer_forward(B, C, nvox, w["W"][l].data_ptr(), w["b"][l].data_ptr(),
+                                             v[l].data_ptr(), kv.data_ptr(), u[l].data_ptr(), v[l + 1].data_ptr(),
+                                             st), "pf_nt_layer_forward")
+        z = t.empty((B, H, nz, ny, nx), **f32)
+        out = t.empty((B, nz, ny, nx), **f32)
+        self._ok(lib.pf_nt_project_forward(B, C, H, nvox, w["Q1"].data_ptr(), w["q1"].data_ptr(), w["Q2"].data_ptr(),
+                                           float(w["q2"][0]), v[L].data_ptr(), eta.data_ptr(), z.data_ptr(),
+                                           out.data_ptr(), st), "pf_nt_project_forward")
+        scale = 2.0 / (B * nvox)
+        g = t.empty((B, nz, ny, nx), **f32)
+        dz = t.empty_like(z)
+        hg = t.empty_like(z)
+        dv = t.empty((B, C, nz, ny, nx), **f32)
+        self._ok(lib.pf_nt_project_backward(B, C, H, nvox, w["Q1"].data_ptr(), w["Q2"].data_ptr(), z.data_ptr(),
+                                            out.data_ptr(), target.data_ptr(), scale, g.data_ptr(), dz.data_ptr(),
+                                            hg.data_ptr(), dv.data_ptr(), st), "pf_nt_project_backward")
+        gr = self.g
+        self._outer(B, H, 1, nvox, hg, g, gr["Q2"])
+        self._outer(B, 1, 1, nvox, g, None, gr["q2"])
+        self._outer(B, H, C, nvox, dz, v[L], gr["Q1"])
+        self._outer(B, H, 1, nvox, dz, None, gr["q1"])
+        del z, dz, hg
+        du = t.empty_like(dv)
+        dvs = t.empty_like(dv)
+        G = t.empty_like(Mb)
+        for l in reversed(range(L)):
+            self._ok(lib.pf_nt_gelu_backward(dv.numel(), dv.data_ptr(), u[l].data_ptr(), du.data_ptr(), st),
+                     "pf_nt_gelu_backward")
+            self._outer(B, C, C, nvox, du, v[l], gr["W"][l])
+            self._outer(B, C, 1, nvox, du, None, gr["b"][l])
+            self._ok(lib.pf_specconv_backward(*d, du.data_ptr(), w["R"][l].data_ptr(), S[l].data_ptr(),
+                                              G.data_ptr(), Mb.data_ptr(), dvs.data_ptr(), gr["R"][l].data_ptr(),
+                                              work.data_ptr(), n.value, st), "pf_specconv_backward")
+            self._ok(lib.pf_nt_layer_input_grad(B, C, nvox, w["W"][l].data_ptr(), du.data_ptr(), dvs.data_ptr(),
+                                                dv.data_ptr(), st), "pf_nt_layer_input_grad")
+        # lift: dP[:, 0] from f, the conditioning columns and p from per-sample channel sums
+        col0 = t.empty((C, 1), **f32)
+        self._outer(B, C, 1, nvox, dv, eta, col0)
+        dK = t.empty((B, C), **f32)
+        for b in range(B):
+            self._outer(1, C, 1, nvox, dv[b], None, dK[b])
+        self._ok(lib.pf_nt_cond_grad(B, C, dK.data_ptr(), cond.data_ptr(), gr["P"].data_ptr(), gr["p"].data_ptr(),
+                                     st), "pf_nt_cond_grad")
+        gr["P"][:, 0] = col0[:, 0]
+        loss = float(t.mean((out - target) ** 2))
+        return out, loss
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.steps += 1
+        st = self._stream()
+        for k in self.KEYS:
+            self._ok(self.lib.pf_nt_adam(self.w[k].numel(), self.w[k].data_ptr(), self.g[k].data_ptr(),
+                                         self.m1[k].data_ptr(), self.m2[k].data_ptr(), lr, beta1, beta2, eps,
+                                         self.steps, st), "pf_nt_adam")
+
+    def params(self):
+        """float64 numpy dict in the checker's layout (R complex)."""
+        gt = lambda x: x.detach().double().cpu().numpy()  # noqa: E731
+        out = {k: gt(v) for k, v in self.w.items() if k != "R"}
+        R = gt(self.w["R"])
+        out["R"] = R[..., 0] + 1j * R[..., 1]
+        out["Q2"] = out["Q2"].reshape(1, -1)
+        return out
