@@ -136,7 +136,7 @@ def cpu_info():
     return cores, model
 
 
-def cpu_baseline(n=96, steps=1, pf_max_iter=1, pf_tol=1e-6):
+def cpu_baseline(n=128, steps=1, pf_max_iter=1, pf_tol=1e-6):
     """The FP64 oracle, as it stands, on the same recipe at n^3 (a bounded
     sample of the workload), in voxel-updates/s."""
     from oracle import crystal as cr
@@ -590,7 +590,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=96)
+    ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--aniso", action="store_true",
                     help="rve-batch: anisotropic gradient energy of Table 5 for every instance")
     ap.add_argument("--pf-max-iter", type=int, default=1,
