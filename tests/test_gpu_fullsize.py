@@ -1,0 +1,101 @@
+"""GPU: the 256^3 polycrystal step (6 variants, 64 grains), the workload the
+benchmark times, checked at full size through the oracle's own steps.
+
+The FP64 oracle cannot run a whole 256^3 step inside a test, so the GPU's
+results are checked through properties the step fixes at any size, each
+evaluated by the oracle in FP64 on the GPU's fields:
+
+* constitutive law and eigenstrain (eq. (5)): the stress the library saved
+  equals C(x) : (eps - eps*) of the strain it returned (stress rel-L2);
+* equilibrium: one further Moulinec-Suquet iteration of the oracle, started
+  from the returned strain, changes it by no more than the solver tolerance
+  (relative Frobenius norm, the oracle's own criterion), i.e. the strain is
+  the oracle's fixed point; the strain-controlled mean holds the load and the
+  stress-controlled mean stresses vanish;
+* the Allen-Cahn update (eqs. (17), (19)-(20)): the oracle's update of the
+  initial state with the stress and elastic strain of that equilibrium equals
+  the library's new order parameters element by element (max-abs <= 1e-4).
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from oracle import mech
+from oracle import phasefield as opf
+from paper_2302_13612_amd import inputs
+from tests import cases
+
+pytestmark = pytest.mark.gpu
+
+ETA_TOL = 1e-4
+SIG_TOL = 1e-5
+
+
+def oracle_checks(cfg, eps6, sig6, eta1):
+    """FP64 checks of one step from the recipe's initial state, given the
+    library's equilibrium strain and stress (tensor-Voigt, (6, nz, ny, nx))
+    and its new order parameters (V, nz, ny, nx)."""
+    t0 = time.time()
+    prob = cases.oracle_problem(cfg, tol=cfg["ms_tol"])
+    C_grain, C_var, eps0 = prob.tables
+    eta0 = cfg["eta0"].astype(np.float64)
+    shape = cfg["shape"]
+    eps = mech.voigt6_to_tensor(np.asarray(eps6, np.float64))
+    eps_p = (np.zeros(shape + (3, 3)) if cfg["eps_p"] is None
+             else mech.voigt6_to_tensor(cfg["eps_p"].astype(np.float64)))
+    _, eps_el, sigma = mech.eigenstrain_and_stress(eps, eta0, eps_p, prob.gid, C_grain, C_var, eps0,
+                                                   prob.h_kind)
+    out = {"sig_rel_l2": cases.stress_rel_l2(sig6, mech.tensor_to_voigt6(sigma))}
+    # one more fixed-point iteration from the returned strain
+    mask = cfg["stress_mask"]
+    ebar = eps.mean(axis=(0, 1, 2))
+    sbar = sigma.mean(axis=(0, 1, 2))
+    M0 = mech.strain_to_stress_voigt(prob.green.C0)
+    ebar_new = mech.mean_update(ebar, sbar, cfg["eps_bar"], cfg["sig_bar"], mask, M0)
+    deps = -mech.ifft_tensor(prob.green.apply(mech.fft_tensor(sigma)), prob.green.shape)
+    eps_new = eps + deps + (ebar_new - ebar)
+    out["ms_change"] = float(np.linalg.norm(eps_new - eps) / np.linalg.norm(eps_new))
+    del deps, eps_new
+    e6 = mech.tensor_to_voigt6(ebar)
+    s6 = mech.tensor_to_voigt6(sbar)
+    strain_ctl = [i for i in range(6) if not mask[i]]
+    stress_ctl = [i for i in range(6) if mask[i]]
+    out["mean_strain_err"] = float(np.abs(e6[strain_ctl] - np.asarray(cfg["eps_bar"])[strain_ctl]).max())
+    out["mean_stress_rel"] = float(np.abs(s6[stress_ctl] - np.asarray(cfg["sig_bar"])[stress_ctl]).max()
+                                   / np.abs(sigma).max())
+    # the update of the initial state with this equilibrium
+    chem = opf.chemical_force(eta0, prob.A)
+    mech_f = opf.mechanical_force(eta0, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
+    eta_o = opf.allen_cahn_update(eta0, chem, mech_f, prob.L, prob.dt, prob.kappa, prob.dx)
+    out["eta_max_abs"] = float(np.abs(np.asarray(eta1, np.float64) - eta_o).max())
+    out["eta_change"] = float(np.abs(eta_o - eta0).max())
+    out["oracle_s"] = time.time() - t0
+    return out
+
+
+# the FP64 oracle side takes about a minute on 16 host cores
+@pytest.mark.timeout(600)
+def test_polycrystal_256_full_size_one_step():
+    from paper_2302_13612_amd import binding
+    cfg = inputs.polycrystal(shape=(256, 256, 256))
+    print(f"\n[fullsize] polycrystal {cfg['shape']} n_var={cfg['n_var']} grains={int(cfg['gid'].max()) + 1}",
+          flush=True)
+    solver, eta1, sig6 = cases.gpu_run(cfg, 1)
+    eps6 = solver.field(binding.PF_FIELD_STRAIN).cpu().numpy()
+    st = solver.stats()
+    solver.close()
+    print(f"  gpu: ms_iters {st['ms_iters']}", flush=True)
+    r = oracle_checks(cfg, eps6, sig6, eta1)
+    print("  " + "  ".join(f"{k} {v:.3e}" for k, v in r.items()), flush=True)
+    assert np.isfinite(eta1).all()
+    assert r["sig_rel_l2"] <= SIG_TOL
+    # the library stops at a change <= tol; one more iteration contracts it
+    assert r["ms_change"] <= cfg["ms_tol"]
+    # the mean strain is held in FP32: rounding of the load and of the means
+    assert r["mean_strain_err"] <= 2e-6 * np.abs(cfg["eps_bar"]).max()
+    assert r["mean_stress_rel"] <= SIG_TOL
+    assert r["eta_max_abs"] <= ETA_TOL
+    # the step moved the interfaces by far more than the tolerance
+    assert r["eta_change"] > 10 * ETA_TOL
