@@ -1545,7 +1545,7 @@ struct pf_fno {
 namespace {
 
 struct FnoLayout {
-  size_t va, vb, x1, y1, x2, y2, tw, W, b, R, Q1, q1, Q2, prev, pred, total;
+  size_t va, vb, x1, y1, x2, y2, tw, xt, W, b, R, Q1, q1, Q2, prev, pred, total;
 };
 
 FnoLayout fno_layout(int nx, int ny, int nz, int m) {
@@ -1561,7 +1561,8 @@ FnoLayout fno_layout(int nx, int ny, int nz, int m) {
   L.y1 = take(x1 * 4);
   L.x2 = take(x2 * 4);
   L.y2 = take(x2 * 4);
-  L.tw = take((size_t)(nx + ny + nz) * 8);
+  L.tw = take((size_t)(ny + nz) * 8);
+  L.xt = take((size_t)2 * 2 * 32 * nx * 2);
   L.W = take((size_t)pfn::kLayers * pfn::kC * pfn::kC * 2);
   L.b = take((size_t)pfn::kLayers * pfn::kC * 4);
   L.R = take((size_t)pfn::kLayers * rl * 2);
@@ -1580,6 +1581,15 @@ uint16_t host_bf16(float f) {
   if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
+}
+
+// w ~ hi + lo with both parts BF16 (relative error about 2^-17)
+void split_bf16(double w, uint16_t* hi, uint16_t* lo) {
+  *hi = host_bf16((float)w);
+  const uint32_t u = (uint32_t)*hi << 16;
+  float h;
+  std::memcpy(&h, &u, 4);
+  *lo = host_bf16((float)(w - (double)h));
 }
 
 int fno_check(const pf_ctx* c, int32_t modes, std::string& why) {
@@ -1645,9 +1655,11 @@ int pf_fno_init(pf_ctx* c, const pf_fno_weights* w, void* workspace, size_t ws_b
   a.X2 = reinterpret_cast<float*>(ws + L.x2);
   a.Y2 = reinterpret_cast<float*>(ws + L.y2);
   float2* tw = reinterpret_cast<float2*>(ws + L.tw);
-  a.twx = tw;
-  a.twy = tw + g.nx;
-  a.twz = tw + g.nx + g.ny;
+  a.twy = tw;
+  a.twz = tw + g.ny;
+  uint16_t* xt = reinterpret_cast<uint16_t*>(ws + L.xt);
+  a.wxf = xt;
+  a.wxi = xt + (size_t)2 * 32 * g.nx;
   a.W = reinterpret_cast<uint16_t*>(ws + L.W);
   a.b = reinterpret_cast<float*>(ws + L.b);
   a.R = reinterpret_cast<uint16_t*>(ws + L.R);
@@ -1663,10 +1675,27 @@ int pf_fno_init(pf_ctx* c, const pf_fno_weights* w, void* workspace, size_t ws_b
   f->p.assign(w->p, w->p + pfn::kC);
   // host conversions: BF16 weights, R reordered to [l][kz'][ky'][kx][o][i][re, im]
   const int C = pfn::kC, my = 2 * m;
-  std::vector<float> twh(2 * (size_t)(g.nx + g.ny + g.nz));
-  twiddles(g.nx, twh.data());
-  twiddles(g.ny, twh.data() + 2 * g.nx);
-  twiddles(g.nz, twh.data() + 2 * (g.nx + g.ny));
+  std::vector<float> twh(2 * (size_t)(g.ny + g.nz));
+  twiddles(g.ny, twh.data());
+  twiddles(g.nz, twh.data() + 2 * g.ny);
+  // the x sums' matrices: row j = 2 kx + (re, im) of the forward sum, column j
+  // of the inverse (1/N and the doubling of kx > 0 folded in), as BF16 hi and
+  // lo parts of the double values
+  std::vector<uint16_t> wx((size_t)4 * 32 * g.nx, 0);
+  uint16_t* wxf = wx.data();
+  uint16_t* wxi = wx.data() + (size_t)2 * 32 * g.nx;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int kx = 0; kx < m; ++kx)
+    for (int x = 0; x < g.nx; ++x) {
+      const double th = two_pi * (double)(((long long)kx * x) % g.nx) / g.nx;
+      const double scale = (kx == 0 ? 1.0 : 2.0) / (double)g.nvox;
+      const double f[2] = {std::cos(th), -std::sin(th)};
+      for (int ri = 0; ri < 2; ++ri) {
+        const int j = 2 * kx + ri;
+        split_bf16(f[ri], &wxf[(size_t)j * g.nx + x], &wxf[(size_t)(32 + j) * g.nx + x]);
+        split_bf16(scale * f[ri], &wxi[(size_t)x * 32 + j], &wxi[(size_t)(g.nx + x) * 32 + j]);
+      }
+    }
   std::vector<uint16_t> Wb((size_t)pfn::kLayers * C * C), Q1b((size_t)pfn::kH * C);
   for (size_t i = 0; i < Wb.size(); ++i) Wb[i] = host_bf16(w->W[i]);
   for (size_t i = 0; i < Q1b.size(); ++i) Q1b[i] = host_bf16(w->Q1[i]);
@@ -1686,7 +1715,8 @@ int pf_fno_init(pf_ctx* c, const pf_fno_weights* w, void* workspace, size_t ws_b
   auto h2d = [&](const void* dst, const void* src, size_t bytes) {
     return hipMemcpyAsync(const_cast<void*>(dst), src, bytes, hipMemcpyHostToDevice, c->stream);
   };
-  if ((e = h2d(tw, twh.data(), twh.size() * 4)) != hipSuccess || (e = h2d(a.W, Wb.data(), Wb.size() * 2)) != hipSuccess ||
+  if ((e = h2d(tw, twh.data(), twh.size() * 4)) != hipSuccess || (e = h2d(xt, wx.data(), wx.size() * 2)) != hipSuccess ||
+      (e = h2d(a.W, Wb.data(), Wb.size() * 2)) != hipSuccess ||
       (e = h2d(a.b, w->b, (size_t)pfn::kLayers * C * 4)) != hipSuccess ||
       (e = h2d(a.R, Rb.data(), Rb.size() * 2)) != hipSuccess || (e = h2d(a.Q1, Q1b.data(), Q1b.size() * 2)) != hipSuccess ||
       (e = h2d(a.q1, w->q1, pfn::kH * 4)) != hipSuccess || (e = h2d(a.Q2, w->Q2, pfn::kH * 4)) != hipSuccess ||

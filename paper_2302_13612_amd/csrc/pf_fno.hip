@@ -8,8 +8,10 @@
 // discrete Fourier sums, not FFTs: x (full real rows -> m complex), y and z
 // (full length -> 2m kept), channel mixing per kept mode, and the inverses.
 // The full-resolution work is the x sums and the pointwise channel mixing;
-// the mixing (32 x 32 per voxel) and the projection's first layer (32 -> 128
-// per voxel) run on the matrix cores as BF16 MFMA with FP32 accumulation.
+// both x sums (2m x nx twiddles against the 32 channels of a row), the mixing
+// (32 x 32 per voxel) and the projection's first layer (32 -> 128 per voxel)
+// run on the matrix cores as BF16 MFMA with FP32 accumulation, FP32 operands
+// (twiddles, transformed rows) entering as BF16 hi and lo parts.
 //
 // Layouts: activations v [z][y][x][C] BF16 (C = 32, channel-last);
 // transforms X [z][y or ky'][kx][re/im][C] FP32.
@@ -37,6 +39,14 @@ __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.f + erff(x
 // Signed kept index -> frequency on an axis of length n.
 __device__ __forceinline__ int kept_freq(int kk, int m, int n) { return kk < m ? kk : n - 2 * m + kk; }
 
+// Inverse sums step the twiddle index k(kk) t mod n by t (< n) along the kept
+// list: from 0 for kk < m, and from (n - m) t mod n = (-m t) mod n for the
+// negative frequencies kk >= m.
+__device__ __forceinline__ int inv_start(int m, int t, int n) {
+  const int r = (m * t) % n;
+  return r == 0 ? 0 : n - r;
+}
+
 // ---------------------------------------------------------------- lift
 // v_0[vox][c] = P0[c] f + K[c] (K folds the constant conditioning channels).
 __global__ __launch_bounds__(256) void k_lift(const FArgs a, const float* __restrict__ eta,
@@ -60,41 +70,94 @@ __global__ __launch_bounds__(256) void k_lift(const FArgs a, const float* __rest
   }
 }
 
+// ------------------------------------------------ matrix-core helpers
+// v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8 (l / 32) + 0..7] and
+// B[8 (l / 32) + 0..7][l % 32]; it receives D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
+// in accumulator r.
+__device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r / 4) + 4 * (lane / 32) + (r % 4); }
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
+  const uint4 q = *reinterpret_cast<const uint4*>(p);
+  bf16x8 out;
+  __builtin_memcpy(&out, &q, 16);
+  return out;
+}
+
+// D (32 voxels x 32 outputs) = v[x0 .. x0+31][0..31] . Wt where Wt[i][o] = Wm[o][i]
+__device__ __forceinline__ f32x16 mix32(const uint16_t* __restrict__ vrow, int x0, const uint16_t* __restrict__ Wm,
+                                        int lane) {
+  const int i = lane % 32, kb = 8 * (lane / 32);
+  f32x16 acc = {};
+  const uint16_t* ap = vrow + (size_t)(x0 + i) * kC + kb;
+  const uint16_t* bp = Wm + (size_t)i * kC + kb;
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(ap), load8(bp), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(ap + 16), load8(bp + 16), acc, 0, 0, 0);
+  return acc;
+}
+
 // ------------------------------------------------------- x forward sums
-// X1[row][kx][ri][c] = sum_x v[row][x][c] e^{-2 pi i kx x / nx}, kx < m.
-// One block per row; the row is staged in LDS as FP32.
+// X1[row][j][c] = sum_x WF[j][x] v[row][x][c], j = 2 kx + (re, im), kx < m,
+// with WF[2 kx][x] = cos(2 pi kx x / nx), WF[2 kx + 1][x] = -sin(2 pi kx x / nx)
+// and rows j >= 2m zero. On the matrix cores: A = WF (32 j by 16 x per
+// product, as the BF16 hi and lo parts of the FP32 twiddle), B = the row's
+// activations. The channel-last row is transposed to [c][x] in the wave's LDS
+// so each lane reads its eight consecutive x of one channel in one 16-byte
+// load. Four waves take one row each per round; the twiddles sit in LDS.
+constexpr int kDftRounds = 4;  // rounds of four rows per block
+
+__device__ __forceinline__ int xpitch(int nx) { return nx + 8; }  // bf16 per LDS row, a 16-byte multiple
+
 __global__ __launch_bounds__(256) void k_xdft(const FArgs a, const uint16_t* __restrict__ v) {
-  extern __shared__ float sm[];
-  float* row = sm;                       // [nx][C]
-  float2* tw = reinterpret_cast<float2*>(sm + a.nx * kC);  // [nx]
-  const int r = blockIdx.x;
-  const uint4* src = reinterpret_cast<const uint4*>(v + (size_t)r * a.nx * kC);
-  for (int i = threadIdx.x; i < a.nx * kC / 8; i += 256) {
-    const uint4 q = src[i];
-    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      row[8 * i + 2 * h] = bf2f((uint16_t)(w[h] & 0xffffu));
-      row[8 * i + 2 * h + 1] = bf2f((uint16_t)(w[h] >> 16));
-    }
+  extern __shared__ __align__(16) uint16_t xs[];
+  const int nx = a.nx, pitch = xpitch(nx), pdw = pitch / 2;
+  uint16_t* wf = xs;                    // [hi, lo][32][pitch]
+  uint16_t* tr = xs + 2 * 32 * pitch;   // [wave][32][pitch]
+  const int n8 = nx / 8;
+  for (int i = threadIdx.x; i < 2 * 32 * n8; i += 256) {
+    const int hj = i / n8, x8 = i % n8;  // hj = h * 32 + j
+    *reinterpret_cast<uint4*>(wf + hj * pitch + 8 * x8) =
+        *reinterpret_cast<const uint4*>(a.wxf + (size_t)hj * nx + 8 * x8);
   }
-  for (int i = threadIdx.x; i < a.nx; i += 256) tw[i] = a.twx[i];
-  __syncthreads();
-  const int c = threadIdx.x % kC, g = threadIdx.x / kC;
-  float* out = a.X1 + (size_t)r * a.m * 2 * kC;
-  for (int kx = g; kx < a.m; kx += 8) {
-    float re = 0.f, im = 0.f;
-    int j = 0;
-    for (int x = 0; x < a.nx; ++x) {
-      const float val = row[x * kC + c];
-      const float2 w = tw[j];
-      re += val * w.x;
-      im += val * w.y;
-      j += kx;
-      if (j >= a.nx) j -= a.nx;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int i = lane % 32, kb = 8 * (lane / 32);
+  uint16_t* t = tr + wave * 32 * pitch;
+  uint32_t* tdw = reinterpret_cast<uint32_t*>(t);
+  const int rows = a.ny * a.nz, m2 = 2 * a.m;
+  for (int k = 0; k < kDftRounds; ++k) {
+    const int row = (blockIdx.x * kDftRounds + k) * 4 + wave;
+    const bool active = row < rows;
+    __syncthreads();  // the twiddles are in place; the previous round's reads are done
+    if (active) {
+      // lane task p: channels 8 (p % 4) .. +7 at x = 2 (p / 4) and x + 1,
+      // stored as BF16 pairs (x, x + 1) per channel
+      const uint4* src = reinterpret_cast<const uint4*>(v + (size_t)row * nx * kC);
+      for (int p = lane; p < 2 * nx; p += 64) {
+        const int x = 2 * (p / 4), g = p % 4;
+        const uint4 q0 = src[x * 4 + g], q1 = src[(x + 1) * 4 + g];
+        const uint32_t w0[4] = {q0.x, q0.y, q0.z, q0.w}, w1[4] = {q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const uint32_t lo = (w0[q / 2] >> (16 * (q % 2))) & 0xffffu;
+          const uint32_t hi = (w1[q / 2] >> (16 * (q % 2))) & 0xffffu;
+          tdw[(8 * g + q) * pdw + x / 2] = lo | (hi << 16);
+        }
+      }
     }
-    out[(kx * 2) * kC + c] = re;
-    out[(kx * 2 + 1) * kC + c] = im;
+    __syncthreads();
+    if (active) {
+      f32x16 acc = {};
+      for (int x0 = 0; x0 < nx; x0 += 16) {
+        const bf16x8 b = load8(t + i * pitch + x0 + kb);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(wf + i * pitch + x0 + kb), b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(wf + (32 + i) * pitch + x0 + kb), b, acc, 0, 0, 0);
+      }
+      float* out = a.X1 + (size_t)row * m2 * kC;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int j = mfma_row(rr, lane);
+        if (j < m2) out[j * kC + i] = acc[rr];
+      }
+    }
   }
 }
 
@@ -134,13 +197,15 @@ __global__ __launch_bounds__(256) void k_ysum(const FArgs a, const float* __rest
         if (j >= ny) j -= ny;
       }
     } else {
+      int j = 0;  // k(kk) o mod ny
       for (int kk = 0; kk < my; ++kk) {
-        const int k = kept_freq(kk, m, ny);
-        const int j = (int)(((long)k * o) % ny);
+        if (kk == m) j = inv_start(m, o, ny);
         const float2 w = tw[j];  // conjugate for the inverse
         const float xr = col[(2 * kk) * kC + c], xi = col[(2 * kk + 1) * kC + c];
         re += xr * w.x + xi * w.y;
         im += xi * w.x - xr * w.y;
+        j += o;
+        if (j >= ny) j -= ny;
       }
     }
     out[out_base + (size_t)o * m * 2 * kC + c] = re;
@@ -202,80 +267,82 @@ __global__ __launch_bounds__(256) void k_zmix(const FArgs a, const uint16_t* __r
   __syncthreads();
   for (int t = g; t < nz; t += 8) {
     float re = 0.f, im = 0.f;
+    int j = 0;  // k(kk) t mod nz
     for (int kk = 0; kk < my; ++kk) {
-      const int k = kept_freq(kk, m, nz);
-      const float2 w = tw[(int)(((long)k * t) % nz)];
+      if (kk == m) j = inv_start(m, t, nz);
+      const float2 w = tw[j];
       const float xr = os[(2 * kk) * kC + c], xi = os[(2 * kk + 1) * kC + c];
       re += xr * w.x + xi * w.y;
       im += xi * w.x - xr * w.y;
+      j += t;
+      if (j >= nz) j -= nz;
     }
     a.Y2[base + (size_t)t * zstride + c] = re;
     a.Y2[base + (size_t)t * zstride + kC + c] = im;
   }
 }
 
-// ------------------------------------------------ matrix-core helpers
-// v_mfma_f32_32x32x16_bf16: lane l supplies A[l % 32][8 (l / 32) + 0..7] and
-// B[8 (l / 32) + 0..7][l % 32]; it receives D[8 (r / 4) + 4 (l / 32) + r % 4][l % 32]
-// in accumulator r.
-__device__ __forceinline__ int mfma_row(int r, int lane) { return 8 * (r / 4) + 4 * (lane / 32) + (r % 4); }
-
-__device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
-  const uint4 q = *reinterpret_cast<const uint4*>(p);
-  bf16x8 out;
-  __builtin_memcpy(&out, &q, 16);
-  return out;
-}
-
-// D (32 voxels x 32 outputs) = v[x0 .. x0+31][0..31] . Wt where Wt[i][o] = Wm[o][i]
-__device__ __forceinline__ f32x16 mix32(const uint16_t* __restrict__ vrow, int x0, const uint16_t* __restrict__ Wm,
-                                        int lane) {
-  const int i = lane % 32, kb = 8 * (lane / 32);
-  f32x16 acc = {};
-  const uint16_t* ap = vrow + (size_t)(x0 + i) * kC + kb;
-  const uint16_t* bp = Wm + (size_t)i * kC + kb;
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(ap), load8(bp), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(ap + 16), load8(bp + 16), acc, 0, 0, 0);
-  return acc;
-}
-
 // ------------------------------------------- x inverse + local mixing
-// v'[x][o] = GELU(sum_i W[o][i] v[x][i] + b[o]
-//                 + s sum_kx w_kx Re(Y1[kx][o] e^{2 pi i kx x / nx})),
-// s = 1 / (nx ny nz), w = 1 (kx = 0) or 2. One block per row, one wave per
-// 32 voxels.
+// v'[x][o] = GELU(sum_i W[o][i] v[x][i] + b[o] + sum_j WI[x][j] Y1[j][o]) with
+// WI[x][2 kx] = s w cos(2 pi kx x / nx), WI[x][2 kx + 1] = -s w sin(2 pi kx x / nx),
+// s = 1 / (nx ny nz), w = 1 (kx = 0) or 2, columns j >= 2m zero: the real
+// part of the inverse x sum (the kx = 0 imaginary part drops out). The sum
+// is a second product into the mixing's accumulator, with WI and Y1 (FP32)
+// as BF16 hi and lo parts: A = WI (LDS), B = Y1 transposed to [o][j] in LDS.
+// A block takes kInvRows rows per group; its waves share the 32-voxel tiles.
+constexpr int kInvRows = 4, kInvGroups = 4;
+constexpr int kYPitch = 40;  // bf16 per LDS row of the 32-wide j axis, a 16-byte multiple
+
 __global__ __launch_bounds__(256) void k_xinv_mix(const FArgs a, const uint16_t* __restrict__ vin,
                                                   uint16_t* __restrict__ vout, const uint16_t* __restrict__ Wm,
                                                   const float* __restrict__ bias) {
-  extern __shared__ float sm[];
-  float* y1 = sm;                                        // [m][2][C]
-  float2* tw = reinterpret_cast<float2*>(sm + a.m * 2 * kC);  // [nx]
-  const int r = blockIdx.x;
-  const float* ysrc = a.Y1 + (size_t)r * a.m * 2 * kC;
-  for (int i = threadIdx.x; i < a.m * 2 * kC; i += blockDim.x) y1[i] = ysrc[i];
-  for (int i = threadIdx.x; i < a.nx; i += blockDim.x) tw[i] = a.twx[i];
-  __syncthreads();
-  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64, nwave = blockDim.x / 64;
-  const int o = lane % 32;
-  const float bo = bias[o];
-  const uint16_t* vrow = vin + (size_t)r * a.nx * kC;
-  uint16_t* orow = vout + (size_t)r * a.nx * kC;
-  for (int x0 = 32 * wave; x0 < a.nx; x0 += 32 * nwave) {
-    const f32x16 acc = mix32(vrow, x0, Wm, lane);
+  extern __shared__ __align__(16) uint16_t xs[];
+  const int nx = a.nx;
+  uint16_t* wi = xs;                         // [hi, lo][nx][kYPitch]
+  uint16_t* yt = xs + 2 * nx * kYPitch;      // [kInvRows][hi, lo][32 o][kYPitch]
+  for (int i = threadIdx.x; i < 2 * nx * 4; i += 256) {
+    const int hx = i / 4, q = i % 4;  // hx = h * nx + x; four 16-byte pieces per x
+    *reinterpret_cast<uint4*>(wi + hx * kYPitch + 8 * q) =
+        *reinterpret_cast<const uint4*>(a.wxi + (size_t)hx * 32 + 8 * q);
+  }
+  const int rows = a.ny * a.nz, m2 = 2 * a.m, ntile = nx / 32;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int i = lane % 32, kb = 8 * (lane / 32);
+  const float bo = bias[i];
+  for (int g = 0; g < kInvGroups; ++g) {
+    const int row0 = (blockIdx.x * kInvGroups + g) * kInvRows;
+    __syncthreads();  // the twiddles are in place; the previous group's reads are done
+    for (int e = threadIdx.x; e < kInvRows * 32 * 32; e += 256) {
+      const int rl = e / 1024, j = (e / 32) % 32, o = e % 32;
+      const int row = row0 + rl;
+      const float y = (row < rows && j < m2) ? a.Y1[((size_t)row * m2 + j) * kC + o] : 0.f;
+      const uint16_t h = f2bf(y);
+      yt[((rl * 2) * 32 + o) * kYPitch + j] = h;
+      yt[((rl * 2 + 1) * 32 + o) * kYPitch + j] = f2bf(y - bf2f(h));
+    }
+    __syncthreads();
+    for (int u = wave; u < kInvRows * ntile; u += 4) {
+      const int rl = u / ntile, x0 = 32 * (u % ntile);
+      const int row = row0 + rl;
+      if (row >= rows) continue;  // uniform over the wave; no barrier follows in this loop
+      const uint16_t* vrow = vin + (size_t)row * nx * kC;
+      f32x16 acc = mix32(vrow, x0, Wm, lane);
 #pragma unroll
-    for (int rr = 0; rr < 16; ++rr) {
-      const int x = x0 + mfma_row(rr, lane);
-      float sp = 0.f;
-      int j = 0;
-      for (int kx = 0; kx < a.m; ++kx) {
-        const float2 w = tw[j];  // e^{-2 pi i kx x / nx}; inverse uses the conjugate
-        const float yr = y1[(2 * kx) * kC + o], yi = y1[(2 * kx + 1) * kC + o];
-        const float re = yr * w.x + yi * w.y;
-        sp += (kx == 0 ? 1.f : 2.f) * re;
-        j += x;
-        if (j >= a.nx) j -= a.nx;
+      for (int j0 = 0; j0 < 32; j0 += 16) {
+        const bf16x8 ah = load8(wi + (x0 + i) * kYPitch + j0 + kb);
+        const bf16x8 al = load8(wi + (nx + x0 + i) * kYPitch + j0 + kb);
+        const bf16x8 bh = load8(yt + ((rl * 2) * 32 + i) * kYPitch + j0 + kb);
+        const bf16x8 bl = load8(yt + ((rl * 2 + 1) * 32 + i) * kYPitch + j0 + kb);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
       }
-      orow[(size_t)x * kC + o] = f2bf(gelu(acc[rr] + bo + a.inv_ntot * sp));
+      uint16_t* orow = vout + (size_t)row * nx * kC;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int x = x0 + mfma_row(rr, lane);
+        orow[(size_t)x * kC + i] = f2bf(gelu(acc[rr] + bo));
+      }
     }
   }
 }
@@ -321,12 +388,12 @@ __global__ __launch_bounds__(256) void k_proj(const FArgs a, const uint16_t* __r
 // ====================================================================== host
 namespace pfn {
 
-size_t lds_xdft(const FArgs& a) { return (size_t)a.nx * kC * 4 + (size_t)a.nx * 8; }
+size_t lds_xdft(const FArgs& a) { return (size_t)(2 + 4) * 32 * (a.nx + 8) * 2; }
 size_t lds_ysum(const FArgs& a, bool fwd) {
   return (size_t)(fwd ? a.ny : 2 * a.m) * 2 * kC * 4 + (size_t)a.ny * 8;
 }
 size_t lds_zmix(const FArgs& a) { return ((size_t)a.nz + 4 * a.m) * 2 * kC * 4 + (size_t)a.nz * 8; }
-size_t lds_xinv(const FArgs& a) { return (size_t)a.m * 2 * kC * 4 + (size_t)a.nx * 8; }
+size_t lds_xinv(const FArgs& a) { return ((size_t)2 * a.nx + kInvRows * 2 * 32) * kYPitch * 2; }
 
 hipError_t forward(const FArgs& a, const float* eta_in, float* eta_out, hipStream_t s) {
   const int rows = a.nz * a.ny;
@@ -334,11 +401,12 @@ hipError_t forward(const FArgs& a, const float* eta_in, float* eta_out, hipStrea
   uint16_t* vin = a.va;
   uint16_t* vout = a.vb;
   for (int l = 0; l < kLayers; ++l) {
-    k_xdft<<<rows, 256, lds_xdft(a), s>>>(a, vin);
+    k_xdft<<<(rows + 4 * kDftRounds - 1) / (4 * kDftRounds), 256, lds_xdft(a), s>>>(a, vin);
     k_ysum<true><<<a.nz * a.m, 256, lds_ysum(a, true), s>>>(a, a.X1, a.X2);
     k_zmix<<<2 * a.m * a.m, 256, lds_zmix(a), s>>>(a, a.R + (size_t)l * a.r_stride);
     k_ysum<false><<<a.nz * a.m, 256, lds_ysum(a, false), s>>>(a, a.Y2, a.Y1);
-    k_xinv_mix<<<rows, 256, lds_xinv(a), s>>>(a, vin, vout, a.W + (size_t)l * kC * kC, a.b + (size_t)l * kC);
+    k_xinv_mix<<<(rows + kInvRows * kInvGroups - 1) / (kInvRows * kInvGroups), 256, lds_xinv(a), s>>>(
+        a, vin, vout, a.W + (size_t)l * kC * kC, a.b + (size_t)l * kC);
     uint16_t* t = vin;
     vin = vout;
     vout = t;

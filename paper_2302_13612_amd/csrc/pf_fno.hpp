@@ -22,7 +22,8 @@ struct FArgs {
   float* X2;                  // [nz][2m][m][2][C]
   float* Y2;                  // [nz][2m][m][2][C]
   float* Y1;                  // [nz][ny][m][2][C]
-  const float2* twx;          // e^{-2 pi i j / nx}, j < nx
+  const uint16_t* wxf;        // [hi, lo][32][nx] BF16 parts of the forward x twiddles
+  const uint16_t* wxi;        // [hi, lo][nx][32] BF16 parts of the scaled inverse x twiddles
   const float2* twy;
   const float2* twz;
   float lift[2 * kC];         // P0[c] (weight of f) and the folded constant K[c]

@@ -48,13 +48,16 @@ def homog_solver(shape, eta, seed=31):
     return cfg, solver
 
 
-@pytest.mark.parametrize("shape", [(32, 32, 32), (32, 32, 64), (128, 128, 128)])
-def test_fno_forward_vs_oracle(shape):
+# (nz, ny, nx), kept modes: every x length the x sums take (32 to 128), and
+# 16 modes, whose 2m = 32 rows fill the whole matrix-core tile
+@pytest.mark.parametrize("shape,modes", [((32, 32, 32), 12), ((32, 32, 64), 12), ((48, 64, 96), 12),
+                                         ((32, 48, 32), 16), ((128, 128, 128), 12)])
+def test_fno_forward_vs_oracle(shape, modes):
     import torch
-    print(f"\n[fno forward] {shape}", flush=True)
+    print(f"\n[fno forward] {shape} modes {modes}", flush=True)
     eta = smooth_field(shape, 3)
     cfg, solver = homog_solver(shape, eta)
-    p = gpu_params(seed=1)
+    p = gpu_params(seed=1, modes=modes)
     cond = np.random.default_rng(2).normal(size=7)
     net = binding.Fno(solver, p)
     out = net.forward(cond, torch.from_numpy(eta).cuda()).cpu().numpy()
