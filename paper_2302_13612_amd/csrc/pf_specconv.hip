@@ -24,10 +24,23 @@ constexpr int kMaxN = 256;
 
 __device__ __forceinline__ int kept_freq(int kk, int m, int n) { return kk < m ? kk : n - 2 * m + kk; }
 
-// e^{sign 2 pi i k j / n} from an exact table of n roots: index (k j) mod n
-__device__ __forceinline__ float2 root(const float2* tw, int k, int j, int n, int sign) {
-  const float2 w = tw[(int)(((long)k * j) % n)];
+// e^{sign 2 pi i idx / n} from an exact table of n roots. A sum over one
+// axis steps idx = (k j) mod n by k (or j), each step below n, with one
+// wrap; an inverse sum over the kept list restarts at the negative
+// frequencies from (n - m) j mod n = (-m j) mod n.
+__device__ __forceinline__ float2 root(const float2* tw, int idx, int sign) {
+  const float2 w = tw[idx];
   return make_float2(w.x, sign > 0 ? w.y : -w.y);
+}
+
+__device__ __forceinline__ int step_idx(int idx, int d, int n) {
+  idx += d;
+  return idx >= n ? idx - n : idx;
+}
+
+__device__ __forceinline__ int neg_start(int m, int j, int n) {
+  const int r = (m * j) % n;
+  return r == 0 ? 0 : n - r;
 }
 
 __device__ __forceinline__ void load_roots(float2* tw, int n) {
@@ -56,10 +69,12 @@ __global__ __launch_bounds__(256) void k_tx_fwd(const float* __restrict__ v, flo
     const int rr = o / m, kx = o % m;
     if (r0 + rr >= rows) continue;
     float re = 0.f, im = 0.f;
+    int idx = 0;  // kx x mod nx
     for (int x = 0; x < nx; ++x) {
-      const float2 w = root(tw, kx, x, nx, -1);
+      const float2 w = root(tw, idx, -1);
       re += row[rr][x] * w.x;
       im += row[rr][x] * w.y;
+      idx = step_idx(idx, kx, nx);
     }
     const float s = scale * ((weight_c && kx > 0) ? 2.f : 1.f);
     X[(r0 + rr) * m + kx] = make_float2(s * re, s * im);
@@ -82,14 +97,17 @@ __global__ __launch_bounds__(256) void k_t_axis(const float2* __restrict__ in, f
     const long o = t / (inner * nout);
     const float2* src = in + o * nin * inner + i;
     float re = 0.f, im = 0.f;
+    // forward: q a kept index, p a grid index, idx = f(q) p mod n;
+    // inverse: p a kept index, q a grid index, idx = f(p) q mod n
+    const int d = dir < 0 ? kept_freq(q, m, n) : q;
+    int idx = 0;
     for (int p = 0; p < nin; ++p) {
-      // forward: q a kept index, p a grid index; inverse: the other way round
-      const int f = dir < 0 ? kept_freq(q, m, n) : kept_freq(p, m, n);
-      const int j = dir < 0 ? p : q;
-      const float2 w = root(tw, f, j, n, dir);
+      if (dir > 0 && p == m) idx = neg_start(m, q, n);
+      const float2 w = root(tw, idx, dir);
       const float2 a = src[(long)p * inner];
       re += a.x * w.x - a.y * w.y;
       im += a.x * w.y + a.y * w.x;
+      idx = step_idx(idx, d, n);
     }
     out[t] = make_float2(re, im);
   }
@@ -126,10 +144,12 @@ __global__ __launch_bounds__(256) void k_tx_inv(const float2* __restrict__ Y, fl
     const long r = t / nx;
     const int x = (int)(t % nx);
     float acc = 0.f;
+    int idx = 0;  // kx x mod nx
     for (int kx = 0; kx < m; ++kx) {
       const float2 a = Y[r * m + kx];
-      const float2 w = root(tw, kx, x, nx, +1);
+      const float2 w = root(tw, idx, +1);
       acc += ((weight_c && kx > 0) ? 2.f : 1.f) * (a.x * w.x - a.y * w.y);
+      idx = step_idx(idx, x, nx);
     }
     y[t] = scale * acc;
   }
