@@ -100,7 +100,8 @@ extern "C" {
 typedef struct pf_ctx pf_ctx;
 
 /* Problem fixed over a run. Supported sizes: nx, ny, nz each in
- * {32, 48, 64, 96, 128, 256}; n_var in 1..6; n_grains in 1..255. */
+ * {32, 48, 64, 96, 128, 192, 256, 384, 512}; n_var in 1..6; n_grains in
+ * 1..255. */
 typedef struct {
   int32_t nx, ny, nz;
   double dx;               /* voxel edge, m                                 */

@@ -104,7 +104,10 @@ template <> struct Plan<48>  { static constexpr int E = 12; using R = Radices<4,
 template <> struct Plan<64>  { static constexpr int E = 8;  using R = Radices<8, 8>; };
 template <> struct Plan<96>  { static constexpr int E = 12; using R = Radices<4, 4, 2, 3>; };
 template <> struct Plan<128> { static constexpr int E = 8;  using R = Radices<8, 4, 4>; };
+template <> struct Plan<192> { static constexpr int E = 12; using R = Radices<4, 4, 4, 3>; };
 template <> struct Plan<256> { static constexpr int E = 8;  using R = Radices<8, 8, 4>; };
+template <> struct Plan<384> { static constexpr int E = 12; using R = Radices<4, 4, 4, 2, 3>; };
+template <> struct Plan<512> { static constexpr int E = 8;  using R = Radices<8, 8, 8>; };
 
 // Plans of the x pass (half-length complex transforms of real rows). Fewer
 // elements per thread leave registers for the fused per-voxel physics.
@@ -114,7 +117,10 @@ template <> struct XPlan<24>  { static constexpr int E = 6; using R = Radices<2,
 template <> struct XPlan<32>  { static constexpr int E = 4; using R = Radices<4, 4, 2>; };
 template <> struct XPlan<48>  { static constexpr int E = 6; using R = Radices<2, 2, 2, 2, 3>; };
 template <> struct XPlan<64>  { static constexpr int E = 4; using R = Radices<4, 4, 4>; };
+template <> struct XPlan<96>  { static constexpr int E = 6; using R = Radices<2, 2, 2, 2, 2, 3>; };
 template <> struct XPlan<128> { static constexpr int E = 4; using R = Radices<4, 4, 4, 2>; };
+template <> struct XPlan<192> { static constexpr int E = 6; using R = Radices<2, 2, 2, 2, 2, 2, 3>; };
+template <> struct XPlan<256> { static constexpr int E = 4; using R = Radices<4, 4, 4, 4>; };
 
 // ------------------------------------------------------------ LDS views
 // Orders the LDS accesses of one wavefront's lanes: the compiler moves no

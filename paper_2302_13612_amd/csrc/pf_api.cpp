@@ -431,7 +431,7 @@ int launch(pf_ctx* c, hipStream_t s, const char* name, F&& f) {
 int validate(const pf_problem* p, std::string& why) {
   if (!p) { why = "null problem"; return PF_EINVAL; }
   if (!axis_ok(p->nx) || !axis_ok(p->ny) || !axis_ok(p->nz)) {
-    why = "grid sizes must each be one of 32, 48, 64, 96, 128, 256";
+    why = "grid sizes must each be one of 32, 48, 64, 96, 128, 192, 256, 384, 512";
     return PF_EINVAL;
   }
   if (p->n_var < 1 || p->n_var > pft::kMaxVar) { why = "n_var must be in 1..6"; return PF_EINVAL; }

@@ -302,7 +302,7 @@ constexpr bool row_in_wave() { return 64 % (M / XPlan<M>::E) == 0; }
 // Threads per x-pass block for half-length M (smaller for the radix-3 rows so
 // the staging slabs stay within 64 KiB of LDS).
 template <int M>
-__host__ __device__ constexpr int xthreads() { return (M == 24 || M == 48) ? 128 : 256; }
+__host__ __device__ constexpr int xthreads() { return (M % 3 == 0) ? 128 : 256; }
 
 // Forward: the NC complex rows held in v (packed real pairs) -> R2C spectra.
 template <int M, int NC>

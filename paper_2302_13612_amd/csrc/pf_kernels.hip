@@ -1022,7 +1022,8 @@ namespace pfl {
 using namespace pft;
 
 bool supported_axis(int n) {
-  return n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 256;
+  return n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 192 || n == 256 || n == 384 ||
+         n == 512;
 }
 
 template <int M>
@@ -1035,7 +1036,10 @@ int rows_per_block(int nx) {
     case 32: return rows_per_block_t<32>();
     case 48: return rows_per_block_t<48>();
     case 64: return rows_per_block_t<64>();
+    case 96: return rows_per_block_t<96>();
     case 128: return rows_per_block_t<128>();
+    case 192: return rows_per_block_t<192>();
+    case 256: return rows_per_block_t<256>();
   }
   return 0;
 }
@@ -1069,7 +1073,10 @@ static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
     case 32: { constexpr int M = 32; BODY; } break;  \
     case 48: { constexpr int M = 48; BODY; } break;  \
     case 64: { constexpr int M = 64; BODY; } break;  \
+    case 96: { constexpr int M = 96; BODY; } break;  \
     case 128: { constexpr int M = 128; BODY; } break; \
+    case 192: { constexpr int M = 192; BODY; } break; \
+    case 256: { constexpr int M = 256; BODY; } break; \
     default: return hipErrorInvalidValue;     \
   }
 
@@ -1080,7 +1087,10 @@ static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
     case 64: { constexpr int N = 64; BODY; } break;   \
     case 96: { constexpr int N = 96; BODY; } break;   \
     case 128: { constexpr int N = 128; BODY; } break; \
+    case 192: { constexpr int N = 192; BODY; } break; \
     case 256: { constexpr int N = 256; BODY; } break; \
+    case 384: { constexpr int N = 384; BODY; } break; \
+    case 512: { constexpr int N = 512; BODY; } break; \
     default: return hipErrorInvalidValue;     \
   }
 

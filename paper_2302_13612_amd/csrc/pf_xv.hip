@@ -693,7 +693,10 @@ using namespace pft;
     case 32: { constexpr int M = 32; BODY; } break;   \
     case 48: { constexpr int M = 48; BODY; } break;   \
     case 64: { constexpr int M = 64; BODY; } break;   \
+    case 96: { constexpr int M = 96; BODY; } break;   \
     case 128: { constexpr int M = 128; BODY; } break; \
+    case 192: { constexpr int M = 192; BODY; } break; \
+    case 256: { constexpr int M = 256; BODY; } break; \
     default: return hipErrorInvalidValue;              \
   }
 

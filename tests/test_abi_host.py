@@ -39,6 +39,14 @@ def test_workspace_size_validation():
     assert n.value >= 4 * nvox * (2 + 6 + 6) + 8 * (33 * 32 * 48) * 6
     p.nx = 40                                   # unsupported axis
     assert lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.PF_EINVAL
+    for bad in (16, 24, 320, 576, 1024):        # outside the supported list
+        p.nx = bad
+        assert lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.PF_EINVAL, bad
+    for good in (32, 48, 64, 96, 128, 192, 256, 384, 512):
+        p.nx, p.ny, p.nz = good, good, 32
+        assert lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(n)) == 0, good
+        assert n.value >= 4 * good * good * 32 * (2 + 6 + 6) + 8 * (good // 2 + 1) * good * 32 * 6
+    p.nx, p.ny, p.nz = 64, 32, 48
     p.nx, p.n_var = 64, 7
     assert lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(n)) == binding.PF_EINVAL
 

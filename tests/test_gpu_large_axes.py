@@ -1,0 +1,49 @@
+"""GPU: grids with the largest supported axes (192 = 2^6 3, 384 = 2^7 3 and
+512 = 2^9) in each role (x: the fused real-to-complex passes, y, z: the
+Green's operator and the Allen-Cahn divide), against the FP64 oracle.
+
+The other two axes stay small so that the oracle finishes in seconds; the
+transform test covers every new length on every axis.
+Tolerances as for the other step parity tests: f max-abs <= 1e-4, stress
+relative L2 <= 1e-5.
+"""
+
+import numpy as np
+import pytest
+
+from tests import cases
+from tests.test_gpu_fft import make_solver
+from tests.test_gpu_step import compare
+
+pytestmark = pytest.mark.gpu
+
+FFT_SHAPES = [(512, 48, 32), (32, 512, 48), (48, 32, 512), (384, 32, 192), (192, 384, 32),
+              (32, 192, 384)]
+
+
+@pytest.mark.parametrize("shape", FFT_SHAPES)
+def test_transform_large_axes(shape):
+    import torch
+    print(f"\n[fft] shape={shape}", flush=True)
+    solver = make_solver(shape)
+    rng = np.random.default_rng(sum(shape) + 1)
+    x = rng.standard_normal((2,) + shape).astype(np.float32)
+    spec = solver.fft_forward(torch.from_numpy(x).cuda())
+    back = solver.fft_inverse(spec)
+    torch.cuda.synchronize()
+    ref = np.fft.rfftn(x.astype(np.float64), axes=(1, 2, 3))
+    got = spec.cpu().numpy()
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    rel2 = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    d_back = np.abs(back.cpu().numpy() - x).max() / np.abs(x).max()
+    print(f"  forward max {err:.2e} rel-L2 {rel2:.2e}; round trip max {d_back:.2e}", flush=True)
+    solver.close()
+    assert rel2 < 2e-7 and err < 2e-6
+    assert d_back < 2e-6
+
+
+@pytest.mark.parametrize("shape,n_var", [((512, 32, 32), 6), ((32, 512, 32), 2), ((32, 32, 512), 6),
+                                         ((384, 32, 48), 2), ((32, 48, 384), 2), ((32, 192, 48), 6)])
+def test_polycrystal_large_axis(shape, n_var):
+    cfg = cases.small_polycrystal(shape=shape, n_grains=6, seed=21, n_var=n_var)
+    compare(cfg, 2, f"polycrystal {shape} {n_var} variants")
