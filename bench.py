@@ -61,10 +61,10 @@ def sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, grid, n_var):
     """HBM bytes per launch of a stage from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated by a device copy), or None
-    if absent or taken on other sources."""
+    if absent, taken on other sources or on another grid or variant count."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -72,6 +72,8 @@ def measured_traffic(kernel):
     except (OSError, ValueError):
         return None
     if t.get("sources_sha256") != sources_digest():
+        return None
+    if t.get("grid") != list(grid) or t.get("n_var") != n_var:
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
@@ -733,7 +735,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(dom[3] / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dom[0]),
+        "traffic": measured_traffic(dom[0], (n, n, n), V),
         "bytes_per_launch": round(dom[4]),
         "avg_launch_us": round(dom[2] * 1e3, 1),
         "launches": dom[1],
