@@ -183,9 +183,16 @@ __global__ __launch_bounds__(256) void k_xdft(const FArgs a, const uint16_t* __r
 // Complex sums along an axis of a [..][n][m][2][C] array for one (outer, kx):
 // forward: out[kk] = sum_t in[t] e^{-2 pi i k(kk) t / n} over the 2m kept k;
 // inverse: out[t] = sum_kk in[kk] e^{+2 pi i k(kk) t / n}.
-// One block per (outer, kx); the input column is staged in LDS.
+// One block per (outer, kx); the input column is staged in LDS. NT threads:
+// groups of kC lanes take the outputs in turn (24 groups: one kept mode each
+// at 2m = 24 forward; 32 groups for the inverse), so a block has enough
+// waves to hide the LDS latency of its sums.
+template <bool FWD> constexpr int ysum_threads() { return FWD ? 768 : 1024; }
+
 template <bool FWD>
-__global__ __launch_bounds__(256) void k_ysum(const FArgs a, const float* __restrict__ in, float* __restrict__ out) {
+__global__ __launch_bounds__(ysum_threads<FWD>()) void k_ysum(const FArgs a, const float* __restrict__ in,
+                                                              float* __restrict__ out) {
+  constexpr int NT = ysum_threads<FWD>(), NG = NT / kC;
   extern __shared__ float sm[];
   const int ny = a.ny, m = a.m, my = 2 * m;
   const int nin = FWD ? ny : my, nout = FWD ? my : ny;
@@ -194,14 +201,14 @@ __global__ __launch_bounds__(256) void k_ysum(const FArgs a, const float* __rest
   const int z = blockIdx.x / m, kx = blockIdx.x % m;
   const size_t in_base = (size_t)z * nin * m * 2 * kC + (size_t)kx * 2 * kC;
   const size_t out_base = (size_t)z * nout * m * 2 * kC + (size_t)kx * 2 * kC;
-  for (int i = threadIdx.x; i < nin * 2 * kC; i += 256) {
+  for (int i = threadIdx.x; i < nin * 2 * kC; i += NT) {
     const int t = i / (2 * kC), e = i % (2 * kC);
     col[i] = in[in_base + (size_t)t * m * 2 * kC + e];
   }
-  for (int i = threadIdx.x; i < ny; i += 256) tw[i] = a.twy[i];
+  for (int i = threadIdx.x; i < ny; i += NT) tw[i] = a.twy[i];
   __syncthreads();
   const int c = threadIdx.x % kC, g = threadIdx.x / kC;
-  for (int o = g; o < nout; o += 8) {
+  for (int o = g; o < nout; o += NG) {
     float re = 0.f, im = 0.f;
     if (FWD) {
       const int k = kept_freq(o, m, ny);
@@ -233,7 +240,12 @@ __global__ __launch_bounds__(256) void k_ysum(const FArgs a, const float* __rest
 
 // z pass: one block per kept (ky', kx): forward z sums to the 2m kept kz,
 // channel mixing by R(kz', ky', kx) (complex, C x C, BF16), inverse z sums.
-__global__ __launch_bounds__(256) void k_zmix(const FArgs a, const uint16_t* __restrict__ R) {
+// There are only 2m^2 blocks (288 at m = 12), so each has kZmixThreads
+// threads (32 groups of kC lanes) to keep the chip's SIMDs busy.
+constexpr int kZmixThreads = 1024;
+
+__global__ __launch_bounds__(kZmixThreads) void k_zmix(const FArgs a, const uint16_t* __restrict__ R) {
+  constexpr int NT = kZmixThreads, NG = NT / kC;
   extern __shared__ float sm[];
   const int nz = a.nz, m = a.m, my = 2 * m;
   float* col = sm;                                // [nz][2][C]
@@ -243,14 +255,14 @@ __global__ __launch_bounds__(256) void k_zmix(const FArgs a, const uint16_t* __r
   const int kyy = blockIdx.x / m, kx = blockIdx.x % m;
   const size_t zstride = (size_t)my * m * 2 * kC;
   const size_t base = (size_t)kyy * m * 2 * kC + (size_t)kx * 2 * kC;
-  for (int i = threadIdx.x; i < nz * 2 * kC; i += 256) {
+  for (int i = threadIdx.x; i < nz * 2 * kC; i += NT) {
     const int t = i / (2 * kC), e = i % (2 * kC);
     col[i] = a.X2[base + (size_t)t * zstride + e];
   }
-  for (int i = threadIdx.x; i < nz; i += 256) tw[i] = a.twz[i];
+  for (int i = threadIdx.x; i < nz; i += NT) tw[i] = a.twz[i];
   __syncthreads();
   const int c = threadIdx.x % kC, g = threadIdx.x / kC;
-  for (int kk = g; kk < my; kk += 8) {
+  for (int kk = g; kk < my; kk += NG) {
     const int k = kept_freq(kk, m, nz);
     float re = 0.f, im = 0.f;
     int j = 0;
@@ -267,7 +279,7 @@ __global__ __launch_bounds__(256) void k_zmix(const FArgs a, const uint16_t* __r
   }
   __syncthreads();
   // mixing: os[kz'][o] = sum_i R[kz'][ky'][kx][o][i] zs[kz'][i]
-  for (int kk = g; kk < my; kk += 8) {
+  for (int kk = g; kk < my; kk += NG) {
     const uint32_t* w = reinterpret_cast<const uint32_t*>(
         R + ((((size_t)kk * my + kyy) * m + kx) * kC + c) * kC * 2);
     float re = 0.f, im = 0.f;
@@ -283,7 +295,7 @@ __global__ __launch_bounds__(256) void k_zmix(const FArgs a, const uint16_t* __r
     os[(2 * kk + 1) * kC + c] = im;
   }
   __syncthreads();
-  for (int t = g; t < nz; t += 8) {
+  for (int t = g; t < nz; t += NG) {
     float re = 0.f, im = 0.f;
     int j = 0;  // k(kk) t mod nz
     for (int kk = 0; kk < my; ++kk) {
@@ -420,9 +432,9 @@ hipError_t forward(const FArgs& a, const float* eta_in, float* eta_out, hipStrea
   uint16_t* vout = a.vb;
   for (int l = 0; l < kLayers; ++l) {
     k_xdft<<<(rows + 4 * kDftRounds - 1) / (4 * kDftRounds), 256, lds_xdft(a), s>>>(a, vin);
-    k_ysum<true><<<a.nz * a.m, 256, lds_ysum(a, true), s>>>(a, a.X1, a.X2);
-    k_zmix<<<2 * a.m * a.m, 256, lds_zmix(a), s>>>(a, a.R + (size_t)l * a.r_stride);
-    k_ysum<false><<<a.nz * a.m, 256, lds_ysum(a, false), s>>>(a, a.Y2, a.Y1);
+    k_ysum<true><<<a.nz * a.m, ysum_threads<true>(), lds_ysum(a, true), s>>>(a, a.X1, a.X2);
+    k_zmix<<<2 * a.m * a.m, kZmixThreads, lds_zmix(a), s>>>(a, a.R + (size_t)l * a.r_stride);
+    k_ysum<false><<<a.nz * a.m, ysum_threads<false>(), lds_ysum(a, false), s>>>(a, a.Y2, a.Y1);
     k_xinv_mix<<<(rows + kInvRows * kInvGroups - 1) / (kInvRows * kInvGroups), 256, lds_xinv(a), s>>>(
         a, vin, vout, a.W + (size_t)l * kC * kC, a.b + (size_t)l * kC);
     uint16_t* t = vin;
