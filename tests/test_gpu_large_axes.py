@@ -47,3 +47,19 @@ def test_transform_large_axes(shape):
 def test_polycrystal_large_axis(shape, n_var):
     cfg = cases.small_polycrystal(shape=shape, n_grains=6, seed=21, n_var=n_var)
     compare(cfg, 2, f"polycrystal {shape} {n_var} variants")
+
+
+@pytest.mark.parametrize("shape", [(512, 32, 32), (32, 512, 32), (32, 32, 512), (384, 48, 32), (32, 192, 48)])
+def test_spectral_path_large_axis(shape):
+    """The homogeneous spectral path (one rotated stiffness, closed-form
+    mechanics per wavevector) with a large axis in each role, 10 steps of a
+    sphere nucleus, against the oracle."""
+    from paper_2302_13612_amd import inputs
+    from tests.test_gpu_batch import spectral_vs_oracle
+    batch = inputs.rve_batch(n_inst=2, seed=17, sizes=(32,))
+    cfg = cases.batch_instance_cfg(batch, 1)
+    nz, ny, nx = shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    r2 = (z - nz // 2) ** 2 + (y - ny // 2) ** 2 + (x - nx // 2) ** 2
+    cfg.update(shape=shape, eta0=(r2 <= 16).astype(np.float32)[None])
+    spectral_vs_oracle(cfg, 10, f"rotated sphere {shape}")
