@@ -3,7 +3,9 @@ lamellae workload (128 x 128 x 256, parent/twin stiffness contrast,
 Gaussian-random-field plastic strain, load ramped to -4e-3 over 2000 steps).
 
 Calls only the oracle and the seeded input generator. Run from the repository
-root:  python tests/golden/make_lamellae_trajectory.py [max_steps]
+root:
+
+    python tests/golden/make_lamellae_trajectory.py [max_steps] [--out PATH] [--state PATH]
 
 Checkpoints are appended as the run goes (every 50 steps, stress samples
 every 250 steps and after the first step), so a partial run is usable. For
@@ -11,6 +13,13 @@ each checkpoint after step n (0-based, i.e. after n+1 steps) it stores the
 order parameter at fixed random voxels and at up to 2048 voxels of the
 interface (0.05 < eta < 0.95), the stress of that step's equilibrium at fixed
 random voxels, and the step's reductions.
+
+--out writes the trajectory somewhere else than the stored file (a long run
+then never replaces it with a shorter one before it ends). --state keeps the
+oracle's full state (order parameter, strain, mean strain, sampling generator
+and the records so far) at every checkpoint and resumes from it when it
+exists; the oracle is deterministic, so a resumed run writes the same values
+as an uninterrupted one.
 """
 
 import os
@@ -34,7 +43,24 @@ N_SAMPLES = 2048
 ORACLE_TOL = 1e-9
 
 
-def main(max_steps):
+def _save_state(path, n, st, rng, rec, rand_idx):
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, n=n, eta=st.eta, eps=st.eps, ebar=st.ebar, rand_idx=rand_idx,
+             rng=np.array(repr(rng.bit_generator.state)),
+             **{"rec_" + k: np.asarray(v) for k, v in rec.items()})
+    os.replace(tmp, path)
+
+
+def _load_state(path, rng):
+    import ast
+    z = np.load(path)
+    rng.bit_generator.state = ast.literal_eval(str(z["rng"]))
+    rec = {k[4:]: list(z[k]) for k in z.files if k.startswith("rec_")}
+    st = pf.State(z["eta"], z["eps"], z["ebar"])
+    return int(z["n"]), st, rec, z["rand_idx"]
+
+
+def main(max_steps, out=OUT, state_path=None):
     cfg = inputs.single_crystal_lamellae()
     shape = cfg["shape"]
     tabs = cr.mg_tables(cfg["rotations"], cfg["variant_ids"])
@@ -49,8 +75,13 @@ def main(max_steps):
     ld = dict(stress_mask=cfg["stress_mask"])
     rec = dict(steps=[], eta_rand=[], iface_idx=[], iface_eta=[], sig_steps=[], sig_rand=[],
                eta_mean=[], sig_mean=[], G=[], ms_iters=[])
+    first = 0
+    if state_path and os.path.exists(state_path):
+        last, st, rec, rand_idx = _load_state(state_path, rng)
+        first = last + 1
+        print(f"resumed after step {last}", flush=True)
     t0 = time.time()
-    for n in range(max_steps):
+    for n in range(first, max_steps):
         ld["eps_bar"], ld["sig_bar"] = inputs.ramp_load(cfg, n)
         st, stats, sigma = pf.step(prob, st, epsp, ld)
         done = n + 1
@@ -76,12 +107,20 @@ def main(max_steps):
             rec["G"].append([stats["G_dw"], stats["G_gd"], stats["G_me"]])
             rec["ms_iters"].append(stats["ms_iters"])
             arrays = {k: np.asarray(v) for k, v in rec.items()}
-            tmp = OUT + ".tmp.npz"
+            tmp = out + ".tmp.npz"
             np.savez_compressed(tmp, rand_idx=rand_idx, shape=np.array(shape), **arrays)
-            os.replace(tmp, OUT)
+            os.replace(tmp, out)
+            if state_path:
+                _save_state(state_path, n, st, rng, rec, rand_idx)
             print(f"step {n} saved ({time.time() - t0:.0f} s, ms_iters {stats['ms_iters']}, "
                   f"eta_mean {stats['eta_mean'][0]:.6f})", flush=True)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2000)
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("max_steps", nargs="?", type=int, default=2000)
+    ap.add_argument("--out", default=OUT)
+    ap.add_argument("--state", default=None)
+    a = ap.parse_args()
+    main(a.max_steps, a.out, a.state)

@@ -261,3 +261,90 @@ def test_gradient_energy_of_a_sine():
     eta = np.broadcast_to(0.5 + a * np.sin(k * x), shape)[None].copy()
     vol = np.prod(shape) * dx ** 3
     np.testing.assert_allclose(pf.gradient_energy(eta, kappa, dx), kappa * a * a * k * k * vol / 2, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- several variants
+# Eq. (13) sums c1 f_a^2 f_b^2 over every pair of phases, the matrix
+# f_M = 1 - sum f (eq. (18)) included. The pins below do not restate the
+# oracle's loops: a value summed by hand, an algebraic identity of the pair
+# sum, the symmetry of the energy under exchanging any two phases, and the
+# exchange derivatives of single pair terms taken by finite differences.
+
+def test_double_well_three_variants_hand_sum():
+    # f = (0.1, 0.2, 0.3), f_M = 0.4: the six pair products f_a^2 f_b^2 are
+    # 0.0004, 0.0009, 0.0016, 0.0036, 0.0064, 0.0144, total 0.0273
+    A = 1e7
+    eta = np.array([0.1, 0.2, 0.3]).reshape(3, 1)
+    np.testing.assert_allclose(pf.double_well_density(eta, A), [0.0273 * A], rtol=1e-13)
+
+
+def test_double_well_pair_sum_identity():
+    # sum_{a<b} x_a^2 x_b^2 = ((sum x^2)^2 - sum x^4) / 2 over all phases
+    A = 3.0
+    rng = np.random.default_rng(11)
+    for V in (2, 3, 6):
+        eta = rng.random((V, 7)) * (1.2 / V) - 0.05
+        x = np.concatenate([eta, 1.0 - eta.sum(0, keepdims=True)])
+        expect = A * 0.5 * ((x ** 2).sum(0) ** 2 - (x ** 4).sum(0))
+        np.testing.assert_allclose(pf.double_well_density(eta, A), expect, rtol=1e-12)
+
+
+def test_double_well_symmetric_in_all_phases():
+    # swapping a variant with the matrix (or with another variant) leaves the
+    # energy unchanged: the matrix enters the pair sum like any variant
+    A = 1.0
+    rng = np.random.default_rng(12)
+    eta = rng.random((3, 9)) * 0.3
+    fm = 1.0 - eta.sum(0)
+    base = pf.double_well_density(eta, A)
+    for a in range(3):
+        sw = eta.copy()
+        sw[a] = fm                      # the old matrix becomes variant a
+        np.testing.assert_allclose(pf.double_well_density(sw, A), base, rtol=1e-12)
+    np.testing.assert_allclose(pf.double_well_density(eta[[2, 0, 1]], A), base, rtol=1e-13)
+
+
+def test_chemical_force_several_variants_exchange_derivatives():
+    # eq. (17), first term: chem_a = sum_{b != a} (d/df_a - d/df_b) of the pair
+    # term A f_a^2 f_b^2, b over the other variants and the matrix; each
+    # exchange derivative is taken here by central differences of the pair
+    # term in the direction e_a - e_b with every phase held independent.
+    A = 2.5e7
+    rng = np.random.default_rng(13)
+    V = 3
+    eta = rng.random((V, 11)) * 0.3
+    phases = np.concatenate([eta, 1.0 - eta.sum(0, keepdims=True)])
+    h = 1e-5
+
+    def pair(x, a, b):
+        return A * x[a] ** 2 * x[b] ** 2
+
+    expect = np.zeros_like(eta)
+    for a in range(V):
+        for b in range(V + 1):
+            if b == a:
+                continue
+            up, dn = phases.copy(), phases.copy()
+            up[a] += h
+            up[b] -= h
+            dn[a] -= h
+            dn[b] += h
+            expect[a] += (pair(up, a, b) - pair(dn, a, b)) / (2 * h)
+    np.testing.assert_allclose(pf.chemical_force(eta, A), expect, rtol=1e-8, atol=1e-8 * A)
+
+
+def test_chemical_force_exchange_forces_cancel_over_all_phases():
+    # the pairwise exchange forces are antisymmetric, so the forces of all
+    # V + 1 phases add up to zero; the matrix's own force is the force of
+    # variant 0 after the matrix and variant 0 trade places
+    A = 1e7
+    rng = np.random.default_rng(14)
+    eta = rng.random((3, 13)) * 0.3
+    fm = 1.0 - eta.sum(0)
+    chem = pf.chemical_force(eta, A)
+    sw = eta.copy()
+    sw[0] = fm
+    chem_m = pf.chemical_force(sw, A)[0]
+    total = chem.sum(0) + chem_m
+    np.testing.assert_allclose(total, 0.0, atol=1e-9 * A)
+    assert np.abs(chem).max() > 1e-3 * A
