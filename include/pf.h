@@ -212,7 +212,16 @@ int pf_init(const pf_problem *prob, void *workspace, size_t ws_bytes,
 int pf_step(pf_ctx *ctx, int32_t n_steps, const pf_load *load);
 
 /* Copy a field between the context and a caller device buffer of the same
- * layout (set = 0: context -> buf, set = 1: buf -> context), on the stream. */
+ * layout (set = 0: context -> buf, set = 1: buf -> context), on the stream.
+ * Setting the order parameters or the strain restarts the extrapolation of
+ * the next step's first fixed-point iterate from the field set; setting the
+ * strain also takes its mean (FP64, on the stream) as the mean strain of the
+ * state. A checkpoint is the order parameters and the strain read back; set
+ * into a context of the same problem they continue the run (to the fixed
+ * point's tolerance, since the extrapolation history is not part of it; bit
+ * for bit on the homogeneous spectral path, whose state is f alone).
+ * Errors: PF_EINVAL for an unknown selector, a null buffer, a set of the
+ * stress, or a get of the strain that the spectral path did not form. */
 int pf_fields(pf_ctx *ctx, int32_t which, int32_t set, float *buf);
 
 /* Synchronise the stream and return the reductions of the last step. */

@@ -1119,6 +1119,15 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         return fail(c, PF_ENOCONV, buf);
       }
       for (size_t k : iterating) {
+        const size_t b = status_base(c, k);
+        for (int j = 0; j < c->groups[k].ninst; ++j)
+          if (c->host_status[b + j].nonfinite) {
+            for (size_t kk : iterating) c->groups[kk].hist = 0;
+            return fail(c, PF_ENONFINITE,
+                        "non-finite strain in the fixed point of instance " + std::to_string(c->groups[k].members[j]));
+          }
+      }
+      for (size_t k : iterating) {
         Group& g = c->groups[k];
         g.cur = (g.cur + 1) % 4;
         g.args.eps = g.args.eps_out = g.ring[g.cur];
@@ -1191,6 +1200,10 @@ int pf_batch_fields(pf_ctx* c, int32_t inst, int32_t which, int32_t set, float* 
   if (set && which == PF_FIELD_ETA) {
     PF_TRY(refresh_gradient_energy(c, g));
     g.lap_valid = false;
+  }
+  if (set && which == PF_FIELD_STRAIN) {
+    hipError_t e = pfl::strain_mean(g.args, f, j, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "pf_fields: strain mean");
   }
   return PF_OK;
 }

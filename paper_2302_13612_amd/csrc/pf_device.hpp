@@ -146,6 +146,9 @@ int rows_per_block(int nx);
 int x_blocks(const KArgs& a);
 int z_blocks(const KArgs& a, int ncomp);
 hipError_t step_begin(const KArgs& a, hipStream_t s);
+// mean of each component of instance inst of a strain field -> its
+// DevState::ebar_field (after the caller replaced the strain)
+hipError_t strain_mean(const KArgs& a, const float* field, int inst, hipStream_t s);
 hipError_t ms_x_forward(const KArgs& a, hipStream_t s);
 hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t ms_z_green(const KArgs& a, hipStream_t s);

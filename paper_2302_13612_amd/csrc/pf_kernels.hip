@@ -741,6 +741,26 @@ __global__ void k_step_begin(const KArgs a) {
   st->st.iters = 0;
 }
 
+// Mean of each strain component of instance j of a caller-set field (one
+// block per component, FP64, fixed summation order): the mean strain the
+// field in memory carries, taken as the base of the next step's first
+// iterate.
+__global__ __launch_bounds__(1024) void k_strain_mean(const KArgs a, const float* __restrict__ f, int j) {
+  __shared__ double part[1024];
+  const int c = blockIdx.x;
+  const size_t nvox = (size_t)a.nx * a.ny * a.nz;
+  const float* src = f + ((size_t)c * a.ninst + j) * nvox;
+  double acc = 0.0;
+  for (size_t i = threadIdx.x; i < nvox; i += blockDim.x) acc += (double)src[i];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h /= 2) {
+    if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.state[j].ebar_field[c] = part[0] / (double)nvox;
+}
+
 // -------------------------------------------------------------- finalizes
 // Deterministic sum over nblk blocks of Q partials ([nblk][Q], FP64). The
 // block reads the array as one flat run with a stride S that is a multiple
@@ -832,6 +852,11 @@ __device__ inline void fin_res(const KArgs& a, int inst, int nblk, double* scrat
   st->st.residual = r;
   st->st.iters += 1;
   st->st.done = r <= a.tol ? 1 : 0;
+  // a non-finite strain never converges: stop iterating and report it
+  if (!isfinite(s[0]) || !isfinite(s[1])) {
+    st->st.nonfinite = 1;
+    st->st.done = 1;
+  }
   for (int c = 0; c < 6; ++c) {
     st->ebar_field[c] = st->ebar_next[c];
     st->ebar_cur[c] = st->ebar_next[c];
@@ -1093,6 +1118,11 @@ static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
     case 512: { constexpr int N = 512; BODY; } break; \
     default: return hipErrorInvalidValue;     \
   }
+
+hipError_t strain_mean(const KArgs& a, const float* field, int inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_strain_mean, dim3(6), dim3(1024), 0, s, a, field, inst);
+  return hipGetLastError();
+}
 
 hipError_t step_begin(const KArgs& a, hipStream_t st) {
   k_step_begin<<<(a.ninst + 63) / 64, 64, 0, st>>>(a);
