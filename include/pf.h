@@ -311,6 +311,18 @@ int pf_nt_layer_input_grad(int32_t B, int32_t C, int64_t nvox, const float *W, c
 int pf_nt_outer_workspace(int32_t B, int32_t MA, int32_t MC, int64_t nvox, size_t *bytes);
 int pf_nt_outer_sum(int32_t B, int32_t MA, int32_t MC, int64_t nvox, const float *X, const float *Y,
                     float *out, int32_t accumulate, float *work, size_t work_bytes, void *stream);
+/* pf_nt_outer_sum without a workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): the same kernels and results, bit for bit, with the
+ * per-chunk partials in a fixed array of the library (16 MiB on each GPU it
+ * runs on, kept until the process ends; its address is looked up on the
+ * first call on a device). The call allocates nothing. PF_ENOMEM when the
+ * partials (pf_nt_outer_workspace bytes) exceed 16 MiB, PF_EINVAL as
+ * pf_nt_outer_sum, PF_EDEVICE when the stream's device cannot be resolved.
+ * Every call on one GPU shares the array: calls that overlap on a GPU (two
+ * streams, two threads) race; calls in order on one stream do not. */
+int pf_nt_outer_sum_noalloc(int32_t B, int32_t MA, int32_t MC, int64_t nvox, const float *X,
+                            const float *Y, float *out, int32_t accumulate, void *stream);
 int pf_nt_cond_grad(int32_t B, int32_t C, const float *dK, const float *cond, float *dP, float *dp,
                     void *stream);
 int pf_nt_adam(int64_t n, float *w, const float *g, float *m, float *v, float lr, float beta1,

@@ -120,6 +120,7 @@ def load():
     lib.pf_nt_layer_input_grad.argtypes = [i32, i32, i64] + [vp] * 5
     lib.pf_nt_outer_workspace.argtypes = [i32, i32, i32, i64, ctypes.POINTER(sz)]
     lib.pf_nt_outer_sum.argtypes = [i32, i32, i32, i64, vp, vp, vp, i32, vp, sz, vp]
+    lib.pf_nt_outer_sum_noalloc.argtypes = [i32, i32, i32, i64, vp, vp, vp, i32, vp]
     lib.pf_nt_cond_grad.argtypes = [i32, i32] + [vp] * 5
     lib.pf_nt_adam.argtypes = [i64, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
     lib.pf_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]

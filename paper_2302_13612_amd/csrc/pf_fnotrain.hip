@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "../../include/pf.h"
 
 namespace pft2 {
@@ -245,6 +247,38 @@ __global__ __launch_bounds__(256) void k_adam(long n, float* __restrict__ w, con
 
 hipError_t done() { return hipGetLastError(); }
 
+// Per-chunk partials of the outer sums for callers that cannot allocate: a
+// fixed array of the library, 16 MiB on every GPU it runs on, held until the
+// process ends. Host code never uses the array's name as an address: its
+// device address is taken once per device (hipGetSymbolAddress, with that
+// device current) and kept in scratch_dev.
+constexpr size_t kScratchFloats = (size_t)4 << 20;
+static __device__ __align__(256) float scratch[kScratchFloats];
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+float* scratch_dev[kMaxDevices] = {};
+
+// Device address of this library's scratch array on the device of stream s
+// (NULL: the current device).
+int scratch_of(hipStream_t s, float** out) {
+  int dev = 0;
+  hipError_t e = s ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) return PF_EDEVICE;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) return PF_EDEVICE;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return PF_EDEVICE;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) hipSetDevice(cur);
+    if (e != hipSuccess || !p) return PF_EDEVICE;
+    scratch_dev[dev] = static_cast<float*>(p);
+  }
+  *out = scratch_dev[dev];
+  return PF_OK;
+}
+
 #define PF_SWITCH_C(c, BODY)                                     \
   switch (c) {                                                    \
     case 4: { constexpr int CC = 4; BODY; } break;                \
@@ -323,6 +357,23 @@ int pf_nt_outer_sum(int32_t B, int32_t MA, int32_t MC, int64_t nvox, const float
   const long nchunk = (long)((nvox + kChunk - 1) / kChunk);
   const dim3 grid((unsigned)(B * nchunk), (unsigned)((MA + kTile - 1) / kTile), (unsigned)((MC + kTile - 1) / kTile));
   hipStream_t s = (hipStream_t)stream;
+  k_outer_part<<<grid, kTile * kTile, 0, s>>>(B, MA, MC, nvox, X, Y, work);
+  k_reduce<<<blocks((long)MA * MC), 256, 0, s>>>((long)MA * MC, (long)B * nchunk, work, out, accumulate);
+  return done() == hipSuccess ? PF_OK : PF_EDEVICE;
+}
+
+int pf_nt_outer_sum_noalloc(int32_t B, int32_t MA, int32_t MC, int64_t nvox, const float* X, const float* Y,
+                            float* out, int32_t accumulate, void* stream) {
+  size_t need = 0;
+  if (pf_nt_outer_workspace(B, MA, MC, nvox, &need) != PF_OK || !X || !out) return PF_EINVAL;
+  if (need > sizeof(float) * kScratchFloats) return PF_ENOMEM;
+  float* work = nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  const int rc = scratch_of(s, &work);
+  if (rc != PF_OK) return rc;
+  // every partial is written before k_reduce reads it: nothing to clear
+  const long nchunk = (long)((nvox + kChunk - 1) / kChunk);
+  const dim3 grid((unsigned)(B * nchunk), (unsigned)((MA + kTile - 1) / kTile), (unsigned)((MC + kTile - 1) / kTile));
   k_outer_part<<<grid, kTile * kTile, 0, s>>>(B, MA, MC, nvox, X, Y, work);
   k_reduce<<<blocks((long)MA * MC), 256, 0, s>>>((long)MA * MC, (long)B * nchunk, work, out, accumulate);
   return done() == hipSuccess ? PF_OK : PF_EDEVICE;
