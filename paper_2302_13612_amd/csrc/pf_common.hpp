@@ -330,9 +330,9 @@ __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* l
       const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
       const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);
       const float2 X = cadd(ev, cmul(tw_n[k], od));
-      if (valid) spec[c * cstride + rowoff + k] = X;
+      if (valid) gst(spec + c * cstride + rowoff + k, X);
     }
-    if (t == 0 && valid) spec[c * cstride + rowoff + M] = make_float2(v[c][0].x - v[c][0].y, 0.f);
+    if (t == 0 && valid) gst(spec + c * cstride + rowoff + M, make_float2(v[c][0].x - v[c][0].y, 0.f));
   }
 }
 
@@ -374,9 +374,9 @@ __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow
     const float2 d = make_float2(zk.x - zm.x, zk.y + zm.y);
     const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);
     const float2 X = cadd(ev, cmul(tw.split[m], od));
-    if (valid) dst[k] = X;
+    if (valid) gst(dst + k, X);
   }
-  if (t == 0 && valid) dst[M] = make_float2(v[0].x - v[0].y, 0.f);
+  if (t == 0 && valid) gst(dst + M, make_float2(v[0].x - v[0].y, 0.f));
 }
 
 // Inverse of one spectral row, in two parts so the global loads of the next
@@ -395,8 +395,8 @@ template <int M>
 __device__ __forceinline__ void c2r_fetch(RowFetch<M>& f, int t, bool valid, const float2* __restrict__ srow) {
   constexpr int E = XPlan<M>::E, T = M / E;
 #pragma unroll
-  for (int m = 0; m < E; ++m) f.x[m] = valid ? srow[t + T * m] : make_float2(0.f, 0.f);
-  f.last = (valid && t == 0) ? srow[M] : make_float2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) f.x[m] = valid ? gld(srow + t + T * m) : make_float2(0.f, 0.f);
+  f.last = (valid && t == 0) ? gld(srow + M) : make_float2(0.f, 0.f);
 }
 
 template <int M>

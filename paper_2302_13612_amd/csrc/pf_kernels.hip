@@ -54,7 +54,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
     // (fetching it one component ahead costs registers and gains nothing)
 #pragma unroll
     for (int m = 0; m < E; ++m)
-      old_c[m] = valid ? *reinterpret_cast<const float2*>(prev + c * vs + rbase + 2 * (t + T * m))
+      old_c[m] = valid ? gld(reinterpret_cast<const float2*>(prev + c * vs + rbase + 2 * (t + T * m)))
                        : make_float2(0.f, 0.f);
     const float shift = (float)(st->ebar_cur[c] - st->ebar_base[c]);
     const float w = c < 3 ? 1.f : 2.f;
@@ -70,7 +70,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
         dsum += dx0 * dx0 + dx1 * dx1;
         nsum += v[m].x * v[m].x + v[m].y * v[m].y;
         // on a first iteration the output is the field read above as the old iterate
-        *reinterpret_cast<float2*>(a.eps_out + off) = v[m];
+        gst(reinterpret_cast<float2*>(a.eps_out + off), v[m]);
       }
     }
     acc[0] += (double)(w * dsum);
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
       if (a.part_pc && q < a.nv) {
         float2 old[E];
 #pragma unroll
-        for (int m = 0; m < E; ++m) old[m] = *reinterpret_cast<const float2*>(dst + rbase + 2 * (t + T * m));
+        for (int m = 0; m < E; ++m) old[m] = gld(reinterpret_cast<const float2*>(dst + rbase + 2 * (t + T * m)));
 #pragma unroll
         for (int m = 0; m < E; ++m)
           dmax = fmaxf(dmax, fmaxf(fabsf(v[m].x - old[m].x), fabsf(v[m].y - old[m].y)));
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
       for (int m = 0; m < E; ++m) {
         const int x0 = 2 * (t + T * m);
         if (q < a.nv && (!isfinite(v[m].x) || !isfinite(v[m].y))) bad[0] += 1.0;
-        *reinterpret_cast<float2*>(dst + rbase + x0) = v[m];
+        gst(reinterpret_cast<float2*>(dst + rbase + x0), v[m]);
       }
     }
     cur = nxt;
@@ -200,11 +200,12 @@ __global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_y(const KArgs a) {
   float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
+  // plain loads (measured faster here than with the hint), streaming stores
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * a.sh] : make_float2(0.f, 0.f);
   fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, a.tw_y);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * a.sh] = v[m];
+    for (int m = 0; m < E; ++m) gst(col + (size_t)(t + T * m) * a.sh, v[m]);
   }
 }
 
@@ -439,7 +440,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   float2* col = a.spec + q * cs + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) v[m] = valid ? gld(col + (size_t)(t + T * m) * zs) : make_float2(0.f, 0.f);
   TwCache<N, Plan<N>, 1> twf;
   twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
     fft_pencil<N, -1>(v, view, t, twf.conj());
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
+      for (int m = 0; m < E; ++m) gst(col + (size_t)(t + T * m) * zs, v[m]);
     }
   }
   if (want_g) {
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
     float2* gcol = mode == 2 ? col : col + (size_t)a.nv * cs;
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) gcol[(size_t)(t + T * m) * zs] = g[m];
+      for (int m = 0; m < E; ++m) gst(gcol + (size_t)(t + T * m) * zs, g[m]);
     }
   }
   // partials ordered [inst][variant][ky][tile] so each instance's are contiguous

@@ -47,7 +47,7 @@ __device__ __forceinline__ int opaque_zero() {
 // vector register, so no 64-bit per-lane addresses are kept live. A field
 // component holds fewer than 2^30 elements (the host checks the batch size).
 __device__ __forceinline__ float2 ld_f2(const float* base, uint32_t elem) {
-  return *reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + (elem << 2));
+  return gld(reinterpret_cast<const float2*>(reinterpret_cast<const char*>(base) + (elem << 2)));
 }
 
 // Inputs of one packed sample (voxels x0, x0+1) of a row.
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
       // (eps_out may be the oldest history field: read above, same element)
 #pragma unroll
       for (int c = 0; c < 6; ++c)
-        *reinterpret_cast<float2*>(a.eps_out + c * vs + rbase + 2 * k) = s.e[c];
+        gst(reinterpret_cast<float2*>(a.eps_out + c * vs + rbase + 2 * k), s.e[c]);
     }
     float o[2][6];
     float e[2][6], ep[2][6], et[2][V];
