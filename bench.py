@@ -255,8 +255,8 @@ def bench_rve_batch(args):
         timed = bs.autotune(cache=args.tune_cache)
         tune_ms = 1e3 * (time.perf_counter() - t0)
         for i, inst in enumerate(insts):
-            plans.setdefault(str(inst["shape"][0]), list(bs.plan(i)))
-        log(f"autotuned {timed} size groups in {tune_ms:.0f} ms: tiles (y, z) {plans}")
+            plans.setdefault(str(inst["shape"][0]), bs.plan(i))
+        log(f"autotuned {timed} size groups in {tune_ms:.0f} ms: plans {plans}")
     eb = np.stack([inst["eps_bar"] for inst in insts])
     steps = args.steps if args.steps_given else batch["steps"]
     every = batch["save_every"]
@@ -658,8 +658,8 @@ def main():
     plan = None
     if not args.no_tune:
         solver.autotune(cache=args.tune_cache)
-        plan = list(solver.plan())
-        log(f"autotuned tiles (y, z): {plan}")
+        plan = solver.plan()
+        log(f"autotuned plan: {plan}")
     iterated = args.pf_max_iter > 1
     # with the fixed point over the update its further forward passes are
     # timed (they and the update's passes dominate the step)

@@ -233,21 +233,54 @@ int pf_stats_get(pf_ctx *ctx, pf_stats *out);
  * spec is overwritten. ncomp in 1..6. */
 int pf_fft(pf_ctx *ctx, int32_t direction, int32_t ncomp, float *real, void *spec);
 
-/* Autotuner (launch plans of a batched launch picked by timing on the device,
- * for uneven RVE sizes): for every group of same-size instances, the column
- * tile of the y passes (8 or 16 columns per block) and, for groups that can
- * take the homogeneous spectral path, of its z pass, each candidate timed on
- * the group's own spectral buffer (zeroed first; it holds nothing between
- * steps; the instances' state is kept). The tile changes no arithmetic: a
- * tuned context computes bit for bit what an untuned one does. cache_path
- * (may be NULL): a text file of one JSON object per line, keyed by the
- * device's architecture name and compute-unit count and by the group's grid,
- * instance count, n_var and path; an entry found there is applied without
- * timing (unless flags has PF_TUNE_RETIME) and each timed group is appended.
- * Synchronises the stream; not during graph capture; call between steps.
- * *n_timed (may be NULL) receives the number of groups timed. */
+/* Launch plan of a group of same-size instances: for each column pass the
+ * FFT plan variant (radix split and elements per thread, see pf_fft_plan)
+ * and the column tile (pencils of consecutive kx per block).
+ *   ytile, yplan:       y passes (tile 8 or 16, variant 0, 1 or 2)
+ *   ztile_ms, zplan_ms: Green z pass of the fixed point (8 or 16; 0 or 1)
+ *   zplan_ac:           z pass of the Allen-Cahn update (16 columns; 0, 1, 2)
+ *   ztile_kh, zplan_kh: z pass of the homogeneous spectral path (8 or 16; 0, 1)
+ * A plan whose block would exceed 1024 threads does not exist. */
+typedef struct {
+  int32_t ytile, yplan;
+  int32_t ztile_ms, zplan_ms;
+  int32_t zplan_ac;
+  int32_t ztile_kh, zplan_kh;
+} pf_plan;
+
+/* Autotuner (the FFT plans and tiles of the column passes picked by timing on
+ * the device; Sec. 3 solves in Fourier space, the plans are this
+ * implementation's): for every group of same-size instances, each pass's
+ * candidates (y: 3 plan variants x 2 tiles; Green z: 2 x 2; Allen-Cahn z: 3;
+ * spectral z: 2 x 2; those that fit a block) are timed within the passes a
+ * step runs around that pass (x forward, y forward, z, y inverse of a
+ * fixed-point iteration, an Allen-Cahn update or a spectral step), on the
+ * group's own fields and spectral buffer (zeroed first; it holds nothing
+ * between steps; no state field is written and the instances' FP64 state is
+ * kept), best of two alternating rounds of 10 sequences. Plans differ in rounding only (each is
+ * the same transform), so a tuned context matches an untuned one to FP32
+ * round-off. cache_path (may be NULL): a text file of one JSON object per
+ * line, keyed by the device's architecture name and compute-unit count and by
+ * the group's grid, instance count, n_var and path, holding the plan and every
+ * candidate's time; an entry found there is applied without timing (unless
+ * flags has PF_TUNE_RETIME) and each timed group is appended. Synchronises
+ * the stream; not during graph capture; call between steps. *n_timed (may be
+ * NULL) receives the number of groups timed. */
 #define PF_TUNE_RETIME 1u
 int pf_autotune(pf_ctx *ctx, const char *cache_path, uint32_t flags, int32_t *n_timed);
+
+/* Plan of the group holding instance inst (the defaults until tuned or set). */
+int pf_batch_plan(pf_ctx *ctx, int32_t inst, pf_plan *out);
+
+/* Set the plan of the group holding instance inst (e.g. one read from a
+ * cache); PF_EINVAL if a pass has no such plan for the group's grid. */
+int pf_batch_set_plan(pf_ctx *ctx, int32_t inst, const pf_plan *plan);
+
+/* FFT plan variant of an axis length n: elements per thread, radix of each
+ * Stockham stage (radices[8]) and the stage count. PF_EINVAL for an
+ * unsupported length or variant (0, 1, 2). */
+int pf_fft_plan(int32_t n, int32_t variant, int32_t *elems_per_thread, int32_t *radices,
+                int32_t *n_stages);
 
 /* Spectral convolution of the learned stepper for training (the layers
  * v_l = GELU(W v + b + K v) of a Fourier neural operator; K v keeps 2m x 2m x m
@@ -327,10 +360,6 @@ int pf_nt_cond_grad(int32_t B, int32_t C, const float *dK, const float *cond, fl
                     void *stream);
 int pf_nt_adam(int64_t n, float *w, const float *g, float *m, float *v, float lr, float beta1,
                float beta2, float eps, int32_t step, void *stream);
-
-/* Plan of the group holding instance inst: *ytile the y-pass tile, *ztile the
- * spectral z-pass tile (0 if the group never takes that path). */
-int pf_batch_plan(pf_ctx *ctx, int32_t inst, int32_t *ytile, int32_t *ztile);
 
 /* Per-kernel timing with HIP events on the context's stream: enable (1) or
  * disable (0) and reset; read returns up to max_n entries of name, launch

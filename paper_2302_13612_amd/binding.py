@@ -22,6 +22,8 @@ ERROR_NAMES = {PF_EINVAL: "PF_EINVAL", PF_ENOMEM: "PF_ENOMEM", PF_EDEVICE: "PF_E
 PF_H_LINEAR, PF_H_QUINTIC = 0, 1
 PF_STEP_SAVE_STRESS, PF_STEP_FIXED_POINT = 1, 2
 PF_FIELD_ETA, PF_FIELD_STRAIN, PF_FIELD_STRESS = 0, 1, 2
+# pf_plan fields, in order
+PLAN_FIELDS = ("ytile", "yplan", "ztile_ms", "zplan_ms", "zplan_ac", "ztile_kh", "zplan_kh")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -123,7 +125,9 @@ def load():
     lib.pf_nt_outer_sum_noalloc.argtypes = [i32, i32, i32, i64, vp, vp, vp, i32, vp]
     lib.pf_nt_cond_grad.argtypes = [i32, i32] + [vp] * 5
     lib.pf_nt_adam.argtypes = [i64, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
-    lib.pf_batch_plan.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    lib.pf_batch_plan.argtypes = [vp, i32, ctypes.POINTER(PfPlan)]
+    lib.pf_batch_set_plan.argtypes = [vp, i32, ctypes.POINTER(PfPlan)]
+    lib.pf_fft_plan.argtypes = [i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
     lib.pf_vmap_workspace_size.argtypes = [i32, i32, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
     lib.pf_vmap_build.argtypes = [i32, i32, i32, ctypes.c_double, i32, vp, vp, ctypes.c_size_t, vp, vp]
     lib.pf_vmap_to_cells.argtypes = [ctypes.c_int64, vp, i32, i32, vp, vp, vp]
@@ -226,10 +230,31 @@ def _autotune(obj, cache, retime):
     return n.value
 
 
+class PfPlan(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int32) for name in PLAN_FIELDS]
+
+
 def _plan(obj, inst):
-    y, z = ctypes.c_int32(), ctypes.c_int32()
-    obj._check(obj.lib.pf_batch_plan(obj.ctx, inst, ctypes.byref(y), ctypes.byref(z)), "pf_batch_plan")
-    return y.value, z.value
+    p = PfPlan()
+    obj._check(obj.lib.pf_batch_plan(obj.ctx, inst, ctypes.byref(p)), "pf_batch_plan")
+    return {name: getattr(p, name) for name in PLAN_FIELDS}
+
+
+def _set_plan(obj, inst, plan):
+    p = PfPlan(**{name: int(plan[name]) for name in PLAN_FIELDS})
+    obj._check(obj.lib.pf_batch_set_plan(obj.ctx, inst, ctypes.byref(p)), "pf_batch_set_plan")
+
+
+def fft_plan(n, variant):
+    """(elements per thread, radices of the stages) of FFT plan variant
+    `variant` on an axis of length n."""
+    lib = load()
+    e, ns = ctypes.c_int32(), ctypes.c_int32()
+    r = (ctypes.c_int32 * 8)()
+    rc = lib.pf_fft_plan(n, variant, ctypes.byref(e), r, ctypes.byref(ns))
+    if rc != PF_OK:
+        raise PfError(rc, f"pf_fft_plan({n}, {variant})")
+    return e.value, [r[i] for i in range(ns.value)]
 
 
 class Solver:
@@ -398,8 +423,11 @@ class Solver:
         return _autotune(self, cache, retime)
 
     def plan(self):
-        """(y-pass tile, spectral z-pass tile or 0)."""
+        """Launch plan of the column passes (dict of the pf_plan fields)."""
         return _plan(self, 0)
+
+    def set_plan(self, plan):
+        _set_plan(self, 0, plan)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -545,8 +573,11 @@ class BatchSolver:
         return _autotune(self, cache, retime)
 
     def plan(self, inst):
-        """(y-pass tile, spectral z-pass tile or 0) of the instance's group."""
+        """Launch plan of the instance's group (dict of the pf_plan fields)."""
         return _plan(self, inst)
+
+    def set_plan(self, inst, plan):
+        _set_plan(self, inst, plan)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -127,6 +127,32 @@ template <> struct Plan<256> { static constexpr int E = 8;  using R = Radices<8,
 template <> struct Plan<384> { static constexpr int E = 12; using R = Radices<4, 4, 4, 2, 3>; };
 template <> struct Plan<512> { static constexpr int E = 8;  using R = Radices<8, 8, 8>; };
 
+// Alternative plans of the y and z passes, picked per grid by the autotuner:
+// variant 0 is Plan<N>; variant 1 holds fewer elements per thread (more
+// threads per pencil, fewer registers, more exchange stages); variant 2 holds
+// more (fewer threads, more registers). Each is the same transform with its
+// own radix split, so results differ only by rounding.
+template <int N, int K> struct PlanV;
+template <int N> struct PlanV<N, 0> { using P = Plan<N>; };
+template <> struct PlanV<32, 1>  { struct P { static constexpr int E = 4;  using R = Radices<4, 4, 2>; }; };
+template <> struct PlanV<48, 1>  { struct P { static constexpr int E = 6;  using R = Radices<2, 2, 2, 2, 3>; }; };
+template <> struct PlanV<64, 1>  { struct P { static constexpr int E = 4;  using R = Radices<4, 4, 4>; }; };
+template <> struct PlanV<96, 1>  { struct P { static constexpr int E = 6;  using R = Radices<2, 2, 2, 2, 2, 3>; }; };
+template <> struct PlanV<128, 1> { struct P { static constexpr int E = 4;  using R = Radices<4, 4, 4, 2>; }; };
+template <> struct PlanV<192, 1> { struct P { static constexpr int E = 6;  using R = Radices<2, 2, 2, 2, 2, 2, 3>; }; };
+template <> struct PlanV<256, 1> { struct P { static constexpr int E = 4;  using R = Radices<4, 4, 4, 4>; }; };
+template <> struct PlanV<384, 1> { struct P { static constexpr int E = 6;  using R = Radices<2, 2, 2, 2, 2, 2, 2, 3>; }; };
+template <> struct PlanV<512, 1> { struct P { static constexpr int E = 4;  using R = Radices<4, 4, 4, 4, 2>; }; };
+template <> struct PlanV<32, 2>  { struct P { static constexpr int E = 16; using R = Radices<8, 4>; }; };
+template <> struct PlanV<48, 2>  { struct P { static constexpr int E = 24; using R = Radices<4, 4, 3>; }; };
+template <> struct PlanV<64, 2>  { struct P { static constexpr int E = 16; using R = Radices<8, 8>; }; };
+template <> struct PlanV<96, 2>  { struct P { static constexpr int E = 24; using R = Radices<4, 4, 2, 3>; }; };
+template <> struct PlanV<128, 2> { struct P { static constexpr int E = 16; using R = Radices<8, 4, 4>; }; };
+template <> struct PlanV<192, 2> { struct P { static constexpr int E = 24; using R = Radices<4, 4, 4, 3>; }; };
+template <> struct PlanV<256, 2> { struct P { static constexpr int E = 16; using R = Radices<8, 8, 4>; }; };
+template <> struct PlanV<384, 2> { struct P { static constexpr int E = 24; using R = Radices<4, 4, 4, 2, 3>; }; };
+template <> struct PlanV<512, 2> { struct P { static constexpr int E = 16; using R = Radices<8, 8, 8>; }; };
+
 // Plans of the x pass (half-length complex transforms of real rows). Fewer
 // elements per thread leave registers for the fused per-voxel physics.
 template <int M> struct XPlan;

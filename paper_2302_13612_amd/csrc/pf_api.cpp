@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
+#include <initializer_list>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -1274,10 +1276,18 @@ int pf_fft(pf_ctx* c, int32_t direction, int32_t ncomp, float* real, void* spec)
 }
 
 // ---------------------------------------------------------------- autotuner
-// Per size group: the column tile (8 or 16 columns per block) of the y passes
-// and of the spectral path's z pass, picked by timing the candidates on the
-// group's own spectral buffer (zeroed first: it holds nothing between steps)
-// and kept in the context; optionally cached as one JSON object per line.
+// Per size group, the launch plan of every column pass: for the y passes the
+// FFT plan variant (radix split and elements per thread, 3 candidates) and
+// the column tile (8 or 16 pencils per block); for the Green z pass of the
+// fixed point the plan variant (2) and tile (8 or 16); for the Allen-Cahn z
+// pass the plan variant (3); for the spectral path's z pass the plan variant
+// (2) and tile (8 or 16). Candidates whose block would exceed 1024 threads
+// are skipped. Each pass is timed within the passes a step runs around it, on
+// the group's own fields and spectral buffer (zeroed first: it holds nothing
+// between steps; no field of the state is written and the instances' FP64
+// state is saved and restored); candidates alternate over two rounds and the
+// best time counts. The choice is kept in the context and
+// optionally cached as one JSON object per line.
 }  // extern "C"
 
 namespace {
@@ -1287,32 +1297,49 @@ struct TuneKey {
   int cus, nx, ny, nz, ninst, nv, spectral;
 };
 
+// candidate lists of the passes, in the order their times are written
+struct Cand {
+  int plan, tile;
+};
+constexpr Cand kYCand[6] = {{0, 8}, {0, 16}, {1, 8}, {1, 16}, {2, 8}, {2, 16}};
+constexpr Cand kZmsCand[4] = {{0, 8}, {0, 16}, {1, 8}, {1, 16}};
+constexpr Cand kZacCand[3] = {{0, 16}, {1, 16}, {2, 16}};
+constexpr Cand kZkhCand[4] = {{0, 8}, {0, 16}, {1, 8}, {1, 16}};
+
 // an entry as written, and the same fields as read back
 const char* kTuneOut =
     "{\"device\":\"%s\",\"cus\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"ninst\":%d,\"nv\":%d,"
-    "\"spectral\":%d,\"ytile\":%d,\"ztile\":%d";
+    "\"spectral\":%d,\"ytile\":%d,\"yplan\":%d,\"ztile_ms\":%d,\"zplan_ms\":%d,\"zplan_ac\":%d,"
+    "\"ztile_kh\":%d,\"zplan_kh\":%d";
 const char* kTuneIn =
     "{\"device\":\"%127[^\"]\",\"cus\":%d,\"nx\":%d,\"ny\":%d,\"nz\":%d,\"ninst\":%d,\"nv\":%d,"
-    "\"spectral\":%d,\"ytile\":%d,\"ztile\":%d";
+    "\"spectral\":%d,\"ytile\":%d,\"yplan\":%d,\"ztile_ms\":%d,\"zplan_ms\":%d,\"zplan_ac\":%d,"
+    "\"ztile_kh\":%d,\"zplan_kh\":%d";
 
 bool same_key(const TuneKey& a, const TuneKey& b) {
   return std::strcmp(a.dev, b.dev) == 0 && a.cus == b.cus && a.nx == b.nx && a.ny == b.ny && a.nz == b.nz &&
          a.ninst == b.ninst && a.nv == b.nv && a.spectral == b.spectral;
 }
 
-// last entry of the cache for key (entries are appended), or false
-bool tune_cache_read(const char* path, const TuneKey& key, int& ytile, int& ztile) {
+// a plan every pass of a group of this grid can launch
+bool plan_valid(const pf_plan& p, int ny, int nz) {
+  return pfl::plan_fits(0, ny, p.yplan, p.ytile) && pfl::plan_fits(1, nz, p.zplan_ms, p.ztile_ms) &&
+         pfl::plan_fits(2, nz, p.zplan_ac, 16) && pfl::plan_fits(3, nz, p.zplan_kh, p.ztile_kh);
+}
+
+// last valid entry of the cache for key (entries are appended), or false
+bool tune_cache_read(const char* path, const TuneKey& key, pf_plan& plan) {
   FILE* f = std::fopen(path, "r");
   if (!f) return false;
-  char line[1024];
+  char line[4096];
   bool hit = false;
   while (std::fgets(line, sizeof(line), f)) {
     TuneKey k{};
-    int y = 0, z = 0;
-    if (std::sscanf(line, kTuneIn, k.dev, &k.cus, &k.nx, &k.ny, &k.nz, &k.ninst, &k.nv, &k.spectral, &y, &z) == 10 &&
-        same_key(k, key) && (y == 8 || y == 16) && (z == 0 || z == 8 || z == 16)) {
-      ytile = y;
-      ztile = z;
+    pf_plan p{};
+    if (std::sscanf(line, kTuneIn, k.dev, &k.cus, &k.nx, &k.ny, &k.nz, &k.ninst, &k.nv, &k.spectral, &p.ytile,
+                    &p.yplan, &p.ztile_ms, &p.zplan_ms, &p.zplan_ac, &p.ztile_kh, &p.zplan_kh) == 15 &&
+        same_key(k, key) && plan_valid(p, key.ny, key.nz)) {
+      plan = p;
       hit = true;
     }
   }
@@ -1320,15 +1347,25 @@ bool tune_cache_read(const char* path, const TuneKey& key, int& ytile, int& ztil
   return hit;
 }
 
-// us: the candidates' times, (y, z) = (8, 8), (16, 8), (8, 16), (16, 16) in that
-// order (the first two only without the spectral path)
-bool tune_cache_append(const char* path, const TuneKey& k, int ytile, int ztile, const double* us, int ncand) {
+void write_times(FILE* f, const char* name, const double* us, int n) {
+  std::fprintf(f, ",\"%s\":[", name);
+  for (int i = 0; i < n; ++i) std::fprintf(f, i ? ",%.2f" : "%.2f", us[i] < 1e29 ? us[i] : -1.0);
+  std::fprintf(f, "]");
+}
+
+// times: microseconds per candidate in the order of the lists above, -1 for
+// candidates not timed (block too large, or a pass the group does not run)
+bool tune_cache_append(const char* path, const TuneKey& k, const pf_plan& p, const double* us_y,
+                       const double* us_zms, const double* us_zac, const double* us_zkh) {
   FILE* f = std::fopen(path, "a");
   if (!f) return false;
-  std::fprintf(f, kTuneOut, k.dev, k.cus, k.nx, k.ny, k.nz, k.ninst, k.nv, k.spectral, ytile, ztile);
-  std::fprintf(f, ",\"us\":[");
-  for (int i = 0; i < ncand; ++i) std::fprintf(f, i ? ",%.2f" : "%.2f", us[i]);
-  std::fprintf(f, "]}\n");
+  std::fprintf(f, kTuneOut, k.dev, k.cus, k.nx, k.ny, k.nz, k.ninst, k.nv, k.spectral, p.ytile, p.yplan,
+               p.ztile_ms, p.zplan_ms, p.zplan_ac, p.ztile_kh, p.zplan_kh);
+  write_times(f, "us_y", us_y, 6);
+  write_times(f, "us_zms", us_zms, 4);
+  write_times(f, "us_zac", us_zac, 3);
+  write_times(f, "us_zkh", us_zkh, 4);
+  std::fprintf(f, "}\n");
   const bool ok = std::ferror(f) == 0;
   return std::fclose(f) == 0 && ok;
 }
@@ -1353,6 +1390,31 @@ int time_us(pf_ctx* c, hipStream_t s, int reps, F&& f, double& us) {
   return PF_OK;
 }
 
+// the plan a group launches with: its tuned or set one, else the defaults
+pf_plan group_plan(const pf_ctx* c, const Group& g) {
+  const KArgs& a = g.args;
+  pf_plan p{};
+  p.ytile = a.ytile ? a.ytile : 16;
+  p.yplan = a.yplan;
+  p.ztile_ms = a.ztile_ms ? a.ztile_ms : pft::kZmsTile;
+  p.zplan_ms = a.zplan_ms;
+  p.zplan_ac = a.zplan_ac;
+  p.ztile_kh = a.ztile_kh ? a.ztile_kh : (c->nv == 1 ? 16 : 8);
+  p.zplan_kh = a.zplan_kh;
+  return p;
+}
+
+void apply_plan(Group& g, const pf_plan& p) {
+  KArgs& a = g.args;
+  a.ytile = p.ytile;
+  a.yplan = p.yplan;
+  a.ztile_ms = p.ztile_ms;
+  a.zplan_ms = p.zplan_ms;
+  a.zplan_ac = p.zplan_ac;
+  a.ztile_kh = p.ztile_kh;
+  a.zplan_kh = p.zplan_kh;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1369,76 +1431,161 @@ int pf_autotune(pf_ctx* c, const char* cache_path, uint32_t flags, int32_t* n_ti
     return hip_fail(c, e, "autotune device");
   int timed = 0;
   constexpr int kReps = 10;
-  const int cand[2] = {8, 16};
   for (auto& g : c->groups) {
     TuneKey key{};
     std::snprintf(key.dev, sizeof(key.dev), "%s", prop.gcnArchName);
     key.cus = prop.multiProcessorCount;
     key.nx = g.nx; key.ny = g.ny; key.nz = g.nz; key.ninst = g.ninst; key.nv = c->nv;
     key.spectral = (g.homogeneous && !g.mobile && g.pf_max_iter <= 1) ? 1 : 0;
-    int ytile = 0, ztile = 0;
-    if (cache_path && !(flags & PF_TUNE_RETIME) && tune_cache_read(cache_path, key, ytile, ztile)) {
-      g.args.ytile = ytile;
-      g.args.ztile_kh = ztile;
+    pf_plan plan = group_plan(c, g);
+    if (cache_path && !(flags & PF_TUNE_RETIME) && tune_cache_read(cache_path, key, plan)) {
+      apply_plan(g, plan);
       continue;
     }
-    // the state of every instance is kept: the spectral z pass writes per-step fields
+    // the state of every instance is kept; during the timing no instance
+    // counts as converged (the Green z pass skips converged instances)
     std::vector<DevState> saved(g.ninst);
     if ((e = hipMemcpyAsync(saved.data(), g.args.state, sizeof(DevState) * g.ninst, hipMemcpyDeviceToHost, s)) !=
             hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+      return hip_fail(c, e, "autotune setup");
+    std::vector<DevState> live = saved;
+    for (auto& st : live) st.st.done = 0;
+    if ((e = hipMemcpyAsync(g.args.state, live.data(), sizeof(DevState) * g.ninst, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
         (e = hipMemsetAsync(g.args.spec, 0, g.L.spec_bytes, s)) != hipSuccess)
       return hip_fail(c, e, "autotune setup");
-    // Each candidate plan is timed as the sequence the step runs: on the
-    // spectral path y forward (2V components), z pass, y inverse (V), every
-    // pair of tiles; in the fixed point y forward and inverse of six
-    // components. Candidates alternate over two rounds; the best time counts.
-    const int ncand = key.spectral ? 4 : 2;
-    double us_best[4] = {1e30, 1e30, 1e30, 1e30};
-    for (int round = 0; round < 2; ++round)
-      for (int k = 0; k < ncand; ++k) {
-        KArgs a = g.args;
-        a.ytile = cand[k & 1];
-        a.ztile_kh = cand[k >> 1];
-        a.skip_done = 0;
-        double us = 0.0;
-        PF_TRY(time_us(c, s, kReps, [&] {
-          if (!key.spectral) {
-            hipError_t r = pfl::y_pass(a, 6, 1, s);
-            return r == hipSuccess ? pfl::y_pass(a, 6, -1, s) : r;
-          }
-          hipError_t r = pfl::y_pass(a, 2 * c->nv, 1, s);
-          if (r == hipSuccess) r = pfl::kh_z_update(a, 1, s);
-          return r == hipSuccess ? pfl::y_pass(a, c->nv, -1, s) : r;
-        }, us));
-        us_best[k] = std::min(us_best[k], us);
+    double us_y[6], us_zms[4], us_zac[3], us_zkh[4];
+    std::fill(us_y, us_y + 6, 1e30);
+    std::fill(us_zms, us_zms + 4, 1e30);
+    std::fill(us_zac, us_zac + 3, 1e30);
+    std::fill(us_zkh, us_zkh + 4, 1e30);
+    const int nv = c->nv;
+    // Candidate k of a pass is timed inside the passes of one fixed-point
+    // iteration (x forward, y forward, z, y inverse: the inverse x pass would
+    // overwrite the strain), of one Allen-Cahn update or of one spectral
+    // step, the other passes with the plan chosen so far (cur): timed alone,
+    // the column passes ran at a different pace than after an x pass.
+    // set(a, k) picks the candidate (false: it does not fit); best: the
+    // fastest, -1 if none ran.
+    KArgs cur = g.args;
+    cur.skip_done = 0;
+    int best = -1;
+    auto tune_pass = [&](int ncand, double* us, auto&& set, auto&& run) -> int {
+      for (int round = 0; round < 2; ++round)
+        for (int k = 0; k < ncand; ++k) {
+          KArgs a = cur;
+          if (!set(a, k)) continue;
+          double t = 0.0;
+          PF_TRY(time_us(c, s, kReps, [&] { return run(a); }, t));
+          us[k] = std::min(us[k], t);
+        }
+      best = -1;
+      for (int k = 0; k < ncand; ++k)
+        if (us[k] < 1e29 && (best < 0 || us[k] < us[best])) best = k;
+      return PF_OK;
+    };
+    // the launches of a sequence stop at the first error
+    auto chain = [](std::initializer_list<std::function<hipError_t()>> fs) {
+      for (auto& f : fs) {
+        const hipError_t r = f();
+        if (r != hipSuccess) return r;
       }
-    int best = 0;
-    for (int k = 1; k < ncand; ++k)
-      if (us_best[k] < us_best[best]) best = k;
-    ytile = cand[best & 1];
-    ztile = key.spectral ? cand[best >> 1] : 0;
+      return hipSuccess;
+    };
+    auto fp_iteration = [&](const KArgs& xa, const KArgs& ya, const KArgs& za) {
+      return chain({[&] { return pfl::ms_x_forward(xa, s); }, [&] { return pfl::y_pass(ya, 6, 1, s); },
+                    [&] { return pfl::ms_z_green(za, s); }, [&] { return pfl::y_pass(ya, 6, -1, s); }});
+    };
+    auto ac_update = [&](const KArgs& ya, const KArgs& za) {
+      return chain({[&] { return pfl::ac_x_forward(cur, s); }, [&] { return pfl::y_pass(ya, nv, 1, s); },
+                    [&] { return pfl::ac_z_update(za, 0, s); }, [&] { return pfl::y_pass(ya, nv, -1, s); }});
+    };
+    auto kh_step = [&](const KArgs& ya, const KArgs& za) {
+      return chain({[&] { return pfl::kh_x_forward(cur, 0, s); }, [&] { return pfl::y_pass(ya, 2 * nv, 1, s); },
+                    [&] { return pfl::kh_z_update(za, 1, s); }, [&] { return pfl::y_pass(ya, nv, -1, s); }});
+    };
+    PF_TRY(tune_pass(6, us_y,
+                     [&](KArgs& a, int k) {
+                       a.yplan = kYCand[k].plan;
+                       a.ytile = kYCand[k].tile;
+                       return pfl::plan_fits(0, g.ny, a.yplan, a.ytile);
+                     },
+                     [&](const KArgs& a) { return key.spectral ? kh_step(a, cur) : fp_iteration(cur, a, cur); }));
+    if (best < 0) return fail(c, PF_EDEVICE, "pf_autotune: no y-pass plan ran");
+    plan.yplan = cur.yplan = kYCand[best].plan;
+    plan.ytile = cur.ytile = kYCand[best].tile;
+    if (!key.spectral) {
+      PF_TRY(tune_pass(4, us_zms,
+                       [&](KArgs& a, int k) {
+                         a.zplan_ms = kZmsCand[k].plan;
+                         a.ztile_ms = kZmsCand[k].tile;
+                         return pfl::plan_fits(1, g.nz, a.zplan_ms, a.ztile_ms);
+                       },
+                       [&](const KArgs& a) { return fp_iteration(cur, cur, a); }));
+      if (best < 0) return fail(c, PF_EDEVICE, "pf_autotune: no Green z-pass plan ran");
+      plan.zplan_ms = cur.zplan_ms = kZmsCand[best].plan;
+      plan.ztile_ms = cur.ztile_ms = kZmsCand[best].tile;
+      PF_TRY(tune_pass(3, us_zac,
+                       [&](KArgs& a, int k) {
+                         a.zplan_ac = kZacCand[k].plan;
+                         return pfl::plan_fits(2, g.nz, a.zplan_ac, 16);
+                       },
+                       [&](const KArgs& a) { return ac_update(cur, a); }));
+      if (best < 0) return fail(c, PF_EDEVICE, "pf_autotune: no Allen-Cahn z-pass plan ran");
+      plan.zplan_ac = cur.zplan_ac = kZacCand[best].plan;
+    } else {
+      PF_TRY(tune_pass(4, us_zkh,
+                       [&](KArgs& a, int k) {
+                         a.zplan_kh = kZkhCand[k].plan;
+                         a.ztile_kh = kZkhCand[k].tile;
+                         return pfl::plan_fits(3, g.nz, a.zplan_kh, a.ztile_kh);
+                       },
+                       [&](const KArgs& a) { return kh_step(cur, a); }));
+      if (best < 0) return fail(c, PF_EDEVICE, "pf_autotune: no spectral z-pass plan ran");
+      plan.zplan_kh = cur.zplan_kh = kZkhCand[best].plan;
+      plan.ztile_kh = cur.ztile_kh = kZkhCand[best].tile;
+    }
     if ((e = hipMemcpyAsync(g.args.state, saved.data(), sizeof(DevState) * g.ninst, hipMemcpyHostToDevice, s)) !=
             hipSuccess ||
         (e = hipStreamSynchronize(s)) != hipSuccess)
       return hip_fail(c, e, "autotune restore");
-    g.args.ytile = ytile;
-    g.args.ztile_kh = ztile;
+    apply_plan(g, plan);
     ++timed;
-    if (cache_path && !tune_cache_append(cache_path, key, ytile, ztile, us_best, ncand))
+    if (cache_path && !tune_cache_append(cache_path, key, plan, us_y, us_zms, us_zac, us_zkh))
       return fail(c, PF_EINVAL, std::string("pf_autotune: cannot write the cache ") + cache_path);
   }
-  drop_graph(c);  // launches of a captured step carry the old tiles
+  drop_graph(c);  // launches of a captured step carry the old plans
   if (n_timed) *n_timed = timed;
   return PF_OK;
 }
 
-int pf_batch_plan(pf_ctx* c, int32_t inst, int32_t* ytile, int32_t* ztile) {
-  if (!c || !ytile || !ztile) return PF_EINVAL;
+int pf_batch_plan(pf_ctx* c, int32_t inst, pf_plan* out) {
+  if (!c || !out) return PF_EINVAL;
   PF_TRY(check_instance(c, inst));
-  const Group& g = c->groups[c->where[inst].first];
-  *ytile = g.args.ytile ? g.args.ytile : 16;
-  const bool spectral = g.homogeneous && !g.mobile && g.pf_max_iter <= 1;
-  *ztile = !spectral ? 0 : (g.args.ztile_kh ? g.args.ztile_kh : (c->nv == 1 ? 16 : 8));
+  *out = group_plan(c, c->groups[c->where[inst].first]);
+  return PF_OK;
+}
+
+int pf_batch_set_plan(pf_ctx* c, int32_t inst, const pf_plan* plan) {
+  if (!c || !plan) return PF_EINVAL;
+  if (c->capturing) return fail(c, PF_EINVAL, "pf_batch_set_plan: not during capture");
+  PF_TRY(check_instance(c, inst));
+  Group& g = c->groups[c->where[inst].first];
+  if (!plan_valid(*plan, g.ny, g.nz)) return fail(c, PF_EINVAL, "pf_batch_set_plan: no such plan for this grid");
+  apply_plan(g, *plan);
+  drop_graph(c);
+  return PF_OK;
+}
+
+int pf_fft_plan(int32_t n, int32_t variant, int32_t* elems_per_thread, int32_t* radices, int32_t* n_stages) {
+  if (!elems_per_thread || !radices || !n_stages || !pfl::supported_axis(n)) return PF_EINVAL;
+  int e = 0, r[8];
+  const int ns = pfl::plan_radices(n, variant, &e, r);
+  if (ns == 0) return PF_EINVAL;
+  *elems_per_thread = e;
+  *n_stages = ns;
+  for (int i = 0; i < ns; ++i) radices[i] = r[i];
   return PF_OK;
 }
 

@@ -7,10 +7,7 @@ namespace pft {
 
 constexpr int kMaxVar = 6;
 constexpr int kColTile = 16;       // spectral columns per y/z block
-#ifndef PF_ZMS_TILE
-#define PF_ZMS_TILE 8
-#endif
-constexpr int kZmsTile = PF_ZMS_TILE;  // spectral columns per block of the Green z pass
+constexpr int kZmsTile = 8;        // default columns per block of the Green z pass
 
 // Quantities reduced per block (FP64 partial sums / extrema).
 constexpr int kQms = 6;                 // sum of stress (mixed condition)
@@ -130,6 +127,10 @@ struct KArgs {
   int ytile;                  // columns per block of the y passes (8 or 16; 0: 16)
   int ztile_kh;               // columns per block of the spectral path's z pass (8 or 16;
                               // 0: 16 for one variant, else 8)
+  int yplan;                  // FFT plan variant of the y passes (0, 1, 2)
+  int ztile_ms, zplan_ms;     // Green z pass: columns per block (0: 8) and plan variant (0, 1)
+  int zplan_ac;               // Allen-Cahn z pass: plan variant (0, 1, 2)
+  int zplan_kh;               // spectral path's z pass: plan variant (0, 1)
 };
 
 // Packed upper-triangle index of a symmetric 6x6 matrix.
@@ -171,6 +172,13 @@ hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s);
 bool supported_axis(int n);
+// FFT plans of the y and z passes: elements per thread and radix stages of
+// variant k on an axis of length n (0 stages if there is no such plan), and
+// whether a pass of that plan and column tile fits one block.
+int plan_radices(int n, int k, int* elems, int (&radices)[8]);
+// pass: 0 y passes (k 0..2, tile 8/16), 1 Green z pass (k 0..1, tile 8/16),
+// 2 Allen-Cahn z pass (k 0..2, tile 16), 3 spectral z pass (k 0..1, tile 8/16)
+bool plan_fits(int pass, int n, int k, int tile);
 // per variant count, one translation unit each
 hipError_t ms_x_forward_v1(const KArgs& a, hipStream_t s);
 hipError_t ms_x_forward_v2(const KArgs& a, hipStream_t s);

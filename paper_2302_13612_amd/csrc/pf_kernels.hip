@@ -186,9 +186,15 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, floa
 // ------------------------------------------------------------ y and z passes
 // y: columns of C consecutive kx at one z, in place. grid (tiles, nz, ncomp).
 // C (8 or 16) is the group's tuned tile.
-template <int N, int DIR, int C>
-__global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_y(const KArgs a) {
-  constexpr int E = Plan<N>::E, T = N / E;
+template <int N, int K>
+using PV = typename PlanV<N, K>::P;
+template <int N, int K, int C>
+constexpr int col_threads() { return C * (N / PV<N, K>::E); }
+
+template <int N, int DIR, int C, int K>
+__global__ __launch_bounds__((col_threads<N, K, C>())) void k_y(const KArgs a) {
+  using P = PV<N, K>;
+  constexpr int E = P::E, T = N / E;
   __shared__ float2 lds[N * C];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
@@ -202,7 +208,7 @@ __global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_y(const KArgs a) {
 #pragma unroll
   // plain loads (measured faster here than with the hint), streaming stores
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * a.sh] : make_float2(0.f, 0.f);
-  fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, a.tw_y);
+  fft_pencil<N, DIR, P>(v, ColView<C>{lds + cc}, t, a.tw_y);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) gst(col + (size_t)(t + T * m) * a.sh, v[m]);
@@ -358,9 +364,10 @@ __device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratc
 // The block holding xi = 0 of an instance first applies the mixed condition
 // (the mean strain of the next iterate from the stress sums of the forward
 // x pass, nblk_x blocks), so no separate launch sits between the passes.
-template <int N>
-__global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArgs a, int nblk_x) {
-  constexpr int E = Plan<N>::E, T = N / E, C = kZmsTile;
+template <int N, int C, int PK>
+__global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs a, int nblk_x) {
+  using P = PV<N, PK>;
+  constexpr int E = P::E, T = N / E;
   __shared__ float2 lds[N * C];
   __shared__ double ebar[6];
   const int ntile = (a.nh + C - 1) / C;
@@ -386,11 +393,11 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 #pragma unroll
     for (int m = 0; m < E; ++m)
       v[c][m] = valid ? col[c * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
-  TwCache<N, Plan<N>, 1> twf;
+  TwCache<N, P, 1> twf;
   twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<N, 1>(v[c], view, t, twf);
+  for (int c = 0; c < 6; ++c) fft_pencil<N, 1, P>(v[c], view, t, twf);
   const int kxv = valid ? kx : 0;
   float xi[3] = {(float)kxv / (float)a.nx, (float)signed_k(ky, a.ny) / (float)a.ny, 0.f};
   const float inz = 1.f / (float)a.nz;
@@ -410,9 +417,9 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 #pragma unroll
     for (int c = 0; c < 6; ++c) v[c][m] = tau[c];
   }
-  const TwCache<N, Plan<N>, -1> twi = twf.conj();
+  const TwCache<N, P, -1> twi = twf.conj();
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<N, -1>(v[c], view, t, twi);
+  for (int c = 0; c < 6; ++c) fft_pencil<N, -1, P>(v[c], view, t, twi);
   if (valid) {
 #pragma unroll
     for (int c = 0; c < 6; ++c)
@@ -427,9 +434,10 @@ __global__ __launch_bounds__(kZmsTile * (N / Plan<N>::E)) void k_z_ms(const KArg
 // mode 1: Parseval sum of the unmodified spectrum only, nothing stored.
 // WG: the gradient force may be wanted (a mobility field, or mode 2); without
 // it the kernel holds one pencil less.
-template <int N, bool GK, bool WG>
-__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArgs a, int mode) {
-  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+template <int N, bool GK, bool WG, int K>
+__global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_ac(const KArgs a, int mode) {
+  using P = PV<N, K>;
+  constexpr int E = P::E, T = N / E, C = kColTile;
   __shared__ float2 lds[N * C];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
@@ -441,10 +449,10 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? gld(col + (size_t)(t + T * m) * zs) : make_float2(0.f, 0.f);
-  TwCache<N, Plan<N>, 1> twf;
+  TwCache<N, P, 1> twf;
   twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
-  fft_pencil<N, 1>(v, view, t, twf);
+  fft_pencil<N, 1, P>(v, view, t, twf);
   const int sy = signed_k(ky, a.ny);
   const double wgt = (kx == 0 || kx == a.nx / 2) ? 1.0 : 2.0;
   const GradSym<GK> gs(a, inst, q, kx, sy);
@@ -465,14 +473,14 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   }
   double en[kQgd] = {valid ? wgt * (double)e0 : 0.0, 0.0, 0.0};
   if (mode == 0) {
-    fft_pencil<N, -1>(v, view, t, twf.conj());
+    fft_pencil<N, -1, P>(v, view, t, twf.conj());
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) gst(col + (size_t)(t + T * m) * zs, v[m]);
     }
   }
   if (want_g) {
-    fft_pencil<N, -1>(g, view, t, twf.conj());
+    fft_pencil<N, -1, P>(g, view, t, twf.conj());
     float2* gcol = mode == 2 ? col : col + (size_t)a.nv * cs;
     if (valid) {
 #pragma unroll
@@ -484,9 +492,11 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_ac(const KArg
   block_sum<kQgd>(en, a.part_gd + blk * kQgd);
 }
 
-template <int N, int DIR>
-__global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KArgs a) {
-  constexpr int E = Plan<N>::E, T = N / E, C = kColTile;
+// Plain z transform (checking the passes) with the Allen-Cahn z pass's plan.
+template <int N, int DIR, int K>
+__global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_raw(const KArgs a) {
+  using P = PV<N, K>;
+  constexpr int E = P::E, T = N / E, C = kColTile;
   __shared__ float2 lds[N * C];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
@@ -498,9 +508,9 @@ __global__ __launch_bounds__(kColTile * (N / Plan<N>::E)) void k_z_raw(const KAr
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
-  TwCache<N, Plan<N>, DIR> tw;
+  TwCache<N, P, DIR> tw;
   tw.load(a.tw_z, t);
-  fft_pencil<N, DIR>(v, ColView<C>{lds + cc}, t, tw);
+  fft_pencil<N, DIR, P>(v, ColView<C>{lds + cc}, t, tw);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) col[(size_t)(t + T * m) * zs] = v[m];
@@ -531,9 +541,10 @@ __host__ __device__ inline int kh_tile_of(const KArgs& a) {
 // L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
 __device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk, double* scratch);
 
-template <int N, int V, bool GK, int C>
-__global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_z_kh(const KArgs a, int mode, int nblk_x) {
-  constexpr int E = Plan<N>::E, T = N / E;
+template <int N, int V, bool GK, int C, int PK>
+__global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_kh(const KArgs a, int mode, int nblk_x) {
+  using P = PV<N, PK>;
+  constexpr int E = P::E, T = N / E;
   __shared__ float2 lds[N * C];
   const int ntile = (a.nh + C - 1) / C;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
@@ -559,13 +570,13 @@ __global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_z_kh(const KArgs a, in
       th[q][m] = valid ? col[q * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
       rh[q][m] = valid ? col[(V + q) * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
     }
-  TwCache<N, Plan<N>, 1> twf;
+  TwCache<N, P, 1> twf;
   twf.load(a.tw_z, t);
   const ColView<C> view{lds + cc};
 #pragma unroll
   for (int q = 0; q < V; ++q) {
-    fft_pencil<N, 1>(th[q], view, t, twf);
-    fft_pencil<N, 1>(rh[q], view, t, twf);
+    fft_pencil<N, 1, P>(th[q], view, t, twf);
+    fft_pencil<N, 1, P>(rh[q], view, t, twf);
   }
   const int kxv = valid ? kx : 0;
   const int sy = signed_k(ky, a.ny);
@@ -655,9 +666,9 @@ __global__ __launch_bounds__(C * (N / Plan<N>::E)) void k_z_kh(const KArgs a, in
       th[q][m] = cscale(nv, a.inv_ntot);
     }
   }
-  const TwCache<N, Plan<N>, -1> twi = twf.conj();
+  const TwCache<N, P, -1> twi = twf.conj();
 #pragma unroll
-  for (int q = 0; q < V; ++q) fft_pencil<N, -1>(th[q], view, t, twi);
+  for (int q = 0; q < V; ++q) fft_pencil<N, -1, P>(th[q], view, t, twi);
   if (valid) {
 #pragma unroll
     for (int q = 0; q < V; ++q)
@@ -1089,8 +1100,6 @@ static int z_blocks_inst(const KArgs& a, int ncomp) {
 
 int z_blocks(const KArgs& a, int ncomp) { return a.ninst * z_blocks_inst(a, ncomp); }
 
-template <int N>
-static dim3 col_block() { return dim3(kColTile * (N / Plan<N>::E)); }
 
 #define PF_SWITCH_M(nx, BODY)                \
   switch ((nx) / 2) {                         \
@@ -1143,19 +1152,80 @@ hipError_t ms_x_forward(const KArgs& a, hipStream_t s) {
 }
 
 
-template <int C>
-static hipError_t y_pass_t(const KArgs& a, int ncomp, int dir, hipStream_t s) {
-  const dim3 grid((a.nh + C - 1) / C, a.nz * a.ninst, ncomp);
-  if (dir > 0) {
-    PF_SWITCH_N(a.ny, (k_y<N, 1, C><<<grid, dim3(C * (N / Plan<N>::E)), 0, s>>>(a)));
-  } else {
-    PF_SWITCH_N(a.ny, (k_y<N, -1, C><<<grid, dim3(C * (N / Plan<N>::E)), 0, s>>>(a)));
+// ---------------------------------------------------- plans of y/z passes
+template <int N, int K>
+static int radices_of(int* elems, int (&r)[8]) {
+  using RI = RadixInfo<typename PV<N, K>::R>;
+  *elems = PV<N, K>::E;
+  for (int i = 0; i < RI::n; ++i) r[i] = RI::r[i];
+  return RI::n;
+}
+
+template <int N>
+static int radices_n(int k, int* elems, int (&r)[8]) {
+  switch (k) {
+    case 0: return radices_of<N, 0>(elems, r);
+    case 1: return radices_of<N, 1>(elems, r);
+    case 2: return radices_of<N, 2>(elems, r);
   }
-  return hipGetLastError();
+  return 0;
+}
+
+int plan_radices(int n, int k, int* elems, int (&radices)[8]) {
+  *elems = 0;
+  switch (n) {
+    case 32: return radices_n<32>(k, elems, radices);
+    case 48: return radices_n<48>(k, elems, radices);
+    case 64: return radices_n<64>(k, elems, radices);
+    case 96: return radices_n<96>(k, elems, radices);
+    case 128: return radices_n<128>(k, elems, radices);
+    case 192: return radices_n<192>(k, elems, radices);
+    case 256: return radices_n<256>(k, elems, radices);
+    case 384: return radices_n<384>(k, elems, radices);
+    case 512: return radices_n<512>(k, elems, radices);
+  }
+  return 0;
+}
+
+bool plan_fits(int pass, int n, int k, int tile) {
+  int e = 0, r[8];
+  if (plan_radices(n, k, &e, r) == 0) return false;
+  const int kmax = (pass == 1 || pass == 3) ? 1 : 2;
+  const bool tile_ok = pass == 2 ? tile == kColTile : (tile == 8 || tile == 16);
+  return k <= kmax && tile_ok && tile * (n / e) <= 1024;
+}
+
+// A column kernel is instantiated only for the plans and tiles whose block
+// fits (the launchers below return hipErrorInvalidValue otherwise).
+template <int N, int DIR, int C, int K>
+static hipError_t y_launch(const KArgs& a, int ncomp, hipStream_t s) {
+  if constexpr (col_threads<N, K, C>() <= 1024) {
+    const dim3 grid((a.nh + C - 1) / C, a.nz * a.ninst, ncomp);
+    k_y<N, DIR, C, K><<<grid, dim3(col_threads<N, K, C>()), 0, s>>>(a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int N, int DIR>
+static hipError_t y_pass_n(const KArgs& a, int ncomp, hipStream_t s) {
+  const bool c8 = a.ytile == 8;
+  switch (a.yplan) {
+    case 0: return c8 ? y_launch<N, DIR, 8, 0>(a, ncomp, s) : y_launch<N, DIR, 16, 0>(a, ncomp, s);
+    case 1: return c8 ? y_launch<N, DIR, 8, 1>(a, ncomp, s) : y_launch<N, DIR, 16, 1>(a, ncomp, s);
+    case 2: return c8 ? y_launch<N, DIR, 8, 2>(a, ncomp, s) : y_launch<N, DIR, 16, 2>(a, ncomp, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t y_pass(const KArgs& a, int ncomp, int dir, hipStream_t s) {
-  return a.ytile == 8 ? y_pass_t<8>(a, ncomp, dir, s) : y_pass_t<kColTile>(a, ncomp, dir, s);
+  if (dir > 0) {
+    PF_SWITCH_N(a.ny, return (y_pass_n<N, 1>(a, ncomp, s)));
+  } else {
+    PF_SWITCH_N(a.ny, return (y_pass_n<N, -1>(a, ncomp, s)));
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
@@ -1164,10 +1234,30 @@ hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
 }
 
 
+template <int N, int C, int K>
+static hipError_t zms_launch(const KArgs& a, hipStream_t s) {
+  if constexpr (K <= 1 && col_threads<N, K, C>() <= 1024) {
+    const dim3 grid(((a.nh + C - 1) / C) * a.ny * a.ninst);
+    k_z_ms<N, C, K><<<grid, dim3(col_threads<N, K, C>()), 0, s>>>(a, x_blocks_inst(a));
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int N>
+static hipError_t ms_z_green_n(const KArgs& a, hipStream_t s) {
+  const bool c16 = a.ztile_ms == 16;
+  switch (a.zplan_ms) {
+    case 0: return c16 ? zms_launch<N, 16, 0>(a, s) : zms_launch<N, 8, 0>(a, s);
+    case 1: return c16 ? zms_launch<N, 16, 1>(a, s) : zms_launch<N, 8, 1>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
 hipError_t ms_z_green(const KArgs& a, hipStream_t s) {
-  const dim3 grid(((a.nh + kZmsTile - 1) / kZmsTile) * a.ny * a.ninst);
-  PF_SWITCH_N(a.nz, (k_z_ms<N><<<grid, dim3(kZmsTile * (N / Plan<N>::E)), 0, s>>>(a, x_blocks_inst(a))));
-  return hipGetLastError();
+  PF_SWITCH_N(a.nz, return ms_z_green_n<N>(a, s));
+  return hipErrorInvalidValue;
 }
 
 hipError_t ms_x_inverse(const KArgs& a, hipStream_t s) {
@@ -1189,19 +1279,39 @@ hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
   return hipErrorInvalidValue;
 }
 
-hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, a.nv);
-  const bool wg = mode == 2 || a.lapf != nullptr;
-  if (a.gk && wg) {
-    PF_SWITCH_N(a.nz, (k_z_ac<N, true, true><<<grid, col_block<N>(), 0, s>>>(a, mode)));
-  } else if (a.gk) {
-    PF_SWITCH_N(a.nz, (k_z_ac<N, true, false><<<grid, col_block<N>(), 0, s>>>(a, mode)));
-  } else if (wg) {
-    PF_SWITCH_N(a.nz, (k_z_ac<N, false, true><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+template <int N, bool GK, bool WG, int K>
+static hipError_t zac_launch(const KArgs& a, int mode, hipStream_t s) {
+  if constexpr (col_threads<N, K, kColTile>() <= 1024) {
+    const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, a.nv);
+    k_z_ac<N, GK, WG, K><<<grid, dim3(col_threads<N, K, kColTile>()), 0, s>>>(a, mode);
+    return hipGetLastError();
   } else {
-    PF_SWITCH_N(a.nz, (k_z_ac<N, false, false><<<grid, col_block<N>(), 0, s>>>(a, mode)));
+    return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+template <int N, bool GK, bool WG>
+static hipError_t ac_z_k(const KArgs& a, int mode, hipStream_t s) {
+  switch (a.zplan_ac) {
+    case 0: return zac_launch<N, GK, WG, 0>(a, mode, s);
+    case 1: return zac_launch<N, GK, WG, 1>(a, mode, s);
+    case 2: return zac_launch<N, GK, WG, 2>(a, mode, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <int N>
+static hipError_t ac_z_n(const KArgs& a, int mode, hipStream_t s) {
+  const bool wg = mode == 2 || a.lapf != nullptr;
+  if (a.gk && wg) return ac_z_k<N, true, true>(a, mode, s);
+  if (a.gk) return ac_z_k<N, true, false>(a, mode, s);
+  if (wg) return ac_z_k<N, false, true>(a, mode, s);
+  return ac_z_k<N, false, false>(a, mode, s);
+}
+
+hipError_t ac_z_update(const KArgs& a, int mode, hipStream_t s) {
+  PF_SWITCH_N(a.nz, return ac_z_n<N>(a, mode, s));
+  return hipErrorInvalidValue;
 }
 
 hipError_t ac_x_inverse(const KArgs& a, hipStream_t s) {
@@ -1249,16 +1359,31 @@ hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream
 }
 
 
-template <bool GK, int V, int C>
+template <int N, bool GK, int V, int C, int K>
+static hipError_t kh_z_nk(const KArgs& a, int mode, hipStream_t s) {
+  if constexpr (K <= 1 && col_threads<N, K, C>() <= 1024) {
+    const dim3 grid(((a.nh + C - 1) / C) * a.ny * a.ninst);
+    k_z_kh<N, V, GK, C, K><<<grid, dim3(col_threads<N, K, C>()), 0, s>>>(a, mode, x_blocks_inst(a));
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <bool GK, int V, int C, int K>
 static hipError_t kh_z_launch(const KArgs& a, int mode, hipStream_t s) {
-  const dim3 grid(((a.nh + C - 1) / C) * a.ny * a.ninst);
-  PF_SWITCH_N(a.nz, (k_z_kh<N, V, GK, C><<<grid, dim3(C * (N / Plan<N>::E)), 0, s>>>(a, mode, x_blocks_inst(a))));
-  return hipGetLastError();
+  PF_SWITCH_N(a.nz, return (kh_z_nk<N, GK, V, C, K>(a, mode, s)));
+  return hipErrorInvalidValue;
 }
 
 template <bool GK, int V>
 static hipError_t kh_z_tile(const KArgs& a, int mode, hipStream_t s) {
-  return kh_tile_of(a) == 8 ? kh_z_launch<GK, V, 8>(a, mode, s) : kh_z_launch<GK, V, 16>(a, mode, s);
+  const bool c8 = kh_tile_of(a) == 8;
+  switch (a.zplan_kh) {
+    case 0: return c8 ? kh_z_launch<GK, V, 8, 0>(a, mode, s) : kh_z_launch<GK, V, 16, 0>(a, mode, s);
+    case 1: return c8 ? kh_z_launch<GK, V, 8, 1>(a, mode, s) : kh_z_launch<GK, V, 16, 1>(a, mode, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <bool GK>
@@ -1281,14 +1406,34 @@ hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream
   return hipGetLastError();
 }
 
-hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s) {
-  const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, ncomp);
-  if (dir > 0) {
-    PF_SWITCH_N(a.nz, (k_z_raw<N, 1><<<grid, col_block<N>(), 0, s>>>(a)));
+template <int N, int DIR, int K>
+static hipError_t zraw_launch(const KArgs& a, int ncomp, hipStream_t s) {
+  if constexpr (col_threads<N, K, kColTile>() <= 1024) {
+    const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, ncomp);
+    k_z_raw<N, DIR, K><<<grid, dim3(col_threads<N, K, kColTile>()), 0, s>>>(a);
+    return hipGetLastError();
   } else {
-    PF_SWITCH_N(a.nz, (k_z_raw<N, -1><<<grid, col_block<N>(), 0, s>>>(a)));
+    return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+}
+
+template <int N, int DIR>
+static hipError_t raw_z_n(const KArgs& a, int ncomp, hipStream_t s) {
+  switch (a.zplan_ac) {
+    case 0: return zraw_launch<N, DIR, 0>(a, ncomp, s);
+    case 1: return zraw_launch<N, DIR, 1>(a, ncomp, s);
+    case 2: return zraw_launch<N, DIR, 2>(a, ncomp, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s) {
+  if (dir > 0) {
+    PF_SWITCH_N(a.nz, return (raw_z_n<N, 1>(a, ncomp, s)));
+  } else {
+    PF_SWITCH_N(a.nz, return (raw_z_n<N, -1>(a, ncomp, s)));
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s) {

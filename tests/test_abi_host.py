@@ -183,8 +183,20 @@ def test_autotune_arguments():
     lib = binding.load()
     n = ctypes.c_int32()
     assert lib.pf_autotune(None, None, 0, ctypes.byref(n)) == binding.PF_EINVAL
-    y, z = ctypes.c_int32(), ctypes.c_int32()
-    assert lib.pf_batch_plan(None, 0, ctypes.byref(y), ctypes.byref(z)) == binding.PF_EINVAL
+    p = binding.PfPlan()
+    assert lib.pf_batch_plan(None, 0, ctypes.byref(p)) == binding.PF_EINVAL
+    assert lib.pf_batch_set_plan(None, 0, ctypes.byref(p)) == binding.PF_EINVAL
+
+
+def test_fft_plans_host():
+    # the plan descriptions need no device: every variant factors its length
+    for n in (32, 48, 64, 96, 128, 192, 256, 384, 512):
+        for k in range(3):
+            e, r = binding.fft_plan(n, k)
+            assert int(np.prod(r)) == n and all(e % x == 0 for x in r)
+    for n, k in ((80, 0), (64, 3), (64, -1)):
+        with pytest.raises(binding.PfError):
+            binding.fft_plan(n, k)
 
 
 def test_specconv_sizes():

@@ -41,7 +41,7 @@ def test_rve_batch_full_size_vs_oracle():
     got = {n: bs.field(i, binding.PF_FIELD_ETA).cpu().numpy() for n, i in first.items()}
     stats = {n: bs.stats(i) for n, i in first.items()}
     bs.close()
-    log(f"  tiles (y, z) per size: {plans}")
+    log(f"  plans per size: {plans}")
     for n, i in sorted(first.items()):
         cfg = cases.batch_instance_cfg(batch, i, variants[i])
         eta_o, sig_o, stats_o = cases.oracle_run(cfg, STEPS)
