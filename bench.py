@@ -343,20 +343,13 @@ def bench_surrogate(args):
     torch.cuda.set_device(dev)
     train_batch = inputs.rve_batch()
     trajs, conds = surrogate.generate_trajectories(binding, torch, train_batch, dev, log=log)
-    model = surrogate.make_model(torch, native=args.trainer == "autograd").to(dev)
-    if args.trainer == "native":
-        # the same initial weights, trained by the library's kernels alone
-        trainer = surrogate.NativeTrainer(torch, binding, surrogate.to_params(model), dev)
-        info = surrogate.train_native(torch, trainer, trajs, conds, seconds=args.train_seconds, log=log)
-        params = trainer.params()
-        del trainer
-    else:
-        info = surrogate.train(torch, model, trajs, conds, seconds=args.train_seconds, log=log)
-        params = surrogate.to_params(model)
-    info["trainer"] = {"native": "library kernels (forward, backward, Adam)",
-                       "autograd": "PyTorch autograd, spectral convolution in library kernels",
-                       "torch": "PyTorch autograd with torch.fft"}[args.trainer]
-    del trajs, model
+    # trained by the library's kernels alone (forward, backward, Adam)
+    trainer = surrogate.NativeTrainer(torch, binding, surrogate.init_params(), dev)
+    info = surrogate.train_native(torch, trainer, trajs, conds, seconds=args.train_seconds, log=log)
+    params = trainer.params()
+    del trainer
+    info["trainer"] = "library kernels (forward, backward, Adam)"
+    del trajs
     torch.cuda.empty_cache()
     held = inputs.rve_batch(n_inst=args.eval_instances, seed=99, sizes=(128,))
     calls, per = held["steps"] // 16, 16
@@ -585,9 +578,6 @@ def main():
     ap.add_argument("--train-seconds", type=float, default=240.0)
     ap.add_argument("--eval-instances", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-3, help="acceptance residual of the learned stepper")
-    ap.add_argument("--trainer", choices=("native", "autograd", "torch"), default="native",
-                    help="surrogate training: the library's kernels alone; PyTorch autograd with the library's "
-                         "spectral convolution; or PyTorch autograd with torch.fft")
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")

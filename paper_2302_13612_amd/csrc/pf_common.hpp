@@ -158,35 +158,8 @@ __device__ __forceinline__ void rotate_sym(const float (&R)[9], const float (&A)
   }
 }
 
-// A wave-uniform table of up to 192 floats held one value per lane in three
-// VGPRs; element i is read with v_readlane (one VALU instruction per distinct
-// element and iteration, CSE-able across the voxels of an iteration; the
-// result is a scalar operand). A table this size does not fit in scalar
-// registers, and the compiler's own spill of it reloads on every use.
-struct LaneTab {
-  float v[3];
-  int base;
-  __device__ __forceinline__ LaneTab operator+(int o) const {
-    LaneTab t = *this;
-    t.base += o;
-    return t;
-  }
-  __device__ __forceinline__ float operator[](int i) const {
-    const int k = base + i;
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[k >> 6]), k & 63));
-  }
-};
-
-__device__ __forceinline__ LaneTab load_lanetab(const float* tab, int n) {
-  LaneTab t;
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int j = 0; j < 3; ++j) t.v[j] = (64 * j + lane < n) ? tab[64 * j + lane] : 0.f;
-  t.base = 0;
-  return t;
-}
-
-// The same table read with scalar loads from kernel-argument memory: each
+// The crystal-frame table of the rotation form, read with scalar loads from
+// kernel-argument memory: each
 // element goes through the constant cache into a scalar register and costs
 // no vector instruction. The table does not fit in scalar registers, so it
 // is read block by block where it is used, and each block's base pointer
@@ -254,36 +227,6 @@ __device__ __forceinline__ void constitutive_rot_pair(ctab_t xtab, int hk, const
     symv6(Cx[v], o[v].gam_c, o[v].sig_c);
     rotate_sym<false>(R[v], o[v].sig_c, o[v].sig);
   }
-}
-
-template <int V, class TT>
-__device__ __forceinline__ void constitutive_rot(const TT& xt, int hk, const float e[6], const float eta[V],
-                                                 const float ep[6], const float (&R)[9], MatR<V>& o) {
-  float h[V];
-#pragma unroll
-  for (int q = 0; q < V; ++q) h[q] = h_of(eta[q], hk);
-  float d[6], dc[6];
-#pragma unroll
-  for (int c = 0; c < 6; ++c) d[c] = e[c] - ep[c];
-  rotate_sym<true>(R, d, dc);
-#pragma unroll
-  for (int c = 0; c < 6; ++c) {
-    float es = 0.f;
-#pragma unroll
-    for (int q = 0; q < V; ++q) es += h[q] * xt[21 * (V + 1) + 6 * q + c];
-    const float el = dc[c] - es;
-    o.gam_c[c] = c < 3 ? el : 2.f * el;
-  }
-  float Cx[21];
-#pragma unroll
-  for (int i = 0; i < 21; ++i) {
-    float v = xt[i];
-#pragma unroll
-    for (int q = 0; q < V; ++q) v += h[q] * xt[21 * (q + 1) + i];
-    Cx[i] = v;
-  }
-  symv6(Cx, o.gam_c, o.sig_c);
-  rotate_sym<false>(R, o.sig_c, o.sig);
 }
 
 __device__ __forceinline__ void load_rotation(const KArgs& a, int g, float (&R)[9]) {

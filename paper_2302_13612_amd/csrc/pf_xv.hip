@@ -21,14 +21,7 @@
 #endif
 // waves per SIMD the forward x passes are compiled for (their LDS staging
 // allows three blocks of 256 threads per CU)
-#ifndef PF_XWAVES
-#define PF_XWAVES 3
-#endif
-// crystal-frame table of the rotation form: scalar loads (1) or one value
-// per lane read with v_readlane (0)
-#ifndef PF_XTAB_SCALAR
-#define PF_XTAB_SCALAR 1
-#endif
+constexpr int kXWaves = 3;
 
 namespace pft {
 
@@ -173,40 +166,26 @@ __device__ __forceinline__ void variant_terms(TP tab, const float (&sig_m)[6], c
   }
 }
 
-// HK: the interpolation h (PF_H_LINEAR or PF_H_QUINTIC) as a constant, so
-// the linear case carries no polynomial.
-template <int V, bool ROT, bool AC, int HK, class TT>
-__device__ __forceinline__ void eval_voxel(const KArgs& a, const TT& xt, const float* tabs, const float (&e)[6],
+// Per-grain sample-frame tables: the stress of one voxel and, for the
+// phase-field pass, its variant terms. HK: the interpolation h (PF_H_LINEAR
+// or PF_H_QUINTIC) as a constant, so the linear case carries no polynomial.
+template <int V, bool AC, int HK>
+__device__ __forceinline__ void eval_voxel(const KArgs& a, const float* tabs, const float (&e)[6],
                                            const float (&et)[V], const float (&ep)[6], int g, VoxelOut& o,
                                            float (&work)[V], float (&quad)[V]) {
-  if constexpr (ROT) {
-    float R[9];
-    load_rotation(a, g, R);
-    MatR<V> m;
-    constitutive_rot<V>(xt, HK, e, et, ep, R, m);
+  with_table(a, tabs, g, [&](auto tab) {
+    Mat<V> m;
+    constitutive<V>(e, et, ep, tab, HK, m);
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
       o.sig[c] = m.sig[c];
-      o.sig_m[c] = m.sig_c[c];
-      o.gam_m[c] = m.gam_c[c];
+      o.sig_m[c] = m.sig[c];
+      o.gam_m[c] = m.gam[c];
     }
-    if constexpr (AC) variant_terms<V>(xt, o.sig_m, o.gam_m, work, quad);
-  } else {
-    with_table(a, tabs, g, [&](auto tab) {
-      Mat<V> m;
-      constitutive<V>(e, et, ep, tab, HK, m);
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        o.sig[c] = m.sig[c];
-        o.sig_m[c] = m.sig[c];
-        o.gam_m[c] = m.gam[c];
-      }
-      if constexpr (AC) variant_terms<V>(tab, o.sig_m, o.gam_m, work, quad);
-    });
-  }
+    if constexpr (AC) variant_terms<V>(tab, o.sig_m, o.gam_m, work, quad);
+  });
 }
 
-#if PF_XTAB_SCALAR
 // variant_terms for the two voxels of a sample, the crystal table read with
 // scalar loads block by block (see smem_after).
 template <int V>
@@ -243,18 +222,16 @@ __device__ __forceinline__ void variant_terms_pair(ctab_t xtab, const VoxelOut (
     quad[1][q] = acc[1];
   }
 }
-#endif
 
 // Both voxels of a packed sample: with the rotation form and scalar table
 // loads the two share every table read.
 // R: the grain rotations of the two voxels (rotation form), loaded by the
 // caller together with the sample.
-template <int V, bool ROT, bool AC, int HK, class TT>
-__device__ __forceinline__ void eval_pair(const KArgs& a, const TT& xt, const float* tabs, const float (&e)[2][6],
+template <int V, bool ROT, bool AC, int HK>
+__device__ __forceinline__ void eval_pair(const KArgs& a, const float* tabs, const float (&e)[2][6],
                                           const float (&et)[2][V], const float (&ep)[2][6], const int (&g)[2],
                                           const float (&R)[2][9], VoxelOut (&vo)[2], float (&work)[2][V],
                                           float (&quad)[2][V]) {
-#if PF_XTAB_SCALAR
   if constexpr (ROT) {
     MatR<V> m[2];
     constitutive_rot_pair<V>(kernarg_xtab(), HK, e, et, ep, R, m);
@@ -267,11 +244,10 @@ __device__ __forceinline__ void eval_pair(const KArgs& a, const TT& xt, const fl
         vo[v].gam_m[c] = m[v].gam_c[c];
       }
     if constexpr (AC) variant_terms_pair<V>(kernarg_xtab(), vo, work, quad);
-    return;
-  }
-#endif
+  } else {
 #pragma unroll
-  for (int v = 0; v < 2; ++v) eval_voxel<V, ROT, AC, HK>(a, xt, tabs, e[v], et[v], ep[v], g[v], vo[v], work[v], quad[v]);
+    for (int v = 0; v < 2; ++v) eval_voxel<V, AC, HK>(a, tabs, e[v], et[v], ep[v], g[v], vo[v], work[v], quad[v]);
+  }
 }
 
 // Chemical force of variant q: 2A f_q sum_{b != q} f_b (f_b - f_q), b over
@@ -288,7 +264,7 @@ __device__ __forceinline__ float chem_force(float A, const float (&et)[V], float
 // Fixed point, forward: polarisation tau = C(x):(eps - eps*) - C0:eps of
 // every voxel, FP64 sum of the stress, R2C of the six components.
 template <int M, int V, bool ROT, int HK>
-__global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(PF_XWAVES))) void k_x_fwd_ms(const KArgs a) {
+__global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(kXWaves))) void k_x_fwd_ms(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[6 * ROWS * LROW];
@@ -298,11 +274,6 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
   if (st->st.done) return;
   const ctab_t C0 = (ctab_t)(a.ref + (size_t)inst * kRefStride);
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
-#if PF_XTAB_SCALAR
-  const LaneTab xt{};
-#else
-  const LaneTab xt = ROT ? load_lanetab(a.xtab, 21 + 27 * V) : LaneTab{};
-#endif
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
@@ -322,7 +293,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
     load_sample<V>(a, vs, (uint32_t)(rbase + 2 * k), s);
     gids.get(m, s.g0, s.g1);
     float R[2][9];
-    if constexpr (ROT && PF_XTAB_SCALAR) {
+    if constexpr (ROT) {
       load_rotation(a, s.g0, R[0]);
       load_rotation(a, s.g1, R[1]);
     }
@@ -348,7 +319,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
     }
     VoxelOut vo[2];
     float work[2][V], quad[2][V];
-    eval_pair<V, ROT, false, HK>(a, xt, tabs, e, et, ep, {s.g0, s.g1}, R, vo, work, quad);
+    eval_pair<V, ROT, false, HK>(a, tabs, e, et, ep, {s.g0, s.g1}, R, vo, work, quad);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       float ge[6], c0e[6];
@@ -389,18 +360,13 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
 // over the update (PB) the part that stays fixed, f_a + L dt m mech_a, is
 // kept (a separate instantiation: the store costs registers).
 template <int M, int V, bool ROT, int HK, bool PB>
-__global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(PF_XWAVES))) void k_x_fwd_ac(const KArgs a) {
+__global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(kXWaves))) void k_x_fwd_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[V * ROWS * LROW];
   const int rpi = a.nz * a.ny;
   const int inst = blockIdx.x * ROWS / rpi;
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
-#if PF_XTAB_SCALAR
-  const LaneTab xt{};
-#else
-  const LaneTab xt = ROT ? load_lanetab(a.xtab, 21 + 27 * V) : LaneTab{};
-#endif
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * rpi;
   const int row = blockIdx.x * ROWS + p;
@@ -421,7 +387,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
     load_sample<V>(a, vs, (uint32_t)(rbase + x0), s);
     gids.get(m, s.g0, s.g1);
     float R[2][9];
-    if constexpr (ROT && PF_XTAB_SCALAR) {
+    if constexpr (ROT) {
       load_rotation(a, s.g0, R[0]);
       load_rotation(a, s.g1, R[1]);
     }
@@ -439,7 +405,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(P
     }
     VoxelOut vo2[2];
     float work2[2][V], quad2[2][V];
-    eval_pair<V, ROT, true, HK>(a, xt, tabs, e2, et2, ep2, {s.g0, s.g1}, R, vo2, work2, quad2);
+    eval_pair<V, ROT, true, HK>(a, tabs, e2, et2, ep2, {s.g0, s.g1}, R, vo2, work2, quad2);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
       const float (&e)[6] = e2[half];

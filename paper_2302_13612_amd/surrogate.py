@@ -3,11 +3,12 @@
 Training is an off-line procedure beside the stepping path: trajectories of
 the batched ensemble (single-crystal cubes of edge 32-96, one twin variant
 each, homogeneous stiffness) come from the library's batched spectral path;
-the network is fitted in FP32 on the GPU, the spectral convolution of every
-layer (forward and backward) in the library's training kernels
-(pf_specconv_*) and the pointwise parts by PyTorch autograd; the weights
-are then handed to the library (pf_fno_init), whose forward pass, acceptance
-residual and fallback run in HIP.
+the network is fitted in FP32 on the GPU by the library's own training
+kernels (NativeTrainer: pf_specconv_* for the spectral convolution of every
+layer, pf_nt_* for the pointwise parts, the loss gradient and Adam; PyTorch
+only holds the memory); the weights are then handed to the library
+(pf_fno_init), whose forward pass, acceptance residual and fallback run in
+HIP.
 
 The network is the one of the library's pf_fno_forward (and of the checker):
 lift of [f, c] to 32 channels, four Fourier layers
@@ -69,77 +70,20 @@ def generate_trajectories(binding, torch, batch, device, log=print):
     return trajs, conds
 
 
-def make_model(torch, width=32, modes=12, hidden=128, n_layers=4, n_cond=7, seed=0, native=False):
-    """The training model. native: the spectral convolution of every layer
-    (forward and backward) runs in the library's kernels (binding.spectral_conv);
-    otherwise in torch.fft."""
-    nn = torch.nn
-    F = torch.nn.functional
-
-    def kept(n, m, device):
-        return torch.cat([torch.arange(m, device=device), torch.arange(n - m, n, device=device)])
-
-    class TorchFno(nn.Module):
-        def __init__(self):
-            super().__init__()
-            g = torch.Generator().manual_seed(seed)
-            cin = 1 + n_cond
-            self.m = modes
-            self.P = nn.Parameter(torch.randn(width, cin, generator=g) / cin ** 0.5)
-            self.p = nn.Parameter(torch.zeros(width))
-            self.W = nn.Parameter(torch.randn(n_layers, width, width, generator=g) / width ** 0.5)
-            self.b = nn.Parameter(torch.zeros(n_layers, width))
-            scale = 1.0 / (width * width)
-            self.R = nn.Parameter(scale * torch.rand(n_layers, width, width, 2 * modes, 2 * modes, modes, 2,
-                                                     generator=g))
-            self.Q1 = nn.Parameter(torch.randn(hidden, width, generator=g) / width ** 0.5)
-            self.q1 = nn.Parameter(torch.zeros(hidden))
-            self.Q2 = nn.Parameter(torch.randn(1, hidden, generator=g) * 1e-3 / hidden ** 0.5)
-            self.q2 = nn.Parameter(torch.zeros(1))
-
-        def forward(self, eta, cond):
-            """eta (B, nz, ny, nx), cond (B, n_cond) -> predicted eta."""
-            B, nz, ny, nx = eta.shape
-            m = self.m
-            const = cond @ self.P[:, 1:].T + self.p                      # (B, C)
-            v = self.P[:, 0].view(1, -1, 1, 1, 1) * eta[:, None] + const[:, :, None, None, None]
-            iz, iy = kept(nz, m, eta.device), kept(ny, m, eta.device)
-            for l in range(self.W.shape[0]):
-                if native:
-                    from . import binding
-                    kv = binding.spectral_conv(v, self.R[l], m)
-                else:
-                    Vh = torch.fft.rfftn(v, dim=(2, 3, 4))
-                    sub = Vh[:, :, iz][:, :, :, iy][..., :m]
-                    Rc = torch.view_as_complex(self.R[l])
-                    out_sub = torch.einsum("bizyx,oizyx->bozyx", sub, Rc)
-                    spec = torch.zeros((B, Rc.shape[0], nz, ny, nx // 2 + 1), dtype=Vh.dtype, device=eta.device)
-                    spec[:, :, iz[:, None], iy[None, :], :m] = out_sub
-                    kv = torch.fft.irfftn(spec, s=(nz, ny, nx), dim=(2, 3, 4))
-                local = torch.einsum("oi,bizyx->bozyx", self.W[l], v) + self.b[l].view(1, -1, 1, 1, 1)
-                v = F.gelu(local + kv)
-            h = F.gelu(torch.einsum("hi,bizyx->bhzyx", self.Q1, v) + self.q1.view(1, -1, 1, 1, 1))
-            d = torch.einsum("oh,bhzyx->bozyx", self.Q2, h)[:, 0] + self.q2
-            return eta + d
-
-    return TorchFno()
-
-
-def to_params(model):
-    """Weights in the checker's / library binding's layout (float64, R complex)."""
-    g = lambda t: t.detach().double().cpu().numpy()  # noqa: E731
-    R = g(model.R)
-    return {"P": g(model.P), "p": g(model.p), "W": g(model.W), "b": g(model.b),
-            "R": R[..., 0] + 1j * R[..., 1], "Q1": g(model.Q1), "q1": g(model.q1), "Q2": g(model.Q2),
-            "q2": g(model.q2)}
-
-
-def load_params(model, params, torch):
-    with torch.no_grad():
-        for k in ("P", "p", "W", "b", "Q1", "q1", "Q2", "q2"):
-            getattr(model, k).copy_(torch.as_tensor(np.asarray(params[k]).reshape(getattr(model, k).shape)))
-        R = np.asarray(params["R"])
-        model.R.copy_(torch.as_tensor(np.stack([R.real, R.imag], axis=-1)))
+def init_params(width=32, modes=12, hidden=128, n_layers=4, n_cond=7, seed=0):
+    """Initial weights of the stepper in the layout of pf_fno_init and
+    NativeTrainer (float64, R complex): P and W scaled by 1/sqrt(fan-in),
+    R uniform in [0, 1/width^2) per real and imaginary part, Q2 small so the
+    untrained network starts near the identity map, biases zero."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cin = 1 + n_cond
+    scale = 1.0 / (width * width)
+    R = scale * rng.random((n_layers, width, width, 2 * modes, 2 * modes, modes, 2))
+    return {"P": rng.standard_normal((width, cin)) / cin ** 0.5, "p": np.zeros(width),
+            "W": rng.standard_normal((n_layers, width, width)) / width ** 0.5, "b": np.zeros((n_layers, width)),
+            "R": R[..., 0] + 1j * R[..., 1],
+            "Q1": rng.standard_normal((hidden, width)) / width ** 0.5, "q1": np.zeros(hidden),
+            "Q2": rng.standard_normal((1, hidden)) * 1e-3 / hidden ** 0.5, "q2": np.zeros(1)}
 
 
 def train_native(torch, trainer, trajs, conds, seconds=240.0, lr=2e-3, batch_size=4, seed=0, log=print):
@@ -174,47 +118,6 @@ def train_native(torch, trainer, trajs, conds, seconds=240.0, lr=2e-3, batch_siz
             log(f"  iter {it} ({el:.0f} s) loss {np.mean(hist[-200:]):.3e}")
     log(f"trained {it} iterations in {time.perf_counter() - t0:.0f} s (library kernels), "
         f"last loss {np.mean(hist[-50:]):.3e}")
-    return {"iterations": it, "final_loss": float(np.mean(hist[-50:])) if hist else None}
-
-
-def train(torch, model, trajs, conds, seconds=240.0, lr=2e-3, batch_size=4, seed=0, log=print):
-    """Adam on MSE of the macro-step increment, pairs (snapshot k, k+1) of
-    every instance, mini-batches of one instance size, cosine-decayed rate,
-    for a wall-clock budget."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    dev = trajs[0].device
-    by_size = {}
-    for i, tr in enumerate(trajs):
-        by_size.setdefault(tuple(tr.shape[1:]), []).append(i)
-    pairs = [(i, k) for i, tr in enumerate(trajs) for k in range(tr.shape[0] - 1)]
-    cond_t = torch.as_tensor(conds, dtype=torch.float32, device=dev)
-    opt = torch.optim.Adam(model.parameters(), lr=lr)
-    t0 = time.perf_counter()
-    it, hist = 0, []
-    while True:
-        el = time.perf_counter() - t0
-        if el > seconds:
-            break
-        for gparam in opt.param_groups:
-            gparam["lr"] = lr * 0.5 * (1 + np.cos(np.pi * min(1.0, el / seconds)))
-        shape = list(by_size)[rng.integers(len(by_size))]
-        members = by_size[shape]
-        pick = [(members[rng.integers(len(members))], int(rng.integers(trajs[0].shape[0] - 1)))
-                for _ in range(batch_size)]
-        x = torch.stack([trajs[i][k] for i, k in pick])
-        y = torch.stack([trajs[i][k + 1] for i, k in pick])
-        c = cond_t[[i for i, _ in pick]]
-        pred = model(x, c)
-        loss = torch.mean((pred - y) ** 2)
-        opt.zero_grad(set_to_none=True)
-        loss.backward()
-        opt.step()
-        hist.append(float(loss))
-        it += 1
-        if it % 200 == 0:
-            log(f"  iter {it} ({el:.0f} s) loss {np.mean(hist[-200:]):.3e}")
-    log(f"trained {it} iterations in {time.perf_counter() - t0:.0f} s, last loss {np.mean(hist[-50:]):.3e}")
-    del pairs
     return {"iterations": it, "final_loss": float(np.mean(hist[-50:])) if hist else None}
 
 

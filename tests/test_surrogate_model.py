@@ -1,10 +1,12 @@
-"""The training model of the learned stepper computes the checker's network
-(CPU, float64): trained weights mean the same thing in the library."""
+"""The PyTorch model of the learned stepper (tests/fno_torch_model.py)
+computes the oracle's network (CPU, float64), and PyTorch autograd through it
+reproduces the oracle's hand-written backward: a third, independent
+derivation that the library's training kernels are checked against."""
 
 import numpy as np
 
 from oracle import fno as ofno
-from paper_2302_13612_amd import surrogate
+from tests import fno_torch_model as surrogate
 
 
 def test_torch_model_matches_oracle_forward():
