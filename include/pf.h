@@ -195,6 +195,8 @@ typedef struct {
                               unless pf_max_iter > 1)                       */
   double pf_change;        /* max |f^i - f^{i-1}| of its last solve (0
                               unless pf_max_iter > 1)                       */
+  int64_t steps_replayed;  /* steps of the context run as one replayed graph
+                              whose fixed point converged on the device     */
 } pf_stats;
 
 /* Workspace bytes for a problem (only the sizes, n_var and n_grains are read). */
@@ -207,8 +209,18 @@ int pf_init(const pf_problem *prob, void *workspace, size_t ws_bytes,
             void *hip_stream, pf_ctx **out);
 
 /* Advance n_steps steps under one load. Work is enqueued on the context's
- * stream; when the fixed point needs more than one iteration the call waits
- * on the stream once per iteration to read the convergence flag. */
+ * stream. A step that needs no decision on the host (the homogeneous spectral
+ * path, or one exact fixed-point iteration) is replayed from a captured graph.
+ * A fixed-point step whose first iterate is extrapolated from four converged
+ * steps (the fifth step on) is also replayed as one graph: as many
+ * iterations as the last step took, each returning at once on the device
+ * once its instance has converged, then the update, which runs only if every
+ * instance of its group converged; the call reads the convergence flags once
+ * per step and, if a group needs more iterations, continues them (one status
+ * read per iteration) and then updates it. Other fixed-point steps (the first
+ * four, after pf_fields sets a field, with profiling, PF_STEP_SAVE_STRESS or
+ * pf_max_iter > 1) read the flags after every iteration. Either way the
+ * kernels and their order are the same, so the results are identical. */
 int pf_step(pf_ctx *ctx, int32_t n_steps, const pf_load *load);
 
 /* Copy a field between the context and a caller device buffer of the same

@@ -83,6 +83,7 @@ class PfStats(ctypes.Structure):
         ("ms_residual", ctypes.c_double),
         ("pf_iters", ctypes.c_int32),
         ("pf_change", ctypes.c_double),
+        ("steps_replayed", ctypes.c_int64),
     ]
 
 
@@ -219,7 +220,7 @@ def _stats_dict(s, n_var):
         "eta_mean": np.array(s.eta_mean[:n_var]),
         "eta_min": s.eta_min, "eta_max": s.eta_max,
         "ms_iters": s.ms_iters, "ms_residual": s.ms_residual,
-        "pf_iters": s.pf_iters, "pf_change": s.pf_change,
+        "pf_iters": s.pf_iters, "pf_change": s.pf_change, "steps_replayed": s.steps_replayed,
     }
 
 

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <functional>
 #include <initializer_list>
+#include <map>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -346,6 +347,7 @@ struct Group {
   std::vector<int> members;
   float* ring[4];        // strain fields: ring[cur] the latest converged one, then
   int cur;               // ring[cur - 1], ring[cur - 2], ring[cur - 3] those of the steps before
+  int last_iters;        // fixed-point iterations of the group's last step (most of its instances')
 };
 
 }  // namespace
@@ -361,6 +363,7 @@ struct pf_ctx {
   uint32_t stress_mask;
   int h_kind;
   int64_t steps;
+  int64_t steps_replayed;  // fixed-point steps replayed as one graph
   Status* host_status;   // pinned, [n_inst]
   double* host_loads;    // pinned, [n_inst][12]
   bool loads_uploaded;
@@ -369,6 +372,8 @@ struct pf_ctx {
   hipStream_t cap_stream;
   hipGraphExec_t gexec;
   std::string gkey;
+  // graphs of single steps whose fixed point runs on the device, by key
+  std::map<std::string, hipGraphExec_t> sgraphs;
   bool capturing;
   // profiling
   bool prof_on;
@@ -586,8 +591,7 @@ int ms_iteration(pf_ctx* c, const KArgs& a, hipStream_t s) {
 // chemical force of the latest iterate (pc_x_forward) while the gradient
 // term stays implicit and the mechanical force stays that of f^n; after each
 // solve the host reads max |f^i - f^{i-1}| and stops at pf_tol.
-int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
-  const KArgs& a = g.args;
+int ac_update_args(pf_ctx* c, const Group& g, const KArgs& a, hipStream_t s) {
   PF_TRY(launch(c, s, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
   for (int it = 1;; ++it) {
     PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
@@ -611,6 +615,8 @@ int ac_update(pf_ctx* c, const Group& g, hipStream_t s) {
   PF_TRY(launch(c, s, "ac_finalize", [&] { return pfl::ac_finalize(a, 0, s); }));
   return PF_OK;
 }
+
+int ac_update(pf_ctx* c, const Group& g, hipStream_t s) { return ac_update_args(c, g, g.args, s); }
 
 // The statistics of the homogeneous spectral path (reductions of the step's
 // passes); needed after the last step of a call only: every pass of a step
@@ -647,6 +653,46 @@ void drop_graph(pf_ctx* c) {
   if (c->gexec) hipGraphExecDestroy(c->gexec);
   c->gexec = nullptr;
   c->gkey.clear();
+  for (auto& kv : c->sgraphs) hipGraphExecDestroy(kv.second);
+  c->sgraphs.clear();
+}
+
+// Replay the graph of one step under key, capturing it with build(stream)
+// first if it is not cached (at most kMaxStepGraphs are kept).
+constexpr size_t kMaxStepGraphs = 32;
+template <class F>
+int run_step_graph(pf_ctx* c, const std::string& key, F&& build) {
+  hipError_t e;
+  auto it = c->sgraphs.find(key);
+  if (it == c->sgraphs.end()) {
+    if (c->sgraphs.size() >= kMaxStepGraphs) {
+      for (auto& kv : c->sgraphs) hipGraphExecDestroy(kv.second);
+      c->sgraphs.clear();
+    }
+    if (!c->cap_stream) {
+      if ((e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(c, e, "capture stream");
+    }
+    if ((e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed)) != hipSuccess)
+      return hip_fail(c, e, "begin capture");
+    c->capturing = true;
+    const int rc = build(c->cap_stream);
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->cap_stream, &graph);
+    if (rc != PF_OK) {
+      if (graph) hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "end capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(c, e, "graph instantiate");
+    it = c->sgraphs.emplace(key, ex).first;
+  }
+  if ((e = hipGraphLaunch(it->second, c->stream)) != hipSuccess) return hip_fail(c, e, "graph launch");
+  return PF_OK;
 }
 
 // Capture (or reuse) the graph of one step of every group and replay it.
@@ -816,6 +862,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
   c->stress_mask = p0.bc_stress_mask;
   c->h_kind = p0.h_kind;
   c->steps = 0;
+  c->steps_replayed = 0;
   c->loads_uploaded = false;
   c->cap_stream = nullptr;
   c->gexec = nullptr;
@@ -884,6 +931,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     g.ring[2] = reinterpret_cast<float*>(ws + L.eps_prev2);
     g.ring[3] = reinterpret_cast<float*>(ws + L.eps_prev3);
     g.cur = 0;
+    g.last_iters = 0;
     a.eps = a.eps_out = g.ring[0];
     a.eps_h1 = a.eps_h2 = a.eps_h3 = nullptr;
     a.iter_mode = 0;
@@ -1060,18 +1108,14 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
       // two previous steps (from the third step on), the step's starting
       // strain kept for that from the second step on
       std::vector<size_t> iterating;
-      for (size_t k = 0; k < c->groups.size(); ++k) {
-        Group& g = c->groups[k];
-        if (use_kh[k] || g.one_iteration) {
-          PF_TRY(fixed_step(c, g, use_kh[k] != 0, n == n_steps - 1, s));
-          continue;
-        }
-        iterating.push_back(k);
-      }
+      for (size_t k = 0; k < c->groups.size(); ++k)
+        if (!use_kh[k] && !c->groups[k].one_iteration) iterating.push_back(k);
       // The first iterate extrapolates the converged strains of the previous
       // steps (linear from the third step on, quadratic from the fourth, cubic
       // from the fifth) and is written over the oldest of the four fields.
       std::vector<KArgs> first(c->groups.size()), later(c->groups.size());
+      bool replay = !save_stress && !c->prof_on && !iterating.empty();
+      int P = 1;  // iterations the replayed graph holds: those of the last step
       for (size_t k : iterating) {
         Group& g = c->groups[k];
         const int order = !g.strain_valid ? 0 : (g.hist >= 4 ? 3 : (g.hist == 3 ? 2 : (g.hist == 2 ? 1 : 0)));
@@ -1092,10 +1136,65 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         l.eps_out = out;
         l.eps_h1 = l.eps_h2 = l.eps_h3 = nullptr;
         l.iter_mode = 0;
-        PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(f, s); }));
+        replay = replay && order == 3 && g.pf_max_iter <= 1;
+        P = std::max(P, g.last_iters);
       }
+      P = std::min(P, c->ms_max_iter);
       std::vector<size_t> active = iterating;
-      for (int it = 0; it < c->ms_max_iter && !active.empty(); ++it) {
+      std::vector<char> updated(c->groups.size(), 0);
+      int it0 = 0;
+      if (replay) {
+        // The whole step as one graph: the fixed point runs P iterations on
+        // the device (iterations after convergence exit at once), then each
+        // group's update runs if all of its instances converged. One status
+        // read per step; a group that needs more iterations continues here.
+        std::string key = "P" + std::to_string(P);
+        for (size_t k = 0; k < c->groups.size(); ++k) {
+          char buf[80];
+          snprintf(buf, sizeof(buf), ";%d:%d:%p", (int)use_kh[k], c->groups[k].cur,
+                   (const void*)c->groups[k].args.epsp);
+          key += buf;
+        }
+        PF_TRY(run_step_graph(c, key, [&](hipStream_t cs) -> int {
+          for (size_t k = 0; k < c->groups.size(); ++k) {
+            const Group& g = c->groups[k];
+            if (use_kh[k] || g.one_iteration) {
+              PF_TRY(fixed_step(c, g, use_kh[k] != 0, false, cs));
+              continue;
+            }
+            PF_TRY(launch(c, cs, "step_begin", [&] { return pfl::step_begin(first[k], cs); }));
+            PF_TRY(ms_iteration(c, first[k], cs));
+            for (int it = 1; it < P; ++it) PF_TRY(ms_iteration(c, later[k], cs));
+            PF_TRY(launch(c, cs, "group_ready", [&] { return pfl::group_ready(later[k], cs); }));
+            KArgs ua = g.args;
+            ua.eps = ua.eps_out = later[k].eps_out;
+            ua.guard_ready = 1;
+            PF_TRY(ac_update_args(c, g, ua, cs));
+          }
+          return PF_OK;
+        }));
+        if (n == n_steps - 1)
+          for (size_t k = 0; k < c->groups.size(); ++k)
+            if (use_kh[k]) PF_TRY(kh_finalize(c, c->groups[k], s));
+        PF_TRY(read_status(c));
+        std::vector<size_t> still;
+        for (size_t k : iterating) {
+          const size_t b = status_base(c, k);
+          bool all = true;
+          for (int j = 0; j < c->groups[k].ninst; ++j) all = all && c->host_status[b + j].done;
+          if (all) updated[k] = 1;
+          else still.push_back(k);
+        }
+        active.swap(still);
+        it0 = P;
+        c->steps_replayed += 1;
+      } else {
+        for (size_t k = 0; k < c->groups.size(); ++k)
+          if (use_kh[k] || c->groups[k].one_iteration)
+            PF_TRY(fixed_step(c, c->groups[k], use_kh[k] != 0, n == n_steps - 1, s));
+        for (size_t k : iterating) PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(first[k], s); }));
+      }
+      for (int it = it0; it < c->ms_max_iter && !active.empty(); ++it) {
         for (size_t k : active) PF_TRY(ms_iteration(c, it == 0 ? first[k] : later[k], s));
         PF_TRY(read_status(c));
         std::vector<size_t> still;
@@ -1131,9 +1230,13 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
       }
       for (size_t k : iterating) {
         Group& g = c->groups[k];
+        const size_t b = status_base(c, k);
+        int most = 0;
+        for (int j = 0; j < g.ninst; ++j) most = std::max(most, (int)c->host_status[b + j].iters);
+        g.last_iters = most;
         g.cur = (g.cur + 1) % 4;
         g.args.eps = g.args.eps_out = g.ring[g.cur];
-        PF_TRY(ac_update(c, g, s));
+        if (!updated[k]) PF_TRY(ac_update(c, g, s));
       }
       for (size_t k = 0; k < c->groups.size(); ++k) {
         Group& g = c->groups[k];
@@ -1243,6 +1346,7 @@ int pf_batch_stats(pf_ctx* c, int32_t inst, pf_stats* out) {
   out->ms_residual = st.st.residual;
   out->pf_iters = g.pf_max_iter > 1 ? st.st.pf_iters : 1;
   out->pf_change = g.pf_max_iter > 1 ? st.st.pf_change : 0.0;
+  out->steps_replayed = c->steps_replayed;
   if (st.st.nonfinite) return fail(c, PF_ENONFINITE, "non-finite order parameter");
   return PF_OK;
 }

@@ -22,7 +22,7 @@ struct Status {
   int32_t iters;
   int32_t done;
   int32_t nonfinite;
-  int32_t pad;
+  int32_t ready;      // instance 0 of a group: every instance converged (guarded update)
   double pf_change;   // max |f^i - f^{i-1}| of the last solve of the update's fixed point
   int32_t pf_iters;   // solves of that fixed point in the last step
   int32_t pf_pad;
@@ -131,6 +131,8 @@ struct KArgs {
   int ztile_ms, zplan_ms;     // Green z pass: columns per block (0: 8) and plan variant (0, 1)
   int zplan_ac;               // Allen-Cahn z pass: plan variant (0, 1, 2)
   int zplan_kh;               // spectral path's z pass: plan variant (0, 1)
+  int guard_ready;            // update passes: run only if state[0].st.ready (a step
+                              // replayed as a graph, its fixed point done on the device)
 };
 
 // Packed upper-triangle index of a symmetric 6x6 matrix.
@@ -147,6 +149,8 @@ int rows_per_block(int nx);
 int x_blocks(const KArgs& a);
 int z_blocks(const KArgs& a, int ncomp);
 hipError_t step_begin(const KArgs& a, hipStream_t s);
+// state[0].st.ready = every instance of the group converged
+hipError_t group_ready(const KArgs& a, hipStream_t s);
 // mean of each component of instance inst of a strain field -> its
 // DevState::ebar_field (after the caller replaced the strain)
 hipError_t strain_mean(const KArgs& a, const float* field, int inst, hipStream_t s);

@@ -88,6 +88,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 lds[ROWS * LROW];
+  if (a.guard_ready && !a.state[0].st.ready) return;
   const int t = threadIdx.x % T, p = threadIdx.x / T;
   const int nrows = a.ninst * a.nz * a.ny;
   const int row = blockIdx.x * ROWS + p;
@@ -202,6 +203,7 @@ __global__ __launch_bounds__((col_threads<N, K, C>())) void k_y(const KArgs a) {
   const int z = blockIdx.y, comp = blockIdx.z;  // z over all instances
   // transforms of a fixed-point iteration are skipped for a converged instance
   if (a.skip_done && a.state[z / a.nz].st.done) return;
+  if (a.guard_ready && !a.state[0].st.ready) return;
   const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
   float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.sh + (valid ? kx : 0);
   float2 v[E];
@@ -439,6 +441,7 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_ac(const 
   using P = PV<N, K>;
   constexpr int E = P::E, T = N / E, C = kColTile;
   __shared__ float2 lds[N * C];
+  if (a.guard_ready && !a.state[0].st.ready) return;
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int kx = blockIdx.x * C + cc;
   const bool valid = kx < a.nh;
@@ -753,6 +756,18 @@ __global__ void k_step_begin(const KArgs a) {
   st->st.iters = 0;
 }
 
+// state[0].st.ready = every instance of the group has converged (one block);
+// the update passes of a step replayed as a graph run only then.
+__global__ __launch_bounds__(256) void k_group_ready(const KArgs a) {
+  __shared__ int all;
+  if (threadIdx.x == 0) all = 1;
+  __syncthreads();
+  for (int i = threadIdx.x; i < a.ninst; i += blockDim.x)
+    if (!a.state[i].st.done) all = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) a.state[0].st.ready = all;
+}
+
 // Mean of each strain component of instance j of a caller-set field (one
 // block per component, FP64, fixed summation order): the mean strain the
 // field in memory carries, taken as the base of the next step's first
@@ -1032,6 +1047,7 @@ __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
 
 __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int mode) {
   __shared__ double scratch[1024];
+  if (a.guard_ready && !a.state[0].st.ready) return;
   fin_ac(a, blockIdx.x, nblk_x, nblk_z, mode, blockIdx.y, scratch);
 }
 
@@ -1128,6 +1144,11 @@ int z_blocks(const KArgs& a, int ncomp) { return a.ninst * z_blocks_inst(a, ncom
     case 512: { constexpr int N = 512; BODY; } break; \
     default: return hipErrorInvalidValue;     \
   }
+
+hipError_t group_ready(const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_group_ready, dim3(1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t strain_mean(const KArgs& a, const float* field, int inst, hipStream_t s) {
   hipLaunchKernelGGL(k_strain_mean, dim3(6), dim3(1024), 0, s, a, field, inst);

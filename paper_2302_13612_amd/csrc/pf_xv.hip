@@ -364,6 +364,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
   __shared__ float2 stage[V * ROWS * LROW];
+  if (a.guard_ready && !a.state[0].st.ready) return;
   const int rpi = a.nz * a.ny;
   const int inst = blockIdx.x * ROWS / rpi;
   const float* tabs = a.tables + (size_t)inst * a.tab_inst;
