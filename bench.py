@@ -61,10 +61,12 @@ def sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic(kernel, grid, n_var):
+def measured_traffic(kernel, grid, n_var, window):
     """HBM bytes per launch of a stage from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated by a device copy), or None
-    if absent, taken on other sources or on another grid or variant count."""
+    if absent, or taken on other sources, on another grid or variant count, or
+    over another window of steps (warm-up, timed): the per-launch average
+    depends on the window through the share of first iterations."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -73,7 +75,7 @@ def measured_traffic(kernel, grid, n_var):
         return None
     if t.get("sources_sha256") != sources_digest():
         return None
-    if t.get("grid") != list(grid) or t.get("n_var") != n_var:
+    if t.get("grid") != list(grid) or t.get("n_var") != n_var or t.get("window") != list(window):
         return None
     k = t.get("kernels", {}).get(kernel)
     return None if k is None else k["fetch_bytes"] + k["write_bytes"]
@@ -138,32 +140,50 @@ def cpu_info():
     return cores, model
 
 
-def cpu_baseline(n=128, steps=1, pf_max_iter=1, pf_tol=1e-6):
-    """The FP64 oracle, as it stands, on the same recipe at n^3 (a bounded
-    sample of the workload), in voxel-updates/s."""
+def cpu_baseline(n=256, iters_per_step=None, pf_max_iter=1, pf_tol=1e-6):
+    """The FP64 oracle, as it stands, on the same recipe at n^3: one step with
+    a single fixed-point iteration (that iteration, the stress of the result,
+    the driving forces, the update and the statistics), and one more
+    iteration of the fixed point alone (constitutive law, forward transform,
+    Green's operator, inverse transform). The oracle's step time is formed
+    with the fixed-point iterations per step the GPU measured in the same run,
+    step = t_step(1 iteration) + (K - 1) t_iteration, so both sides are priced
+    for the same work."""
     from oracle import crystal as cr
+    from oracle import mech
     from oracle import phasefield as opf
     from paper_2302_13612_amd import inputs
     cfg = inputs.polycrystal(shape=(n, n, n))
     tabs = cr.mg_tables(cfg["rotations"], cfg["variant_ids"])
     C0 = opf.reference_stiffness_average(tabs[0], tabs[1])
     prob = opf.Problem(cfg["shape"], cfg["dx"], tabs, cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], C0,
-                       gid=cfg["gid"], ms_tol=cfg["ms_tol"], ms_max_iter=cfg["ms_max_iter"],
+                       gid=cfg["gid"], ms_tol=cfg["ms_tol"], ms_max_iter=1,
                        pf_tol=pf_tol, pf_max_iter=pf_max_iter)
     st = opf.State.initial(cfg["eta0"].astype(np.float64), np.zeros(6))
-    epsp = cfg["eps_p"].astype(np.float64)
+    epsp6 = cfg["eps_p"].astype(np.float64)
     ld = dict(eps_bar=cfg["eps_bar"], sig_bar=cfg["sig_bar"], stress_mask=cfg["stress_mask"])
     t0 = time.perf_counter()
-    for _ in range(steps):
-        st, stats, _ = opf.step(prob, st, epsp, ld)
-    dt = time.perf_counter() - t0
+    new, stats, _ = opf.step(prob, st, epsp6, ld)
+    t_step1 = time.perf_counter() - t0
+    # one more iteration of the fixed point from the strain the step reached
+    eps_p = mech.voigt6_to_tensor(epsp6)
+    t0 = time.perf_counter()
+    _, _, sigma = mech.eigenstrain_and_stress(new.eps, st.eta, eps_p, prob.gid, *prob.tables, prob.h_kind)
+    deps = -mech.ifft_tensor(prob.green.apply(mech.fft_tensor(sigma)), prob.shape)
+    t_iter = time.perf_counter() - t0
+    del deps, sigma
+    K = float(iters_per_step) if iters_per_step else 1.0
+    t_step = t_step1 + (K - 1.0) * t_iter
     cores, model = cpu_info()
     return {
-        "value": n ** 3 * steps / dt, "unit": "voxel-updates/s", "cores": cores, "kind": "oracle",
-        "sample": f"{steps} oracle step(s) of the same polycrystal recipe at {n}^3 (64 grains, 6 variants, "
-                  f"fixed-point tol {cfg['ms_tol']:g}, {stats['ms_iters']} iterations"
+        "value": n ** 3 / t_step, "unit": "voxel-updates/s", "cores": cores, "kind": "oracle",
+        "sample": f"the oracle on the same polycrystal recipe at {n}^3 (64 grains, 6 variants): one step with one "
+                  f"fixed-point iteration {t_step1:.1f} s and one further iteration {t_iter:.1f} s, "
+                  f"priced at the GPU's {K:.2f} iterations per step ({t_step:.1f} s per step)"
                   + (f", update fixed point tol {pf_tol:g}, {stats['pf_iters']} solves" if pf_max_iter > 1 else "")
-                  + f"), {dt:.1f} s on {model}",
+                  + f", on {model}",
+        "s_per_iteration": round(t_iter, 2), "s_per_step_one_iteration": round(t_step1, 2),
+        "iterations_per_step": round(K, 3),
     }
 
 
@@ -582,7 +602,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--n", type=int, default=256, help="grid edge (default 256)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--cpu-n", type=int, default=256, help="grid edge of the oracle's timed sample")
     ap.add_argument("--aniso", action="store_true",
                     help="rve-batch: anisotropic gradient energy of Table 5 for every instance")
     ap.add_argument("--pf-max-iter", type=int, default=1,
@@ -609,13 +629,15 @@ def main():
         return bench_vmap(args)
     if args.workload == "pillar":
         return bench_pillar(args)
-    # polycrystal: steps 11-110 of the 1000-step run (10 warm-up steps, then
-    # 100 timed); the fixed-point iteration count per step falls as the run
-    # settles, so a short window early in the run is not representative
+    # polycrystal: steps 6-25 of the 1000-step run by default (5 warm-up
+    # steps, then 20 timed). The fixed-point iteration count per step falls as
+    # the run settles (about 3.5 per step here, 2 later), so the line states
+    # its window, the iterations per step and the time per iteration and per
+    # update, which compare across windows.
     if args.steps is None:
-        args.steps = 100
+        args.steps = 20
     if args.warmup is None:
-        args.warmup = 10
+        args.warmup = 5
 
     import torch
     from paper_2302_13612_amd import binding, inputs
@@ -712,7 +734,11 @@ def main():
         # bytes of a step from the launches each stage made in those steps
         step_bytes = sum(stage_bytes(nm, c2, nprof) for nm, (c2, _) in allp.items()) / nprof
     total_ms = sum(v[1] for v in allp.values())
-    log(f"per-stage times over {nprof} further steps:")
+    fp_iters = allp.get("ms_x_forward", (0, 0.0))[0]
+    ms_iter = sum(m2 for nm, (_, m2) in allp.items() if nm.startswith("ms_")) / max(1, fp_iters)
+    ms_update = sum(m2 for nm, (_, m2) in allp.items() if nm.startswith(("ac_", "pc_"))) / nprof
+    log(f"per-stage times over {nprof} further steps ({fp_iters / nprof:.2f} iterations per step): "
+        f"{ms_iter:.3f} ms per fixed-point iteration, {ms_update:.3f} ms per update")
     for name, (c2, m2) in sorted(allp.items(), key=lambda kv: -kv[1][1]):
         b = stage_bytes(name, c2, nprof)
         gbs = b / (m2 * 1e-3) / 1e9 if b else 0.0
@@ -725,7 +751,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(dom[3] / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(dom[0], (n, n, n), V),
+        "traffic": measured_traffic(dom[0], (n, n, n), V, (args.warmup, args.steps)),
         "bytes_per_launch": round(dom[4]),
         "avg_launch_us": round(dom[2] * 1e3, 1),
         "launches": dom[1],
@@ -756,6 +782,8 @@ def main():
             "grid": [n, n, n], "n_var": V, "n_grains": 64,
             "ms_iters_last_step": stats["ms_iters"],
             "fixed_point_iters_per_step": round(n_iter / args.steps, 3),
+            "ms_per_fixed_point_iteration": round(ms_iter, 4),
+            "ms_per_update": round(ms_update, 4),
             "variant_updates_per_s": value * V,
             "timed_steps": f"{args.warmup + 1}-{args.warmup + args.steps} of the run",
             "plan": plan,
@@ -768,8 +796,9 @@ def main():
         out["config"]["pf_max_iter"] = args.pf_max_iter
     solver.close()
     if not args.no_cpu_baseline:
-        log(f"cpu baseline (oracle at {args.cpu_n}^3)")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n, pf_max_iter=args.pf_max_iter, pf_tol=args.pf_tol)
+        k_fp = fp_iters / nprof if iterated else n_iter / args.steps
+        log(f"cpu baseline (oracle at {args.cpu_n}^3, {k_fp:.2f} iterations per step)")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n, k_fp, pf_max_iter=args.pf_max_iter, pf_tol=args.pf_tol)
         log(f"cpu baseline {out['cpu_baseline']['value']:.3e} voxel-updates/s")
     print(json.dumps(out), flush=True)
 

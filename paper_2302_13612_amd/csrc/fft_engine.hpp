@@ -95,8 +95,9 @@ __device__ __forceinline__ void dft(float2* v) {
 // Fields and spectra of a pass are touched once per pass and far larger than
 // the caches, so the passes that move whole rows or 128-byte column runs
 // load and store them with the nontemporal hint (measured at 256^3: the x
-// passes 15-27% faster). The Green z pass keeps plain accesses: its 64-byte
-// column runs share lines with the neighbouring tile, which the hint evicts.
+// passes 15-27% faster). The Green z pass and the y passes load without the
+// hint: the Green pass's 64-byte column runs share lines with the
+// neighbouring tile, which the hint evicts.
 typedef float f2v_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ float2 gld(const float2* p) {
   const f2v_t v = __builtin_nontemporal_load(reinterpret_cast<const f2v_t*>(p));

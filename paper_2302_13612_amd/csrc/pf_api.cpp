@@ -348,6 +348,8 @@ struct Group {
   float* ring[4];        // strain fields: ring[cur] the latest converged one, then
   int cur;               // ring[cur - 1], ring[cur - 2], ring[cur - 3] those of the steps before
   int last_iters;        // fixed-point iterations of the group's last step (most of its instances')
+  int32_t fin_seq;       // status publications enqueued for each instance (k_fin_res launches)
+  size_t status_off;     // index of its first instance in the host status array
 };
 
 }  // namespace
@@ -567,6 +569,30 @@ int read_status(pf_ctx* c) {
   hipError_t e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "stream sync");
   return PF_OK;
+}
+
+// Wait until the fixed point's finalize of every instance of the given
+// groups has published its status (seq reached the launches enqueued), by
+// polling the host-visible array; a stream that went idle without it (or an
+// error) falls back to copying the status.
+int wait_published(pf_ctx* c, const std::vector<size_t>& groups) {
+  for (int spin = 0;; ++spin) {
+    bool all = true;
+    for (size_t k : groups) {
+      const Group& g = c->groups[k];
+      for (int j = 0; j < g.ninst && all; ++j) {
+        const int seq = __atomic_load_n(&c->host_status[g.status_off + j].seq, __ATOMIC_ACQUIRE);
+        all = seq == g.fin_seq;
+      }
+      if (!all) break;
+    }
+    if (all) return PF_OK;
+    if ((spin & 1023) == 1023) {
+      const hipError_t q = hipStreamQuery(c->stream);
+      if (q == hipSuccess) return read_status(c);
+      if (q != hipErrorNotReady) return hip_fail(c, q, "stream query");
+    }
+  }
 }
 
 // host_status index range of a group
@@ -883,9 +909,13 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     delete c;
     return PF_EDEVICE;
   };
+  // the status array is written by the device directly (fine-grained, mapped)
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&c->host_status), sizeof(Status) * n_inst,
-                         hipHostMallocDefault)) != hipSuccess)
+                         hipHostMallocMapped | hipHostMallocCoherent)) != hipSuccess)
     return bail(e, "hipHostMalloc");
+  Status* status_dev = nullptr;
+  if ((e = hipHostGetDevicePointer(reinterpret_cast<void**>(&status_dev), c->host_status, 0)) != hipSuccess)
+    return bail(e, "hipHostGetDevicePointer");
   if ((e = hipHostMalloc(reinterpret_cast<void**>(&c->host_loads), sizeof(double) * 12 * n_inst,
                          hipHostMallocDefault)) != hipSuccess)
     return bail(e, "hipHostMalloc");
@@ -893,6 +923,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
   std::memset(c->host_loads, 0, sizeof(double) * 12 * n_inst);
 
   const int nv = p0.n_var;
+  size_t status_off = 0;
   for (auto& g : c->groups) {
     const Layout& L = g.L;
     const pf_problem& pg = probs[g.members[0]];
@@ -932,6 +963,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     g.ring[3] = reinterpret_cast<float*>(ws + L.eps_prev3);
     g.cur = 0;
     g.last_iters = 0;
+    g.fin_seq = 0;
     a.eps = a.eps_out = g.ring[0];
     a.eps_h1 = a.eps_h2 = a.eps_h3 = nullptr;
     a.iter_mode = 0;
@@ -978,6 +1010,9 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.part_mm = reinterpret_cast<float*>(ws + L.part_mm);
     a.part_gd = reinterpret_cast<double*>(ws + L.part_gd);
     a.state = reinterpret_cast<DevState*>(ws + L.state);
+    a.pub = status_dev + status_off;
+    g.status_off = status_off;
+    status_off += g.ninst;
     a.save_stress = 0;
 
     // per-instance tables, stacked
@@ -1091,6 +1126,8 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
   }
   if (graphable) {
     PF_TRY(run_graph(c, n_steps, use_kh, key));
+    for (size_t k = 0; k < c->groups.size(); ++k)
+      if (!use_kh[k]) c->groups[k].fin_seq += n_steps;
     for (size_t k = 0; k < c->groups.size(); ++k) {
       Group& g = c->groups[k];
       if (use_kh[k]) {
@@ -1176,7 +1213,9 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         if (n == n_steps - 1)
           for (size_t k = 0; k < c->groups.size(); ++k)
             if (use_kh[k]) PF_TRY(kh_finalize(c, c->groups[k], s));
-        PF_TRY(read_status(c));
+        for (size_t k = 0; k < c->groups.size(); ++k)
+          if (!use_kh[k]) c->groups[k].fin_seq += c->groups[k].one_iteration ? 1 : P;
+        PF_TRY(wait_published(c, iterating));
         std::vector<size_t> still;
         for (size_t k : iterating) {
           const size_t b = status_base(c, k);
@@ -1190,13 +1229,18 @@ int pf_batch_step(pf_ctx* c, int32_t n_steps, const pf_load* loads) {
         c->steps_replayed += 1;
       } else {
         for (size_t k = 0; k < c->groups.size(); ++k)
-          if (use_kh[k] || c->groups[k].one_iteration)
+          if (use_kh[k] || c->groups[k].one_iteration) {
             PF_TRY(fixed_step(c, c->groups[k], use_kh[k] != 0, n == n_steps - 1, s));
+            if (!use_kh[k]) c->groups[k].fin_seq += 1;
+          }
         for (size_t k : iterating) PF_TRY(launch(c, s, "step_begin", [&] { return pfl::step_begin(first[k], s); }));
       }
       for (int it = it0; it < c->ms_max_iter && !active.empty(); ++it) {
-        for (size_t k : active) PF_TRY(ms_iteration(c, it == 0 ? first[k] : later[k], s));
-        PF_TRY(read_status(c));
+        for (size_t k : active) {
+          PF_TRY(ms_iteration(c, it == 0 ? first[k] : later[k], s));
+          c->groups[k].fin_seq += 1;
+        }
+        PF_TRY(wait_published(c, active));
         std::vector<size_t> still;
         for (size_t k : active) {
           const size_t b = status_base(c, k);

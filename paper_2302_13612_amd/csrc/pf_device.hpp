@@ -25,7 +25,7 @@ struct Status {
   int32_t ready;      // instance 0 of a group: every instance converged (guarded update)
   double pf_change;   // max |f^i - f^{i-1}| of the last solve of the update's fixed point
   int32_t pf_iters;   // solves of that fixed point in the last step
-  int32_t pf_pad;
+  int32_t seq;        // status publications of the fixed point (one per k_fin_res launch)
 };
 
 // Device-resident state of a context (FP64 scalars).
@@ -131,6 +131,8 @@ struct KArgs {
   int ztile_ms, zplan_ms;     // Green z pass: columns per block (0: 8) and plan variant (0, 1)
   int zplan_ac;               // Allen-Cahn z pass: plan variant (0, 1, 2)
   int zplan_kh;               // spectral path's z pass: plan variant (0, 1)
+  Status* pub;                // [ninst] host-visible copy of each instance's Status, or null:
+                              // the fixed point's finalize writes it there for the host to poll
   int guard_ready;            // update passes: run only if state[0].st.ready (a step
                               // replayed as a graph, its fixed point done on the device)
 };

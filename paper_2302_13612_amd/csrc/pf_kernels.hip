@@ -422,11 +422,12 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs 
   const TwCache<N, P, -1> twi = twf.conj();
 #pragma unroll
   for (int c = 0; c < 6; ++c) fft_pencil<N, -1, P>(v[c], view, t, twi);
+  // streaming stores (the loads stay plain: see gld)
   if (valid) {
 #pragma unroll
     for (int c = 0; c < 6; ++c)
 #pragma unroll
-      for (int m = 0; m < E; ++m) col[c * cs + (size_t)(t + T * m) * zs] = v[c][m];
+      for (int m = 0; m < E; ++m) gst(col + c * cs + (size_t)(t + T * m) * zs, v[c][m]);
   }
 }
 
@@ -1039,10 +1040,29 @@ __device__ inline void resid_fin(const KArgs& a, int inst, int nblk) {
 // One-block-per-instance finalize kernels. (Folding them into the last
 // block of the x passes needs a device-scope fence in every block, which on
 // this multi-L2 part writes back the L2 and costs far more than a launch.)
+// Convergence test of every instance (skipped for converged ones), then the
+// instance's status published: seq counts the launches, and with a.pub the
+// whole Status goes to host-visible memory, seq last after a system-scope
+// fence, so the host can wait on seq instead of copying and synchronising.
 __global__ __launch_bounds__(1024) void k_fin_res(const KArgs a, int nblk) {
   __shared__ double scratch[1024];
-  if (a.state[blockIdx.x].st.done) return;
-  fin_res(a, blockIdx.x, nblk, scratch);
+  DevState* st = a.state + blockIdx.x;
+  if (!st->st.done) fin_res(a, blockIdx.x, nblk, scratch);
+  if (threadIdx.x != 0) return;
+  const int seq = st->st.seq + 1;
+  st->st.seq = seq;
+  if (a.pub) {
+    Status* dst = a.pub + blockIdx.x;
+    dst->residual = st->st.residual;
+    dst->iters = st->st.iters;
+    dst->done = st->st.done;
+    dst->nonfinite = st->st.nonfinite;
+    dst->ready = st->st.ready;
+    dst->pf_change = st->st.pf_change;
+    dst->pf_iters = st->st.pf_iters;
+    __threadfence_system();
+    __hip_atomic_store(&dst->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_fin_ac(const KArgs a, int nblk_x, int nblk_z, int mode) {

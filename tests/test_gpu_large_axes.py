@@ -2,8 +2,10 @@
 512 = 2^9) in each role (x: the fused real-to-complex passes, y, z: the
 Green's operator and the Allen-Cahn divide), against the FP64 oracle.
 
-The other two axes stay small so that the oracle finishes in seconds; the
-transform test covers every new length on every axis.
+Every one of these lengths is run as z, as y and as x in the polycrystal step
+and in the spectral path; the other two axes stay small so that the oracle
+finishes in seconds. The transform test covers every new length on every
+axis.
 Tolerances as for the other step parity tests: f max-abs <= 1e-4, stress
 relative L2 <= 1e-5.
 """
@@ -42,14 +44,17 @@ def test_transform_large_axes(shape):
     assert d_back < 2e-6
 
 
+# every large length in every role: 512 as z, y, x; 384 as z, y, x; 192 as z, y, x
 @pytest.mark.parametrize("shape,n_var", [((512, 32, 32), 6), ((32, 512, 32), 2), ((32, 32, 512), 6),
-                                         ((384, 32, 48), 2), ((32, 48, 384), 2), ((32, 192, 48), 6)])
+                                         ((384, 32, 48), 2), ((32, 384, 32), 2), ((32, 48, 384), 2),
+                                         ((192, 32, 48), 6), ((32, 192, 48), 6), ((32, 32, 192), 6)])
 def test_polycrystal_large_axis(shape, n_var):
     cfg = cases.small_polycrystal(shape=shape, n_grains=6, seed=21, n_var=n_var)
     compare(cfg, 2, f"polycrystal {shape} {n_var} variants")
 
 
-@pytest.mark.parametrize("shape", [(512, 32, 32), (32, 512, 32), (32, 32, 512), (384, 48, 32), (32, 192, 48)])
+@pytest.mark.parametrize("shape", [(512, 32, 32), (32, 512, 32), (32, 32, 512), (384, 48, 32), (32, 384, 32),
+                                   (32, 48, 384), (192, 32, 32), (32, 192, 48), (32, 32, 192)])
 def test_spectral_path_large_axis(shape):
     """The homogeneous spectral path (one rotated stiffness, closed-form
     mechanics per wavevector) with a large axis in each role, 10 steps of a
