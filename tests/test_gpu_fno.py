@@ -68,12 +68,14 @@ def test_fno_forward_vs_oracle(shape, modes):
           f"(increment max {np.abs(d_ref).max():.2e})", flush=True)
     assert np.isfinite(out).all()
     assert rel <= 2e-2
-    # element by element: the activations pass through five BF16 roundings
-    # (the lift and the four layer outputs, unit roundoff 2^-8 relative to
-    # their scale); each reaches the increment at most at the increment's own
-    # scale, so no output may be off by more than 5 * 2^-8 of the largest
-    # increment
-    assert np.abs(d_gpu - d_ref).max() <= 5 * 2.0 ** -8 * np.abs(d_ref).max()
+    # element by element: fourteen quantities are rounded to BF16 (unit
+    # roundoff 2^-8): the activations v_0..v_4, the spectral weights R and the
+    # channel-mixing weights W of the four layers, and Q_1 (the matrix-core
+    # operands; the twiddles and transformed rows enter as BF16 hi and lo
+    # parts, FP32-accurate). Each rounding reaches the output increment at
+    # most at the increment's own scale, so no voxel may be off by more than
+    # 14 * 2^-8 of the largest increment (measured: about 5 * 2^-8)
+    assert np.abs(d_gpu - d_ref).max() <= 14 * 2.0 ** -8 * np.abs(d_ref).max()
     net.close()
     solver.close()
 
