@@ -55,10 +55,26 @@ int tab_stride_for(int nv) { return 21 * (nv + 1) + 6 * nv; }
 
 bool axis_ok(int n) { return pfl::supported_axis(n); }
 
-// Spectral rows of nx/2+1 coefficients are padded to a multiple of 16
-// complex values (128 bytes) so every 16-column tile of the y and z passes is
-// one aligned cache line per row.
-int spec_stride(int nx) { return (nx / 2 + 1 + 15) / 16 * 16; }
+// A spectral component holds the rows of coefficients kx < nx/2, padded to a
+// multiple of 16 complex values (128 bytes) so every 16-column tile of the y
+// and z passes is one aligned cache line per row, then the Nyquist plane
+// (kx = nx/2) as [inst][z][y]: keeping that one column in the rows would add a
+// 16-wide tile of one useful column to every pass.
+int spec_stride(int nx) { return (nx / 2 + 15) / 16 * 16; }
+
+// Spectral elements (complex) of one component of ninst instances.
+size_t spec_comp(int nx, int ny, int nz, int ninst) {
+  return (size_t)ny * nz * ninst * (spec_stride(nx) + 1);
+}
+
+void set_spec_layout(KArgs& a) {
+  const size_t rows = (size_t)a.ny * a.nz * a.ninst;
+  a.sh = spec_stride(a.nx);
+  a.ncol = a.nx / 2;
+  a.nq_row = 0;
+  a.nqo = rows * a.sh;
+  a.cs = spec_comp(a.nx, a.ny, a.nz, a.ninst);
+}
 
 // ninst instances of one size; own_epsp: the group keeps its own stacked
 // plastic strain (batches), else the caller's buffer is used in place.
@@ -69,10 +85,11 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
                    bool picard) {
   Layout L{};
   const size_t nvox = (size_t)nx * ny * nz * ninst;
-  const size_t nspec = (size_t)spec_stride(nx) * ny * nz * ninst;
+  const size_t nspec = spec_comp(nx, ny, nz, ninst);
   const int G = n_grains > 0 ? n_grains : 1;
   KArgs a{};
-  a.nx = nx; a.ny = ny; a.nz = nz; a.nh = nx / 2 + 1; a.sh = spec_stride(nx); a.nv = nv; a.ninst = ninst;
+  a.nx = nx; a.ny = ny; a.nz = nz; a.nh = nx / 2 + 1; a.nv = nv; a.ninst = ninst;
+  set_spec_layout(a);
   const size_t xb = (size_t)pfl::x_blocks(a);
   const size_t zb = (size_t)pfl::z_blocks(a, nv);
   size_t off = 0;
@@ -940,8 +957,9 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     char* ws = c->ws + g.base;
     KArgs& a = g.args;
     std::memset(&a, 0, sizeof(a));
-    a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.nh = g.nh; a.sh = spec_stride(g.nx); a.nv = nv;
+    a.nx = g.nx; a.ny = g.ny; a.nz = g.nz; a.nh = g.nh; a.nv = nv;
     a.ninst = g.ninst;
+    set_spec_layout(a);
     a.h_kind = p0.h_kind;
     a.n_grains = G;
     a.tab_stride = L.tab_stride;
@@ -1408,7 +1426,11 @@ int pf_fft(pf_ctx* c, int32_t direction, int32_t ncomp, float* real, void* spec)
   const Group& g = c->groups[0];
   KArgs a = g.args;
   a.spec = reinterpret_cast<float2*>(spec);
-  a.sh = g.nh;  // caller layout: unpadded rows
+  // caller layout: unpadded rows of nx/2+1 coefficients, Nyquist in its row
+  a.sh = a.ncol = g.nh;
+  a.nq_row = 1;
+  a.nqo = 0;
+  a.cs = (size_t)g.nh * g.ny * g.nz;
   hipStream_t s = c->stream;
   if (direction == 1) {
     PF_TRY(launch(c, s, "fft_x_forward", [&] { return pfl::raw_x_forward(a, real, ncomp, s); }));

@@ -251,7 +251,7 @@ __host__ __device__ constexpr int xthreads() { return (M % 3 == 0) ? 128 : 256; 
 template <int M, int NC>
 __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* ldsrow, int t, bool valid,
                                          float2* __restrict__ spec, size_t rowoff, size_t cstride,
-                                         const float2* __restrict__ tw_m,
+                                         float2* __restrict__ nq, const float2* __restrict__ tw_m,
                                          const float2* __restrict__ tw_n) {
   constexpr int E = XPlan<M>::E, T = M / E;
   static_assert(row_in_wave<M>(), "the threads of a row must lie in one wavefront");
@@ -275,7 +275,7 @@ __device__ __forceinline__ void r2c_rows(float2 (&v)[NC][XPlan<M>::E], float2* l
       const float2 X = cadd(ev, cmul(tw_n[k], od));
       if (valid) gst(spec + c * cstride + rowoff + k, X);
     }
-    if (t == 0 && valid) gst(spec + c * cstride + rowoff + M, make_float2(v[c][0].x - v[c][0].y, 0.f));
+    if (t == 0 && valid) gst(nq + c * cstride, make_float2(v[c][0].x - v[c][0].y, 0.f));
   }
 }
 
@@ -297,10 +297,11 @@ struct XTw {
 };
 
 // Forward of one staged row: v (packed real pairs) -> FFT -> split into the
-// nx/2+1 coefficients stored at dst. ldsrow is this row's exchange buffer.
+// nx/2+1 coefficients, kx < nx/2 stored at dst, kx = nx/2 at nq. ldsrow is
+// this row's exchange buffer.
 template <int M>
 __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
-                                        float2* __restrict__ dst, const XTw<M, 1>& tw) {
+                                        float2* __restrict__ dst, float2* __restrict__ nq, const XTw<M, 1>& tw) {
   constexpr int E = XPlan<M>::E, T = M / E;
   RowView view{ldsrow};
   fft_pencil<M, 1, XPlan<M>>(v, view, t, tw.fft);
@@ -319,7 +320,7 @@ __device__ __forceinline__ void r2c_one(float2 (&v)[XPlan<M>::E], float2* ldsrow
     const float2 X = cadd(ev, cmul(tw.split[m], od));
     if (valid) gst(dst + k, X);
   }
-  if (t == 0 && valid) gst(dst + M, make_float2(v[0].x - v[0].y, 0.f));
+  if (t == 0 && valid) gst(nq, make_float2(v[0].x - v[0].y, 0.f));
 }
 
 // Inverse of one spectral row, in two parts so the global loads of the next
@@ -335,11 +336,12 @@ struct RowFetch {
 };
 
 template <int M>
-__device__ __forceinline__ void c2r_fetch(RowFetch<M>& f, int t, bool valid, const float2* __restrict__ srow) {
+__device__ __forceinline__ void c2r_fetch(RowFetch<M>& f, int t, bool valid, const float2* __restrict__ srow,
+                                          const float2* __restrict__ nq) {
   constexpr int E = XPlan<M>::E, T = M / E;
 #pragma unroll
   for (int m = 0; m < E; ++m) f.x[m] = valid ? gld(srow + t + T * m) : make_float2(0.f, 0.f);
-  f.last = (valid && t == 0) ? gld(srow + M) : make_float2(0.f, 0.f);
+  f.last = (valid && t == 0) ? gld(nq) : make_float2(0.f, 0.f);
 }
 
 template <int M>
@@ -371,9 +373,10 @@ __device__ __forceinline__ void c2r_from_regs(float2 (&v)[XPlan<M>::E], const Ro
 
 template <int M>
 __device__ __forceinline__ void c2r_row(float2 (&v)[XPlan<M>::E], float2* ldsrow, int t, bool valid,
-                                        const float2* __restrict__ srow, const XTw<M, -1>& tw) {
+                                        const float2* __restrict__ srow, const float2* __restrict__ nq,
+                                        const XTw<M, -1>& tw) {
   RowFetch<M> f;
-  c2r_fetch<M>(f, t, valid, srow);
+  c2r_fetch<M>(f, t, valid, srow, nq);
   c2r_from_regs<M>(v, f, ldsrow, t, tw);
 }
 

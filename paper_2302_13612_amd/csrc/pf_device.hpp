@@ -71,7 +71,13 @@ constexpr int kKhMaxVar = 3;       // variants handled by the spectral path (2 V
 struct KArgs {
   int nx, ny, nz, nh, nv;     // grid of one instance, nh = nx/2+1, number of variants
   int ninst;                  // instances stacked along z
-  int sh;                     // spectral row stride (complex elements, >= nh)
+  int sh;                     // spectral row stride (complex elements, >= ncol)
+  int ncol;                   // columns of a spectral row: nx/2, the Nyquist coefficient
+                              // kx = nx/2 being kept in a plane of its own (nqo), or nh
+                              // when it stays in the row (nq_row: the caller's layout)
+  int nq_row;                 // 1: Nyquist coefficient at column nx/2 of its row
+  size_t cs;                  // stride between spectral components (complex elements)
+  size_t nqo;                 // offset of the Nyquist plane [inst][z][y] in a component
   int h_kind;
   int n_grains, tab_stride;
   float A, LDt;               // double-well height, L*dt
@@ -136,6 +142,12 @@ struct KArgs {
   int guard_ready;            // update passes: run only if state[0].st.ready (a step
                               // replayed as a graph, its fixed point done on the device)
 };
+
+// Nyquist coefficient (kx = nx/2) of spectral row `row` (counted over all
+// instances) of component c.
+__host__ __device__ inline float2* nyq_at(const KArgs& a, int c, size_t row) {
+  return a.spec + c * a.cs + (a.nq_row ? row * a.sh + a.nx / 2 : a.nqo + row);
+}
 
 // Packed upper-triangle index of a symmetric 6x6 matrix.
 __host__ __device__ constexpr int sym6(int i, int j) {

@@ -35,12 +35,13 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   const int nx = a.nx;
   const size_t vs = (size_t)nrows * nx;
   const size_t rbase = (size_t)(valid ? row : 0) * nx;
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   const size_t roff = (size_t)(valid ? row : 0) * a.sh;
+  const size_t rowv = valid ? row : 0;
   double acc[2] = {0.0, 0.0};
   // component c+1's spectral row is fetched while component c is transformed
   RowFetch<M> cur, nxt;
-  c2r_fetch<M>(cur, t, valid, a.spec + roff);
+  c2r_fetch<M>(cur, t, valid, a.spec + roff, nyq_at(a, 0, rowv));
   XTw<M, -1> tw;
   tw.load(a, t);
   // the iterate this iteration started from: the stored strain, or on the
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ms(const KArgs a) {
   float2 old_c[E];
 #pragma unroll 1
   for (int c = 0; c < 6; ++c) {
-    if (c + 1 < 6) c2r_fetch<M>(nxt, t, valid, a.spec + (c + 1) * cs + roff);
+    if (c + 1 < 6) c2r_fetch<M>(nxt, t, valid, a.spec + (c + 1) * cs + roff, nyq_at(a, c + 1, rowv));
     // this component's old iterate, in flight while its row is transformed
     // (fetching it one component ahead costs registers and gains nothing)
 #pragma unroll
@@ -95,12 +96,13 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   const size_t roff = (size_t)(valid ? row : 0) * a.sh;
+  const size_t rowv = valid ? row : 0;
   double bad[1] = {0.0};
   float dmax = 0.f;
   RowFetch<M> cur, nxt;
-  c2r_fetch<M>(cur, t, valid, a.spec + roff);
+  c2r_fetch<M>(cur, t, valid, a.spec + roff, nyq_at(a, 0, rowv));
   XTw<M, -1> tw;
   tw.load(a, t);
   // components 0..nv-1: the new f; with a mobility field also nv..2nv-1:
@@ -108,7 +110,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_ac(const KArgs a) {
   const int nc = a.lapf ? 2 * a.nv : a.nv;
 #pragma unroll 1
   for (int q = 0; q < nc; ++q) {
-    if (q + 1 < nc) c2r_fetch<M>(nxt, t, valid, a.spec + (q + 1) * cs + roff);
+    if (q + 1 < nc) c2r_fetch<M>(nxt, t, valid, a.spec + (q + 1) * cs + roff, nyq_at(a, q + 1, rowv));
     float2 v[E];
     c2r_from_regs<M>(v, cur, lds + p * LROW, t, tw);
     if (valid) {
@@ -153,9 +155,9 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_raw(const KArgs a, cons
     const int x0 = 2 * (t + T * m);
     v[0][m] = valid ? *reinterpret_cast<const float2*>(real + comp * vs + rbase + x0) : make_float2(0.f, 0.f);
   }
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   r2c_rows<M, 1>(v, lds + p * LROW, t, valid, a.spec + comp * cs, (size_t)(valid ? row : 0) * a.sh, cs,
-                 a.tw_xh, a.tw_x);
+                 nyq_at(a, comp, valid ? row : 0), a.tw_xh, a.tw_x);
 }
 
 template <int M>
@@ -170,11 +172,12 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, floa
   const int comp = blockIdx.y;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   XTw<M, -1> tw;
   tw.load(a, t);
   float2 v[E];
-  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.sh, tw);
+  c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + comp * cs + (size_t)(valid ? row : 0) * a.sh,
+             nyq_at(a, comp, valid ? row : 0), tw);
   if (valid) {
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -185,8 +188,11 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_inv_raw(const KArgs a, floa
 }
 
 // ------------------------------------------------------------ y and z passes
-// y: columns of C consecutive kx at one z, in place. grid (tiles, nz, ncomp).
-// C (8 or 16) is the group's tuned tile.
+// y: columns of C consecutive kx at one z, in place. grid (tiles, nz, ncomp),
+// where with a Nyquist plane the last x index holds the plane: its block y
+// takes the C consecutive z (all of one instance: nz is a multiple of C) whose
+// y pencils, contiguous in the plane, are its C columns; the blocks past the
+// plane's z range have nothing to do. C (8 or 16) is the group's tuned tile.
 template <int N, int K>
 using PV = typename PlanV<N, K>::P;
 template <int N, int K, int C>
@@ -198,22 +204,37 @@ __global__ __launch_bounds__((col_threads<N, K, C>())) void k_y(const KArgs a) {
   constexpr int E = P::E, T = N / E;
   __shared__ float2 lds[N * C];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = blockIdx.x * C + cc;
-  const bool valid = kx < a.nh;
-  const int z = blockIdx.y, comp = blockIdx.z;  // z over all instances
+  const int comp = blockIdx.z;
+  const int nzt = a.nz * a.ninst;                // z over all instances
+  const bool plane = !a.nq_row && (int)blockIdx.x == (a.ncol + C - 1) / C;
+  int z0;                                        // first z of the block
+  bool valid;
+  float2* col;
+  size_t es;                                     // stride between consecutive ky
+  if (!plane) {
+    const int kx = blockIdx.x * C + cc;
+    z0 = blockIdx.y;
+    valid = kx < a.ncol;
+    es = a.sh;
+    col = a.spec + comp * a.cs + (size_t)z0 * a.ny * a.sh + (valid ? kx : 0);
+  } else {
+    z0 = blockIdx.y * C;
+    if (z0 >= nzt) return;                       // the whole block: no barrier skipped
+    valid = true;
+    es = 1;
+    col = a.spec + comp * a.cs + a.nqo + (size_t)(z0 + cc) * a.ny;
+  }
   // transforms of a fixed-point iteration are skipped for a converged instance
-  if (a.skip_done && a.state[z / a.nz].st.done) return;
+  if (a.skip_done && a.state[z0 / a.nz].st.done) return;
   if (a.guard_ready && !a.state[0].st.ready) return;
-  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
-  float2* col = a.spec + comp * cs + (size_t)z * a.ny * a.sh + (valid ? kx : 0);
   float2 v[E];
 #pragma unroll
   // plain loads (measured faster here than with the hint), streaming stores
-  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * a.sh] : make_float2(0.f, 0.f);
+  for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * es] : make_float2(0.f, 0.f);
   fft_pencil<N, DIR, P>(v, ColView<C>{lds + cc}, t, a.tw_y);
   if (valid) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) gst(col + (size_t)(t + T * m) * a.sh, v[m]);
+    for (int m = 0; m < E; ++m) gst(col + (size_t)(t + T * m) * es, v[m]);
   }
 }
 
@@ -358,6 +379,79 @@ __device__ __forceinline__ void green_apply(const KArgs& a, const double* ebar, 
   tau[5] = make_float2(h * (xi[0] * u[1].x + xi[1] * u[0].x), h * (xi[0] * u[1].y + xi[1] * u[0].y));
 }
 
+// Column tiles of a z pass per instance: C consecutive kx of one ky row, then,
+// with a Nyquist plane, C consecutive ky of that plane (kx = nx/2).
+__host__ __device__ inline int z_tiles_inst(const KArgs& a, int C) {
+  const int rows = ((a.ncol + C - 1) / C) * a.ny;
+  return a.nq_row ? rows : rows + (a.ny + C - 1) / C;
+}
+
+// The column of thread cc of logical block lb of a one-dimensional z-pass
+// grid (z_tiles_inst blocks per instance).
+struct ZCol {
+  int inst, kx, ky;
+  bool valid;
+  bool first;    // the block holding xi = 0 of its instance (row tile 0 of ky 0)
+  float2* col;   // element kz = 0 of component 0
+  size_t zs;     // stride between consecutive kz
+};
+
+__device__ __forceinline__ ZCol z_col(const KArgs& a, int lb, int C, int cc) {
+  const int ntile = (a.ncol + C - 1) / C;
+  const int per = z_tiles_inst(a, C);
+  ZCol z;
+  z.inst = lb / per;
+  const int r = lb % per;
+  if (r < ntile * a.ny) {
+    const int tile = r % ntile;
+    z.ky = r / ntile;
+    z.kx = tile * C + cc;
+    z.valid = z.kx < a.ncol;
+    z.first = r == 0;
+    z.zs = (size_t)a.ny * a.sh;
+    z.col = a.spec + (size_t)z.inst * a.nz * z.zs + (size_t)z.ky * a.sh + (z.valid ? z.kx : 0);
+  } else {
+    z.kx = a.nx / 2;
+    z.ky = (r - ntile * a.ny) * C + cc;
+    z.valid = z.ky < a.ny;
+    z.first = false;
+    z.zs = a.ny;
+    z.col = a.spec + a.nqo + (size_t)z.inst * a.nz * a.ny + (z.valid ? z.ky : 0);
+  }
+  return z;
+}
+
+// The same for a three-dimensional z-pass grid: x the row tiles, then (with a
+// Nyquist plane) one more index whose blocks take the plane's tiles; y the
+// row ky of an instance (ky + instance ny), or the plane tile (ky < its count;
+// the other blocks of that x index hold no column).
+__host__ __device__ inline int z_tiles_x(const KArgs& a, int C) {
+  return (a.ncol + C - 1) / C + (a.nq_row ? 0 : 1);
+}
+
+__device__ __forceinline__ ZCol z_col3(const KArgs& a, int bx, int by, int C, int cc) {
+  const int ntile = (a.ncol + C - 1) / C;
+  ZCol z;
+  z.inst = by / a.ny;
+  const int r = by % a.ny;
+  if (bx < ntile) {
+    z.ky = r;
+    z.kx = bx * C + cc;
+    z.valid = z.kx < a.ncol;
+    z.first = bx == 0 && r == 0;
+    z.zs = (size_t)a.ny * a.sh;
+    z.col = a.spec + (size_t)z.inst * a.nz * z.zs + (size_t)z.ky * a.sh + (z.valid ? z.kx : 0);
+  } else {
+    z.kx = a.nx / 2;
+    z.ky = r * C + cc;
+    z.valid = z.ky < a.ny;
+    z.first = false;
+    z.zs = a.ny;
+    z.col = a.spec + a.nqo + (size_t)z.inst * a.nz * a.ny + (z.valid ? z.ky : 0);
+  }
+  return z;
+}
+
 __device__ inline void fin_ms(const KArgs& a, int inst, int nblk, double* scratch, double* ebar_out);
 
 // z pass of the fixed point: forward z transform of the six polarisation
@@ -372,23 +466,21 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs 
   constexpr int E = P::E, T = N / E;
   __shared__ float2 lds[N * C];
   __shared__ double ebar[6];
-  const int ntile = (a.nh + C - 1) / C;
-  const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  const ZCol zc = z_col(a, xcd_logical(blockIdx.x, gridDim.x), C, cc);
+  const int inst = zc.inst, kx = zc.kx, ky = zc.ky;
+  const bool valid = zc.valid;
   const DevState* st = a.state + inst;
   if (st->st.done) return;
-  if (tile == 0 && ky == 0) {
+  if (zc.first) {
     // the pass's LDS (N C float2 >= blockDim doubles) is free until the transforms
     fin_ms(a, inst, nblk_x, reinterpret_cast<double*>(lds), ebar);
     __syncthreads();
   }
   const ctab_t ref = (ctab_t)(a.ref + (size_t)inst * kRefStride);
-  const int cc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = tile * C + cc;
-  const bool valid = kx < a.nh;
-  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
-  const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
+  const size_t cs = a.cs;
+  const size_t zs = zc.zs;
+  float2* col = zc.col;
   float2 v[6][E];
 #pragma unroll
   for (int c = 0; c < 6; ++c)
@@ -444,12 +536,20 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_ac(const 
   __shared__ float2 lds[N * C];
   if (a.guard_ready && !a.state[0].st.ready) return;
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = blockIdx.x * C + cc;
-  const bool valid = kx < a.nh;
-  const int ky = blockIdx.y % a.ny, inst = blockIdx.y / a.ny, q = blockIdx.z;
-  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
-  const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + q * cs + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
+  const ZCol zc = z_col3(a, blockIdx.x, blockIdx.y, C, cc);
+  const int kx = zc.kx, ky = zc.ky, inst = zc.inst, q = blockIdx.z;
+  const bool valid = zc.valid;
+  const size_t cs = a.cs;
+  const size_t zs = zc.zs;
+  // partials ordered [inst][variant][ky row][x index] so each instance's are contiguous
+  const size_t blk = (((size_t)inst * a.nv + q) * a.ny + blockIdx.y % a.ny) * gridDim.x + blockIdx.x;
+  if ((int)blockIdx.x >= (a.ncol + C - 1) / C && (int)(blockIdx.y % a.ny) * C >= a.ny) {
+    // a plane index with no column: its partials are zero
+    double en[kQgd] = {0.0, 0.0, 0.0};
+    block_sum<kQgd>(en, a.part_gd + blk * kQgd);
+    return;
+  }
+  float2* col = zc.col + q * cs;
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? gld(col + (size_t)(t + T * m) * zs) : make_float2(0.f, 0.f);
@@ -491,8 +591,6 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_ac(const 
       for (int m = 0; m < E; ++m) gst(gcol + (size_t)(t + T * m) * zs, g[m]);
     }
   }
-  // partials ordered [inst][variant][ky][tile] so each instance's are contiguous
-  const size_t blk = (((size_t)inst * a.nv + q) * a.ny + ky) * gridDim.x + blockIdx.x;
   block_sum<kQgd>(en, a.part_gd + blk * kQgd);
 }
 
@@ -503,12 +601,11 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_raw(const
   constexpr int E = P::E, T = N / E, C = kColTile;
   __shared__ float2 lds[N * C];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = blockIdx.x * C + cc;
-  const bool valid = kx < a.nh;
-  const int ky = blockIdx.y % a.ny, inst = blockIdx.y / a.ny, q = blockIdx.z;
-  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
-  const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + q * cs + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
+  if ((int)blockIdx.x >= (a.ncol + C - 1) / C && (int)(blockIdx.y % a.ny) * C >= a.ny) return;  // no column
+  const ZCol zc = z_col3(a, blockIdx.x, blockIdx.y, C, cc);
+  const bool valid = zc.valid;
+  const size_t zs = zc.zs;
+  float2* col = zc.col + blockIdx.z * a.cs;
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) v[m] = valid ? col[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
@@ -550,22 +647,21 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_kh(const KArgs 
   using P = PV<N, PK>;
   constexpr int E = P::E, T = N / E;
   __shared__ float2 lds[N * C];
-  const int ntile = (a.nh + C - 1) / C;
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const int lb = xcd_logical(blockIdx.x, gridDim.x);
-  const int tile = lb % ntile, ky = (lb / ntile) % a.ny, inst = lb / (ntile * a.ny);
-  if (tile == 0 && ky == 0) {
+  const ZCol zc = z_col(a, lb, C, cc);
+  const int kx = zc.kx, ky = zc.ky, inst = zc.inst;
+  const bool valid = zc.valid;
+  if (zc.first) {
     // this block holds xi = 0: the mean fields of the instance first
     // the pass's LDS (N C float2 >= blockDim doubles) is free until the transforms
     kh_begin_mean(a, inst, nblk_x, reinterpret_cast<double*>(lds));
     __syncthreads();
   }
   const ctab_t kt = (ctab_t)(a.kh + (size_t)inst * kKhStride);
-  const int cc = threadIdx.x % C, t = threadIdx.x / C;
-  const int kx = tile * C + cc;
-  const bool valid = kx < a.nh;
-  const size_t cs = (size_t)a.ninst * a.nz * a.ny * a.sh;
-  const size_t zs = (size_t)a.ny * a.sh;
-  float2* col = a.spec + (size_t)inst * a.nz * zs + (size_t)ky * a.sh + (valid ? kx : 0);
+  const size_t cs = a.cs;
+  const size_t zs = zc.zs;
+  float2* col = zc.col;
   float2 th[V][E], rh[V][E];
 #pragma unroll
   for (int q = 0; q < V; ++q)
@@ -701,14 +797,15 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_resid(const KArgs a, const 
   const bool valid = row < nrows;
   const size_t vs = (size_t)nrows * a.nx;
   const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   float mx = 0.f;
   XTw<M, -1> tw;
   tw.load(a, t);
 #pragma unroll 1
   for (int q = 0; q < a.nv; ++q) {
     float2 v[E];
-    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + (size_t)(valid ? row : 0) * a.sh, tw);
+    c2r_row<M>(v, lds + p * LROW, t, valid, a.spec + q * cs + (size_t)(valid ? row : 0) * a.sh,
+               nyq_at(a, q, valid ? row : 0), tw);
     if (valid) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -834,11 +931,8 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
 // pass (16-column tiles, one per variant), the spectral path (16 columns for
 // one variant, else 8).
 __host__ __device__ inline int z_partials_inst(const KArgs& a, int mode) {
-  if (mode == 2) {
-    const int C = kh_tile_of(a);
-    return ((a.nh + C - 1) / C) * a.ny;
-  }
-  return ((a.nh + kColTile - 1) / kColTile) * a.ny * a.nv;
+  if (mode == 2) return z_tiles_inst(a, kh_tile_of(a));
+  return z_tiles_x(a, kColTile) * a.ny * a.nv;
 }
 
 // Mixed condition after the forward x pass of an iteration: the mean strain
@@ -1129,8 +1223,8 @@ int x_blocks(const KArgs& a) { return a.ninst * x_blocks_inst(a); }
 // z-pass partial blocks per instance, for the widest use (the Allen-Cahn
 // pass over ncomp variants, or the spectral path's narrower tiles).
 static int z_blocks_inst(const KArgs& a, int ncomp) {
-  const int ac = ((a.nh + kColTile - 1) / kColTile) * a.ny * ncomp;
-  const int kh = ((a.nh + kZmsTile - 1) / kZmsTile) * a.ny;
+  const int ac = z_tiles_x(a, kColTile) * a.ny * ncomp;
+  const int kh = z_tiles_inst(a, 8);
   return ac > kh ? ac : kh;
 }
 
@@ -1241,7 +1335,8 @@ bool plan_fits(int pass, int n, int k, int tile) {
 template <int N, int DIR, int C, int K>
 static hipError_t y_launch(const KArgs& a, int ncomp, hipStream_t s) {
   if constexpr (col_threads<N, K, C>() <= 1024) {
-    const dim3 grid((a.nh + C - 1) / C, a.nz * a.ninst, ncomp);
+    if (a.nz % C) return hipErrorInvalidValue;  // a plane block's z lie in one instance
+    const dim3 grid(z_tiles_x(a, C), a.nz * a.ninst, ncomp);
     k_y<N, DIR, C, K><<<grid, dim3(col_threads<N, K, C>()), 0, s>>>(a);
     return hipGetLastError();
   } else {
@@ -1278,7 +1373,7 @@ hipError_t ms_finalize_residual(const KArgs& a, hipStream_t s) {
 template <int N, int C, int K>
 static hipError_t zms_launch(const KArgs& a, hipStream_t s) {
   if constexpr (K <= 1 && col_threads<N, K, C>() <= 1024) {
-    const dim3 grid(((a.nh + C - 1) / C) * a.ny * a.ninst);
+    const dim3 grid(z_tiles_inst(a, C) * a.ninst);
     k_z_ms<N, C, K><<<grid, dim3(col_threads<N, K, C>()), 0, s>>>(a, x_blocks_inst(a));
     return hipGetLastError();
   } else {
@@ -1323,7 +1418,7 @@ hipError_t ac_x_forward(const KArgs& a, hipStream_t s) {
 template <int N, bool GK, bool WG, int K>
 static hipError_t zac_launch(const KArgs& a, int mode, hipStream_t s) {
   if constexpr (col_threads<N, K, kColTile>() <= 1024) {
-    const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, a.nv);
+    const dim3 grid(z_tiles_x(a, kColTile), a.ny * a.ninst, a.nv);
     k_z_ac<N, GK, WG, K><<<grid, dim3(col_threads<N, K, kColTile>()), 0, s>>>(a, mode);
     return hipGetLastError();
   } else {
@@ -1403,7 +1498,7 @@ hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream
 template <int N, bool GK, int V, int C, int K>
 static hipError_t kh_z_nk(const KArgs& a, int mode, hipStream_t s) {
   if constexpr (K <= 1 && col_threads<N, K, C>() <= 1024) {
-    const dim3 grid(((a.nh + C - 1) / C) * a.ny * a.ninst);
+    const dim3 grid(z_tiles_inst(a, C) * a.ninst);
     k_z_kh<N, V, GK, C, K><<<grid, dim3(col_threads<N, K, C>()), 0, s>>>(a, mode, x_blocks_inst(a));
     return hipGetLastError();
   } else {
@@ -1450,7 +1545,7 @@ hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream
 template <int N, int DIR, int K>
 static hipError_t zraw_launch(const KArgs& a, int ncomp, hipStream_t s) {
   if constexpr (col_threads<N, K, kColTile>() <= 1024) {
-    const dim3 grid((a.nh + kColTile - 1) / kColTile, a.ny * a.ninst, ncomp);
+    const dim3 grid(z_tiles_x(a, kColTile), a.ny * a.ninst, ncomp);
     k_z_raw<N, DIR, K><<<grid, dim3(col_threads<N, K, kColTile>()), 0, s>>>(a);
     return hipGetLastError();
   } else {

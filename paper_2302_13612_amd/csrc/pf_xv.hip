@@ -336,7 +336,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
     for (int c = 0; c < 6; ++c)
       stage[(c * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][c], o[1][c]);
   }
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
   XTw<M, 1> tw;
   tw.load(a, t);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + c * cs, tw);
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, nyq_at(a, c, valid ? row : 0), tw);
   }
   double ssum[6];
 #pragma unroll
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
     for (int q = 0; q < V; ++q)
       stage[(q * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][q], o[1][q]);
   }
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
   XTw<M, 1> tw;
   tw.load(a, t);
@@ -482,7 +482,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + q * cs, tw);
+    r2c_one<M>(v, slab, t, valid, dst + q * cs, nyq_at(a, q, valid ? row : 0), tw);
   }
   double acc[kQac];
 #pragma unroll
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_pc(const KArgs a) {
     for (int q = 0; q < V; ++q)
       stage[(q * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][q], o[1][q]);
   }
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
   XTw<M, 1> tw;
   tw.load(a, t);
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_pc(const KArgs a) {
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + q * cs, tw);
+    r2c_one<M>(v, slab, t, valid, dst + q * cs, nyq_at(a, q, valid ? row : 0), tw);
   }
 }
 
@@ -623,7 +623,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int r
       stage[((V + q) * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][q], o[1][q]);
     }
   }
-  const size_t cs = (size_t)nrows * a.sh;
+  const size_t cs = a.cs;
   float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
   XTw<M, 1> tw;
   tw.load(a, t);
@@ -633,7 +633,7 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int r
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
-    r2c_one<M>(v, slab, t, valid, dst + c * cs, tw);
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, nyq_at(a, c, valid ? row : 0), tw);
   }
   double acc[kQac];
 #pragma unroll
