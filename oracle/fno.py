@@ -19,13 +19,23 @@ with kept modes kx in [0, m), ky and kz in [0, m) u [n - m, n) (ordered
 positive then negative), R(k) a complex width x width matrix per kept mode,
 and GELU(x) = x Phi(x) with the exact normal CDF.
 
-The prediction is accepted when the backward-Euler residual of the macro
-step of S plain steps (the Allen-Cahn equation integrated implicitly over
-S dt),
-    rho = max_x | f~ - f^n + S L dt dF/df (f~) |,
-    dF/df = chem - 2 kappa lap f - mech (at the equilibrium of f~),
-is below a tolerance (surrogate acceptance test; the reading is stated in the
-design notes: the paper has no surrogate).
+The prediction is accepted when the residual of the macro step of S plain
+steps is below a tolerance (surrogate acceptance test; the paper has no
+surrogate, so this is a reading). The plain step (Sec. 3, eqs. (19)-(20))
+takes the local force E = chem - mech at the old state and the gradient force
+G f = -2 kappa lap f at the new one; summed over S steps it gives exactly
+    f^{n+S} - f^n + L dt [ sum_{s=0}^{S-1} E(f^{n+s}) + G sum_{s=1}^{S} f^{n+s} ] = 0.
+Both sums are replaced by the trapezoid rule with the end correction of a
+left (right) Riemann sum, exact when the summand is linear in s:
+    sum_{s=0}^{S-1} x_s ~ (S+1)/2 x_0 + (S-1)/2 x_S,
+    sum_{s=1}^{S}   x_s ~ (S-1)/2 x_0 + (S+1)/2 x_S,
+so with dF/df = E + G f (mech at the equilibrium of each state)
+    r   = f~ - f^n + L dt [ (S+1)/2 dF/df(f^n) + (S-1)/2 dF/df(f~) + G (f~ - f^n) ],
+    rho = max_x |r|.
+For S = 1 it is the plain step itself (zero on an exact step); on an exact
+trajectory of S steps it is the quadrature defect, second order in the step
+count times dt, where the backward-Euler residual f~ - f^n + S L dt dF/df(f~)
+is first order.
 """
 
 import numpy as np
@@ -198,17 +208,28 @@ def variational_derivative(prob, eta, load, eps_p6=None):
                                             load, prob.ms_tol, prob.ms_max_iter, prob.h_kind)
     chem = chemical_force(eta, prob.A)
     mech = mechanical_force(eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
+    return chem + gradient_force(prob, eta) - mech
+
+
+def gradient_force(prob, eta):
+    """G f = -2 div(K grad f) per variant (-2 kappa lap f when isotropic),
+    through the spectral symbol of the plain step."""
     kv = getattr(prob, "kappa_var", None)
-    grad_force = np.stack([
-        spectral.irfft3(2.0 * gradient_symbol(shape, prob.dx, prob.kappa, None if kv is None else kv[a]) *
-                        spectral.rfft3(eta[a]), shape)
+    return np.stack([
+        spectral.irfft3(2.0 * gradient_symbol(prob.shape, prob.dx, prob.kappa, None if kv is None else kv[a]) *
+                        spectral.rfft3(eta[a]), prob.shape)
         for a in range(eta.shape[0])])
-    return chem + grad_force - mech
 
 
 def macro_residual(prob, eta_prev, eta_pred, n_steps, load, eps_p6=None):
-    """Field and max-norm of f~ - f^n + S L dt dF/df(f~) over V variants."""
-    g = variational_derivative(prob, np.asarray(eta_pred, dtype=np.float64), load, eps_p6)
-    r = np.asarray(eta_pred, dtype=np.float64) - np.asarray(eta_prev, dtype=np.float64) + \
-        n_steps * prob.L * prob.dt * g
+    """Field and max-norm of the macro-step residual
+    f~ - f^n + L dt [ (S+1)/2 dF/df(f^n) + (S-1)/2 dF/df(f~) + G (f~ - f^n) ]
+    over V variants (S = n_steps; the module docstring derives it)."""
+    f0 = np.asarray(eta_prev, dtype=np.float64)
+    f1 = np.asarray(eta_pred, dtype=np.float64)
+    S = float(n_steps)
+    g0 = variational_derivative(prob, f0, load, eps_p6)
+    g1 = variational_derivative(prob, f1, load, eps_p6)
+    r = f1 - f0 + prob.L * prob.dt * (0.5 * (S + 1.0) * g0 + 0.5 * (S - 1.0) * g1 +
+                                      gradient_force(prob, f1 - f0))
     return r, float(np.abs(r).max())
