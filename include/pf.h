@@ -513,10 +513,19 @@ int pf_fno_advance(pf_fno *fno, int32_t n_calls, int32_t steps_per_call,
                    pf_fno_report *report);
 int pf_fno_destroy(pf_fno *fno);
 
-/* Backward-Euler residual of a macro step of n_steps plain steps that ends
- * at the context's current order parameter, from eta_prev (device
- * [nz][ny][nx]) under load: *rho = max |f - eta_prev + n_steps L dt dF/df(f)|.
- * Homogeneous single-instance contexts; waits on the stream. */
+/* Residual of a macro step of n = n_steps plain steps from eta_prev (device
+ * [nz][ny][nx]) to the context's current order parameter f, under load.
+ * The n plain steps summed (Sec. 3, eqs. (19)-(20): local force chem - mech
+ * at the old state, gradient force G f = -2 kappa lap f at the new one) with
+ * both sums taken by the trapezoid rule with the end correction of a left
+ * (right) Riemann sum, p = (n+1)/2, m = (n-1)/2:
+ *   r = f - eta_prev + L dt [p dF/df(eta_prev) + m dF/df(f) + G (f - eta_prev)],
+ * dF/df = chem + G f - mech at the equilibrium of each state; *rho = max |r|.
+ * Zero up to rounding when f is one exact plain step from eta_prev (n = 1),
+ * second order in n dt over n exact steps. Homogeneous single-instance
+ * contexts (the spectral path: one stiffness, linear h, n_var <= 3, no
+ * plastic strain, uniform mobility), else PF_EUNSUPPORTED; uses the
+ * context's spectral buffer; waits on the stream. */
 int pf_macro_residual(pf_ctx *ctx, const float *eta_prev, int32_t n_steps,
                       const pf_load *load, double *rho);
 

@@ -101,7 +101,12 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   L.eps_prev3 = take(sizeof(float) * nvox * 6);
   L.sig = take(sizeof(float) * nvox * 6);
   L.epsp = own_epsp ? take(sizeof(float) * nvox * 6) : 0;
-  L.spec_bytes = sizeof(float) * 2 * nspec * (mobile && 2 * nv > 6 ? 2 * nv : 6);
+  // six components (the fixed point's polarisation), 2V with a mobility
+  // field, 3V for the macro-step residual of the spectral path (V <= 3)
+  int ncomp = 6;
+  if (mobile && 2 * nv > ncomp) ncomp = 2 * nv;
+  if (nv <= pft::kKhMaxVar && 3 * nv > ncomp) ncomp = 3 * nv;
+  L.spec_bytes = sizeof(float) * 2 * nspec * ncomp;
   L.spec = take(L.spec_bytes);
   L.lapf = mobile ? take(sizeof(float) * nvox * nv) : 0;
   L.pf_base = picard ? take(sizeof(float) * nvox * nv) : 0;
@@ -1849,9 +1854,9 @@ int pf_macro_residual(pf_ctx* c, const float* eta_prev, int32_t n_steps, const p
   PF_TRY(upload_loads(c, load));
   const KArgs& a = g.args;
   hipStream_t s = c->stream;
-  PF_TRY(launch(c, s, "res_x_forward", [&] { return pfl::kh_x_forward(a, 1, s); }));
-  PF_TRY(launch(c, s, "res_y_forward", [&] { return pfl::y_pass(a, 2 * a.nv, 1, s); }));
-  PF_TRY(launch(c, s, "res_z", [&] { return pfl::kh_z_update(a, 1, s); }));
+  PF_TRY(launch(c, s, "res_x_forward", [&] { return pfl::ct_x_forward(a, eta_prev, n_steps, s); }));
+  PF_TRY(launch(c, s, "res_y_forward", [&] { return pfl::y_pass(a, 3 * a.nv, 1, s); }));
+  PF_TRY(launch(c, s, "res_z", [&] { return pfl::kh_z_update(a, 2, s); }));
   PF_TRY(launch(c, s, "res_y_inverse", [&] { return pfl::y_pass(a, a.nv, -1, s); }));
   PF_TRY(launch(c, s, "res_x_inverse", [&] { return pfl::kh_residual(a, eta_prev, n_steps, s); }));
   double r = 0.0;

@@ -219,11 +219,16 @@ hipError_t pc_x_forward_v6(const KArgs& a, hipStream_t s);
 hipError_t kh_x_forward_v1(const KArgs& a, int resid, hipStream_t s);
 hipError_t kh_x_forward_v2(const KArgs& a, int resid, hipStream_t s);
 hipError_t kh_x_forward_v3(const KArgs& a, int resid, hipStream_t s);
-// resid = 1: the backward-Euler residual of a macro step (see kh_residual)
+// resid = 1: the transforms of f and L dt chem(f), for kh_z_update(mode 1)
 hipError_t kh_x_forward(const KArgs& a, int resid, hipStream_t s);
-// Residual of a macro step of n_steps plain steps ending at the current
-// order parameter f~: r = f~ - prev + n_steps L dt dF/df(f~), after
-// kh_x_forward(resid = 1), y forward (2V) and kh_z_update(mode 1),
-// y inverse (V): per-instance max |r| into DevState::resid_max.
+hipError_t ct_x_forward_v1(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
+hipError_t ct_x_forward_v2(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
+hipError_t ct_x_forward_v3(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
+// Forward x pass of the residual of a macro step of n_steps plain steps from
+// prev to the current order parameter: 3V spectral components (see k_x_fwd_ct)
+hipError_t ct_x_forward(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
+// Residual of that macro step, inverse pass: r = f~ - prev + n_steps g, g the
+// output of ct_x_forward, y forward (3V), kh_z_update(mode 2), y inverse (V):
+// per-instance max |r| into DevState::resid_max.
 hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
 }  // namespace pfl

@@ -640,6 +640,9 @@ __host__ __device__ inline int kh_tile_of(const KArgs& a) {
 // mode 1: instead of the update, L dt dF/df of the state whose transforms
 // are in components 0..V-1 (f_hat) and V..2V-1 (L dt chem_hat):
 // L dt (chem_hat + 2 kappa |xi|^2 f_hat - mech_hat); no energy sums.
+// mode 2: the same with the gradient term taken on components 2V..3V-1
+// (w_hat) instead of f_hat: L dt (chem_hat + 2 kappa |xi|^2 w_hat -
+// mech_hat(f_hat)), the macro-step residual's force (k_x_fwd_ct).
 __device__ inline void kh_begin_mean(const KArgs& a, int inst, int nblk, double* scratch);
 
 template <int N, int V, bool GK, int C, int PK>
@@ -702,6 +705,24 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_kh(const KArgs 
   GradSym<GK> gsq[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) gsq[q] = GradSym<GK>(a, inst, q, kxv, sy);
+  if (mode == 2) {
+    // gradient force of w into the chemical part, one variant at a time
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      float2 w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m)
+        w[m] = valid ? col[(2 * V + q) * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+      fft_pencil<N, 1, P>(w, view, t, twf);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int sz = signed_k(t + T * m, a.nz);
+        const float g = gsq[q].den(cross_k(sz, a.nz), (float)sz * (float)sz) - 1.f;
+        rh[q][m].x += g * w[m].x;
+        rh[q][m].y += g * w[m].y;
+      }
+    }
+  }
   float ef[kQgd] = {0.f, 0.f, 0.f};  // this thread's terms, then FP64
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -759,7 +780,8 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_kh(const KArgs 
         if (dc && valid) nv = make_float2(rh[q][m].x + (float)a.state[inst].kh_drive[q], 0.f);
         ef[0] += x2 * (nv.x * nv.x + nv.y * nv.y);
       } else {
-        const float g = den - 1.f;
+        // mode 2: the gradient term is already in rh
+        const float g = mode == 1 ? den - 1.f : 0.f;
         nv = make_float2(rh[q][m].x + g * th[q][m].x + a.LDt * y[q].x, rh[q][m].y + g * th[q][m].y + a.LDt * y[q].y);
         if (dc && valid) nv = make_float2(rh[q][m].x - (float)a.state[inst].kh_drive[q], 0.f);
       }
@@ -1483,6 +1505,15 @@ hipError_t kh_x_forward(const KArgs& a, int resid, hipStream_t s) {
     case 1: return kh_x_forward_v1(a, resid, s);
     case 2: return kh_x_forward_v2(a, resid, s);
     case 3: return kh_x_forward_v3(a, resid, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t ct_x_forward(const KArgs& a, const float* prev, int n_steps, hipStream_t s) {
+  switch (a.nv) {
+    case 1: return ct_x_forward_v1(a, prev, n_steps, s);
+    case 2: return ct_x_forward_v2(a, prev, n_steps, s);
+    case 3: return ct_x_forward_v3(a, prev, n_steps, s);
   }
   return hipErrorInvalidValue;
 }

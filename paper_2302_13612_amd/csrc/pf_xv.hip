@@ -561,9 +561,10 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_pc(const KArgs a) {
 
 #if PF_NV <= 3
 // Homogeneous spectral path, forward: R2C of f_a (components 0..V-1) and of
-// f_a - L dt chem_a (components V..2V-1; with resid, L dt chem_a); FP64
-// double-well and mean sums, extrema of f. The elastic force is applied per
-// wavevector in the z pass.
+// f_a - L dt chem_a (components V..2V-1; with resid, L dt chem_a: the force
+// of one state, as the autotuner times the z pass); FP64 double-well and mean
+// sums, extrema of f. The elastic force is applied per wavevector in the z
+// pass.
 template <int M, int V>
 __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int resid) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
@@ -644,6 +645,105 @@ __global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_kh(const KArgs a, int r
   block_sum<kQac, xthreads<M>() / 64>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
   block_minmax<xthreads<M>() / 64>(mn, mx, a.part_mm + 2 * (size_t)blockIdx.x);
 }
+
+// Residual of a macro step of S plain steps from f0 (prev) to f1 (the
+// current order parameter), forward x pass. Summing S plain steps (local
+// force explicit, gradient force implicit: Sec. 3, eqs. (19)-(20)) and taking
+// both sums by the trapezoid rule with the end correction of a left (right)
+// Riemann sum, with p = (S+1)/2, m = (S-1)/2:
+//   r = f1 - f0 + L dt [p chem(f0) + m chem(f1)] - L dt [p mech(f0) + m mech(f1)]
+//       + L dt G (m f0 + p f1).
+// mech is affine in f with one stiffness and linear h, so its two terms are
+// S mech(u) with u = (p f0 + m f1) / S. R2C of u (components 0..V-1, whose
+// FP64 sums feed the mixed condition of the z pass), of L dt (p chem(f0) +
+// m chem(f1)) / S (V..2V-1) and of w = (m f0 + p f1) / S (2V..3V-1); the z
+// pass (mode 2) forms L dt [chem part / S + G w - mech(u)], and the inverse
+// pass r = f1 - f0 + S times that. u and the chemical part are staged
+// together; w, which needs no other component, row by row after them.
+template <int M, int V>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_fwd_ct(const KArgs a, const float* __restrict__ prev,
+                                                           float S) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 stage[2 * V * ROWS * LROW];
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.ninst * a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t vs = (size_t)nrows * a.nx;
+  const size_t rbase = (size_t)(valid ? row : 0) * a.nx;
+  const float wp = 0.5f * (S + 1.f) / S, wm = 0.5f * (S - 1.f) / S;
+  float facc[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) facc[q] = 0.f;
+#pragma unroll 1
+  for (int m = 0; m < E; ++m) {
+    const int k = t + T * m;
+    float2 h0[V], h1[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const size_t off = q * vs + rbase + 2 * k;
+      h0[q] = valid ? *reinterpret_cast<const float2*>(prev + off) : make_float2(0.f, 0.f);
+      h1[q] = valid ? *reinterpret_cast<const float2*>(a.eta + off) : make_float2(0.f, 0.f);
+    }
+    float o[2][2][V];  // [half][u, chemical part][q]
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+      float e0[V], e1[V];
+      float fm0 = 1.f, fm1 = 1.f;
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        e0[q] = half ? h0[q].y : h0[q].x;
+        e1[q] = half ? h1[q].y : h1[q].x;
+        fm0 -= e0[q];
+        fm1 -= e1[q];
+      }
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        o[half][0][q] = wp * e0[q] + wm * e1[q];
+        o[half][1][q] = a.LDt * (wp * chem_force<V>(a.A, e0, fm0, q) + wm * chem_force<V>(a.A, e1, fm1, q));
+        if (valid) facc[q] += o[half][0][q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      stage[(q * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][0][q], o[1][0][q]);
+      stage[((V + q) * ROWS + p) * LROW + RowView::pad(k)] = make_float2(o[0][1][q], o[1][1][q]);
+    }
+  }
+  const size_t cs = a.cs;
+  float2* dst = a.spec + (size_t)(valid ? row : 0) * a.sh;
+  XTw<M, 1> tw;
+  tw.load(a, t);
+#pragma unroll 1
+  for (int c = 0; c < 2 * V; ++c) {
+    float2* slab = stage + (c * ROWS + p) * LROW;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = slab[RowView::pad(t + T * m)];
+    r2c_one<M>(v, slab, t, valid, dst + c * cs, nyq_at(a, c, valid ? row : 0), tw);
+  }
+#pragma unroll 1
+  for (int q = 0; q < V; ++q) {
+    // w of variant q straight from the two fields, through this row's first slab
+    float2* slab = stage + p * LROW;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const size_t off = q * vs + rbase + 2 * (t + T * m);
+      const float2 x0 = valid ? *reinterpret_cast<const float2*>(prev + off) : make_float2(0.f, 0.f);
+      const float2 x1 = valid ? *reinterpret_cast<const float2*>(a.eta + off) : make_float2(0.f, 0.f);
+      v[m] = make_float2(wm * x0.x + wp * x1.x, wm * x0.y + wp * x1.y);
+    }
+    r2c_one<M>(v, slab, t, valid, dst + (2 * V + q) * cs, nyq_at(a, 2 * V + q, valid ? row : 0), tw);
+  }
+  double acc[kQac];
+#pragma unroll
+  for (int q = 0; q < kQac; ++q) acc[q] = 0.0;
+#pragma unroll
+  for (int q = 0; q < V; ++q) acc[14 + q] = (double)facc[q];
+  block_sum<kQac, xthreads<M>() / 64>(acc, a.part_ac + (size_t)blockIdx.x * kQac);
+}
 #endif
 }  // namespace pft
 
@@ -691,6 +791,12 @@ hipError_t PF_CAT(ms_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
 hipError_t PF_CAT(kh_x_forward_v, PF_NV)(const KArgs& a, int resid, hipStream_t s) {
   const dim3 grid(x_blocks(a));
   PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_kh<M, PF_NV><<<grid, xthreads<M>(), 0, s>>>(a, resid)));
+  return hipGetLastError();
+}
+
+hipError_t PF_CAT(ct_x_forward_v, PF_NV)(const KArgs& a, const float* prev, int n_steps, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M_LOCAL(a.nx, (k_x_fwd_ct<M, PF_NV><<<grid, xthreads<M>(), 0, s>>>(a, prev, (float)n_steps)));
   return hipGetLastError();
 }
 #endif

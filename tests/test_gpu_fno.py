@@ -106,8 +106,43 @@ def test_macro_residual_vs_oracle():
                                     bumped.cpu().numpy().astype(np.float64), 16, load)
     assert abs(rho_b - rho_bo) <= 1e-5 + 1e-3 * rho_bo
     assert rho_b > rho + 0.2
+    # one exact plain step satisfies the residual of one step up to FP32 rounding
+    solver.set_field(binding.PF_FIELD_ETA, cur)
+    solver.step(1, cfg["eps_bar"], cfg["sig_bar"])
+    rho_1 = binding.macro_residual(solver, cur, 1, cfg["eps_bar"], cfg["sig_bar"])
+    print(f"[residual] one exact step: {rho_1:.3e}", flush=True)
+    assert rho_1 <= 1e-5
     solver.close()
     del torch
+
+
+def test_macro_residual_accepts_exact_rejects_perturbed():
+    # late in the relaxation of a 32^3 instance: the exact 16-step window is
+    # accepted at 1e-3, the same state with a 2e-3 bump is not; both as the
+    # oracle computes them on the library's fields
+    batch = inputs.rve_batch(n_inst=2, seed=99, sizes=(32,))
+    cfg = cases.batch_instance_cfg(batch, 0)
+    solver, _ = cases.gpu_solver(cfg)
+    solver.step(64, cfg["eps_bar"], cfg["sig_bar"])
+    prev = solver.field(binding.PF_FIELD_ETA)
+    solver.step(16, cfg["eps_bar"], cfg["sig_bar"])
+    cur = solver.field(binding.PF_FIELD_ETA)
+    rho = binding.macro_residual(solver, prev, 16, cfg["eps_bar"], cfg["sig_bar"])
+    bumped = cur.clone()
+    bumped[0, 16, 16, 16] += 2e-3
+    solver.set_field(binding.PF_FIELD_ETA, bumped)
+    rho_b = binding.macro_residual(solver, prev, 16, cfg["eps_bar"], cfg["sig_bar"])
+    prob = cases.oracle_problem(cfg, tol=1e-12)
+    load = dict(eps_bar=cfg["eps_bar"], sig_bar=cfg["sig_bar"], stress_mask=cfg["stress_mask"])
+    p64 = prev.cpu().numpy().astype(np.float64)
+    _, rho_o = ofno.macro_residual(prob, p64, cur.cpu().numpy().astype(np.float64), 16, load)
+    _, rho_bo = ofno.macro_residual(prob, p64, bumped.cpu().numpy().astype(np.float64), 16, load)
+    print(f"\n[accept] exact gpu {rho:.3e} oracle {rho_o:.3e}; bumped gpu {rho_b:.3e} oracle {rho_bo:.3e}",
+          flush=True)
+    assert abs(rho - rho_o) <= 1e-5 + 1e-3 * rho_o
+    assert abs(rho_b - rho_bo) <= 1e-5 + 1e-3 * rho_bo
+    assert rho <= 0.5e-3 < 2e-3 <= rho_b
+    solver.close()
 
 
 def test_fno_advance_accept_and_fallback():
