@@ -35,9 +35,19 @@ Readings (stated once here, used below):
   symmetric tensor K_a (sample frame, J/m) and the gradient term becomes
   grad f_a . K_a . grad f_a, so its force is -2 div(K_a grad f_a) and its
   Fourier symbol xi . K_a . xi replaces kappa |xi|^2. K_a = kappa I is the
-  isotropic case. K_a is constant in space: one grain (a polycrystal would
-  need a spatially varying K, which the spectral implicit step does not
-  solve exactly).
+  isotropic case. With one grain K_a is constant and the implicit step is
+  exact in Fourier space.
+* Anisotropic gradient energy on a polycrystal: K_a(x) = K_a^g of the voxel's
+  grain g (each grain's tensors turned by its rotation). The spectral
+  implicit step needs a constant coefficient, so the gradient force is split
+  as G = Gbar + (G - Gbar): Gbar f = -2 kbar_a lap f implicit, with kbar_a the
+  largest eigenvalue of K_a^g over the grains, and the remainder
+  -2 div((K_a(x) - kbar_a I) grad f) explicit at f^n, through spectral first
+  derivatives (zero at a Nyquist index). Since kbar_a I - K_a(x) is positive
+  semidefinite the amplification of a mode in a region of constant K,
+  (1 + 2 L dt (kbar |xi|^2 - xi.K.xi)) / (1 + 2 L dt kbar |xi|^2), lies in
+  (0, 1] at any dt. The gradient energy is reported for the same operator:
+  the Parseval sum of kbar_a |xi|^2 plus int grad f . (K - kbar I) . grad f.
 * Variable mobility (Sec. 4: a pad layer of very low mobility around the
   specimen suppresses the flux into it, a Neumann-like condition): optionally
   a relative mobility m(x) in [0, 1] with L(x) = L m(x). The gradient term is
@@ -140,19 +150,86 @@ def gradient_symbol(shape, dx, kappa, K=None):
     return diag + cross
 
 
-def gradient_energy(eta, kappa, dx, kappa_var=None):
+def gradient_energy(eta, kappa, dx, kappa_var=None, grains=None):
     """sum_a int grad f_a . K_a . grad f_a dV (K_a = kappa I unless kappa_var
-    gives the (V, 3, 3) tensors) by Parseval."""
+    gives the (V, 3, 3) tensors) by Parseval. grains = (kbar, rem, gid): per
+    grain tensors split as in grain_split; the energy is then the Parseval
+    sum of kbar_a |xi|^2 plus the remainder's int grad f . (K - kbar I) . grad f
+    with spectral first derivatives (the operator the step uses)."""
     shape = eta.shape[1:]
     w = spectral.half_spectrum_weights(shape)
     ntot = np.prod(shape)
     dV = dx ** 3
     total = 0.0
     for a in range(eta.shape[0]):
-        q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
+        if grains is not None:
+            q = gradient_symbol(shape, dx, grains[0][a])
+        else:
+            q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
         F = spectral.rfft3(eta[a], workers=-1)
         total += (w * q * np.abs(F) ** 2).sum() * dV / ntot
+        if grains is not None:
+            g = spectral_gradient(eta[a], dx)
+            total += np.einsum("izyx,zyxij,jzyx->", g, grains[1][:, a][grains[2]], g) * dV
     return total
+
+
+def derivative_wavevectors(shape, dx):
+    """xi[..., (x, y, z)] for first derivatives on the half spectrum: a
+    component at the Nyquist index of its (even) axis is zero, since the
+    derivative is odd in it and that index stands for both signs."""
+    xi = spectral.wavevectors(shape, dx).copy()
+    nz, ny, nx = shape
+    if nx % 2 == 0:
+        xi[:, :, nx // 2, 0] = 0.0
+    if ny % 2 == 0:
+        xi[:, ny // 2, :, 1] = 0.0
+    if nz % 2 == 0:
+        xi[nz // 2, :, :, 2] = 0.0
+    return xi
+
+
+def spectral_gradient(f, dx):
+    """grad f as (3, nz, ny, nx) [(x, y, z) components] by spectral first
+    derivatives."""
+    shape = f.shape
+    F = spectral.rfft3(f, workers=-1)
+    xi = derivative_wavevectors(shape, dx)
+    return np.stack([spectral.irfft3(1j * xi[..., j] * F, shape, workers=-1) for j in range(3)])
+
+
+def spectral_divergence(q, dx):
+    """div q of a (3, nz, ny, nx) field by spectral first derivatives."""
+    shape = q.shape[1:]
+    xi = derivative_wavevectors(shape, dx)
+    D = sum(1j * xi[..., j] * spectral.rfft3(q[j], workers=-1) for j in range(3))
+    return spectral.irfft3(D, shape, workers=-1)
+
+
+def remainder_divergence(f, K_field, dx):
+    """2 div(K(x) grad f) for a field of symmetric tensors K_field
+    (nz, ny, nx, 3, 3), through spectral first derivatives."""
+    g = spectral_gradient(f, dx)
+    flux = np.einsum("zyxij,jzyx->izyx", K_field, g)
+    return 2.0 * spectral_divergence(flux, dx)
+
+
+def grain_split(kappa_grain):
+    """Constant-coefficient split of per-grain gradient tensors K_a^g
+    (G, V, 3, 3): the implicit part kbar_a I with kbar_a the largest
+    eigenvalue of K_a^g over the grains (then kbar_a I - K_a^g is positive
+    semidefinite everywhere, which keeps the step stable at any dt), and the
+    explicit remainder K_a^g - kbar_a I. Returns (kbar (V,), rem (G, V, 3, 3))."""
+    K = np.asarray(kappa_grain, dtype=np.float64)
+    kbar = np.linalg.eigvalsh(K).max(axis=(0, 2))
+    rem = K - kbar[None, :, None, None] * np.eye(3)
+    return kbar, rem
+
+
+def grain_remainder_divergence(f_a, rem_a, gid, dx):
+    """2 div((K_a(x) - kbar_a I) grad f_a) with K_a(x) the tensor of the
+    voxel's grain (rem_a: (G, 3, 3))."""
+    return remainder_divergence(f_a, rem_a[gid], dx)
 
 
 def gradient_force(f, q, shape):
@@ -160,17 +237,25 @@ def gradient_force(f, q, shape):
     return spectral.irfft3(-2.0 * q * spectral.rfft3(f, workers=-1), shape, workers=-1)
 
 
-def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx, kappa_var=None, mobility=None):
+def allen_cahn_update(eta, chem, mech, L, dt, kappa, dx, kappa_var=None, mobility=None, grains=None):
     """f_a^{n+1} = IFFT[ FFT(f_a^n - L dt (chem_a - mech_a)) / (1 + 2 L dt q_a(xi)) ]
     with q_a the gradient symbol (kappa |xi|^2, or xi . K_a . xi); with a
     relative mobility m the right-hand side is f_a^n - L dt m (chem_a - mech_a)
-    + L dt (m - 1) G(f_a^n)."""
+    + L dt (m - 1) G(f_a^n). With per-grain tensors (grains = (kbar, rem,
+    gid), see grain_split) q_a = kbar_a |xi|^2 and the right-hand side gains
+    the explicit remainder L dt 2 div((K_a(x) - kbar_a I) grad f_a^n)."""
     shape = eta.shape[1:]
     out = np.empty_like(eta)
     for a in range(eta.shape[0]):
-        q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
+        if grains is not None:
+            q = gradient_symbol(shape, dx, grains[0][a])
+        else:
+            q = gradient_symbol(shape, dx, kappa, None if kappa_var is None else kappa_var[a])
         denom = 1.0 + 2.0 * L * dt * q
-        if mobility is None:
+        if grains is not None:
+            rhs = eta[a] - L * dt * (chem[a] - mech[a]) + \
+                L * dt * grain_remainder_divergence(eta[a], grains[1][:, a], grains[2], dx)
+        elif mobility is None:
             rhs = eta[a] - L * dt * (chem[a] - mech[a])
         else:
             rhs = eta[a] - L * dt * mobility * (chem[a] - mech[a]) + \
@@ -205,6 +290,9 @@ class Problem:
     tables = (C_grain, C_var, eps0) as returned by crystal.mg_tables.
     C0: reference stiffness (3,3,3,3) for the fixed point.
     kappa_var: optional (V, 3, 3) gradient tensors (one grain only).
+    kappa_grain: optional (G, V, 3, 3) gradient tensors per grain (with gid):
+    the step takes kbar_a I implicitly and the rest explicitly (grain_split);
+    not with kappa_var, a mobility field or the fixed point over the update.
     mobility: optional (nz, ny, nx) relative mobility in [0, 1].
     pf_tol, pf_max_iter: the paper's fixed point i over the phase-field update
     (pf_max_iter = 1: the plain semi-implicit step).
@@ -212,7 +300,7 @@ class Problem:
 
     def __init__(self, shape, dx, tables, A, kappa, L, dt, C0, gid=None,
                  h_kind="linear", ms_tol=1e-12, ms_max_iter=200, kappa_var=None, mobility=None,
-                 pf_tol=1e-12, pf_max_iter=1):
+                 pf_tol=1e-12, pf_max_iter=1, kappa_grain=None):
         self.shape = tuple(shape)
         self.dx = float(dx)
         self.tables = tables
@@ -229,6 +317,17 @@ class Problem:
         self.mobility = mobility
         self.pf_tol, self.pf_max_iter = float(pf_tol), int(pf_max_iter)
         self.gid = None if gid is None else np.asarray(gid, dtype=np.int64)
+        self.grains = None
+        if kappa_grain is not None:
+            if kappa_var is not None or mobility is not None or self.pf_max_iter > 1:
+                raise ValueError("per-grain gradient tensors go without kappa_var, mobility and the update's "
+                                 "fixed point")
+            kg = np.asarray(kappa_grain, dtype=np.float64)
+            gidf = np.zeros(self.shape, dtype=np.int64) if self.gid is None else self.gid
+            if kg.ndim != 4 or kg.shape[2:] != (3, 3) or gidf.max() >= kg.shape[0]:
+                raise ValueError("kappa_grain must be (G, V, 3, 3) covering every grain id")
+            kbar, rem = grain_split(kg)
+            self.grains = (kbar, rem, gidf)
         self.h_kind = h_kind
         self.ms_tol, self.ms_max_iter = ms_tol, ms_max_iter
         self.green = GreenOperator(C0, self.shape, self.dx)
@@ -269,7 +368,9 @@ def step(prob, state, eps_p6, load):
     chem = chemical_force(state.eta, prob.A)
     mech = mechanical_force(state.eta, sigma, eps_el, prob.gid, C_grain, C_var, eps0, prob.h_kind)
     mob = getattr(prob, "mobility", None)
-    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var, mob)
+    grains = getattr(prob, "grains", None)
+    eta_new = allen_cahn_update(state.eta, chem, mech, prob.L, prob.dt, prob.kappa, prob.dx, prob.kappa_var, mob,
+                                grains)
     # the paper's fixed point i: the guess is f^n, each solve re-evaluates the
     # chemical force at the latest iterate, stop when max |f^i - f^{i-1}| <= tol
     pf_max = max(1, getattr(prob, "pf_max_iter", 1))
@@ -283,7 +384,7 @@ def step(prob, state, eps_p6, load):
     dV = prob.dx ** 3
     stats = {
         "G_dw": float(double_well_density(state.eta, prob.A).sum() * dV),
-        "G_gd": float(gradient_energy(state.eta, prob.kappa, prob.dx, prob.kappa_var)),
+        "G_gd": float(gradient_energy(state.eta, prob.kappa, prob.dx, prob.kappa_var, grains)),
         "G_me": float(0.5 * np.einsum("...ij,...ij->...", eps_el, sigma).sum() * dV),
         "sig_mean": tensor_to_voigt6(sigma.mean(axis=(0, 1, 2))),
         "eps_mean": tensor_to_voigt6(eps.mean(axis=(0, 1, 2))),
