@@ -169,6 +169,23 @@ typedef struct {
                               batch) and takes the generic path. With
                               f_M = 1 - sum f the conservation check of
                               Table 1 holds identically.                    */
+  const double *kappa_grain; /* optional host [n_grains][n_var][6]: per-grain
+                              anisotropic gradient tensors K_a^g of a
+                              polycrystal (tensor-Voigt, J/m, sample frame;
+                              pf_mg_twin_gradient builds them from the grain
+                              rotations; Table 5, Sec. 4.3). The gradient
+                              force -2 div(K_a(x) grad f_a) is split: kbar_a I
+                              implicit, kbar_a the largest eigenvalue of K_a^g
+                              over the grains, and the remainder
+                              2 div((K_a(x) - kbar_a I) grad f_a) explicit at
+                              f^n through spectral first derivatives (zero at
+                              a Nyquist index), three more spectral passes
+                              over 3 n_var components per step. Stable at any
+                              dt (kbar_a I - K_a(x) is positive semidefinite).
+                              G_gd reports the energy of the same operator.
+                              Not with kappa_var (PF_EINVAL); not with a
+                              mobility field, pf_max_iter > 1 or in a batch
+                              (PF_EUNSUPPORTED). Copied at init.            */
 } pf_problem;
 
 /* Load of one pf_step call. */

@@ -49,6 +49,7 @@ class PfProblem(ctypes.Structure):
         ("mobility", ctypes.c_void_p),
         ("pf_tol", ctypes.c_double),
         ("pf_max_iter", ctypes.c_int32),
+        ("kappa_grain", _dp),
     ]
 
 
@@ -269,12 +270,14 @@ class Solver:
     kappa_var: optional (V,3,3) or (V,6) anisotropic gradient tensors (sample
     frame; one grain only). mobility: optional float32 CUDA tensor (nz, ny, nx)
     of relative mobilities in [0, 1]. pf_max_iter > 1: the fixed point over the
-    update (Table 1), stopping at max |f^i - f^{i-1}| <= pf_tol.
+    update (Table 1), stopping at max |f^i - f^{i-1}| <= pf_tol. kappa_grain:
+    optional (G,V,3,3) or (G,V,6) per-grain gradient tensors of a polycrystal
+    (see pf_problem.kappa_grain).
     """
 
     def __init__(self, eta0, dx, A, kappa, L, dt, tables, stress_mask, gid=None, C_ref=None,
                  h_kind=PF_H_LINEAR, ms_tol=1e-6, ms_max_iter=50, rotations=None, kappa_var=None,
-                 mobility=None, pf_tol=1e-6, pf_max_iter=1):
+                 mobility=None, pf_tol=1e-6, pf_max_iter=1, kappa_grain=None):
         import torch
         self.lib = load()
         self.torch = torch
@@ -336,6 +339,15 @@ class Solver:
             p.mobility = None
         p.pf_tol = pf_tol
         p.pf_max_iter = pf_max_iter
+        if kappa_grain is not None:
+            kg = np.asarray(kappa_grain, dtype=np.float64)
+            kg = np.ascontiguousarray(_kappa_var_voigt(kg.reshape((-1,) + kg.shape[2:]), kg.shape[0] * V))
+            if kg.shape[0] != G * V:
+                raise ValueError("kappa_grain must be (n_grains, n_var, 3, 3) or (n_grains, n_var, 6)")
+            self._keep.append(kg)
+            p.kappa_grain = _ptr(kg)
+        else:
+            p.kappa_grain = None
         nbytes = ctypes.c_size_t()
         rc = self.lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(nbytes))
         if rc != PF_OK:

@@ -44,6 +44,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
   size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, gk, tw;
+  size_t remf, part_rem, krem;
   size_t lapf;  // gradient force of the state (with a mobility field), else 0
   size_t pf_base, part_pc;  // fixed point over the update (pf_max_iter > 1), else 0
   size_t spec_bytes;        // size of the spectral buffer
@@ -61,6 +62,23 @@ bool axis_ok(int n) { return pfl::supported_axis(n); }
 // (kx = nx/2) as [inst][z][y]: keeping that one column in the rows would add a
 // 16-wide tile of one useful column to every pass.
 int spec_stride(int nx) { return (nx / 2 + 15) / 16 * 16; }
+
+// Largest eigenvalue of a symmetric 3x3 matrix (tensor-Voigt xx yy zz yz xz
+// xy) by the trigonometric closed form (O. K. Smith, Eigenvalues of a
+// symmetric 3 x 3 matrix, Comm. ACM 4 (1961) 168).
+double sym3_max_eigenvalue(const double* K) {
+  const double a = K[0], b = K[1], c = K[2], d = K[3], e = K[4], f = K[5];
+  const double p1 = d * d + e * e + f * f;
+  if (p1 == 0.0) return std::max(a, std::max(b, c));
+  const double q = (a + b + c) / 3.0;
+  const double p2 = (a - q) * (a - q) + (b - q) * (b - q) + (c - q) * (c - q) + 2.0 * p1;
+  const double p = std::sqrt(p2 / 6.0);
+  // B = (K - q I) / p; r = det(B) / 2
+  const double ba = (a - q) / p, bb = (b - q) / p, bc = (c - q) / p, bd = d / p, be = e / p, bf = f / p;
+  const double det = ba * (bb * bc - bd * bd) - bf * (bf * bc - bd * be) + be * (bf * bd - bb * be);
+  const double r = std::min(1.0, std::max(-1.0, 0.5 * det));
+  return q + 2.0 * p * std::cos(std::acos(r) / 3.0);
+}
 
 // Spectral elements (complex) of one component of ninst instances.
 size_t spec_comp(int nx, int ny, int nz, int ninst) {
@@ -82,7 +100,7 @@ void set_spec_layout(KArgs& a) {
 // the spectra hold 2 nv components). picard: a fixed point over the update
 // (the step's fixed base of the right-hand side and the per-block changes).
 Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool own_epsp, bool mobile,
-                   bool picard) {
+                   bool picard, bool grain_k) {
   Layout L{};
   const size_t nvox = (size_t)nx * ny * nz * ninst;
   const size_t nspec = spec_comp(nx, ny, nz, ninst);
@@ -105,10 +123,14 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   // field, 3V for the macro-step residual of the spectral path (V <= 3)
   int ncomp = 6;
   if (mobile && 2 * nv > ncomp) ncomp = 2 * nv;
-  if (nv <= pft::kKhMaxVar && 3 * nv > ncomp) ncomp = 3 * nv;
+  if ((nv <= pft::kKhMaxVar || grain_k) && 3 * nv > ncomp) ncomp = 3 * nv;
   L.spec_bytes = sizeof(float) * 2 * nspec * ncomp;
   L.spec = take(L.spec_bytes);
   L.lapf = mobile ? take(sizeof(float) * nvox * nv) : 0;
+  // per-grain gradient tensors: the remainder field, its energy partials, the tables
+  L.remf = grain_k ? take(sizeof(float) * nvox * nv) : 0;
+  L.part_rem = grain_k ? take(sizeof(double) * xb) : 0;
+  L.krem = grain_k ? take(sizeof(float) * 6 * (size_t)G * nv) : 0;
   L.pf_base = picard ? take(sizeof(float) * nvox * nv) : 0;
   L.part_pc = picard ? take(sizeof(float) * xb * 2) : 0;
   L.tab_stride = tab_stride_for(nv);
@@ -204,7 +226,9 @@ struct InstanceHost {
   float kh[pft::kKhStride];
   double khd[pft::kKhdStride];
   float gk[pft::kGkStride]; // gradient-energy coefficients (see kGkStride)
-  bool aniso;               // kappa_var given
+  bool aniso;               // kappa_var or kappa_grain given (gk holds K_a or kbar_a I)
+  bool grain_k;             // kappa_grain given: krem holds K_a^g - kbar_a I
+  std::vector<float> krem;  // [G][nv][6]
   bool one_iteration;       // one stiffness everywhere, equal to the reference
   bool homogeneous;         // one stiffness everywhere (spectral path possible)
 };
@@ -263,10 +287,25 @@ int prepare_instance(const pf_problem* p, InstanceHost& h, std::string& why) {
     const double c[3] = {tp / p->nx, tp / p->ny, tp / p->nz};
     const double f = 2.0 * p->L * p->dt;
     std::memset(h.gk, 0, sizeof(h.gk));
-    h.aniso = p->kappa_var != nullptr;
+    h.aniso = p->kappa_var != nullptr || p->kappa_grain != nullptr;
+    h.grain_k = p->kappa_grain != nullptr;
+    double kbar[pft::kMaxVar] = {};
+    if (h.grain_k) {
+      // the split of per-grain tensors: kbar_a I implicit, the rest explicit
+      h.krem.assign((size_t)G * nv * 6, 0.f);
+      for (int q = 0; q < nv; ++q)
+        for (int g = 0; g < G; ++g) kbar[q] = std::max(kbar[q], sym3_max_eigenvalue(p->kappa_grain + 6 * ((size_t)g * nv + q)));
+      for (int g = 0; g < G; ++g)
+        for (int q = 0; q < nv; ++q)
+          for (int k = 0; k < 6; ++k)
+            h.krem[6 * ((size_t)g * nv + q) + k] =
+                (float)(p->kappa_grain[6 * ((size_t)g * nv + q) + k] - (k < 3 ? kbar[q] : 0.0));
+    }
     for (int q = 0; q < nv; ++q) {
       double K[6] = {p->kappa, p->kappa, p->kappa, 0.0, 0.0, 0.0};
-      if (h.aniso)
+      if (h.grain_k)
+        K[0] = K[1] = K[2] = kbar[q];
+      else if (h.aniso)
         for (int k = 0; k < 6; ++k) K[k] = p->kappa_var[6 * q + k];
       const double g[6] = {K[0] * c[0] * c[0], K[1] * c[1] * c[1], K[2] * c[2] * c[2],
                            2.0 * K[3] * c[1] * c[2], 2.0 * K[4] * c[0] * c[2], 2.0 * K[5] * c[0] * c[1]};
@@ -297,7 +336,7 @@ int prepare_instance(const pf_problem* p, InstanceHost& h, std::string& why) {
   bool one = homog;
   for (int i = 0; i < 36 && one; ++i)
     if (Cg_s[i] != C0[i]) one = false;
-  h.homogeneous = homog;
+  h.homogeneous = homog && !p->kappa_grain;
   h.one_iteration = one;
   pack_sym(C0, h.ref);
   double M0[36], S0[36];
@@ -491,7 +530,21 @@ int validate(const pf_problem* p, std::string& why) {
       if (K[0] < 0 || K[1] < 0 || K[2] < 0) { why = "kappa_var diagonal must be >= 0"; return PF_EINVAL; }
     }
     if (p->n_grains != 1) {
-      why = "an anisotropic gradient energy (kappa_var) needs one grain";
+      why = "an anisotropic gradient energy (kappa_var) needs one grain; kappa_grain takes one tensor per grain";
+      return PF_EUNSUPPORTED;
+    }
+  }
+  if (p->kappa_grain) {
+    if (p->kappa_var) { why = "kappa_var and kappa_grain exclude each other"; return PF_EINVAL; }
+    for (size_t i = 0; i < (size_t)p->n_grains * p->n_var; ++i) {
+      const double* K = p->kappa_grain + 6 * i;
+      for (int k = 0; k < 6; ++k)
+        if (!std::isfinite(K[k])) { why = "kappa_grain must be finite"; return PF_EINVAL; }
+      if (K[0] < 0 || K[1] < 0 || K[2] < 0) { why = "kappa_grain diagonal must be >= 0"; return PF_EINVAL; }
+    }
+    if (p->mobility) { why = "kappa_grain does not combine with a mobility field"; return PF_EUNSUPPORTED; }
+    if (p->pf_max_iter > 1) {
+      why = "kappa_grain does not combine with the fixed point over the update (pf_max_iter > 1)";
       return PF_EUNSUPPORTED;
     }
   }
@@ -522,6 +575,10 @@ int validate_batch(const pf_problem* probs, int n, std::string& why) {
   for (int i = 0; i < n; ++i) {
     if (probs[i].mobility) {
       why = "a mobility field needs a one-instance context";
+      return PF_EUNSUPPORTED;
+    }
+    if (probs[i].kappa_grain) {
+      why = "per-grain gradient tensors (kappa_grain) need a one-instance context";
       return PF_EUNSUPPORTED;
     }
     if (probs[i].pf_max_iter > 1) {
@@ -567,7 +624,7 @@ std::vector<Group> plan_groups(const pf_problem* probs, int n) {
     g.pf_max_iter = std::max(1, (int)probs[g.members[0]].pf_max_iter);
     g.pf_tol = probs[g.members[0]].pf_tol;
     g.L = make_layout(g.nx, g.ny, g.nz, probs[0].n_var, probs[g.members[0]].n_grains, g.ninst, g.own_epsp,
-                      g.mobile, g.pf_max_iter > 1);
+                      g.mobile, g.pf_max_iter > 1, probs[g.members[0]].kappa_grain != nullptr);
     g.base = off;
     off += g.L.total;
   }
@@ -639,7 +696,25 @@ int ms_iteration(pf_ctx* c, const KArgs& a, hipStream_t s) {
 // chemical force of the latest iterate (pc_x_forward) while the gradient
 // term stays implicit and the mechanical force stays that of f^n; after each
 // solve the host reads max |f^i - f^{i-1}| and stops at pf_tol.
+// Per-grain gradient tensors: the explicit remainder 2 div((K(x) - kbar I)
+// grad f) of the order parameters into a.remf (and its energy into
+// a.part_rem): gradient, flux and divergence around raw x and y transforms.
+int remainder_force(pf_ctx* c, const KArgs& a, hipStream_t s) {
+  const int V = a.nv;
+  PF_TRY(launch(c, s, "rem_x_forward", [&] { return pfl::raw_x_forward(a, a.eta, V, s); }));
+  PF_TRY(launch(c, s, "rem_y_forward", [&] { return pfl::y_pass(a, V, 1, s); }));
+  PF_TRY(launch(c, s, "rem_z_gradient", [&] { return pfl::grad_z(a, s); }));
+  PF_TRY(launch(c, s, "rem_y_inverse", [&] { return pfl::y_pass(a, 3 * V, -1, s); }));
+  PF_TRY(launch(c, s, "rem_x_flux", [&] { return pfl::flux_x(a, s); }));
+  PF_TRY(launch(c, s, "rem_y_forward", [&] { return pfl::y_pass(a, 3 * V, 1, s); }));
+  PF_TRY(launch(c, s, "rem_z_divergence", [&] { return pfl::div_z(a, s); }));
+  PF_TRY(launch(c, s, "rem_y_inverse", [&] { return pfl::y_pass(a, V, -1, s); }));
+  PF_TRY(launch(c, s, "rem_x_inverse", [&] { return pfl::raw_x_inverse(a, a.remf, V, a.inv_ntot, s); }));
+  return PF_OK;
+}
+
 int ac_update_args(pf_ctx* c, const Group& g, const KArgs& a, hipStream_t s) {
+  if (a.remf) PF_TRY(remainder_force(c, a, s));
   PF_TRY(launch(c, s, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
   for (int it = 1;; ++it) {
     PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
@@ -976,6 +1051,7 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     const double f = 2.0 * p0.L * p0.dt * p0.kappa;
     a.ax = (float)(f * kx * kx); a.ay = (float)(f * ky * ky); a.az = (float)(f * kz * kz);
     a.gx = kx * kx; a.gy = ky * ky; a.gz = kz * kz;
+    a.cdx = (float)kx; a.cdy = (float)ky; a.cdz = (float)kz;
     a.inv_ntot = (float)(1.0 / (double)g.nvox);
     a.tol = p0.ms_tol;
     a.stress_mask = p0.bc_stress_mask;
@@ -1004,6 +1080,10 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.gk = aniso ? reinterpret_cast<float*>(ws + L.gk) : nullptr;
     a.mob = g.mobile ? pg.mobility : nullptr;
     a.lapf = g.mobile ? reinterpret_cast<float*>(ws + L.lapf) : nullptr;
+    const bool grain_k = hosts[g.members[0]].grain_k;
+    a.remf = grain_k ? reinterpret_cast<float*>(ws + L.remf) : nullptr;
+    a.part_rem = grain_k ? reinterpret_cast<double*>(ws + L.part_rem) : nullptr;
+    a.krem = grain_k ? reinterpret_cast<const float*>(ws + L.krem) : nullptr;
     a.pf_base = g.pf_max_iter > 1 ? reinterpret_cast<float*>(ws + L.pf_base) : nullptr;
     a.part_pc = g.pf_max_iter > 1 ? reinterpret_cast<float*>(ws + L.part_pc) : nullptr;
     a.gscale = (float)(aniso ? 2.0 : 2.0 * p0.kappa);
@@ -1070,6 +1150,9 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     if ((e = h2d(a.khd, khd.data(), khd.size() * sizeof(double))) != hipSuccess) return bail(e, "spectral tables");
     if (a.gk && (e = h2d(a.gk, gk.data(), gk.size() * sizeof(float))) != hipSuccess)
       return bail(e, "gradient tables");
+    if (a.krem && (e = h2d(a.krem, hosts[g.members[0]].krem.data(), hosts[g.members[0]].krem.size() * sizeof(float))) !=
+                      hipSuccess)
+      return bail(e, "per-grain gradient tables");
     if ((e = h2d(tw, twh.data(), twh.size() * sizeof(float))) != hipSuccess) return bail(e, "twiddles");
     if ((e = h2d(a.state, st0.data(), st0.size() * sizeof(DevState))) != hipSuccess) return bail(e, "state");
     // the host vectors above are pageable: the copies complete before return

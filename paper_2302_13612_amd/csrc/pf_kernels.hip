@@ -618,6 +618,181 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_raw(const
   }
 }
 
+// ------------------------------------------------- per-grain gradient tensors
+// With per-grain tensors K_a^g the implicit step takes kbar_a I (the largest
+// eigenvalue over the grains) and the remainder 2 div((K_a(x) - kbar_a I)
+// grad f_a) enters the update explicitly at f^n. It is formed with spectral
+// first derivatives i xi_j (xi_j zero at a Nyquist index, where the
+// derivative, odd in it, has no value), in three passes around raw x and y
+// transforms: gradient (z), flux (x), divergence (z).
+
+// First-derivative wave numbers of a column (kx, ky) of a z pass.
+__device__ __forceinline__ void deriv_xy(const KArgs& a, int kx, int ky, float& dxk, float& dyk) {
+  dxk = kx == a.nx / 2 ? 0.f : a.cdx * (float)kx;
+  const int sy = signed_k(ky, a.ny);
+  dyk = 2 * sy == -a.ny ? 0.f : a.cdy * (float)sy;
+}
+
+__device__ __forceinline__ float deriv_z(const KArgs& a, int kz) {
+  const int sz = signed_k(kz, a.nz);
+  return 2 * sz == -a.nz ? 0.f : a.cdz * (float)sz;
+}
+
+// Gradient: the (x, y)-transformed f_q (components 0..V-1) -> forward z
+// transform, i xi_j f_hat for j = x, y, z, inverse z transforms into
+// components 3q + j. Variants are taken from the last down, so each output
+// component is written after the input it replaces has been read.
+template <int N, int K>
+__global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_grad(const KArgs a) {
+  using P = PV<N, K>;
+  constexpr int E = P::E, T = N / E, C = kColTile;
+  __shared__ float2 lds[N * C];
+  if (a.guard_ready && !a.state[0].st.ready) return;
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  if ((int)blockIdx.x >= (a.ncol + C - 1) / C && (int)(blockIdx.y % a.ny) * C >= a.ny) return;  // no column
+  const ZCol zc = z_col3(a, blockIdx.x, blockIdx.y, C, cc);
+  const bool valid = zc.valid;
+  const size_t zs = zc.zs;
+  float dk[3];
+  deriv_xy(a, zc.kx, zc.ky, dk[0], dk[1]);
+  TwCache<N, P, 1> twf;
+  twf.load(a.tw_z, t);
+  const TwCache<N, P, -1> twi = twf.conj();
+  const ColView<C> view{lds + cc};
+#pragma unroll 1
+  for (int q = a.nv - 1; q >= 0; --q) {
+    const float2* in = zc.col + q * a.cs;
+    float2 v[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = valid ? in[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+    fft_pencil<N, 1, P>(v, view, t, twf);
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+      float2 w[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const float xi = j < 2 ? dk[j] : deriv_z(a, t + T * m);
+        w[m] = make_float2(-xi * v[m].y, xi * v[m].x);
+      }
+      fft_pencil<N, -1, P>(w, view, t, twi);
+      float2* out = zc.col + (3 * q + j) * a.cs;
+      if (valid) {
+#pragma unroll
+        for (int m = 0; m < E; ++m) out[(size_t)(t + T * m) * zs] = w[m];
+      }
+    }
+  }
+}
+
+// Divergence: the (x, y)-transformed flux components 3q + j -> forward z
+// transforms, 2 sum_j i xi_j q_hat_j, inverse z transform into component q
+// (variants in ascending order: component q is written after components
+// 3q .. 3q + 2 were read, and no later variant reads it).
+template <int N, int K>
+__global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_div(const KArgs a) {
+  using P = PV<N, K>;
+  constexpr int E = P::E, T = N / E, C = kColTile;
+  __shared__ float2 lds[N * C];
+  if (a.guard_ready && !a.state[0].st.ready) return;
+  const int cc = threadIdx.x % C, t = threadIdx.x / C;
+  if ((int)blockIdx.x >= (a.ncol + C - 1) / C && (int)(blockIdx.y % a.ny) * C >= a.ny) return;  // no column
+  const ZCol zc = z_col3(a, blockIdx.x, blockIdx.y, C, cc);
+  const bool valid = zc.valid;
+  const size_t zs = zc.zs;
+  float dk[3];
+  deriv_xy(a, zc.kx, zc.ky, dk[0], dk[1]);
+  TwCache<N, P, 1> twf;
+  twf.load(a.tw_z, t);
+  const TwCache<N, P, -1> twi = twf.conj();
+  const ColView<C> view{lds + cc};
+#pragma unroll 1
+  for (int q = 0; q < a.nv; ++q) {
+    float2 acc[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) acc[m] = make_float2(0.f, 0.f);
+#pragma unroll 1
+    for (int j = 0; j < 3; ++j) {
+      const float2* in = zc.col + (3 * q + j) * a.cs;
+      float2 v[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = valid ? in[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
+      fft_pencil<N, 1, P>(v, view, t, twf);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const float xi = 2.f * (j < 2 ? dk[j] : deriv_z(a, t + T * m));
+        acc[m].x -= xi * v[m].y;
+        acc[m].y += xi * v[m].x;
+      }
+    }
+    fft_pencil<N, -1, P>(acc, view, t, twi);
+    float2* out = zc.col + q * a.cs;
+    if (valid) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) out[(size_t)(t + T * m) * zs] = acc[m];
+    }
+  }
+}
+
+// Flux, x pass: per row and variant q, the inverse x transforms of the three
+// gradient components (scaled by 1/N: grad f), the flux (K_q^g - kbar_q I)
+// grad f with g the voxel's grain, the sum of grad f . flux (FP64 per block:
+// the remainder's gradient energy), and the forward x transforms of the flux
+// into the same components.
+template <int M>
+__global__ __launch_bounds__(xthreads<M>()) void k_x_flux(const KArgs a) {
+  constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
+  constexpr int LROW = RowView::padded(M) + 1;
+  __shared__ float2 lds[ROWS * LROW];
+  if (a.guard_ready && !a.state[0].st.ready) return;
+  const int t = threadIdx.x % T, p = threadIdx.x / T;
+  const int nrows = a.ninst * a.nz * a.ny;
+  const int row = blockIdx.x * ROWS + p;
+  const bool valid = row < nrows;
+  const size_t rowv = valid ? row : 0;
+  const size_t rbase = rowv * a.nx;
+  const float s = a.inv_ntot;
+  XTw<M, -1> twi;
+  twi.load(a, t);
+  XTw<M, 1> twf;
+  twf.load(a, t);
+  float en = 0.f;
+#pragma unroll 1
+  for (int q = 0; q < a.nv; ++q) {
+    float2 g[3][E];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      c2r_row<M>(g[j], lds + p * LROW, t, valid, a.spec + (3 * q + j) * a.cs + rowv * a.sh,
+                 nyq_at(a, 3 * q + j, rowv), twi);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const size_t x0 = rbase + 2 * (t + T * m);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int gr = a.gid ? a.gid[x0 + h] : 0;
+        const float* kr = a.krem + ((size_t)gr * a.nv + q) * 6;
+        const float gx = s * (h ? g[0][m].y : g[0][m].x);
+        const float gy = s * (h ? g[1][m].y : g[1][m].x);
+        const float gz = s * (h ? g[2][m].y : g[2][m].x);
+        const float fx = kr[0] * gx + kr[5] * gy + kr[4] * gz;
+        const float fy = kr[5] * gx + kr[1] * gy + kr[3] * gz;
+        const float fz = kr[4] * gx + kr[3] * gy + kr[2] * gz;
+        if (valid) en += gx * fx + gy * fy + gz * fz;
+        if (h) {
+          g[0][m].y = fx; g[1][m].y = fy; g[2][m].y = fz;
+        } else {
+          g[0][m].x = fx; g[1][m].x = fy; g[2][m].x = fz;
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      r2c_one<M>(g[j], lds + p * LROW, t, valid, a.spec + (3 * q + j) * a.cs + rowv * a.sh,
+                 nyq_at(a, 3 * q + j, rowv), twf);
+  }
+  double acc[1] = {(double)en};
+  block_sum<1, xthreads<M>() / 64>(acc, a.part_rem + blockIdx.x);
+}
+
 // z pass of the homogeneous spectral path (one stiffness C per instance,
 // linear h, no plastic strain) for V variants. With a single stiffness the
 // equilibrium stress is known in closed form per wavevector, so no fixed
@@ -1021,12 +1196,16 @@ __device__ inline void fin_ac(const KArgs& a, int inst, int nblk_x, int nblk_z, 
   if (part == 0) {
     double gd[kQgd];
     sum_partials<kQgd>(a.part_gd + (size_t)inst * nblk_z * kQgd, nblk_z, gd, scratch);
+    // per-grain tensors: the remainder's energy of the starting state, from this step's flux pass
+    double rem[1] = {0.0};
+    if (a.part_rem && mode == 0) sum_partials<1>(a.part_rem + (size_t)inst * nblk_x, nblk_x, rem, scratch);
     if (threadIdx.x != 0) return;
     if (mode == 1) {
       st->gd_cur = gd[0];
       return;
     }
-    st->stats[kQac] = st->gd_cur;  // the starting state's
+    // the starting state's (the Parseval sums carry a factor N the host removes)
+    st->stats[kQac] = st->gd_cur + rem[0] * ((double)a.nx * a.ny * a.nz);
     if (mode == 2) {
       const double ntot = (double)a.nx * a.ny * a.nz;
       st->stats[kQac] = gd[2];  // the starting state's, from the spectral z pass
@@ -1601,6 +1780,46 @@ hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s) {
     PF_SWITCH_N(a.nz, return (raw_z_n<N, -1>(a, ncomp, s)));
   }
   return hipErrorInvalidValue;
+}
+
+template <int N, int K, bool DIV>
+static hipError_t gd_launch(const KArgs& a, hipStream_t s) {
+  if constexpr (col_threads<N, K, kColTile>() <= 1024) {
+    const dim3 grid(z_tiles_x(a, kColTile), a.ny * a.ninst);
+    if constexpr (DIV)
+      k_z_div<N, K><<<grid, dim3(col_threads<N, K, kColTile>()), 0, s>>>(a);
+    else
+      k_z_grad<N, K><<<grid, dim3(col_threads<N, K, kColTile>()), 0, s>>>(a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <int N, bool DIV>
+static hipError_t gd_n(const KArgs& a, hipStream_t s) {
+  switch (a.zplan_ac) {
+    case 0: return gd_launch<N, 0, DIV>(a, s);
+    case 1: return gd_launch<N, 1, DIV>(a, s);
+    case 2: return gd_launch<N, 2, DIV>(a, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t grad_z(const KArgs& a, hipStream_t s) {
+  PF_SWITCH_N(a.nz, return (gd_n<N, false>(a, s)));
+  return hipErrorInvalidValue;
+}
+
+hipError_t div_z(const KArgs& a, hipStream_t s) {
+  PF_SWITCH_N(a.nz, return (gd_n<N, true>(a, s)));
+  return hipErrorInvalidValue;
+}
+
+hipError_t flux_x(const KArgs& a, hipStream_t s) {
+  const dim3 grid(x_blocks(a));
+  PF_SWITCH_M(a.nx, (k_x_flux<M><<<grid, xthreads<M>(), 0, s>>>(a)));
+  return hipGetLastError();
 }
 
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s) {

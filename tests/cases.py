@@ -36,10 +36,15 @@ def oracle_problem(cfg, tol=1e-10):
     if cfg.get("aniso"):
         # the oracle's own gradient tensors (one grain)
         kv = cr.twin_gradient_tensors(np.asarray(cfg["rotations"])[:1], cfg["variant_ids"], **cfg["aniso"])[0]
+    kg = None
+    if cfg.get("aniso_grains"):
+        # the oracle's own per-grain tensors
+        kg = cr.twin_gradient_tensors(np.asarray(cfg["rotations"]), cfg["variant_ids"], **cfg["aniso_grains"])
     return opf.Problem(cfg["shape"], cfg["dx"], tabs, cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], C0,
                        gid=cfg["gid"], h_kind=cfg.get("h_kind", "linear"), ms_tol=tol, ms_max_iter=300,
                        kappa_var=kv, mobility=cfg.get("mobility"),
-                       pf_tol=cfg.get("pf_tol_oracle", 1e-12), pf_max_iter=cfg.get("pf_max_iter", 1))
+                       pf_tol=cfg.get("pf_tol_oracle", 1e-12), pf_max_iter=cfg.get("pf_max_iter", 1),
+                       kappa_grain=kg)
 
 
 def oracle_run(cfg, steps, tol=1e-10):
@@ -77,13 +82,18 @@ def gpu_solver(cfg, device="cuda", rotation_form=True):
     if cfg.get("aniso"):
         # the library's own gradient tensors (one grain, sample frame)
         kv = binding.mg_twin_gradient(np.asarray(cfg["rotations"])[:1], cfg["variant_ids"], **cfg["aniso"])[0]
+    kg = None
+    if cfg.get("aniso_grains"):
+        # the library's own per-grain tensors (sample frame)
+        kg = binding.mg_twin_gradient(np.asarray(cfg["rotations"]), cfg["variant_ids"], **cfg["aniso_grains"])
     mob = None
     if cfg.get("mobility") is not None:
         mob = torch.from_numpy(np.ascontiguousarray(cfg["mobility"], dtype=np.float32)).to(device)
     solver = binding.Solver(eta0, cfg["dx"], cfg["A"], cfg["kappa"], cfg["L"], cfg["dt"], (Cg, Cv, e0),
                             cfg["stress_mask"], gid=gid, h_kind=h_kind, ms_tol=cfg["ms_tol"],
                             ms_max_iter=cfg["ms_max_iter"], rotations=rotations, kappa_var=kv, mobility=mob,
-                            pf_tol=cfg.get("pf_tol", 1e-6), pf_max_iter=cfg.get("pf_max_iter", 1))
+                            pf_tol=cfg.get("pf_tol", 1e-6), pf_max_iter=cfg.get("pf_max_iter", 1),
+                            kappa_grain=kg)
     epsp = None if cfg["eps_p"] is None else torch.from_numpy(np.ascontiguousarray(cfg["eps_p"])).to(device)
     return solver, epsp
 

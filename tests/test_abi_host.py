@@ -209,3 +209,42 @@ def test_specconv_sizes():
         assert lib.pf_specconv_workspace_size(*bad, ctypes.byref(n)) == binding.PF_EINVAL, bad
     assert lib.pf_specconv_forward(2, 4, 16, 16, 16, 3, None, None, None, None, None, None, 0, None) == \
         binding.PF_EINVAL
+
+
+def test_grain_tensor_arguments():
+    lib = binding.load()
+    keep = []
+    p = valid_problem(lib, n_grains=2, keep=keep)
+    kg = np.ascontiguousarray(np.tile([2.81e-6, 2.81e-7, 2.81e-7, 0.0, 0.0, 1e-8], (2, 1)))
+    keep.append(kg)
+    p.kappa_grain = binding._ptr(kg)
+    size = ctypes.c_size_t()
+    assert lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(size)) == binding.PF_OK
+    with_k = size.value
+    p.kappa_grain = None
+    assert lib.pf_workspace_size(ctypes.byref(p), ctypes.byref(size)) == binding.PF_OK
+    # the remainder field (V fields) and three spectral components per variant
+    assert with_k > size.value + 4 * 32 ** 3
+    p.kappa_grain = binding._ptr(kg)
+    ctx = ctypes.c_void_p()
+    kv = np.ascontiguousarray(np.array([[1e-9, 1e-9, 1e-9, 0.0, 0.0, 0.0]]))
+    keep.append(kv)
+    p.kappa_var = binding._ptr(kv)                 # both given (one grain, so kappa_var alone would do)
+    p.n_grains, p.grain_id = 1, None
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EINVAL
+    p.n_grains, p.grain_id = 2, 0x1000
+    p.kappa_var = None
+    p.mobility = 0x3000
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
+    p.mobility = None
+    p.pf_max_iter, p.pf_tol = 4, 1e-6
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
+    p.pf_max_iter = 1
+    kg[1, 2] = -1.0                                 # negative diagonal
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EINVAL
+    kg[1, 2] = float("nan")
+    assert lib.pf_batch_init(ctypes.byref(p), 1, None, 0, None, ctypes.byref(ctx)) == binding.PF_EINVAL
+    kg[1, 2] = 2.81e-7
+    probs = (binding.PfProblem * 2)(p, p)          # a batch
+    assert lib.pf_batch_init(probs, 2, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
+    assert not ctx.value
