@@ -142,7 +142,8 @@ typedef struct {
                               diagonal term. NULL: isotropic kappa. Needs
                               n_grains == 1 (PF_EUNSUPPORTED otherwise: a
                               spatially varying K is not solved exactly by
-                              the spectral implicit step). Copied at init.  */
+                              the spectral implicit step; kappa_grain takes
+                              one tensor per grain). Copied at init.        */
   const float *mobility;   /* optional device [nz][ny][nx]: relative mobility
                               m in [0, 1] of each cell, L(x) = L m (the pad
                               layer of very low mobility around a specimen,

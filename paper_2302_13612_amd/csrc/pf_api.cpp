@@ -44,7 +44,7 @@ size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 // Workspace layout of one group (byte offsets from the group's base).
 struct Layout {
   size_t eta, eps, eps_prev, eps_prev2, eps_prev3, sig, epsp, spec, tables, rot, ref, bss, loads, kh, khd, gk, tw;
-  size_t remf, part_rem, krem;
+  size_t part_rem, krem;
   size_t lapf;  // gradient force of the state (with a mobility field), else 0
   size_t pf_base, part_pc;  // fixed point over the update (pf_max_iter > 1), else 0
   size_t spec_bytes;        // size of the spectral buffer
@@ -123,12 +123,12 @@ Layout make_layout(int nx, int ny, int nz, int nv, int n_grains, int ninst, bool
   // field, 3V for the macro-step residual of the spectral path (V <= 3)
   int ncomp = 6;
   if (mobile && 2 * nv > ncomp) ncomp = 2 * nv;
-  if ((nv <= pft::kKhMaxVar || grain_k) && 3 * nv > ncomp) ncomp = 3 * nv;
+  if (nv <= pft::kKhMaxVar && 3 * nv > ncomp) ncomp = 3 * nv;
+  if (grain_k && 4 * nv > ncomp) ncomp = 4 * nv;  // the update's V and the remainder's 3V
   L.spec_bytes = sizeof(float) * 2 * nspec * ncomp;
   L.spec = take(L.spec_bytes);
   L.lapf = mobile ? take(sizeof(float) * nvox * nv) : 0;
-  // per-grain gradient tensors: the remainder field, its energy partials, the tables
-  L.remf = grain_k ? take(sizeof(float) * nvox * nv) : 0;
+  // per-grain gradient tensors: the remainder's energy partials, the tables
   L.part_rem = grain_k ? take(sizeof(double) * xb) : 0;
   L.krem = grain_k ? take(sizeof(float) * 6 * (size_t)G * nv) : 0;
   L.pf_base = picard ? take(sizeof(float) * nvox * nv) : 0;
@@ -696,28 +696,30 @@ int ms_iteration(pf_ctx* c, const KArgs& a, hipStream_t s) {
 // chemical force of the latest iterate (pc_x_forward) while the gradient
 // term stays implicit and the mechanical force stays that of f^n; after each
 // solve the host reads max |f^i - f^{i-1}| and stops at pf_tol.
-// Per-grain gradient tensors: the explicit remainder 2 div((K(x) - kbar I)
-// grad f) of the order parameters into a.remf (and its energy into
-// a.part_rem): gradient, flux and divergence around raw x and y transforms.
-int remainder_force(pf_ctx* c, const KArgs& a, hipStream_t s) {
+// Per-grain gradient tensors, first part of the explicit remainder
+// 2 div((K(x) - kbar I) grad f^n): the gradient of the order parameters and
+// the flux (K - kbar I) grad f (with its energy into a.part_rem), held after
+// their x and y transforms in the spectral components V .. 4V-1; the update's
+// divergence pass (k_z_div) adds the rest after the update's y transform.
+int remainder_flux(pf_ctx* c, const KArgs& a, hipStream_t s) {
   const int V = a.nv;
-  PF_TRY(launch(c, s, "rem_x_forward", [&] { return pfl::raw_x_forward(a, a.eta, V, s); }));
-  PF_TRY(launch(c, s, "rem_y_forward", [&] { return pfl::y_pass(a, V, 1, s); }));
-  PF_TRY(launch(c, s, "rem_z_gradient", [&] { return pfl::grad_z(a, s); }));
-  PF_TRY(launch(c, s, "rem_y_inverse", [&] { return pfl::y_pass(a, 3 * V, -1, s); }));
-  PF_TRY(launch(c, s, "rem_x_flux", [&] { return pfl::flux_x(a, s); }));
-  PF_TRY(launch(c, s, "rem_y_forward", [&] { return pfl::y_pass(a, 3 * V, 1, s); }));
-  PF_TRY(launch(c, s, "rem_z_divergence", [&] { return pfl::div_z(a, s); }));
-  PF_TRY(launch(c, s, "rem_y_inverse", [&] { return pfl::y_pass(a, V, -1, s); }));
-  PF_TRY(launch(c, s, "rem_x_inverse", [&] { return pfl::raw_x_inverse(a, a.remf, V, a.inv_ntot, s); }));
+  KArgs r = a;
+  r.spec = a.spec + (size_t)V * a.cs;  // components V .. 4V-1
+  PF_TRY(launch(c, s, "rem_x_forward", [&] { return pfl::raw_x_forward(r, a.eta, V, s); }));
+  PF_TRY(launch(c, s, "rem_y_forward", [&] { return pfl::y_pass(r, V, 1, s); }));
+  PF_TRY(launch(c, s, "rem_z_gradient", [&] { return pfl::grad_z(r, s); }));
+  PF_TRY(launch(c, s, "rem_y_inverse3", [&] { return pfl::y_pass(r, 3 * V, -1, s); }));
+  PF_TRY(launch(c, s, "rem_x_flux", [&] { return pfl::flux_x(r, s); }));
+  PF_TRY(launch(c, s, "rem_y_forward3", [&] { return pfl::y_pass(r, 3 * V, 1, s); }));
   return PF_OK;
 }
 
 int ac_update_args(pf_ctx* c, const Group& g, const KArgs& a, hipStream_t s) {
-  if (a.remf) PF_TRY(remainder_force(c, a, s));
+  if (a.krem) PF_TRY(remainder_flux(c, a, s));
   PF_TRY(launch(c, s, "ac_x_forward", [&] { return pfl::ac_x_forward(a, s); }));
   for (int it = 1;; ++it) {
     PF_TRY(launch(c, s, "ac_y_forward", [&] { return pfl::y_pass(a, a.nv, 1, s); }));
+    if (a.krem) PF_TRY(launch(c, s, "rem_z_divergence", [&] { return pfl::div_z(a, s); }));
     PF_TRY(launch(c, s, "ac_z_update", [&] { return pfl::ac_z_update(a, 0, s); }));
     PF_TRY(launch(c, s, "ac_y_inverse", [&] { return pfl::y_pass(a, a.lapf ? 2 * a.nv : a.nv, -1, s); }));
     PF_TRY(launch(c, s, "ac_x_inverse", [&] { return pfl::ac_x_inverse(a, s); }));
@@ -1081,7 +1083,6 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
     a.mob = g.mobile ? pg.mobility : nullptr;
     a.lapf = g.mobile ? reinterpret_cast<float*>(ws + L.lapf) : nullptr;
     const bool grain_k = hosts[g.members[0]].grain_k;
-    a.remf = grain_k ? reinterpret_cast<float*>(ws + L.remf) : nullptr;
     a.part_rem = grain_k ? reinterpret_cast<double*>(ws + L.part_rem) : nullptr;
     a.krem = grain_k ? reinterpret_cast<const float*>(ws + L.krem) : nullptr;
     a.pf_base = g.pf_max_iter > 1 ? reinterpret_cast<float*>(ws + L.pf_base) : nullptr;

@@ -94,10 +94,9 @@ struct KArgs {
   const float* gk;            // [ninst][kGkStride] or null (isotropic kappa)
   const float* mob;           // [nz][ny][nx] relative mobility, or null (uniform)
   float* lapf;                // [nv][nz][ny][nx] 2 div(K grad f) of the state (with mob)
-  float* remf;                // [nv][nz][ny][nx] 2 div((K(x) - kbar I) grad f) of f^n with
-                              // per-grain gradient tensors (the explicit remainder), or null
-  const float* krem;          // [n_grains][nv][6] K_a^g - kbar_a I (tensor-Voigt), with remf
-  double* part_rem;           // [x blocks] sums of grad f . (K - kbar I) . grad f, with remf
+  const float* krem;          // [n_grains][nv][6] K_a^g - kbar_a I (tensor-Voigt): per-grain
+                              // gradient tensors (the explicit remainder), or null
+  double* part_rem;           // [x blocks] sums of grad f . (K - kbar I) . grad f, with krem
   float cdx, cdy, cdz;        // 2 pi / (n dx) per axis (first derivatives)
   float gscale;               // 2 kappa (isotropic symbol) or 2 (tables carry K)
   float* pf_base;             // [nv][nz][ny][nx] f^n + L dt m mech of the step, kept for
@@ -237,9 +236,10 @@ hipError_t ct_x_forward(const KArgs& a, const float* prev, int n_steps, hipStrea
 // per-instance max |r| into DevState::resid_max.
 hipError_t kh_residual(const KArgs& a, const float* prev, int n_steps, hipStream_t s);
 // The explicit remainder of per-grain gradient tensors, 2 div((K(x) - kbar I)
-// grad f) of the order parameters into a.remf (with the gradient energy of the
-// remainder into a.part_rem): grad_z, flux_x and div_z around raw x and y
-// transforms; 3V spectral components.
+// grad f) of the order parameters: grad_z and flux_x (with the remainder's
+// gradient energy into a.part_rem) around raw x and y transforms on the
+// components V .. 4V-1, then div_z adds L dt times the divergence to the
+// update's y-transformed right-hand side (components 0 .. V-1).
 hipError_t grad_z(const KArgs& a, hipStream_t s);
 hipError_t flux_x(const KArgs& a, hipStream_t s);
 hipError_t div_z(const KArgs& a, hipStream_t s);

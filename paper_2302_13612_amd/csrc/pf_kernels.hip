@@ -684,10 +684,12 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_grad(cons
   }
 }
 
-// Divergence: the (x, y)-transformed flux components 3q + j -> forward z
-// transforms, 2 sum_j i xi_j q_hat_j, inverse z transform into component q
-// (variants in ascending order: component q is written after components
-// 3q .. 3q + 2 were read, and no later variant reads it).
+// Divergence into the update: the (x, y)-transformed flux components, held
+// from component V on (V + 3q + j), -> forward z transforms, 2 sum_j i xi_j
+// q_hat_j, inverse z transform, added times L dt / nz (the z transforms carry
+// nz) to component q: the update's right-hand side f - L dt (chem - mech)
+// after its x and y transforms, so the update gains + L dt 2 div((K - kbar I)
+// grad f^n) before its z pass.
 template <int N, int K>
 __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_div(const KArgs a) {
   using P = PV<N, K>;
@@ -705,6 +707,7 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_div(const
   twf.load(a.tw_z, t);
   const TwCache<N, P, -1> twi = twf.conj();
   const ColView<C> view{lds + cc};
+  const float w = a.LDt / (float)a.nz;
 #pragma unroll 1
   for (int q = 0; q < a.nv; ++q) {
     float2 acc[E];
@@ -712,7 +715,7 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_div(const
     for (int m = 0; m < E; ++m) acc[m] = make_float2(0.f, 0.f);
 #pragma unroll 1
     for (int j = 0; j < 3; ++j) {
-      const float2* in = zc.col + (3 * q + j) * a.cs;
+      const float2* in = zc.col + (a.nv + 3 * q + j) * a.cs;
       float2 v[E];
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = valid ? in[(size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
@@ -728,7 +731,11 @@ __global__ __launch_bounds__((col_threads<N, K, kColTile>())) void k_z_div(const
     float2* out = zc.col + q * a.cs;
     if (valid) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) out[(size_t)(t + T * m) * zs] = acc[m];
+      for (int m = 0; m < E; ++m) {
+        float2* o = out + (size_t)(t + T * m) * zs;
+        const float2 r = *o;
+        *o = make_float2(r.x + w * acc[m].x, r.y + w * acc[m].y);
+      }
     }
   }
 }

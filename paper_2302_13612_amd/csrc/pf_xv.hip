@@ -359,10 +359,7 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
 // mean sums, extrema of f; R2C of the V right-hand sides. With a fixed point
 // over the update (PB) the part that stays fixed, f_a + L dt m mech_a, is
 // kept (a separate instantiation: the store costs registers).
-// RM: per-grain gradient tensors, the explicit remainder a.remf added to the
-// right-hand side (a variant of its own: the branch would cost the plain
-// kernel registers).
-template <int M, int V, bool ROT, int HK, bool PB, bool RM = false>
+template <int M, int V, bool ROT, int HK, bool PB>
 __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(kXWaves))) void k_x_fwd_ac(const KArgs a) {
   constexpr int E = XPlan<M>::E, T = M / E, ROWS = xthreads<M>() / T;
   constexpr int LROW = RowView::padded(M) + 1;
@@ -450,12 +447,6 @@ __global__ __launch_bounds__(xthreads<M>()) __attribute__((amdgpu_waves_per_eu(k
 #pragma unroll
         for (int q = 0; q < V; ++q)
           o[half][q] = et[q] + mb * (o[half][q] - et[q]) + a.LDt * (mb - 1.f) * a.lapf[q * vs + vox];
-      }
-      if constexpr (RM) {
-        // per-grain gradient tensors: the explicit remainder 2 div((K - kbar I) grad f^n)
-        const size_t vox = rbase + x0 + half;
-#pragma unroll
-        for (int q = 0; q < V; ++q) o[half][q] += a.LDt * a.remf[q * vs + vox];
       }
       if (valid) {
         facc[0] += fdw;
@@ -813,8 +804,6 @@ hipError_t PF_CAT(ct_x_forward_v, PF_NV)(const KArgs& a, const float* prev, int 
 hipError_t PF_CAT(ac_x_forward_v, PF_NV)(const KArgs& a, hipStream_t s) {
   if (a.pf_base) {
     PF_LAUNCH_X(k_x_fwd_ac, , true);
-  } else if (a.remf) {
-    PF_LAUNCH_X(k_x_fwd_ac, , false, true);
   } else {
     PF_LAUNCH_X(k_x_fwd_ac, , false);
   }

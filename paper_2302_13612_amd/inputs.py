@@ -166,10 +166,13 @@ def grain_pair_interfaces(gid):
     return {k: np.concatenate(v) for k, v in sorted(pairs.items())}
 
 
-def boundary_nuclei(gid, n_var, fraction, radius, rng):
-    """eta0 (n_var, ...) with spheres of a random variant centred on random
-    boundary voxels of a random `fraction` (at least one) of the grain-pair
-    interfaces. A voxel already inside a nucleus keeps its first variant."""
+def boundary_nuclei(gid, n_var, fraction, radius, rng, grain_variant=None):
+    """eta0 (n_var, ...) with spheres centred on random boundary voxels of a
+    random `fraction` (at least one) of the grain-pair interfaces, each of the
+    variant grain_variant[g] of the grain g of its centre voxel (a random
+    variant without it; the draw is made either way, so both choices place
+    the same spheres). A voxel already inside a nucleus keeps its first
+    variant."""
     shape = gid.shape
     pairs = grain_pair_interfaces(gid)
     keys = list(pairs.keys())
@@ -182,6 +185,8 @@ def boundary_nuclei(gid, n_var, fraction, radius, rng):
         flat = vox[rng.integers(len(vox))]
         center = np.unravel_index(flat, shape)
         var = int(rng.integers(n_var))
+        if grain_variant is not None:
+            var = int(grain_variant[gid[center]])
         ball = sphere(shape, center, radius) & ~taken
         eta[var][ball] = 1.0
         taken |= ball
@@ -243,15 +248,22 @@ def ramp_load(cfg, n):
 
 def polycrystal(shape=(256, 256, 256), n_grains=64, seed=3, n_var=6,
                 nuc_fraction=0.05, radius=3, rms=2e-3, corr_len=8.0,
-                strain=-5e-3, steps=1000):
-    """Voronoi polycrystal with all six twin variants per voxel."""
+                strain=-5e-3, steps=1000, variant_for=None):
+    """Voronoi polycrystal with all six twin variants per voxel.
+
+    variant_for: optional callable (rotations (G, 3, 3), eps_bar (6,)) ->
+    the variant (0..n_var-1) each grain's nuclei take, e.g. its largest
+    Schmid factor under the load; the caller computes it with its own
+    crystallography (this module holds none). Without it each nucleus takes
+    a random variant."""
     rng = rng_for(seed)
     gid = voronoi_grains(shape, n_grains, rng)
     rot = random_rotations(n_grains, rng)
-    eta0, n_nuc, n_pairs = boundary_nuclei(gid, n_var, nuc_fraction, radius, rng)
-    eps_p = plastic_strain_grf(shape, corr_len, rms, rng)
     eps_bar = np.zeros(6)
     eps_bar[0] = strain
+    gv = None if variant_for is None else np.asarray(variant_for(rot, eps_bar), dtype=np.int64)
+    eta0, n_nuc, n_pairs = boundary_nuclei(gid, n_var, nuc_fraction, radius, rng, gv)
+    eps_p = plastic_strain_grf(shape, corr_len, rms, rng)
     # Six variants couple through the elastic energy: the largest eigenvalue of
     # the Gram matrix eps0_a : C : eps0_b of the Mg variants is ~1.5e9 J/m^3,
     # so the explicit update needs L dt (2A + 1.5e9) < 2; dt = 4e-5 s keeps the

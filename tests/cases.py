@@ -111,8 +111,21 @@ def gpu_run(cfg, steps, save_stress_last=True, rotation_form=True):
     return solver, eta, sig
 
 
+def load_variants(n_var):
+    """variant_for of the polycrystal recipe, from the oracle's crystallography:
+    per grain the variant (of the first n_var) whose eigenstrain does the most
+    work against the applied mean strain, eps_bar : eps0_a (for uniaxial
+    compression the largest Schmid factor)."""
+    def pick(R, eps_bar):
+        _, _, e0 = cr.mg_tables(np.asarray(R), list(range(n_var)))
+        eb = mech.voigt6_to_tensor(np.asarray(eps_bar, dtype=np.float64))
+        return np.argmax(np.einsum("gaij,ij->ga", e0, eb), axis=1)
+    return pick
+
+
 def small_polycrystal(shape=(32, 32, 32), n_grains=6, seed=5, n_var=6):
-    return inputs.polycrystal(shape=shape, n_grains=n_grains, seed=seed, n_var=n_var)
+    return inputs.polycrystal(shape=shape, n_grains=n_grains, seed=seed, n_var=n_var,
+                              variant_for=load_variants(n_var))
 
 
 def small_lamellae(shape=(64, 32, 32), seed=7):

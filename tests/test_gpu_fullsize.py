@@ -79,7 +79,7 @@ def oracle_checks(cfg, eps6, sig6, eta1):
 @pytest.mark.timeout(600)
 def test_polycrystal_256_full_size_one_step():
     from paper_2302_13612_amd import binding
-    cfg = inputs.polycrystal(shape=(256, 256, 256))
+    cfg = inputs.polycrystal(shape=(256, 256, 256), variant_for=cases.load_variants(6))
     print(f"\n[fullsize] polycrystal {cfg['shape']} n_var={cfg['n_var']} grains={int(cfg['gid'].max()) + 1}",
           flush=True)
     solver, eta1, sig6 = cases.gpu_run(cfg, 1)
