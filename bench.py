@@ -117,18 +117,27 @@ def kernel_bytes(name, nx, ny, nz, V, multigrain, save_stress=False):
     return table.get(name, 0)
 
 
-def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10):
+def copy_bandwidth(torch, dev, nbytes=1 << 30, reps=10, own=False):
     """Device-to-device copy rate (bytes read + written per second) of a
-    1 GiB buffer: the bandwidth a plain streaming kernel reaches on this
-    device, reported beside the datasheet peak."""
+    1 GiB buffer, by torch's copy or (own) by the library's streaming copy
+    kernel (16 bytes per lane, nontemporal hints): the bandwidth a kernel
+    that only moves bytes reaches on this device, reported beside the
+    datasheet peak. Events on the stream both copies run on."""
+    from paper_2302_13612_amd import binding
     src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
-    dst.copy_(src)
+
+    def copy():
+        if own:
+            binding.stream_copy(dst, src)
+        else:
+            dst.copy_(src)
+    copy()
     s = torch.cuda.current_stream(dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        dst.copy_(src)
+        copy()
     e1.record(s)
     e1.synchronize()
     gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
@@ -797,10 +806,13 @@ def main():
         "step_algorithmic_GBs": round(step_bytes / (ms_step * 1e-3) / 1e9, 1),
         "step_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
     }
-    copy_gbs = copy_bandwidth(torch, dev)
+    copy_gbs = copy_bandwidth(torch, dev, own=True)
+    torch_gbs = copy_bandwidth(torch, dev)
     roofline["copy_GBs"] = round(copy_gbs, 1)
+    roofline["torch_copy_GBs"] = round(torch_gbs, 1)
     roofline["frac_of_copy"] = round(dom[3] / copy_gbs, 4)
-    log(f"device copy {copy_gbs:.0f} GB/s; {dom[0]} at {100 * dom[3] / copy_gbs:.1f}% of it")
+    log(f"streaming copy {copy_gbs:.0f} GB/s (torch copy {torch_gbs:.0f}); {dom[0]} at "
+        f"{100 * dom[3] / copy_gbs:.1f}% of it")
     out = {
         "metric": METRIC,
         "value": value,

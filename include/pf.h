@@ -547,6 +547,14 @@ int pf_fno_destroy(pf_fno *fno);
 int pf_macro_residual(pf_ctx *ctx, const float *eta_prev, int32_t n_steps,
                       const pf_load *load, double *rho);
 
+/* Streaming device copy of bytes (a multiple of 16, both pointers 16-byte
+ * aligned, else PF_EINVAL; PF_EDEVICE if the launch fails) on hip_stream:
+ * 16 bytes per lane with the nontemporal hint on both sides, grid-stride.
+ * Not part of the method: the attainable HBM rate of a kernel that only
+ * moves bytes, measured beside the passes as the reference for their rates
+ * (the roofline's peak stays the 8 TB/s datasheet figure). Asynchronous. */
+int pf_stream_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Host helper: sample-frame tables of Mg tension twins for n_grains grains.
  * Crystal frame x || [10-10], y || [-12-10], z || [0001]; c_over_a and
  * gamma_tw as in Sec. 2.1 (1.633, 0.129); C_hex = {C11, C12, C13, C33, C44}

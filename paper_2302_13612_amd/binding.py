@@ -637,9 +637,27 @@ def _declare_fno(lib):
     lib._fno_declared = True
 
 
+def stream_copy(dst, src):
+    """Streaming device copy src -> dst (torch CUDA tensors of the same byte
+    size, 16-byte multiples) on torch's current stream (pf_stream_copy)."""
+    import torch
+    lib = load()
+    if not getattr(lib, "_stream_declared", False):
+        lib.pf_stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.pf_stream_copy.restype = ctypes.c_int
+        lib._stream_declared = True
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("stream_copy needs contiguous tensors of the same byte size")
+    rc = lib.pf_stream_copy(dst.data_ptr(), src.data_ptr(), nbytes, torch.cuda.current_stream().cuda_stream)
+    if rc != PF_OK:
+        raise PfError(rc, "pf_stream_copy")
+
+
 def macro_residual(solver, eta_prev, n_steps, eps_bar, sig_bar=None):
-    """Backward-Euler residual max of the macro step ending at the solver's
-    current order parameter (see pf_macro_residual)."""
+    """Residual max of the macro step from eta_prev to the solver's current
+    order parameter (end-corrected trapezoid of the summed plain steps; see
+    pf_macro_residual)."""
     lib = solver.lib
     _declare_fno(lib)
     ld = PfLoad()

@@ -22,6 +22,7 @@ UNITS = [("pf_kernels.hip", [], "pf_kernels.o"),
          ("pf_vmap.hip", [], "pf_vmap.o"),
          ("pf_specconv.hip", [], "pf_specconv.o"),
          ("pf_fnotrain.hip", [], "pf_fnotrain.o"),
+         ("pf_stream.hip", [], "pf_stream.o"),
          ("pf_api.cpp", [], "pf_api.o"),
          ("pf_crystal.cpp", [], "pf_crystal.o")] + \
         [("pf_xv.hip", [f"-DPF_NV={v}"], f"pf_xv{v}.o") for v in range(1, 7)]

@@ -249,3 +249,13 @@ def test_grain_tensor_arguments():
     probs = (binding.PfProblem * 2)(p, p)          # a batch
     assert lib.pf_batch_init(probs, 2, None, 0, None, ctypes.byref(ctx)) == binding.PF_EUNSUPPORTED
     assert not ctx.value
+
+
+def test_stream_copy_arguments():
+    lib = binding.load()
+    lib.pf_stream_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    # rejected before any launch: null, size not a multiple of 16, misaligned
+    assert lib.pf_stream_copy(None, 0x1000, 64, None) == binding.PF_EINVAL
+    assert lib.pf_stream_copy(0x2000, 0x1000, 60, None) == binding.PF_EINVAL
+    assert lib.pf_stream_copy(0x2008, 0x1000, 64, None) == binding.PF_EINVAL
+    assert lib.pf_stream_copy(0x2000, 0x1000, 0, None) == binding.PF_OK      # nothing to move

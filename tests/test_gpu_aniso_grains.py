@@ -73,3 +73,10 @@ def test_isotropic_grain_tensors_equal_the_isotropic_step():
     assert abs(ga - gb) <= 1e-5 * abs(gb)
     s1.close()
     s2.close()
+
+
+def test_aniso_polycrystal_radix3_axes():
+    # 96 along y and 48 along z: the radix-3 plans in the gradient and divergence z passes and
+    # the y passes of 3V components
+    cfg = dict(cases.small_polycrystal(shape=(48, 96, 32), n_grains=4, seed=17, n_var=2), aniso_grains=PAPER)
+    grain_case(cfg, 3, "4 grains, 2 variants, 48 x 96 x 32")
