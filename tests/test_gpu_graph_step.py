@@ -59,6 +59,22 @@ def test_polycrystal_graph_steps_match_host_driven(jump_at):
         assert st_g[k] == st_h[k], k
 
 
+def test_per_grain_tensors_graph_steps_match_host_driven():
+    # the remainder's passes (gradient, flux, divergence) inside the replayed step graph,
+    # the update guarded by the fixed point's flag
+    cfg = dict(cases.small_polycrystal(n_var=2), aniso_grains=dict(c2n=2.81e-7, c2s=2.81e-6))
+    steps = 10
+    eta_g, st_g, it_g = poly_run(cfg, steps, False)
+    eta_h, st_h, it_h = poly_run(cfg, steps, True)
+    log(f"\n[graph step] per-grain tensors 32^3 {steps} steps: iterations {it_g}, "
+        f"replayed {st_g['steps_replayed']}")
+    assert st_g["steps_replayed"] >= steps - 5 and st_h["steps_replayed"] == 0
+    assert it_g == it_h
+    assert np.array_equal(eta_g, eta_h)
+    for k in ("G_dw", "G_gd", "G_me"):
+        assert st_g[k] == st_h[k], k
+
+
 def mixed_batch():
     """Sizes 32 and 48 with a parent/twin contrast in one instance of each
     (those groups iterate), size 64 homogeneous (spectral path)."""
