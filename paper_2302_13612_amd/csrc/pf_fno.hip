@@ -101,15 +101,17 @@ __device__ __forceinline__ bf16x8 load8(const uint16_t* p) {
   return out;
 }
 
-// D (32 voxels x 32 outputs) = v[x0 .. x0+31][0..31] . Wt where Wt[i][o] = Wm[o][i]
+// D (32 outputs x 32 voxels) = Wm . v[x0 .. x0+31][0..31]^T: accumulator r of
+// lane l holds output o = mfma_row(r, l) of voxel x0 + l % 32, so a lane owns
+// four runs of four consecutive outputs of one voxel (stored as 8 bytes each).
 __device__ __forceinline__ f32x16 mix32(const uint16_t* __restrict__ vrow, int x0, const uint16_t* __restrict__ Wm,
                                         int lane) {
   const int i = lane % 32, kb = 8 * (lane / 32);
   f32x16 acc = {};
-  const uint16_t* ap = vrow + (size_t)(x0 + i) * kC + kb;
-  const uint16_t* bp = Wm + (size_t)i * kC + kb;
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(ap), load8(bp), acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(ap + 16), load8(bp + 16), acc, 0, 0, 0);
+  const uint16_t* wp = Wm + (size_t)i * kC + kb;
+  const uint16_t* vp = vrow + (size_t)(x0 + i) * kC + kb;
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(wp), load8(vp), acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load8(wp + 16), load8(vp + 16), acc, 0, 0, 0);
   return acc;
 }
 
@@ -338,7 +340,9 @@ __global__ __launch_bounds__(256) void k_xinv_mix(const FArgs a, const uint16_t*
   const int rows = a.ny * a.nz, m2 = 2 * a.m, ntile = nx / 32;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int i = lane % 32, kb = 8 * (lane / 32);
-  const float bo = bias[i];
+  float bo[16];  // the bias of the output each accumulator holds
+#pragma unroll
+  for (int rr = 0; rr < 16; ++rr) bo[rr] = bias[mfma_row(rr, lane)];
   for (int g = 0; g < kInvGroups; ++g) {
     const int row0 = (blockIdx.x * kInvGroups + g) * kInvRows;
     __syncthreads();  // the twiddles are in place; the previous group's reads are done
@@ -357,21 +361,29 @@ __global__ __launch_bounds__(256) void k_xinv_mix(const FArgs a, const uint16_t*
       if (row >= rows) continue;  // uniform over the wave; no barrier follows in this loop
       const uint16_t* vrow = vin + (size_t)row * nx * kC;
       f32x16 acc = mix32(vrow, x0, Wm, lane);
+      // the inverse x sum as the second product, transposed like the mixing:
+      // A = Y1 [o][j] (hi, lo), B = WI^T [j][x] (hi, lo)
 #pragma unroll
       for (int j0 = 0; j0 < 32; j0 += 16) {
-        const bf16x8 ah = load8(wi + (x0 + i) * kYPitch + j0 + kb);
-        const bf16x8 al = load8(wi + (nx + x0 + i) * kYPitch + j0 + kb);
-        const bf16x8 bh = load8(yt + ((rl * 2) * 32 + i) * kYPitch + j0 + kb);
-        const bf16x8 bl = load8(yt + ((rl * 2 + 1) * 32 + i) * kYPitch + j0 + kb);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+        const bf16x8 wh = load8(wi + (x0 + i) * kYPitch + j0 + kb);
+        const bf16x8 wl = load8(wi + (nx + x0 + i) * kYPitch + j0 + kb);
+        const bf16x8 yh = load8(yt + ((rl * 2) * 32 + i) * kYPitch + j0 + kb);
+        const bf16x8 yl = load8(yt + ((rl * 2 + 1) * 32 + i) * kYPitch + j0 + kb);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(yh, wh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(yl, wh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(yh, wl, acc, 0, 0, 0);
       }
-      uint16_t* orow = vout + (size_t)row * nx * kC;
+      // lane: voxel x0 + i, outputs 8 g + 4 (lane / 32) .. +3 for g = 0..3: 8 bytes each
+      uint16_t* ov = vout + ((size_t)row * nx + x0 + i) * kC + 4 * (lane / 32);
 #pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        const int x = x0 + mfma_row(rr, lane);
-        orow[(size_t)x * kC + i] = f2bf(gelu(acc[rr] + bo));
+      for (int g = 0; g < 4; ++g) {
+        uint32_t w[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rr = 4 * g + 2 * h;
+          w[h] = (uint32_t)f2bf(gelu(acc[rr] + bo[rr])) | ((uint32_t)f2bf(gelu(acc[rr + 1] + bo[rr + 1])) << 16);
+        }
+        *reinterpret_cast<uint2*>(ov + 8 * g) = make_uint2(w[0], w[1]);
       }
     }
   }
@@ -385,31 +397,22 @@ __global__ __launch_bounds__(256) void k_proj(const FArgs a, const uint16_t* __r
   const size_t tile = (size_t)blockIdx.x * 4 + wave;   // 32 voxels per wave
   const size_t x0 = tile * 32;
   if (x0 >= a.nvox) return;
-  float part[16];
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) part[rr] = 0.f;
+  // accumulator rr of lane l: hidden unit h0 + mfma_row(rr, l) of voxel x0 + l % 32;
+  // a lane sums its 16 units of each block of 32, its partner lane l ^ 32 the other 16
+  float part = 0.f;
   const uint16_t* vt = v + x0 * kC;
   for (int h0 = 0; h0 < kH; h0 += 32) {
     const f32x16 acc = mix32(vt, 0, a.Q1 + (size_t)h0 * kC, lane);
-    const int h = h0 + lane % 32;
-    const float qb = a.q1[h], q2w = a.Q2[h];
-#pragma unroll
-    for (int rr = 0; rr < 16; ++rr) part[rr] += q2w * gelu(acc[rr] + qb);
-  }
-  // sum over the 32 hidden units held by lanes of the same half-wave
-#pragma unroll
-  for (int rr = 0; rr < 16; ++rr) {
-    float s = part[rr];
-#pragma unroll
-    for (int off = 16; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    part[rr] = s;
-  }
-  if (lane % 32 == 0) {
 #pragma unroll
     for (int rr = 0; rr < 16; ++rr) {
-      const size_t x = x0 + mfma_row(rr, lane);
-      out[x] = eta[x] + part[rr] + a.q2;
+      const int h = h0 + mfma_row(rr, lane);
+      part += a.Q2[h] * gelu(acc[rr] + a.q1[h]);
     }
+  }
+  part += __shfl_xor(part, 32, 64);
+  if (lane < 32) {
+    const size_t x = x0 + lane;
+    out[x] = eta[x] + part + a.q2;
   }
 }
 
