@@ -487,10 +487,10 @@ int pf_batch_size(const pf_ctx *ctx);  /* number of instances, 0 for NULL */
  * 5e-3). The forward pass runs with BF16 activations and weights and FP32
  * accumulation (matrix cores for the channel mixing and the projection).
  *
- * The prediction is accepted when the backward-Euler residual of the macro
- * step, rho = max |f~ - f^n + S L dt dF/df(f~)| with dF/df = chem
- * - 2 kappa lap f - mech at the equilibrium of f~, is <= tol; otherwise the
- * context falls back to S plain steps from f^n. Supported: a single-instance
+ * The prediction is accepted when the residual of the macro step of S plain
+ * steps from f^n to f~ (the summed plain steps with both sums by the
+ * end-corrected trapezoid rule; see pf_macro_residual) is <= tol; otherwise
+ * the context falls back to S plain steps from f^n. Supported: a single-instance
  * context, n_var = 1, the homogeneous spectral path (one stiffness, linear h,
  * no plastic strain), nx a multiple of 32, every axis <= 128, modes <= 16. */
 typedef struct pf_fno pf_fno;
