@@ -121,7 +121,9 @@ typedef struct {
                               the crystal-frame material every grain shares;
                               grain g uses it turned by its rotation.       */
   const uint8_t *grain_id; /* device [nz][ny][nx], or NULL if n_grains == 1;
-                              must stay valid until pf_destroy              */
+                              every value below n_grains (read once by
+                              pf_init: PF_EINVAL otherwise); must stay
+                              valid until pf_destroy                        */
   const float *eta0;       /* device [n_var][nz][ny][nx] initial f          */
   double C_ref[36];        /* reference medium of the fixed point (6x6)     */
   int32_t C_ref_auto;      /* 1: use the mean of all C_grain and C_var      */

@@ -1103,6 +1103,25 @@ int pf_batch_init(const pf_problem* probs, int32_t n_inst, void* workspace, size
       }
     }
     a.spec = reinterpret_cast<float2*>(ws + L.spec);
+    if (a.gid) {
+      // every grain id must index the tables: block maxima of the field in
+      // the spectral buffer (unused until the first transform), reduced here
+      constexpr int kGidBlocks = 256;
+      int gmax[kGidBlocks];
+      int* dmax = reinterpret_cast<int*>(a.spec);
+      if ((e = pfl::grain_id_max(a.gid, g.nvox, dmax, kGidBlocks, c->stream)) != hipSuccess ||
+          (e = hipMemcpyAsync(gmax, dmax, sizeof(gmax), hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+          (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return bail(e, "grain id check");
+      const int mx = *std::max_element(gmax, gmax + kGidBlocks);
+      if (mx >= G) {
+        fprintf(stderr, "pf_init: grain_id holds %d, not below n_grains = %d\n", mx, G);
+        hipHostFree(c->host_status);
+        hipHostFree(c->host_loads);
+        delete c;
+        return PF_EINVAL;
+      }
+    }
     float2* tw = reinterpret_cast<float2*>(ws + L.tw);
     a.tw_xh = tw;
     a.tw_x = tw + g.nx / 2;

@@ -193,6 +193,8 @@ hipError_t kh_z_update(const KArgs& a, int mode, hipStream_t s);
 hipError_t raw_x_forward(const KArgs& a, const float* real, int ncomp, hipStream_t s);
 hipError_t raw_z(const KArgs& a, int ncomp, int dir, hipStream_t s);
 hipError_t raw_x_inverse(const KArgs& a, float* real, int ncomp, float scale, hipStream_t s);
+// block maxima (nblk of them, into out) of n grain ids
+hipError_t grain_id_max(const uint8_t* gid, size_t n, int* out, int nblk, hipStream_t s);
 bool supported_axis(int n);
 // FFT plans of the y and z passes: elements per thread and radix stages of
 // variant k on an axis of length n (0 stages if there is no such plan), and

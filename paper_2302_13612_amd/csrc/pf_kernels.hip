@@ -1390,6 +1390,22 @@ __global__ __launch_bounds__(1024) void k_fin_pc(const KArgs a, int nblk, int it
   }
 }
 
+// Largest grain id of a field (checked against the grain count at set-up):
+// block maxima of a grid-stride pass, reduced on the host.
+__global__ __launch_bounds__(256) void k_gid_max(const uint8_t* __restrict__ gid, size_t n, int* __restrict__ out) {
+  __shared__ int red[256];
+  int m = 0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256)
+    m = max(m, (int)gid[i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
 }  // namespace pft
 
 // ====================================================================== host
@@ -1826,6 +1842,11 @@ hipError_t div_z(const KArgs& a, hipStream_t s) {
 hipError_t flux_x(const KArgs& a, hipStream_t s) {
   const dim3 grid(x_blocks(a));
   PF_SWITCH_M(a.nx, (k_x_flux<M><<<grid, xthreads<M>(), 0, s>>>(a)));
+  return hipGetLastError();
+}
+
+hipError_t grain_id_max(const uint8_t* gid, size_t n, int* out, int nblk, hipStream_t s) {
+  k_gid_max<<<nblk, 256, 0, s>>>(gid, n, out);
   return hipGetLastError();
 }
 

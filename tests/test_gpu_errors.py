@@ -12,6 +12,7 @@
   the same checkpoint set back into the running context (both restart the
   strain extrapolation), and within the fixed point's tolerance against the
   uninterrupted run.
+* A grain id at or above n_grains is rejected by pf_init (PF_EINVAL).
 """
 
 import math
@@ -140,3 +141,20 @@ def test_restart_fixed_point_path():
     # the extrapolated first iterates differ; each step's fixed point stops at
     # a relative strain change of 1e-6, an order below what reaches f
     assert d <= 1e-6
+
+
+def test_grain_id_out_of_range_rejected():
+    # a grain id at or above n_grains would index past the per-grain tables
+    cfg = cases.small_polycrystal(n_var=2)
+    G = cfg["rotations"].shape[0]      # n_grains handed to the library
+    bad = cfg["gid"].copy()
+    bad[3, 4, 5] = G
+    print(f"\n[errors] grain id {G} with n_grains = {G}, polycrystal 32^3", flush=True)
+    with pytest.raises(binding.PfError) as ei:
+        cases.gpu_solver(dict(cfg, gid=bad))
+    assert ei.value.code == binding.PF_EINVAL
+    # the same field with every id in range is accepted
+    ok = bad.copy()
+    ok[3, 4, 5] = G - 1
+    solver, _ = cases.gpu_solver(dict(cfg, gid=ok))
+    solver.close()
