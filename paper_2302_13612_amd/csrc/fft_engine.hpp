@@ -333,4 +333,65 @@ __device__ __forceinline__ void fft_pencil(float2 (&v)[P::E], const View& lds, i
   run_stages<N, P, 1, 0, DIR, true>(v, lds, t, tw, typename P::R{});
 }
 
+// NC pencils of one block transformed in lockstep: every stage's LDS
+// exchange of all NC pencils (disjoint views) shares one pair of barriers.
+template <int N, class P, int R, int NS, int SI, int DIR, bool FIRST, bool LAST, int NC, class View, class TW>
+__device__ __forceinline__ void stockham_stage_n(float2 (&v)[NC][P::E], const View (&lds)[NC], int t, const TW& tw) {
+  constexpr int E = P::E;
+  constexpr int T = N / E;
+  constexpr int NB = E / R;
+  static_assert(E % R == 0, "radix must divide elements per thread");
+  float2 a[NC][E];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int j = t + T * q;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if constexpr (FIRST) a[c][q * R + r] = v[c][q + r * NB];
+        else a[c][q * R + r] = lds[c].read(j + r * (N / R));
+      }
+      if constexpr (!FIRST) {
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+          a[c][q * R + r] = cmul(a[c][q * R + r], stage_twiddle<N, P, R, NS, SI, DIR>(tw, t, q, r));
+      }
+      dft<R, DIR>(&a[c][q * R]);
+    }
+  if constexpr (LAST) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int q = 0; q < NB; ++q)
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[c][q + r * NB] = a[c][q * R + r];
+  } else {
+    View::sync();
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int j = t + T * q;
+        const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds[c].write(base + r * NS, a[c][q * R + r]);
+      }
+    View::sync();
+  }
+}
+
+template <int N, class P, int NS, int SI, int DIR, bool FIRST, int NC, class View, class TW, int R0, int... Rest>
+__device__ __forceinline__ void run_stages_n(float2 (&v)[NC][P::E], const View (&lds)[NC], int t, const TW& tw,
+                                             Radices<R0, Rest...>) {
+  constexpr bool LAST = sizeof...(Rest) == 0;
+  stockham_stage_n<N, P, R0, NS, SI, DIR, FIRST, LAST, NC>(v, lds, t, tw);
+  if constexpr (!LAST) run_stages_n<N, P, NS * R0, SI + 1, DIR, false, NC>(v, lds, t, tw, Radices<Rest...>{});
+}
+
+template <int N, int DIR, class P, int NC, class View, class TW>
+__device__ __forceinline__ void fft_pencils(float2 (&v)[NC][P::E], const View (&lds)[NC], int t, const TW& tw) {
+  run_stages_n<N, P, 1, 0, DIR, true, NC>(v, lds, t, tw, typename P::R{});
+}
+
 }  // namespace pft

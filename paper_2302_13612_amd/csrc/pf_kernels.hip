@@ -464,7 +464,10 @@ template <int N, int C, int PK>
 __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs a, int nblk_x) {
   using P = PV<N, PK>;
   constexpr int E = P::E, T = N / E;
-  __shared__ float2 lds[N * C];
+  // two pencils per LDS exchange round (half the barriers of one at a time)
+  // where their two buffers fit in 64 KiB
+  constexpr int NC = (2 * N * C * 8 <= 65536) ? 2 : 1;
+  __shared__ float2 lds[NC * N * C];
   __shared__ double ebar[6];
   const int cc = threadIdx.x % C, t = threadIdx.x / C;
   const ZCol zc = z_col(a, xcd_logical(blockIdx.x, gridDim.x), C, cc);
@@ -473,7 +476,7 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs 
   const DevState* st = a.state + inst;
   if (st->st.done) return;
   if (zc.first) {
-    // the pass's LDS (N C float2 >= blockDim doubles) is free until the transforms
+    // the pass's LDS (NC N C float2 >= blockDim doubles) is free until the transforms
     fin_ms(a, inst, nblk_x, reinterpret_cast<double*>(lds), ebar);
     __syncthreads();
   }
@@ -489,9 +492,12 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs 
       v[c][m] = valid ? col[c * cs + (size_t)(t + T * m) * zs] : make_float2(0.f, 0.f);
   TwCache<N, P, 1> twf;
   twf.load(a.tw_z, t);
-  const ColView<C> view{lds + cc};
+  ColView<C> views[NC];
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<N, 1, P>(v[c], view, t, twf);
+  for (int c = 0; c < NC; ++c) views[c] = ColView<C>{lds + c * N * C + cc};
+#pragma unroll
+  for (int g = 0; g < 6; g += NC)
+    fft_pencils<N, 1, P, NC>(*reinterpret_cast<float2(*)[NC][E]>(&v[g]), views, t, twf);
   const int kxv = valid ? kx : 0;
   float xi[3] = {(float)kxv / (float)a.nx, (float)signed_k(ky, a.ny) / (float)a.ny, 0.f};
   const float inz = 1.f / (float)a.nz;
@@ -513,7 +519,8 @@ __global__ __launch_bounds__((col_threads<N, PK, C>())) void k_z_ms(const KArgs 
   }
   const TwCache<N, P, -1> twi = twf.conj();
 #pragma unroll
-  for (int c = 0; c < 6; ++c) fft_pencil<N, -1, P>(v[c], view, t, twi);
+  for (int g = 0; g < 6; g += NC)
+    fft_pencils<N, -1, P, NC>(*reinterpret_cast<float2(*)[NC][E]>(&v[g]), views, t, twi);
   // streaming stores (the loads stay plain: see gld)
   if (valid) {
 #pragma unroll
